@@ -1,0 +1,370 @@
+"""Pins for the CPU oracle: each check compares it with something other than
+itself -- dense linear algebra, closed forms of Algorithm 1 and of the V-cycle,
+characterisations of the greedy set constructions, and published generator
+values.  No GPU involved."""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import amg
+from paper_2103_07537_amd.inputs import make_system, rng_u64
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden_splitmix():
+    vals = []
+    with open(os.path.join(HERE, "golden", "splitmix64.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                vals.append(int(line, 16))
+    return vals
+
+
+def test_splitmix_golden_values():
+    gold = _golden_splitmix()
+    got = rng_u64(0, 0, np.arange(3))
+    assert [int(v) for v in got] == gold
+    keys = amg.priority_keys(4, seed=0, level=0)
+    assert int(keys[0]) >> 32 == gold[0] >> 32
+    assert [int(k) & 0xFFFFFFFF for k in keys] == [0, 1, 2, 3]
+
+
+def _systems():
+    return [make_system(5, 2, 0.7, seed=3, blk1_scale=2.0, a10_scale=0.5),
+            make_system(3, 3, 0.4, seed=5, kappa="lognormal", blk1_scale=0.5, a10_scale=1.5)]
+
+
+def _dense(s):
+    return [[s.blocks[f][g].to_scipy().toarray() for g in range(2)] for f in range(2)]
+
+
+# ----------------------------------------------------------------------------- strength
+
+def test_strength_matches_frobenius_and_is_symmetric():
+    s = make_system(6, 2, 0.3, seed=2, kappa="lognormal")
+    A = amg.BsrM(s.N, s.N, s.blocks[0][0].row_ptr, s.blocks[0][0].col_idx, s.blocks[0][0].vals)
+    ptr, idx, w2 = amg.strength_graph(A, 0.0)
+    S = sp.csr_matrix((w2, idx, ptr), shape=(s.N, s.N)).toarray()
+    assert np.allclose(S, S.T, rtol=0, atol=0)
+    Ad = s.blocks[0][0].to_scipy().toarray()
+    d = 3
+    for i in range(s.N):
+        for j in range(s.N):
+            if i == j:
+                continue
+            a = np.linalg.norm(Ad[i * d:(i + 1) * d, j * d:(j + 1) * d]) ** 2
+            b = np.linalg.norm(Ad[j * d:(j + 1) * d, i * d:(i + 1) * d]) ** 2
+            assert S[i, j] == pytest.approx(max(a, b), rel=1e-14, abs=0)
+
+
+def test_strength_threshold_drops_weak_edges():
+    # path 0-1-2 with a weak (0,1) edge and a strong (1,2) edge, 1x1 blocks
+    rp = np.array([0, 2, 5, 7], np.int32)
+    ci = np.array([0, 1, 0, 1, 2, 1, 2], np.int32)
+    v = np.array([4.0, -0.01, -0.01, 4.0, -2.0, -2.0, 4.0]).reshape(-1, 1, 1)
+    A = amg.BsrM(3, 3, rp, ci, v)
+    ptr, idx, w2 = amg.strength_graph(A, 0.25)
+    assert list(idx[ptr[1]:ptr[2]]) == [2] and list(idx[ptr[0]:ptr[1]]) == []
+    ptr, idx, w2 = amg.strength_graph(A, 0.0)
+    assert list(idx[ptr[1]:ptr[2]]) == [0, 2]
+
+
+# ----------------------------------------------------------------------------- aggregation
+
+def _hops(ptr, idx, n):
+    G = sp.csr_matrix((np.ones(idx.shape[0]), idx, ptr), shape=(n, n))
+    I = sp.identity(n, format="csr")
+    G1 = ((G + I) > 0).astype(np.int32)
+    G2 = ((G1 @ G1) > 0)
+    return G1.toarray().astype(bool), G2.toarray()
+
+
+def _random_graph(n, p, seed):
+    rng = np.random.default_rng(seed)
+    M = rng.random((n, n)) < p
+    M = np.triu(M, 1)
+    M = M | M.T
+    w = rng.integers(1, 4, size=(n, n)).astype(float)
+    w = np.triu(w, 1)
+    w = w + w.T
+    S = sp.csr_matrix(np.where(M, w, 0.0))
+    S.sort_indices()
+    return S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.astype(np.float64)
+
+
+@pytest.mark.parametrize("case", ["grid2d", "grid3d", "random"])
+def test_aggregates_are_the_greedy_distance2_mis(case):
+    lib = amg._load()
+    if case == "random":
+        ptr, idx, w2 = _random_graph(60, 0.06, 11)
+        n = 60
+    else:
+        s = make_system(9, 2, 0.5, seed=4) if case == "grid2d" else make_system(5, 3, 0.5, seed=4)
+        A = amg.BsrM(s.N, s.N, s.blocks[0][0].row_ptr, s.blocks[0][0].col_idx, s.blocks[0][0].vals)
+        ptr, idx, w2 = amg.strength_graph(A, 0.0)
+        n = s.N
+    keys = amg.priority_keys(n, seed=7, level=1)
+    agg = np.zeros(n, np.int32)
+    nagg = np.zeros(1, np.int32)
+    assert lib.or_aggregate(n, ptr, idx, w2, keys, agg, nagg) == 0
+    nagg = int(nagg[0])
+    G1, G2 = _hops(ptr, idx, n)
+    # partition: every node in exactly one aggregate, none empty
+    assert agg.min() >= 0 and agg.max() == nagg - 1
+    assert np.all(np.bincount(agg, minlength=nagg) > 0)
+    # reconstruct the greedy root set by its characterisation and compare with the aggregates
+    order = sorted(range(n), key=lambda i: int(keys[i]), reverse=True)
+    R = []
+    for v in order:
+        if not any(G2[v, r] for r in R):
+            R.append(v)
+    R = sorted(R)
+    assert len(R) == nagg
+    # roots pairwise >= 3 hops apart, every node within 2 hops of a root of larger key
+    for a in R:
+        for b in R:
+            assert a == b or not G2[a, b]
+    for v in range(n):
+        if v not in R:
+            assert any(G2[v, r] and int(keys[r]) > int(keys[v]) for r in R)
+    # aggregate k has root R[k] (ids ordered by root index) and contains its neighbours
+    for k, r in enumerate(R):
+        assert agg[r] == k
+        for j in np.nonzero(G1[r])[0]:
+            assert agg[j] == k
+    # every other node is attached to a neighbouring aggregate of maximal weight
+    W = sp.csr_matrix((w2, idx, ptr), shape=(n, n)).toarray()
+    phase1 = set(R) | {j for r in R for j in np.nonzero(G1[r])[0]}
+    for v in range(n):
+        if v in phase1:
+            continue
+        nb = [j for j in np.nonzero(W[v])[0] if j in phase1]
+        best = max(W[v, j] for j in nb)
+        assert W[v, [j for j in nb if agg[j] == agg[v]]].max() == best
+        assert agg[v] == min(agg[j] for j in nb if W[v, j] == best)
+
+
+def test_isolated_nodes_are_singletons():
+    lib = amg._load()
+    ptr = np.array([0, 0, 1, 2, 2], np.int32)
+    idx = np.array([2, 1], np.int32)
+    w2 = np.ones(2)
+    keys = amg.priority_keys(4, 0, 0)
+    agg = np.zeros(4, np.int32)
+    nagg = np.zeros(1, np.int32)
+    lib.or_aggregate(4, ptr, idx, w2, keys, agg, nagg)
+    assert int(nagg[0]) == 3 and agg[0] != agg[3] and agg[1] == agg[2]
+
+
+# ----------------------------------------------------------------------------- transfers and RAP
+
+@pytest.mark.parametrize("si", [0, 1])
+def test_tentative_reproduces_near_null_space(si):
+    s = _systems()[si]
+    h = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=1))
+    assert len(h.levels) >= 2
+    B = [np.ones(s.N * d) for d in s.dofs]
+    for lev in h.levels[:-1]:
+        nxt = []
+        for f in range(2):
+            P = lev.P[f].toarray()
+            # one nonzero per row, in the aggregate's column of the same component
+            assert np.all((P != 0).sum(axis=1) == 1)
+            assert np.allclose(P.T @ P, np.eye(P.shape[1]), atol=1e-15)
+            Bc = np.linalg.lstsq(P, B[f], rcond=None)[0]
+            assert np.allclose(P @ Bc, B[f], rtol=1e-15, atol=1e-15)
+            nxt.append(Bc)
+        B = nxt
+
+
+@pytest.mark.parametrize("si", [0, 1])
+def test_galerkin_equals_dense_triple_product(si):
+    s = _systems()[si]
+    h = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=1))
+    for lvl in range(len(h.levels) - 1):
+        lev, nxt = h.levels[lvl], h.levels[lvl + 1]
+        for f in range(2):
+            for g in range(2):
+                Af = lev.csr[f][g].toarray()
+                Pf, Pg = lev.P[f].toarray(), lev.P[g].toarray()
+                ref = Pf.T @ Af @ Pg
+                got = nxt.csr[f][g].toarray()
+                # forward-error scale of the sum: |P_f|^T |A_fg| |P_g|
+                scale = np.abs(Pf).T @ np.abs(Af) @ np.abs(Pg)
+                assert np.all(np.abs(got - ref) <= 1e-13 * scale)
+        # monolithic form with the block-diagonal transfers
+        Afull = sp.bmat([[lev.csr[0][0], lev.csr[0][1]], [lev.csr[1][0], lev.csr[1][1]]]).toarray()
+        Pfull = sp.block_diag([lev.P[0], lev.P[1]]).toarray()
+        Acfull = sp.bmat([[nxt.csr[0][0], nxt.csr[0][1]], [nxt.csr[1][0], nxt.csr[1][1]]]).toarray()
+        scale = np.abs(Pfull).T @ np.abs(Afull) @ np.abs(Pfull)
+        assert np.all(np.abs(Pfull.T @ Afull @ Pfull - Acfull) <= 1e-13 * scale)
+
+
+# ----------------------------------------------------------------------------- smoother
+
+def _gs_matrix(Ad, colour, d):
+    """Block lower triangle in colour order: D_i on the diagonal and A_ij for colour(j) < colour(i)."""
+    n = colour.shape[0]
+    M = np.zeros_like(Ad)
+    for i in range(n):
+        for j in range(n):
+            if i == j or colour[j] < colour[i]:
+                M[i * d:(i + 1) * d, j * d:(j + 1) * d] = Ad[i * d:(i + 1) * d, j * d:(j + 1) * d]
+    return M
+
+
+def test_colouring_is_valid_first_fit():
+    for s in _systems() + [make_system(7, 2, 0.1, seed=9)]:
+        h = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=1))
+        for lev in h.levels[:-1]:
+            for f in range(2):
+                A = lev.csr[f][f]
+                d = lev.dofs[f]
+                Pn = (abs(A) @ sp.kron(sp.identity(lev.n), np.ones((d, 1))))
+                node = (sp.kron(sp.identity(lev.n), np.ones((1, d))) @ Pn).toarray() != 0
+                node = node | node.T
+                col = lev.colour[f]
+                for i in range(lev.n):
+                    nb = [j for j in np.nonzero(node[i])[0] if j != i]
+                    assert all(col[j] != col[i] for j in nb)
+                    lower = {col[j] for j in nb if j < i}
+                    assert col[i] == min(c for c in range(len(lower) + 1) if c not in lower)
+
+
+@pytest.mark.parametrize("si", [0, 1])
+def test_inner_gs_is_forward_substitution(si):
+    s = _systems()[si]
+    h = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=1))
+    lev = h.levels[0]
+    rng = np.random.default_rng(1)
+    for f in range(2):
+        Ad = lev.csr[f][f].toarray()
+        M = _gs_matrix(Ad, lev.colour[f], lev.dofs[f])
+        r = rng.standard_normal(Ad.shape[0])
+        e = amg.inner_gs(lev, f, r, 1)
+        assert np.allclose(e, np.linalg.solve(M, r), rtol=1e-13, atol=1e-13 * np.abs(e).max())
+        # two sweeps: e2 = e1 + M^-1 (r - A e1)
+        e2 = amg.inner_gs(lev, f, r, 2)
+        e1 = np.linalg.solve(M, r)
+        assert np.allclose(e2, e1 + np.linalg.solve(M, r - Ad @ e1), rtol=1e-12, atol=1e-12 * np.abs(e2).max())
+
+
+@pytest.mark.parametrize("si", [0, 1])
+def test_bgs_closed_form(si):
+    s = _systems()[si]
+    p = amg.Params(max_coarse=1, omega=0.6)
+    h = amg.setup(s.blocks, s.dofs, p)
+    lev = h.levels[0]
+    A = [[lev.csr[f][g].toarray() for g in range(2)] for f in range(2)]
+    M = [np.linalg.inv(_gs_matrix(A[f][f], lev.colour[f], lev.dofs[f])) for f in range(2)]
+    rng = np.random.default_rng(5)
+    b0, b1 = rng.standard_normal(A[0][0].shape[0]), rng.standard_normal(A[1][1].shape[0])
+    x0, x1 = rng.standard_normal(b0.shape), rng.standard_normal(b1.shape)
+    w = p.omega
+    # from zero: x0 = w M0 b0 ; x1 = w M1 (b1 - A10 x0)
+    z0, z1 = amg.bgs(lev, np.zeros_like(b0), np.zeros_like(b1), b0, b1, p)
+    r0 = w * M[0] @ b0
+    assert np.allclose(z0, r0, rtol=1e-12, atol=1e-12)
+    assert np.allclose(z1, w * M[1] @ (b1 - A[1][0] @ r0), rtol=1e-12, atol=1e-12)
+    # from a nonzero iterate: line 7 uses the updated x0
+    y0, y1 = amg.bgs(lev, x0, x1, b0, b1, p)
+    n0 = x0 + w * M[0] @ (b0 - A[0][0] @ x0 - A[0][1] @ x1)
+    n1 = x1 + w * M[1] @ (b1 - A[1][0] @ n0 - A[1][1] @ x1)
+    assert np.allclose(y0, n0, rtol=1e-12, atol=1e-12)
+    assert np.allclose(y1, n1, rtol=1e-12, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------- V-cycle
+
+def test_one_level_vcycle_is_direct_solve():
+    s = _systems()[0]
+    h = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=10 ** 9))
+    assert len(h.levels) == 1
+    A = s.to_scipy().toarray()
+    assert np.allclose(amg.vcycle(h, s.b), np.linalg.solve(A, s.b), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("si", [0, 1])
+def test_two_grid_vcycle_dense(si):
+    s = _systems()[si]
+    p = amg.Params(max_levels=2, max_coarse=1, omega=0.7)
+    h = amg.setup(s.blocks, s.dofs, p)
+    assert len(h.levels) == 2
+    lev = h.levels[0]
+    A = [[lev.csr[f][g].toarray() for g in range(2)] for f in range(2)]
+    Afull = np.block(A)
+    M = [np.linalg.inv(_gs_matrix(A[f][f], lev.colour[f], lev.dofs[f])) for f in range(2)]
+    n0 = A[0][0].shape[0]
+    w = p.omega
+
+    def smooth(x, b):
+        x0, x1 = x[:n0], x[n0:]
+        x0 = x0 + w * M[0] @ (b[:n0] - A[0][0] @ x0 - A[0][1] @ x1)
+        x1 = x1 + w * M[1] @ (b[n0:] - A[1][0] @ x0 - A[1][1] @ x1)
+        return np.concatenate([x0, x1])
+
+    P = np.block([[lev.P[0].toarray(), np.zeros((n0, lev.P[1].shape[1]))],
+                  [np.zeros((A[1][1].shape[0], lev.P[0].shape[1])), lev.P[1].toarray()]])
+    Ac = P.T @ Afull @ P
+    b = s.b
+    x = smooth(np.zeros_like(b), b)
+    x = x + P @ np.linalg.solve(Ac, P.T @ (b - Afull @ x))
+    x = smooth(x, b)
+    assert np.allclose(amg.vcycle(h, b), x, rtol=1e-11, atol=1e-11 * np.abs(x).max())
+
+
+def test_vcycle_is_linear():
+    s = make_system(12, 2, 0.5, seed=8)
+    h = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=60))
+    assert len(h.levels) >= 3
+    rng = np.random.default_rng(3)
+    r, t = rng.standard_normal(s.n_dofs), rng.standard_normal(s.n_dofs)
+    lhs = amg.vcycle(h, 2.5 * r - 0.75 * t)
+    rhs = 2.5 * amg.vcycle(h, r) - 0.75 * amg.vcycle(h, t)
+    assert np.linalg.norm(lhs - rhs) <= 1e-13 * np.linalg.norm(rhs)
+
+
+def test_decoupled_blocks_when_gamma_is_zero():
+    s = make_system(10, 2, 0.0, seed=2, blk1_scale=3.0)
+    h = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=50))
+    rng = np.random.default_rng(0)
+    r = rng.standard_normal(s.n_dofs)
+    r2 = r.copy()
+    n0 = s.N * s.dofs[0]
+    r2[n0:] = rng.standard_normal(s.n_dofs - n0)
+    assert np.array_equal(amg.vcycle(h, r)[:n0], amg.vcycle(h, r2)[:n0])
+
+
+# ----------------------------------------------------------------------------- GMRES
+
+@pytest.mark.parametrize("si", [0, 1])
+def test_two_grid_gmres_matches_dense_lu(si):
+    s = _systems()[si]
+    h = amg.setup(s.blocks, s.dofs, amg.Params(max_levels=2, max_coarse=1))
+    x, info = amg.gmres(h, s.b, rtol=1e-12)
+    assert info.converged
+    xr = np.linalg.solve(s.to_scipy().toarray(), s.b)
+    assert np.linalg.norm(x - xr) <= 1e-10 * np.linalg.norm(xr)
+
+
+def test_gmres_with_exact_preconditioner_takes_one_iteration():
+    s = _systems()[1]
+    h = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=1))
+    A = s.to_scipy().toarray()
+    Ainv = np.linalg.inv(A)
+    x, info = amg.gmres(h, s.b, rtol=1e-10, precond=lambda v: Ainv @ v)
+    assert info.iterations == 1 and info.converged
+
+
+def test_gmres_restarts_and_reports_true_residual():
+    s = make_system(16, 2, 0.5, seed=1)
+    h = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=100))
+    x, info = amg.gmres(h, s.b, rtol=1e-9, restart=5)
+    A = s.to_scipy()
+    rel = np.linalg.norm(s.b - A @ x) / np.linalg.norm(s.b)
+    assert info.converged and info.iterations > 5 and rel <= 1e-9
+    assert info.rel_residual == pytest.approx(rel, rel=1e-6)
