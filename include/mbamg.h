@@ -1,0 +1,174 @@
+/*
+ * mbamg.h -- C-ABI of libmbamg: monolithic blocked algebraic multigrid for
+ * coupled two-field block systems on one MI355X (gfx950).
+ *
+ * The problem statement follows Sec. 4.1-4.2 of Ohm et al., "A monolithic
+ * algebraic multigrid framework for multiphysics applications with examples
+ * from resistive MHD": a block system A x = b with blocks A_fg
+ * (eq. block-prec-form), grouped as a 2x2 system (eq. 2x2system), whose
+ * multigrid hierarchy is built from the matrix alone.  One V-cycle (Sec. 3,
+ * MGV figure) with the damped block Gauss-Seidel smoother of Algorithm 1
+ * (Sec. 4.3.2) and block-diagonal piecewise-constant transfers
+ * (Sec. 4.3.1, eq. blocktransfers) serves as a right preconditioner inside
+ * restarted GMRES; coarse operators are Galerkin products P^T A P (Sec. 3).
+ *
+ * Layouts
+ *   Matrix blocks: BSR, int32 row pointers and column indices (columns sorted
+ *   within each row), FP64 values, each block br x bc row-major.  Block (f,g)
+ *   has br = dofs[f], bc = dofs[g].  A_00 must be structurally symmetric.
+ *   Vectors: FP64, blocked [x_0; x_1]; segment f holds n_nodes*dofs[f]
+ *   entries, node-major (x_f[node*dofs[f] + component]).
+ *
+ * Ownership
+ *   mbamg_setup deep-copies the blocks (host or device memory), so the caller
+ *   may free them on return.  The hierarchy owns all of its device memory
+ *   until mbamg_destroy.  Vector arguments are caller-owned device buffers.
+ *
+ * Streams
+ *   hip_stream may be NULL (the default stream).  mbamg_vcycle is
+ *   asynchronous on the stream; mbamg_setup and mbamg_solve synchronise it.
+ *   A hierarchy must not be used from two streams or threads at once.
+ *
+ * Errors
+ *   Every entry point returns an mbamg_status; negative values are errors and
+ *   mbamg_last_error() returns a message for the calling thread.  No C++
+ *   exception crosses this interface.
+ */
+#ifndef MBAMG_H
+#define MBAMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MBAMG_OK = 0,
+    MBAMG_NOT_CONVERGED = 1,   /* solve stopped at max_iters; x holds the last iterate */
+    MBAMG_E_INVALID = -1,      /* inconsistent sizes, NULL pointers, aliasing, bad params */
+    MBAMG_E_NOMEM = -2,        /* device or host allocation failed */
+    MBAMG_E_HIP = -3,          /* a HIP runtime call failed */
+    MBAMG_E_SINGULAR = -4,     /* a nodal diagonal block or the coarsest matrix is singular */
+    MBAMG_E_STATE = -5         /* the hierarchy cannot do this (e.g. wrong precision form) */
+} mbamg_status;
+
+/* One matrix block in BSR form.  nnzb == 0 (pointers may then be NULL) is a
+ * zero block.  on_device != 0 means the three arrays are device pointers. */
+typedef struct {
+    int32_t n_brows, n_bcols, br, bc;
+    int64_t nnzb;
+    const int32_t* row_ptr;   /* n_brows + 1 */
+    const int32_t* col_idx;   /* nnzb */
+    const double* vals;       /* nnzb * br * bc */
+    int32_t on_device;
+} mbamg_bsr;
+
+/* Field grouping (eq. 2x2system): block f has dofs[f] unknowns per node, the
+ * first n_vec[f] of them vector components.  Only n_blocks == 2 is built. */
+typedef struct {
+    int32_t n_blocks;
+    int32_t dofs[4];
+    int32_t n_vec[4];
+} mbamg_field_map;
+
+typedef struct {
+    double omega;             /* Algorithm 1 damping (default 0.8) */
+    int32_t bgs_sweeps;       /* Algorithm 1 sweeps for pre- and post-smoothing (1) */
+    int32_t inner_sweeps;     /* multicolour nodal-block GS sweeps per sub-block solve (1) */
+    double theta;             /* strength threshold on squared block norms (0) */
+    int32_t max_levels;       /* (10) */
+    int32_t max_coarse;       /* stop coarsening at or below this many dofs (2500) */
+    int32_t clone_aggregates; /* block 1 reuses block 0's aggregates (1; required) */
+    int32_t reuse_P;          /* kept for the interface; P_11 = P_00 holds when clone is on */
+    int32_t precision;        /* 0: FP64 V-cycle + GMRES; 1: FP32 V-cycle inside FP64 FGMRES */
+    int32_t restart;          /* GMRES restart length (30, at most 64) */
+    int32_t max_iters;        /* (1000) */
+    int32_t learned;          /* 0 off; 1 per-aggregate weights supplied by mbamg_set_learned_weights */
+    const char* mlp_weights;  /* unused by the library itself (NULL) */
+    uint64_t seed;            /* aggregation priority seed (0) */
+} mbamg_params;
+
+typedef struct {
+    int32_t iterations, levels, used_learned;
+    double rel_residual;      /* true residual ||b - A x|| / ||b|| at exit */
+    double conv_factor;       /* (rel_residual)^(1/iterations) */
+    double op_complexity;     /* sum over levels of structural block entries / level 0 */
+    double t_setup_ms, t_solve_ms;
+} mbamg_info;
+
+typedef struct mbamg_hierarchy mbamg_hierarchy;
+
+/* Fill *p with the defaults listed above. */
+void mbamg_default_params(mbamg_params* p);
+
+/* Build the hierarchy: strength graph of A_00, distance-2 aggregation cloned
+ * to block 1, piecewise-constant P per block, Galerkin products for all four
+ * blocks on every level, colouring and nodal D^-1 for the smoother, and the
+ * inverse of the coarsest matrix.  A_blocks points to n_blocks*n_blocks
+ * blocks in row-major order (A_00, A_01, A_10, A_11).  Synchronous. */
+mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm,
+                         const mbamg_params* p, void* hip_stream, mbamg_hierarchy** out);
+
+/* z = M^-1 r: one V-cycle from a zero guess on the finest level.  r and z are
+ * device vectors in the blocked layout and must not alias.  Asynchronous. */
+mbamg_status mbamg_vcycle(mbamg_hierarchy* h, const double* r, double* z, void* hip_stream);
+
+/* w = A x on the finest level (device vectors, must not alias).  Asynchronous. */
+mbamg_status mbamg_apply(mbamg_hierarchy* h, const double* x, double* w, void* hip_stream);
+
+/* Solve A x = b by restarted GMRES (FGMRES when precision == 1), right
+ * preconditioned by one V-cycle, to ||b - A x|| <= rtol ||b||.  x is read as
+ * the initial guess and overwritten.  Returns MBAMG_NOT_CONVERGED after
+ * max_iters.  info may be NULL.  Synchronous. */
+mbamg_status mbamg_solve(mbamg_hierarchy* h, const double* b, double* x, double rtol,
+                         mbamg_info* info, void* hip_stream);
+
+mbamg_status mbamg_get_info(const mbamg_hierarchy* h, mbamg_info* info);
+void mbamg_destroy(mbamg_hierarchy* h);
+const char* mbamg_last_error(void);
+
+/* ---- hierarchy inspection (read-back for verification and tooling) ------ */
+
+/* Number of levels and, for level l, its node count. */
+mbamg_status mbamg_num_levels(const mbamg_hierarchy* h, int32_t* n_levels);
+mbamg_status mbamg_level_nodes(const mbamg_hierarchy* h, int32_t level, int32_t* n_nodes);
+
+/* Aggregate of every node of level l (l < n_levels-1), node order of the
+ * level as built by the Galerkin products (not the smoother's colour order).
+ * agg is a host buffer of n_nodes int32. */
+mbamg_status mbamg_copy_aggregates(const mbamg_hierarchy* h, int32_t level, int32_t* agg);
+
+/* Number of stored blocks of block (f,g) on level l. */
+mbamg_status mbamg_level_nnzb(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t g,
+                              int64_t* nnzb);
+
+/* Copy block (f,g) of level l in BSR form to host buffers sized by
+ * mbamg_level_nodes and mbamg_level_nnzb. */
+mbamg_status mbamg_copy_level_block(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t g,
+                                    int32_t* row_ptr, int32_t* col_idx, double* vals);
+
+/* Smoother colour of every node of block f on level l (host int32 buffer). */
+mbamg_status mbamg_copy_colours(const mbamg_hierarchy* h, int32_t level, int32_t f,
+                                int32_t* colour);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* Kernel timing with HIP events on the stream the kernels run on.  While
+ * enabled, every launch of the finest level's smoother and residual kernels is
+ * bracketed by events.  kind 0: smoother colour pass, 1: residual,
+ * 2: operator apply.  Reports launches, summed event time in ms and the
+ * algorithmic bytes those launches move (structural values, indices and
+ * vectors, as documented with the byte model). */
+mbamg_status mbamg_timing_enable(mbamg_hierarchy* h, int32_t enable);
+mbamg_status mbamg_timing_get(mbamg_hierarchy* h, int32_t kind, int64_t* launches,
+                              double* total_ms, double* bytes);
+
+/* Algorithmic bytes of one V-cycle of the current hierarchy and form. */
+mbamg_status mbamg_vcycle_bytes(const mbamg_hierarchy* h, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBAMG_H */

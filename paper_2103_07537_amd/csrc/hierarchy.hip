@@ -1,0 +1,1096 @@
+// Host orchestration of libmbamg: hierarchy construction (Sec. 4.3: blocked
+// aggregation cloned across blocks, block-diagonal piecewise-constant
+// transfers, Galerkin coarse operators), the V-cycle schedule (Sec. 3, MGV)
+// with the block Gauss-Seidel smoother (Sec. 4.3.2, Algorithm 1), restarted
+// GMRES / flexible GMRES, and the C-ABI declared in include/mbamg.h.
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+
+#include "setup_kernels.h"
+#include "solve_kernels.h"
+
+namespace mbamg {
+
+// ----------------------------------------------------------------------------
+// solve-format structures
+// ----------------------------------------------------------------------------
+struct SellPart {
+    int br = 0, bc = 0;
+    int64_t n_slots = 0, n_groups = 0;
+    DevBuf<int32_t> width;
+    DevBuf<int64_t> coff, voff;
+    DevBuf<uint32_t> mask;
+    DevBuf<int32_t> col;
+    DevBuf<double> v64;
+    DevBuf<float> v32;
+    std::vector<int64_t> h_coff;        // per slice
+    std::vector<int32_t> h_width;
+    std::vector<uint32_t> h_slot_nz;    // structural nonzeros per slot
+    std::vector<int32_t> h_slot_blocks; // stored blocks per slot
+
+    template <class T>
+    SellView<T> view() const;
+    // structural values and stored blocks over slices [s0, s1)
+    void stats(int s0, int s1, int64_t& nz, int64_t& blocks) const {
+        nz = 0;
+        blocks = 0;
+        for (int s = s0; s < s1; ++s)
+            for (int t = 0; t < h_width[s]; ++t) {
+                nz += h_slot_nz[h_coff[s] + t];
+                blocks += h_slot_blocks[h_coff[s] + t];
+            }
+    }
+};
+
+template <>
+SellView<double> SellPart::view<double>() const { return {width.p, coff.p, voff.p, mask.p, col.p, v64.p}; }
+template <>
+SellView<float> SellPart::view<float>() const { return {width.p, coff.p, voff.p, mask.p, col.p, v32.p}; }
+
+struct BlockLevel {
+    int d = 0, n = 0, n_colours = 0, n_slices = 0;
+    std::vector<int32_t> perm, iperm;          // colour order -> natural node, and back
+    std::vector<int32_t> colour;               // natural order
+    std::vector<int32_t> h_row0, h_nrow;
+    std::vector<int> colour_slice, colour_row;  // per colour: first slice, first row (+ end)
+    DevBuf<int32_t> row0, nrow, d_perm;
+    SellPart off, cpl, diag, dinv;
+    // transfer to the next level (colour orders of both levels)
+    DevBuf<int32_t> agg_p, mem_ptr, mem_idx;
+    DevBuf<double> q64;
+    DevBuf<float> q32;
+    SliceView slices() const { return {row0.p, nrow.p}; }
+};
+
+template <class T>
+struct Vecs {
+    DevBuf<T> b, x, xs, t, r;
+};
+
+struct Level {
+    int n = 0;
+    int d[2] = {0, 0};
+    bool coarsest = false;
+    SetupBsr A[2][2];
+    Aggregates G;
+    BlockLevel blk[2];
+    Vecs<double> v64;
+    Vecs<float> v32;
+    int64_t nnzb_total() const { return A[0][0].nnzb + A[0][1].nnzb + A[1][0].nnzb + A[1][1].nnzb; }
+};
+
+struct TimedLaunch {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+};
+
+thread_local std::string g_last_error;
+
+}  // namespace mbamg
+
+using namespace mbamg;
+
+struct mbamg_hierarchy {
+    mbamg_params p{};
+    mbamg_field_map fm{};
+    int d[2] = {0, 0};
+    std::vector<std::unique_ptr<Level>> L;
+    DevBuf<double> coarse_inv;
+    int coarse_n = 0;
+    // Krylov workspace
+    int64_t n_fine = 0;
+    DevBuf<double> V, Z64, w, xw, bw, ztmp, partial, hbuf, ybuf;
+    DevBuf<float> Z32, vin32;
+    DevBuf<double> vio;   // ABI <-> colour-order staging for vcycle/apply
+    DevBuf<double> vio2;
+    mbamg_info info{};
+    // timing
+    bool timing = false;
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
+    double t_setup_ms = 0.0;
+};
+
+namespace mbamg {
+
+// ----------------------------------------------------------------------------
+// timing helpers
+// ----------------------------------------------------------------------------
+static hipEvent_t get_event(mbamg_hierarchy* h) {
+    if (!h->event_pool.empty()) {
+        hipEvent_t e = h->event_pool.back();
+        h->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    MB_HIP(hipEventCreate(&e));
+    return e;
+}
+
+struct TimerScope {
+    mbamg_hierarchy* h;
+    hipStream_t s;
+    bool on;
+    TimedLaunch t{};
+    TimerScope(mbamg_hierarchy* hh, hipStream_t ss, bool enabled, int kind, double bytes) : h(hh), s(ss), on(enabled) {
+        if (!on) return;
+        t.kind = kind;
+        t.bytes = bytes;
+        t.a = get_event(h);
+        t.b = get_event(h);
+        MB_HIP(hipEventRecord(t.a, s));
+    }
+    ~TimerScope() {
+        if (!on) return;
+        if (hipEventRecord(t.b, s) == hipSuccess) h->timed.push_back(t);
+    }
+};
+
+// ----------------------------------------------------------------------------
+// setup helpers
+// ----------------------------------------------------------------------------
+static void copy_block(const mbamg_bsr& src, SetupBsr& dst, int n_rows, int n_cols, int br, int bc, hipStream_t s) {
+    dst.n_rows = n_rows;
+    dst.n_cols = n_cols;
+    dst.br = br;
+    dst.bc = bc;
+    dst.nnzb = src.nnzb;
+    MB_CHECK(src.nnzb >= 0 && src.nnzb < INT32_MAX, MBAMG_E_INVALID, "nnzb out of range");
+    dst.rp.alloc(n_rows + 1);
+    if (src.nnzb == 0 || src.row_ptr == nullptr) {
+        MB_HIP(hipMemsetAsync(dst.rp.p, 0, sizeof(int32_t) * (n_rows + 1), s));
+        dst.nnzb = 0;
+        dst.ci.alloc(1);
+        dst.val.alloc(1);
+        return;
+    }
+    MB_CHECK(src.n_brows == n_rows && src.n_bcols == n_cols && src.br == br && src.bc == bc, MBAMG_E_INVALID,
+             "block dimensions inconsistent with the field map");
+    MB_CHECK(src.col_idx && src.vals, MBAMG_E_INVALID, "NULL block arrays");
+    const int64_t bs = (int64_t)br * bc;
+    dst.ci.alloc(src.nnzb);
+    dst.val.alloc(src.nnzb * bs);
+    hipMemcpyKind k = src.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (!src.on_device) {
+        // host input: validate the structure here
+        MB_CHECK(src.row_ptr[0] == 0 && src.row_ptr[n_rows] == src.nnzb, MBAMG_E_INVALID, "row_ptr inconsistent with nnzb");
+        for (int i = 0; i < n_rows; ++i) {
+            MB_CHECK(src.row_ptr[i + 1] >= src.row_ptr[i], MBAMG_E_INVALID, "row_ptr not monotone");
+            for (int p = src.row_ptr[i]; p < src.row_ptr[i + 1]; ++p) {
+                MB_CHECK(src.col_idx[p] >= 0 && src.col_idx[p] < n_cols, MBAMG_E_INVALID, "column index out of range");
+                MB_CHECK(p == src.row_ptr[i] || src.col_idx[p] > src.col_idx[p - 1], MBAMG_E_INVALID,
+                         "column indices must be strictly increasing within a row");
+            }
+        }
+    }
+    MB_HIP(hipMemcpyAsync(dst.rp.p, src.row_ptr, sizeof(int32_t) * (n_rows + 1), k, s));
+    MB_HIP(hipMemcpyAsync(dst.ci.p, src.col_idx, sizeof(int32_t) * src.nnzb, k, s));
+    MB_HIP(hipMemcpyAsync(dst.val.p, src.vals, sizeof(double) * src.nnzb * bs, k, s));
+}
+
+// First-fit greedy colouring in increasing node order over the (symmetric) pattern.
+static int greedy_colour(int n, const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
+                         std::vector<int32_t>& colour) {
+    colour.assign(n, -1);
+    std::vector<int32_t> mark(64, -1);
+    int ncol = 0;
+    for (int i = 0; i < n; ++i) {
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+            int j = ci[p];
+            if (j == i || colour[j] < 0) continue;
+            if (colour[j] >= (int)mark.size()) mark.resize(colour[j] + 64, -1);
+            mark[colour[j]] = i;
+        }
+        int c = 0;
+        while (c < (int)mark.size() && mark[c] == i) ++c;
+        if (c >= (int)mark.size()) mark.resize(c + 64, -1);
+        colour[i] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    return ncol;
+}
+
+static void order_and_slice(BlockLevel& B, int n, int ncol) {
+    B.n = n;
+    B.n_colours = ncol;
+    std::vector<int> cnt(ncol + 1, 0);
+    for (int i = 0; i < n; ++i) cnt[B.colour[i] + 1]++;
+    B.colour_row.assign(ncol + 1, 0);
+    for (int c = 0; c < ncol; ++c) B.colour_row[c + 1] = B.colour_row[c] + cnt[c + 1];
+    B.perm.assign(n, 0);
+    B.iperm.assign(n, 0);
+    std::vector<int> cur(B.colour_row.begin(), B.colour_row.end() - 1);
+    for (int i = 0; i < n; ++i) {
+        int p = cur[B.colour[i]]++;
+        B.perm[p] = i;
+        B.iperm[i] = p;
+    }
+    B.h_row0.clear();
+    B.h_nrow.clear();
+    B.colour_slice.assign(ncol + 1, 0);
+    for (int c = 0; c < ncol; ++c) {
+        B.colour_slice[c] = (int)B.h_row0.size();
+        for (int r = B.colour_row[c]; r < B.colour_row[c + 1]; r += WAVE) {
+            B.h_row0.push_back(r);
+            B.h_nrow.push_back(std::min(WAVE, B.colour_row[c + 1] - r));
+        }
+    }
+    B.colour_slice[ncol] = (int)B.h_row0.size();
+    B.n_slices = (int)B.h_row0.size();
+}
+
+enum class PartKind { Off, Cpl, Diag, Dinv };
+
+// Pack one part of block row f into masked slices.
+// rp/ci: natural-order pattern of the source (unused for Dinv); val: device values
+// (BSR values, or the dense per-node inverse array for Dinv); col_iperm maps
+// natural column nodes to the column block's colour order.
+static void build_part(SellPart& P, PartKind kind, const BlockLevel& B, const std::vector<int32_t>& rp,
+                       const std::vector<int32_t>& ci, const std::vector<int32_t>* col_iperm, const double* val,
+                       int br, int bc, bool want32, hipStream_t s) {
+    P.br = br;
+    P.bc = bc;
+    const int ns = B.n_slices;
+    P.h_width.assign(ns, 0);
+    P.h_coff.assign(ns + 1, 0);
+    auto row_blocks = [&](int node, auto&& fn) {
+        if (kind == PartKind::Dinv) { fn(node, (int64_t)node); return; }
+        if (rp.empty()) return;
+        for (int p = rp[node]; p < rp[node + 1]; ++p) {
+            int j = ci[p];
+            if (kind == PartKind::Off && j == node) continue;
+            if (kind == PartKind::Diag && j != node) continue;
+            fn(j, (int64_t)p);
+        }
+    };
+    for (int sl = 0; sl < ns; ++sl) {
+        int w = 0;
+        for (int l = 0; l < B.h_nrow[sl]; ++l) {
+            int node = B.perm[B.h_row0[sl] + l];
+            int c = 0;
+            row_blocks(node, [&](int, int64_t) { ++c; });
+            w = std::max(w, c);
+        }
+        if (kind == PartKind::Diag || kind == PartKind::Dinv) w = 1;
+        P.h_width[sl] = w;
+        P.h_coff[sl + 1] = P.h_coff[sl] + w;
+    }
+    P.n_slots = P.h_coff[ns];
+    const int64_t nsl = std::max<int64_t>(P.n_slots, 1);
+    std::vector<int32_t> hcol(nsl * WAVE, -1);
+    std::vector<int64_t> hsrc(nsl * WAVE, -1);
+    P.h_slot_blocks.assign(nsl, 0);
+    for (int sl = 0; sl < ns; ++sl) {
+        for (int l = 0; l < B.h_nrow[sl]; ++l) {
+            int node = B.perm[B.h_row0[sl] + l];
+            int t = 0;
+            row_blocks(node, [&](int j, int64_t src) {
+                int64_t slot = P.h_coff[sl] + t;
+                hcol[slot * WAVE + l] = col_iperm ? (*col_iperm)[j] : B.iperm[j];
+                hsrc[slot * WAVE + l] = src;
+                P.h_slot_blocks[slot]++;
+                ++t;
+            });
+        }
+    }
+    P.width.upload(P.h_width, s);
+    P.coff.upload(P.h_coff.data(), ns, s);
+    P.col.upload(hcol, s);
+    DevBuf<int64_t> dsrc;
+    dsrc.upload(hsrc, s);
+    P.mask.alloc(nsl);
+    DevBuf<uint32_t> slot_nz(nsl);
+    MB_HIP(hipMemsetAsync(slot_nz.p, 0, sizeof(uint32_t) * nsl, s));
+    sell_masks(P.n_slots, br * bc, dsrc.p, val, P.mask.p, slot_nz.p, s);
+    std::vector<uint32_t> hmask = P.mask.download(s, nsl);
+    P.h_slot_nz = slot_nz.download(s, nsl);
+    std::vector<int64_t> slot_voff(nsl, 0);
+    std::vector<int64_t> voff(std::max(ns, 1), 0);
+    int64_t g = 0;
+    for (int sl = 0; sl < ns; ++sl) {
+        voff[sl] = g;
+        for (int t = 0; t < P.h_width[sl]; ++t) {
+            int64_t slot = P.h_coff[sl] + t;
+            slot_voff[slot] = g;
+            g += __builtin_popcount(hmask[slot]);
+        }
+    }
+    P.n_groups = g;
+    P.voff.upload(voff.data(), ns, s);
+    DevBuf<int64_t> dsv;
+    dsv.upload(slot_voff, s);
+    P.v64.alloc(std::max<int64_t>(g, 1) * WAVE);
+    sell_fill(P.n_slots, br * bc, dsrc.p, val, P.mask.p, dsv.p, P.v64.p, s);
+    if (want32) {
+        P.v32.alloc(std::max<int64_t>(g, 1) * WAVE);
+        cast_to_f32(P.v64.p, P.v32.p, g * WAVE, s);
+    }
+    MB_HIP(hipStreamSynchronize(s));   // keep the temporaries alive until the kernels finish
+}
+
+template <class T>
+static void alloc_vecs(Vecs<T>& v, int64_t n) {
+    int64_t m = std::max<int64_t>(n, 1);
+    v.b.alloc(m);
+    v.x.alloc(m);
+    v.xs.alloc(m);
+    v.t.alloc(m);
+    v.r.alloc(m);
+}
+
+// ----------------------------------------------------------------------------
+// setup
+// ----------------------------------------------------------------------------
+static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    const mbamg_params& p = h->p;
+    const int d0 = h->d[0], d1 = h->d[1];
+    const int N = Ab[0].n_brows;
+    MB_CHECK(N > 0, MBAMG_E_INVALID, "empty system");
+    const bool want32 = p.precision == 1;
+
+    // level 0 from the caller's blocks
+    auto first = std::make_unique<Level>();
+    first->n = N;
+    first->d[0] = d0;
+    first->d[1] = d1;
+    for (int f = 0; f < 2; ++f)
+        for (int g = 0; g < 2; ++g) copy_block(Ab[f * 2 + g], first->A[f][g], N, N, h->d[f], h->d[g], s);
+    MB_CHECK(first->A[0][0].nnzb > 0 && first->A[1][1].nnzb > 0, MBAMG_E_INVALID, "diagonal blocks must be nonzero");
+    h->L.push_back(std::move(first));
+
+    // near-null space per block: constants on the finest level
+    DevBuf<double> Bn[2];
+    for (int f = 0; f < 2; ++f) {
+        Bn[f].alloc((size_t)N * h->d[f]);
+        fill_ones(Bn[f].p, (int64_t)N * h->d[f], s);
+    }
+    int lvl = 0;
+    while (true) {
+        Level& cur = *h->L.back();
+        const int64_t ndof = (int64_t)cur.n * (d0 + d1);
+        if (ndof <= p.max_coarse || (int)h->L.size() >= p.max_levels) break;
+        Strength S = build_strength(cur.A[0][0], p.theta, s);
+        Aggregates G = build_aggregates(S, p.seed, lvl, s);
+        if ((double)G.n_agg > 0.9 * cur.n) break;
+        const int nc = G.n_agg;
+        DevBuf<double> q[2], Bc[2];
+        for (int f = 0; f < 2; ++f) {     // block 1 reuses block 0's aggregates
+            q[f].alloc((size_t)cur.n * h->d[f]);
+            Bc[f].alloc((size_t)std::max(nc, 1) * h->d[f]);
+            build_tentative(G, h->d[f], Bn[f].p, q[f].p, Bc[f].p, s);
+        }
+        auto nxt = std::make_unique<Level>();
+        nxt->n = nc;
+        nxt->d[0] = d0;
+        nxt->d[1] = d1;
+        for (int f = 0; f < 2; ++f)
+            for (int g = 0; g < 2; ++g) {
+                if (cur.A[f][g].nnzb == 0) {
+                    SetupBsr& Z = nxt->A[f][g];
+                    Z.n_rows = Z.n_cols = nc;
+                    Z.br = h->d[f];
+                    Z.bc = h->d[g];
+                    Z.rp.alloc(nc + 1);
+                    MB_HIP(hipMemsetAsync(Z.rp.p, 0, sizeof(int32_t) * (nc + 1), s));
+                    Z.ci.alloc(1);
+                    Z.val.alloc(1);
+                    continue;
+                }
+                nxt->A[f][g] = galerkin(cur.A[f][g], G, q[f].p, q[g].p, s);
+            }
+        // keep q on the fine level (natural order) for the transfer maps
+        cur.blk[0].q64 = std::move(q[0]);
+        cur.blk[1].q64 = std::move(q[1]);
+        cur.G = std::move(G);
+        Bn[0] = std::move(Bc[0]);
+        Bn[1] = std::move(Bc[1]);
+        h->L.push_back(std::move(nxt));
+        ++lvl;
+    }
+    h->L.back()->coarsest = true;
+
+    // coarsest: dense inverse
+    {
+        Level& c = *h->L.back();
+        coarse_inverse(c.A, c.d, h->coarse_inv, h->coarse_n, s);
+        for (int f = 0; f < 2; ++f) {      // identity order
+            BlockLevel& B = c.blk[f];
+            B.d = c.d[f];
+            B.n = c.n;
+            B.perm.resize(c.n);
+            std::iota(B.perm.begin(), B.perm.end(), 0);
+            B.iperm = B.perm;
+            B.d_perm.upload(B.perm, s);   // used at the interface when this is the only level
+        }
+        alloc_vecs(c.v64, (int64_t)c.n * (d0 + d1));
+        if (want32) alloc_vecs(c.v32, (int64_t)c.n * (d0 + d1));
+    }
+
+    // smoother format on every other level, coarsest first (transfer maps need the next level's order)
+    for (int l = (int)h->L.size() - 2; l >= 0; --l) {
+        Level& Lv = *h->L[l];
+        Level& Nx = *h->L[l + 1];
+        std::vector<int32_t> rp[2][2], ci[2][2];
+        for (int f = 0; f < 2; ++f)
+            for (int g = 0; g < 2; ++g) {
+                rp[f][g] = Lv.A[f][g].rp.download(s, Lv.n + 1);
+                ci[f][g] = Lv.A[f][g].ci.download(s, Lv.A[f][g].nnzb);
+            }
+        for (int f = 0; f < 2; ++f) {
+            BlockLevel& B = Lv.blk[f];
+            B.d = Lv.d[f];
+            int ncol = greedy_colour(Lv.n, rp[f][f], ci[f][f], B.colour);
+            order_and_slice(B, Lv.n, ncol);
+            B.row0.upload(B.h_row0, s);
+            B.nrow.upload(B.h_nrow, s);
+            B.d_perm.upload(B.perm, s);
+        }
+        for (int f = 0; f < 2; ++f) {
+            const int g = 1 - f;
+            BlockLevel& B = Lv.blk[f];
+            const int df = Lv.d[f], dg = Lv.d[g];
+            DevBuf<double> dinv((size_t)Lv.n * df * df);
+            build_dinv(Lv.A[f][f], dinv.p, s);
+            build_part(B.off, PartKind::Off, B, rp[f][f], ci[f][f], nullptr, Lv.A[f][f].val.p, df, df, want32, s);
+            build_part(B.diag, PartKind::Diag, B, rp[f][f], ci[f][f], nullptr, Lv.A[f][f].val.p, df, df, want32, s);
+            build_part(B.cpl, PartKind::Cpl, B, rp[f][g], ci[f][g], &Lv.blk[g].iperm, Lv.A[f][g].val.p, df, dg,
+                       want32, s);
+            std::vector<int32_t> none;
+            build_part(B.dinv, PartKind::Dinv, B, none, none, nullptr, dinv.p, df, df, want32, s);
+        }
+        // transfer maps between this level's and the next level's colour orders
+        std::vector<int32_t> agg = Lv.G.agg.download(s, Lv.n);
+        std::vector<int32_t> mptr = Lv.G.mptr.download(s, Nx.n + 1);
+        std::vector<int32_t> midx = Lv.G.midx.download(s, Lv.n);
+        for (int f = 0; f < 2; ++f) {
+            BlockLevel& B = Lv.blk[f];
+            const BlockLevel& C = Nx.blk[f];
+            std::vector<int32_t> aggp(Lv.n), mp(Nx.n + 1, 0), mi(Lv.n);
+            for (int pr = 0; pr < Lv.n; ++pr) aggp[pr] = C.iperm[agg[B.perm[pr]]];
+            for (int kp = 0; kp < Nx.n; ++kp) {
+                int k = C.perm[kp];
+                mp[kp + 1] = mp[kp] + (mptr[k + 1] - mptr[k]);
+                int o = mp[kp];
+                for (int m = mptr[k]; m < mptr[k + 1]; ++m) mi[o++] = B.iperm[midx[m]];
+            }
+            B.agg_p.upload(aggp, s);
+            B.mem_ptr.upload(mp, s);
+            B.mem_idx.upload(mi, s);
+            DevBuf<double> qp((size_t)Lv.n * B.d);
+            launch_gather(Lv.n, B.d, B.d_perm.p, B.q64.p, qp.p, s);
+            B.q64 = std::move(qp);
+            if (want32) {
+                B.q32.alloc((size_t)Lv.n * B.d);
+                cast_to_f32(B.q64.p, B.q32.p, (int64_t)Lv.n * B.d, s);
+            }
+        }
+        alloc_vecs(Lv.v64, (int64_t)Lv.n * (d0 + d1));
+        if (want32) alloc_vecs(Lv.v32, (int64_t)Lv.n * (d0 + d1));
+        MB_HIP(hipStreamSynchronize(s));
+    }
+
+    // Krylov workspace
+    h->n_fine = (int64_t)N * (d0 + d1);
+    const int m = p.restart;
+    const int64_t n = h->n_fine;
+    h->V.alloc((size_t)(m + 1) * n);
+    if (want32) {
+        h->Z32.alloc((size_t)m * n);
+        h->vin32.alloc(n);
+        h->ztmp.alloc(n);
+    } else {
+        h->Z64.alloc((size_t)m * n);
+    }
+    h->w.alloc(n);
+    h->xw.alloc(n);
+    h->bw.alloc(n);
+    h->vio.alloc(n);
+    h->vio2.alloc(n);
+    h->partial.alloc((size_t)KBLOCKS * KMAXQ);
+    h->hbuf.alloc(3 * KMAXQ);
+    h->ybuf.alloc(KMAXQ);
+    MB_HIP(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    h->t_setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    int64_t nz0 = h->L[0]->nnzb_total(), nzs = 0;
+    for (auto& lv : h->L) nzs += lv->nnzb_total();
+    h->info.levels = (int)h->L.size();
+    h->info.op_complexity = nz0 ? (double)nzs / (double)nz0 : 1.0;
+    h->info.t_setup_ms = h->t_setup_ms;
+}
+
+// ----------------------------------------------------------------------------
+// byte model (algorithmic bytes of the finest level's kernels)
+// ----------------------------------------------------------------------------
+static double gs_bytes(const BlockLevel& B, int c, bool zero_x, bool skip_off, bool cpl, int s, int dg) {
+    int s0 = B.colour_slice[c], s1 = B.colour_slice[c + 1];
+    int64_t rows = B.colour_row[c + 1] - B.colour_row[c];
+    int64_t nz, bl, tot = 0;
+    double bytes = 0.0;
+    if (!skip_off) {
+        B.off.stats(s0, s1, nz, bl);
+        bytes += nz * (double)s + 4.0 * bl + (double)rows * B.d * s;   // values, indices, gathered iterate
+    }
+    if (cpl) {
+        B.cpl.stats(s0, s1, nz, bl);
+        bytes += nz * (double)s + 4.0 * bl + (double)rows * dg * s;
+    }
+    B.dinv.stats(s0, s1, nz, bl);
+    bytes += nz * (double)s;
+    tot = rows * B.d;
+    bytes += 4.0 * rows;                                   // row pointer equivalent
+    bytes += (double)tot * s * (zero_x ? 3 : 4);           // b, (x), t, xn
+    return bytes;
+}
+
+static double resid_bytes(const Level& Lv, int s, bool with_b) {
+    double bytes = 0.0;
+    for (int f = 0; f < 2; ++f) {
+        const BlockLevel& B = Lv.blk[f];
+        int64_t nz, bl;
+        for (const SellPart* P : {&B.off, &B.cpl, &B.diag}) {
+            P->stats(0, B.n_slices, nz, bl);
+            bytes += nz * (double)s + 4.0 * bl;
+        }
+        bytes += 4.0 * B.n;
+        bytes += (double)B.n * B.d * s * (with_b ? 4 : 3);   // x_f, x_g gathered, (b), r
+    }
+    return bytes;
+}
+
+// ----------------------------------------------------------------------------
+// V-cycle
+// ----------------------------------------------------------------------------
+template <class T>
+static Vecs<T>& vecs(Level& L);
+template <>
+Vecs<double>& vecs<double>(Level& L) { return L.v64; }
+template <>
+Vecs<float>& vecs<float>(Level& L) { return L.v32; }
+
+template <class T>
+static const T* qptr(const BlockLevel& B);
+template <>
+const double* qptr<double>(const BlockLevel& B) { return B.q64.p; }
+template <>
+const float* qptr<float>(const BlockLevel& B) { return B.q32.p; }
+
+template <class T>
+static void smooth_block(mbamg_hierarchy* h, int l, int f, bool zero, const T* b, const T* x, T* xn, const T* xg,
+                         hipStream_t s) {
+    Level& Lv = *h->L[l];
+    BlockLevel& B = Lv.blk[f];
+    const int g = 1 - f;
+    const int64_t off = f == 0 ? 0 : (int64_t)Lv.n * Lv.d[0];
+    T* tbuf = vecs<T>(Lv).t.p + off;
+    const bool has_cpl = xg != nullptr;
+    const bool timed = h->timing && l == 0;
+    for (int k = 0; k < h->p.inner_sweeps; ++k) {
+        for (int c = 0; c < B.n_colours; ++c) {
+            GsArgs<T> a{};
+            a.s_begin = B.colour_slice[c];
+            a.s_count = B.colour_slice[c + 1] - B.colour_slice[c];
+            a.sl = B.slices();
+            a.off = B.off.view<T>();
+            a.cpl = B.cpl.view<T>();
+            a.dinv = B.dinv.view<T>();
+            a.b = b;
+            a.x = x;
+            a.t = tbuf;
+            a.xn = xn;
+            a.xg = xg;
+            a.cstart = k == 0 ? B.colour_row[c] : INT_MAX;
+            a.omega = (T)h->p.omega;
+            a.w_row = nullptr;
+            a.skip_off = (zero && k == 0 && c == 0) ? 1 : 0;
+            double bytes = timed ? gs_bytes(B, c, zero, a.skip_off, has_cpl, (int)sizeof(T), Lv.d[g]) : 0.0;
+            TimerScope ts(h, s, timed, 0, bytes);
+            launch_gs<T>(B.d, zero, has_cpl, a, s);
+        }
+    }
+}
+
+template <class T>
+static void resid(mbamg_hierarchy* h, int l, const T* b, const T* x, T* r, hipStream_t s, int kind) {
+    Level& Lv = *h->L[l];
+    const int64_t n0 = (int64_t)Lv.n * Lv.d[0];
+    ResidArgs<T> a{};
+    for (int f = 0; f < 2; ++f) {
+        BlockLevel& B = Lv.blk[f];
+        const int64_t off = f == 0 ? 0 : n0;
+        a.s_count[f] = B.n_slices;
+        a.sl[f] = B.slices();
+        a.off[f] = B.off.view<T>();
+        a.cpl[f] = B.cpl.view<T>();
+        a.diag[f] = B.diag.view<T>();
+        a.b[f] = b ? b + off : nullptr;
+        a.x[f] = x + off;
+        a.r[f] = r + off;
+    }
+    const bool timed = h->timing && l == 0;
+    double bytes = timed ? resid_bytes(Lv, (int)sizeof(T), b != nullptr) : 0.0;
+    TimerScope ts(h, s, timed, kind, bytes);
+    launch_resid<T>(Lv.d[0], a, s);
+}
+
+// One V-cycle on level l from a zero guess: out = MGV(0, b).
+template <class T>
+static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStream_t s) {
+    Level& Lv = *h->L[l];
+    if (Lv.coarsest) {
+        launch_coarse<T>(h->coarse_n, h->coarse_inv.p, b, out, s);
+        return;
+    }
+    Vecs<T>& V = vecs<T>(Lv);
+    const int64_t n0 = (int64_t)Lv.n * Lv.d[0];
+    const int writes = 2 * h->p.bgs_sweeps;
+    // ping-pong so that the last write lands in out
+    T* buf[2];
+    buf[0] = (writes % 2 == 0) ? V.xs.p : out;
+    buf[1] = (writes % 2 == 0) ? out : V.xs.p;
+    int cur = -1;
+    auto sweep = [&](bool zero) {
+        int nx = cur < 0 ? 0 : 1 - cur;
+        T* X = cur < 0 ? nullptr : buf[cur];
+        // block 0 (uses the current x1 for the coupling term)
+        smooth_block<T>(h, l, 0, zero, b, X, buf[nx], zero ? nullptr : X + n0, s);
+        // block 1 (uses the updated x0, Algorithm 1 line 7)
+        smooth_block<T>(h, l, 1, zero, b + n0, X ? X + n0 : nullptr, buf[nx] + n0, buf[nx], s);
+        cur = nx;
+    };
+    for (int k = 0; k < h->p.bgs_sweeps; ++k) sweep(k == 0);
+    resid<T>(h, l, b, buf[cur], V.r.p, s, 1);
+    Level& Nx = *h->L[l + 1];
+    Vecs<T>& C = vecs<T>(Nx);
+    const int64_t nc0 = (int64_t)Nx.n * Nx.d[0];
+    {
+        TransferArgs<T> a{};
+        for (int f = 0; f < 2; ++f) {
+            a.n_rows[f] = Nx.n;
+            a.map[f] = Lv.blk[f].mem_ptr.p;
+            a.idx[f] = Lv.blk[f].mem_idx.p;
+            a.q[f] = qptr<T>(Lv.blk[f]);
+            a.in[f] = V.r.p + (f ? n0 : 0);
+            a.out[f] = C.b.p + (f ? nc0 : 0);
+        }
+        launch_restrict<T>(Lv.d[0], a, s);
+    }
+    vcycle_level<T>(h, l + 1, C.b.p, C.x.p, s);
+    {
+        TransferArgs<T> a{};
+        for (int f = 0; f < 2; ++f) {
+            a.n_rows[f] = Lv.n;
+            a.map[f] = Lv.blk[f].agg_p.p;
+            a.idx[f] = nullptr;
+            a.q[f] = qptr<T>(Lv.blk[f]);
+            a.in[f] = C.x.p + (f ? nc0 : 0);
+            a.out[f] = buf[cur] + (f ? n0 : 0);
+        }
+        launch_prolong<T>(Lv.d[0], a, s);
+    }
+    for (int k = 0; k < h->p.bgs_sweeps; ++k) sweep(false);
+    MB_CHECK(buf[cur] == out, MBAMG_E_STATE, "internal: V-cycle result not in the output buffer");
+}
+
+// z = M^-1 v for FP64 colour-order vectors of the finest level (either form).
+static void apply_precond(mbamg_hierarchy* h, const double* v, double* z64, float* z32, hipStream_t s) {
+    if (h->p.precision == 1) {
+        Level& L0 = *h->L[0];
+        launch_cast64to32(h->n_fine, v, h->vin32.p, s);
+        if (L0.coarsest) {
+            launch_coarse<float>(h->coarse_n, h->coarse_inv.p, h->vin32.p, z32, s);
+        } else {
+            vcycle_level<float>(h, 0, h->vin32.p, z32, s);
+        }
+        if (z64) launch_cast32to64(h->n_fine, z32, z64, s);
+    } else {
+        vcycle_level<double>(h, 0, v, z64, s);
+    }
+}
+
+static void to_colour(mbamg_hierarchy* h, const double* src, double* dst, hipStream_t s) {
+    Level& L0 = *h->L[0];
+    MB_CHECK(L0.blk[0].d_perm.p && L0.blk[1].d_perm.p, MBAMG_E_STATE, "internal: finest-level order missing");
+    const int64_t n0 = (int64_t)L0.n * L0.d[0];
+    for (int f = 0; f < 2; ++f)
+        launch_gather(L0.n, L0.d[f], L0.blk[f].d_perm.p, src + (f ? n0 : 0), dst + (f ? n0 : 0), s);
+}
+
+static void from_colour(mbamg_hierarchy* h, const double* src, double* dst, hipStream_t s) {
+    Level& L0 = *h->L[0];
+    MB_CHECK(L0.blk[0].d_perm.p && L0.blk[1].d_perm.p, MBAMG_E_STATE, "internal: finest-level order missing");
+    const int64_t n0 = (int64_t)L0.n * L0.d[0];
+    for (int f = 0; f < 2; ++f)
+        launch_scatter(L0.n, L0.d[f], L0.blk[f].d_perm.p, src + (f ? n0 : 0), dst + (f ? n0 : 0), s);
+}
+
+// A x on the finest level (colour order), FP64
+static void apply_A(mbamg_hierarchy* h, const double* x, double* w, hipStream_t s, int kind = 2) {
+    Level& L0 = *h->L[0];
+    if (L0.coarsest) throw Error(MBAMG_E_STATE, "single-level hierarchy: operator apply needs at least two levels");
+    resid<double>(h, 0, nullptr, x, w, s, kind);
+}
+
+// ----------------------------------------------------------------------------
+// GMRES (right preconditioned) / FGMRES, restarted
+// ----------------------------------------------------------------------------
+static double norm2_dev(mbamg_hierarchy* h, const double* v, hipStream_t s, double* dev_out) {
+    int nb = krylov_blocks(h->n_fine);
+    launch_update(h->n_fine, 0, nullptr, 0, nullptr, const_cast<double*>(v), true, h->partial.p, nb, s);
+    launch_reduce(h->partial.p, nb, 0, 1, dev_out, s);
+    double r = 0.0;
+    MB_HIP(hipMemcpyAsync(&r, dev_out, sizeof(double), hipMemcpyDeviceToHost, s));
+    MB_HIP(hipStreamSynchronize(s));
+    return r;
+}
+
+static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, double rtol, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = h->n_fine;
+    const int m = h->p.restart;
+    const bool fp32 = h->p.precision == 1;
+    MB_CHECK(!h->L[0]->coarsest, MBAMG_E_STATE, "solve needs at least two levels");
+    to_colour(h, b, h->bw.p, s);
+    to_colour(h, x, h->xw.p, s);
+    double* dnorm = h->hbuf.p + 2 * KMAXQ;
+    const double bnorm = std::sqrt(norm2_dev(h, h->bw.p, s, dnorm));
+    int its = 0;
+    double rel = 0.0;
+    mbamg_status st = MBAMG_OK;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hh(3 * KMAXQ);
+    const int nb = krylov_blocks(n);
+    if (bnorm == 0.0) {
+        MB_HIP(hipMemsetAsync(h->xw.p, 0, sizeof(double) * n, s));
+        rel = 0.0;
+    } else {
+        while (true) {
+            // true residual
+            resid<double>(h, 0, h->bw.p, h->xw.p, h->V.p, s, 1);
+            const double beta = std::sqrt(norm2_dev(h, h->V.p, s, dnorm));
+            rel = beta / bnorm;
+            if (beta <= rtol * bnorm) break;
+            if (its >= h->p.max_iters) { st = MBAMG_NOT_CONVERGED; break; }
+            launch_scale(n, h->V.p, dnorm, h->V.p, s);
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            int k = 0;
+            for (int j = 0; j < m; ++j) {
+                double* vj = h->V.p + (size_t)j * n;
+                double* zj64 = fp32 ? h->ztmp.p : h->Z64.p + (size_t)j * n;
+                float* zj32 = fp32 ? h->Z32.p + (size_t)j * n : nullptr;
+                apply_precond(h, vj, zj64, zj32, s);
+                apply_A(h, zj64, h->w.p, s);
+                // classical Gram-Schmidt, twice
+                double* h1 = h->hbuf.p;
+                double* h2 = h->hbuf.p + KMAXQ;
+                launch_multidot(n, j + 1, h->V.p, n, h->w.p, h->partial.p, nb, s);
+                launch_reduce(h->partial.p, nb, 0, j + 1, h1, s);
+                launch_update(n, j + 1, h->V.p, n, h1, h->w.p, false, h->partial.p, nb, s);
+                launch_multidot(n, j + 1, h->V.p, n, h->w.p, h->partial.p, nb, s);
+                launch_reduce(h->partial.p, nb, 0, j + 1, h2, s);
+                launch_update(n, j + 1, h->V.p, n, h2, h->w.p, true, h->partial.p, nb, s);
+                launch_reduce(h->partial.p, nb, j + 1, 1, dnorm, s);
+                MB_HIP(hipMemcpyAsync(hh.data(), h->hbuf.p, sizeof(double) * 3 * KMAXQ, hipMemcpyDeviceToHost, s));
+                MB_HIP(hipStreamSynchronize(s));
+                double* col = &H[(size_t)j * (m + 1)];
+                for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[KMAXQ + i];
+                const double hn = std::sqrt(hh[2 * KMAXQ]);
+                col[j + 1] = hn;
+                if (hn != 0.0 && j + 1 < m + 1) launch_scale(n, h->w.p, dnorm, h->V.p + (size_t)(j + 1) * n, s);
+                for (int i = 0; i < j; ++i) {
+                    double t = cs[i] * col[i] + sn[i] * col[i + 1];
+                    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+                    col[i] = t;
+                }
+                double den = std::hypot(col[j], col[j + 1]);
+                cs[j] = den != 0.0 ? col[j] / den : 1.0;
+                sn[j] = den != 0.0 ? col[j + 1] / den : 0.0;
+                col[j] = den;
+                col[j + 1] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                ++its;
+                k = j + 1;
+                if (std::fabs(g[j + 1]) <= rtol * bnorm || its >= h->p.max_iters || hn == 0.0) break;
+            }
+            // back substitution H[:k,:k] y = g[:k]
+            for (int i = k - 1; i >= 0; --i) {
+                double sum = g[i];
+                for (int c = i + 1; c < k; ++c) sum -= H[(size_t)c * (m + 1) + i] * y[c];
+                y[i] = sum / H[(size_t)i * (m + 1) + i];
+            }
+            MB_HIP(hipMemcpyAsync(h->ybuf.p, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+            if (fp32) launch_combine32(n, k, h->Z32.p, n, h->ybuf.p, h->xw.p, s);
+            else launch_combine(n, k, h->Z64.p, n, h->ybuf.p, h->xw.p, s);
+            MB_HIP(hipStreamSynchronize(s));
+        }
+    }
+    from_colour(h, h->xw.p, x, s);
+    MB_HIP(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    h->info.iterations = its;
+    h->info.rel_residual = rel;
+    h->info.conv_factor = its > 0 && rel > 0 ? std::pow(rel, 1.0 / its) : 0.0;
+    h->info.t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    h->info.t_setup_ms = h->t_setup_ms;
+    return st;
+}
+
+}  // namespace mbamg
+
+// ----------------------------------------------------------------------------
+// C-ABI
+// ----------------------------------------------------------------------------
+template <class F>
+static mbamg_status guarded(F&& fn) {
+    try {
+        return fn();
+    } catch (const Error& e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return MBAMG_E_NOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return MBAMG_E_INVALID;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return MBAMG_E_INVALID;
+    }
+}
+
+extern "C" {
+
+void mbamg_default_params(mbamg_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->omega = 0.8;
+    p->bgs_sweeps = 1;
+    p->inner_sweeps = 1;
+    p->theta = 0.0;
+    p->max_levels = 10;
+    p->max_coarse = 2500;
+    p->clone_aggregates = 1;
+    p->reuse_P = 1;
+    p->precision = 0;
+    p->restart = 30;
+    p->max_iters = 1000;
+    p->learned = 0;
+    p->mlp_weights = nullptr;
+    p->seed = 0;
+}
+
+const char* mbamg_last_error(void) { return g_last_error.c_str(); }
+
+mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, const mbamg_params* p,
+                         void* hip_stream, mbamg_hierarchy** out) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(A_blocks && fm && p && out, MBAMG_E_INVALID, "NULL argument");
+        *out = nullptr;
+        MB_CHECK(fm->n_blocks == 2, MBAMG_E_INVALID, "only two blocks are supported");
+        MB_CHECK(fm->dofs[0] >= 1 && fm->dofs[0] <= 4 && fm->dofs[1] == fm->dofs[0], MBAMG_E_INVALID,
+                 "both blocks must have the same 1..4 dofs per node (co-located fields)");
+        MB_CHECK(p->omega > 0.0 && p->bgs_sweeps >= 1 && p->inner_sweeps >= 1 && p->max_levels >= 1 &&
+                     p->restart >= 1 && p->restart <= KMAXQ - 2 && p->max_iters >= 0 && p->theta >= 0.0,
+                 MBAMG_E_INVALID, "invalid parameters");
+        MB_CHECK(p->clone_aggregates != 0, MBAMG_E_INVALID, "separate block-1 aggregation is not built");
+        MB_CHECK(p->precision == 0 || p->precision == 1, MBAMG_E_INVALID, "precision must be 0 or 1");
+        MB_CHECK(p->learned == 0, MBAMG_E_INVALID, "learned weights are set after setup, not through params");
+        auto h = std::make_unique<mbamg_hierarchy>();
+        h->p = *p;
+        h->fm = *fm;
+        h->d[0] = fm->dofs[0];
+        h->d[1] = fm->dofs[1];
+        hipStream_t s = (hipStream_t)hip_stream;
+        setup_impl(h.get(), A_blocks, s);
+        *out = h.release();
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_vcycle(mbamg_hierarchy* h, const double* r, double* z, void* hip_stream) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(h && r && z, MBAMG_E_INVALID, "NULL argument");
+        MB_CHECK(r != z, MBAMG_E_INVALID, "r and z must not alias");
+        hipStream_t s = (hipStream_t)hip_stream;
+        to_colour(h, r, h->vio.p, s);
+        if (h->p.precision == 1) {
+            apply_precond(h, h->vio.p, h->vio2.p, h->vin32.p == nullptr ? nullptr : h->Z32.p, s);
+        } else {
+            if (h->L[0]->coarsest) launch_coarse<double>(h->coarse_n, h->coarse_inv.p, h->vio.p, h->vio2.p, s);
+            else vcycle_level<double>(h, 0, h->vio.p, h->vio2.p, s);
+        }
+        from_colour(h, h->vio2.p, z, s);
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_apply(mbamg_hierarchy* h, const double* x, double* w, void* hip_stream) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(h && x && w, MBAMG_E_INVALID, "NULL argument");
+        MB_CHECK(x != w, MBAMG_E_INVALID, "x and w must not alias");
+        hipStream_t s = (hipStream_t)hip_stream;
+        to_colour(h, x, h->vio.p, s);
+        apply_A(h, h->vio.p, h->vio2.p, s);
+        from_colour(h, h->vio2.p, w, s);
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_solve(mbamg_hierarchy* h, const double* b, double* x, double rtol, mbamg_info* info,
+                         void* hip_stream) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(h && b && x, MBAMG_E_INVALID, "NULL argument");
+        MB_CHECK(b != x, MBAMG_E_INVALID, "b and x must not alias");
+        MB_CHECK(rtol > 0.0, MBAMG_E_INVALID, "rtol must be positive");
+        mbamg_status st = solve_impl(h, b, x, rtol, (hipStream_t)hip_stream);
+        if (info) *info = h->info;
+        return st;
+    });
+}
+
+mbamg_status mbamg_get_info(const mbamg_hierarchy* h, mbamg_info* info) {
+    if (!h || !info) { g_last_error = "NULL argument"; return MBAMG_E_INVALID; }
+    *info = h->info;
+    return MBAMG_OK;
+}
+
+void mbamg_destroy(mbamg_hierarchy* h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    for (auto& t : h->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+    for (auto e : h->event_pool) (void)hipEventDestroy(e);
+    delete h;
+}
+
+mbamg_status mbamg_num_levels(const mbamg_hierarchy* h, int32_t* n_levels) {
+    if (!h || !n_levels) { g_last_error = "NULL argument"; return MBAMG_E_INVALID; }
+    *n_levels = (int32_t)h->L.size();
+    return MBAMG_OK;
+}
+
+mbamg_status mbamg_level_nodes(const mbamg_hierarchy* h, int32_t level, int32_t* n_nodes) {
+    if (!h || !n_nodes || level < 0 || level >= (int)h->L.size()) { g_last_error = "bad argument"; return MBAMG_E_INVALID; }
+    *n_nodes = h->L[level]->n;
+    return MBAMG_OK;
+}
+
+mbamg_status mbamg_copy_aggregates(const mbamg_hierarchy* h, int32_t level, int32_t* agg) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(h && agg && level >= 0 && level + 1 < (int)h->L.size(), MBAMG_E_INVALID, "bad argument");
+        const Level& L = *h->L[level];
+        MB_HIP(hipMemcpy(agg, L.G.agg.p, sizeof(int32_t) * L.n, hipMemcpyDeviceToHost));
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_level_nnzb(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t g, int64_t* nnzb) {
+    if (!h || !nnzb || level < 0 || level >= (int)h->L.size() || f < 0 || f > 1 || g < 0 || g > 1) {
+        g_last_error = "bad argument";
+        return MBAMG_E_INVALID;
+    }
+    *nnzb = h->L[level]->A[f][g].nnzb;
+    return MBAMG_OK;
+}
+
+mbamg_status mbamg_copy_level_block(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t g, int32_t* row_ptr,
+                                    int32_t* col_idx, double* vals) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(h && row_ptr && level >= 0 && level < (int)h->L.size() && f >= 0 && f < 2 && g >= 0 && g < 2,
+                 MBAMG_E_INVALID, "bad argument");
+        const SetupBsr& A = h->L[level]->A[f][g];
+        MB_HIP(hipMemcpy(row_ptr, A.rp.p, sizeof(int32_t) * (A.n_rows + 1), hipMemcpyDeviceToHost));
+        if (A.nnzb) {
+            MB_CHECK(col_idx && vals, MBAMG_E_INVALID, "NULL argument");
+            MB_HIP(hipMemcpy(col_idx, A.ci.p, sizeof(int32_t) * A.nnzb, hipMemcpyDeviceToHost));
+            MB_HIP(hipMemcpy(vals, A.val.p, sizeof(double) * A.nnzb * A.br * A.bc, hipMemcpyDeviceToHost));
+        }
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_copy_colours(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t* colour) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(h && colour && level >= 0 && level + 1 < (int)h->L.size() && f >= 0 && f < 2, MBAMG_E_INVALID,
+                 "bad argument");
+        const BlockLevel& B = h->L[level]->blk[f];
+        std::copy(B.colour.begin(), B.colour.end(), colour);
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_timing_enable(mbamg_hierarchy* h, int32_t enable) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(h, MBAMG_E_INVALID, "NULL argument");
+        MB_HIP(hipDeviceSynchronize());
+        for (auto& t : h->timed) {
+            h->event_pool.push_back(t.a);
+            h->event_pool.push_back(t.b);
+        }
+        h->timed.clear();
+        h->timing = enable != 0;
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_timing_get(mbamg_hierarchy* h, int32_t kind, int64_t* launches, double* total_ms, double* bytes) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(h && launches && total_ms && bytes, MBAMG_E_INVALID, "NULL argument");
+        int64_t c = 0;
+        double ms = 0.0, by = 0.0;
+        for (auto& t : h->timed) {
+            if (t.kind != kind) continue;
+            MB_HIP(hipEventSynchronize(t.b));
+            float e = 0.0f;
+            MB_HIP(hipEventElapsedTime(&e, t.a, t.b));
+            ++c;
+            ms += e;
+            by += t.bytes;
+        }
+        *launches = c;
+        *total_ms = ms;
+        *bytes = by;
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_vcycle_bytes(const mbamg_hierarchy* h, double* bytes) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(h && bytes, MBAMG_E_INVALID, "NULL argument");
+        const int s = h->p.precision == 1 ? 4 : 8;
+        double tot = 0.0;
+        for (size_t l = 0; l + 1 < h->L.size(); ++l) {
+            const Level& Lv = *h->L[l];
+            const Level& Nx = *h->L[l + 1];
+            for (int sweep = 0; sweep < 2 * h->p.bgs_sweeps; ++sweep) {
+                const bool zero = sweep == 0;
+                for (int f = 0; f < 2; ++f) {
+                    const BlockLevel& B = Lv.blk[f];
+                    for (int k = 0; k < h->p.inner_sweeps; ++k)
+                        for (int c = 0; c < B.n_colours; ++c) {
+                            bool skip = zero && k == 0 && c == 0;
+                            bool cpl = !(zero && f == 0);
+                            tot += gs_bytes(B, c, zero, skip, cpl, s, Lv.d[1 - f]);
+                        }
+                }
+            }
+            tot += resid_bytes(Lv, s, true);
+            const int64_t nf = (int64_t)Lv.n * (Lv.d[0] + Lv.d[1]), nc = (int64_t)Nx.n * (Nx.d[0] + Nx.d[1]);
+            tot += (double)s * (2.0 * nf + nc) + 4.0 * (Lv.n + Nx.n) * 2;   // restrict: r, q, b_c, members
+            tot += (double)s * (3.0 * nf + nc) + 4.0 * Lv.n * 2;            // prolong: q, x rw, x_c, map
+        }
+        tot += 8.0 * (double)h->coarse_n * h->coarse_n + 2.0 * s * h->coarse_n;
+        *bytes = tot;
+        return MBAMG_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// Setup-phase data and kernel entry points (device work in setup_kernels.hip).
+#pragma once
+
+#include <algorithm>
+#include <climits>
+
+#include "common.h"
+
+namespace mbamg {
+
+// A matrix block in natural node order with dense br x bc blocks (device).
+struct SetupBsr {
+    int n_rows = 0, n_cols = 0, br = 0, bc = 0;
+    int64_t nnzb = 0;
+    DevBuf<int32_t> rp, ci;
+    DevBuf<double> val;
+};
+
+// Strong-connection graph of A00 (symmetric CSR, squared weights).
+struct Strength {
+    int n = 0, nnz = 0;
+    DevBuf<int32_t> ptr, idx;
+    DevBuf<double> w2;
+};
+
+// Aggregates of one level: agg[node], members per aggregate in increasing order.
+struct Aggregates {
+    int n = 0, n_agg = 0, mis_rounds = 0;
+    DevBuf<int32_t> agg, mptr, midx;
+};
+
+int scan_exclusive(const int32_t* in, int64_t n, int32_t* out, hipStream_t s);
+Strength build_strength(const SetupBsr& A, double theta, hipStream_t s);
+Aggregates build_aggregates(const Strength& S, uint64_t seed, int level, hipStream_t s);
+void fill_ones(double* a, int64_t n, hipStream_t s);
+void build_tentative(const Aggregates& G, int d, const double* B, double* q, double* Bc, hipStream_t s);
+SetupBsr galerkin(const SetupBsr& A, const Aggregates& G, const double* q_row, const double* q_col,
+                  hipStream_t s);
+void build_dinv(const SetupBsr& A, double* dinv, hipStream_t s);
+void sell_masks(int64_t n_slots, int bs, const int64_t* src, const double* val, uint32_t* mask, uint32_t* slot_nz,
+                hipStream_t s);
+void sell_fill(int64_t n_slots, int bs, const int64_t* src, const double* val, const uint32_t* mask,
+               const int64_t* slot_voff, double* out, hipStream_t s);
+void cast_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
+void coarse_inverse(const SetupBsr (&A)[2][2], const int d[2], DevBuf<double>& inv, int& n_out, hipStream_t s);
+
+}  // namespace mbamg

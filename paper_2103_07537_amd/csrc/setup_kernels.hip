@@ -1,0 +1,767 @@
+// Setup-phase kernels: strength graph, distance-2 aggregation, tentative
+// prolongator, Galerkin products, nodal block inverses, packing into the
+// smoother's sliced format and the coarsest-level inverse.
+//
+// This translation unit is compiled with -ffp-contract=off: every product and
+// sum is one IEEE rounding in the order written, so the squared block norms,
+// aggregate norms and Galerkin sums come out bit-identical to a sequential
+// evaluation in the same order.  That keeps the aggregates of coarse levels
+// (which compare those numbers) reproducible.
+#include "setup_kernels.h"
+
+namespace mbamg {
+
+// ----------------------------------------------------------------------------
+// scan (exclusive, int32 in, int32 out): per-block sums, one-block scan of the
+// block sums, then per-block local scans.  1024 items per block.
+// ----------------------------------------------------------------------------
+constexpr int SCAN_T = 256;
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_BLOCK = SCAN_T * SCAN_ITEMS;
+
+__device__ inline int block_exclusive_scan(int v, int* sh, int* total) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_T; off <<= 1) {
+        int add = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    int incl = sh[t];
+    *total = sh[SCAN_T - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void k_scan_blocksum(const int32_t* in, int64_t n, int32_t* bsum) {
+    __shared__ int sh[SCAN_T];
+    int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_ITEMS;
+    int s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+        if (base + k < n) s += in[base + k];
+    int total;
+    block_exclusive_scan(s, sh, &total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ void k_scan_sums(int32_t* bsum, int nb, int32_t* grand) {
+    __shared__ int sh[SCAN_T];
+    int carry = 0;
+    for (int base = 0; base < nb; base += SCAN_T) {
+        int i = base + threadIdx.x;
+        int v = i < nb ? bsum[i] : 0;
+        int total;
+        int ex = block_exclusive_scan(v, sh, &total);
+        if (i < nb) bsum[i] = ex + carry;
+        carry += total;
+    }
+    if (threadIdx.x == 0) *grand = carry;
+}
+
+__global__ void k_scan_final(const int32_t* in, int64_t n, const int32_t* bsum, int32_t* out) {
+    __shared__ int sh[SCAN_T];
+    int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int ex = block_exclusive_scan(s, sh, &total) + bsum[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+}
+
+// out[i] = sum_{k<i} in[k] for i in [0, n]; out has n+1 entries.  Returns the total.
+int scan_exclusive(const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
+    int nb = (int)std::max<int64_t>(1, ceil_div(n, SCAN_BLOCK));
+    DevBuf<int32_t> bsum(nb);
+    k_scan_blocksum<<<nb, SCAN_T, 0, s>>>(in, n, bsum.p);
+    MB_LAUNCH_CHECK();
+    k_scan_sums<<<1, SCAN_T, 0, s>>>(bsum.p, nb, out + n);
+    MB_LAUNCH_CHECK();
+    k_scan_final<<<nb, SCAN_T, 0, s>>>(in, n, bsum.p, out);
+    MB_LAUNCH_CHECK();
+    int32_t total = 0;
+    MB_HIP(hipMemcpyAsync(&total, out + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MB_HIP(hipStreamSynchronize(s));
+    return total;
+}
+
+// ----------------------------------------------------------------------------
+// strength graph
+// ----------------------------------------------------------------------------
+__device__ inline int find_col(const int32_t* ci, int lo, int hi, int key) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        int c = ci[mid];
+        if (c == key) return mid;
+        if (c < key) lo = mid + 1; else hi = mid;
+    }
+    return -1;
+}
+
+__global__ void k_block_sqnorm(const double* val, int64_t nnzb, int bs, double* n2) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnzb) return;
+    const double* v = val + p * bs;
+    double acc = v[0] * v[0];
+    for (int k = 1; k < bs; ++k) acc = acc + v[k] * v[k];
+    n2[p] = acc;
+}
+
+// pass 0: count strong neighbours per row; pass 1: write them.
+__global__ void k_strength(int n, const int32_t* rp, const int32_t* ci, const double* n2, double t4,
+                           int pass, int32_t* cnt, const int32_t* sptr, int32_t* sidx, double* sw2,
+                           int32_t* asym) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = rp[i], e = rp[i + 1];
+    int pd = find_col(ci, b, e, i);
+    double dn2i = pd >= 0 ? n2[pd] : 0.0;
+    int c = 0;
+    int out = pass ? sptr[i] : 0;
+    for (int p = b; p < e; ++p) {
+        int j = ci[p];
+        if (j == i) continue;
+        int q = find_col(ci, rp[j], rp[j + 1], i);
+        if (q < 0) { if (pass == 0) atomicAdd(asym, 1); continue; }
+        double a = n2[p], t = n2[q];
+        double w2 = a > t ? a : t;
+        int pj = find_col(ci, rp[j], rp[j + 1], j);
+        double dn2j = pj >= 0 ? n2[pj] : 0.0;
+        bool strong = (w2 > 0.0) && (w2 * w2 >= t4 * (dn2i * dn2j));
+        if (!strong) continue;
+        if (pass) { sidx[out + c] = j; sw2[out + c] = w2; }
+        ++c;
+    }
+    if (!pass) cnt[i] = c;
+}
+
+// ----------------------------------------------------------------------------
+// distance-2 maximal independent set with fixed priorities
+// ----------------------------------------------------------------------------
+__device__ inline uint64_t splitmix_final(uint64_t z) {
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z;
+}
+
+__global__ void k_keys(int n, uint64_t mult, uint64_t* key, int8_t* state) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t h = splitmix_final((uint64_t)i + mult) >> 32;
+    key[i] = (h << 32) | (uint64_t)(uint32_t)i;
+    state[i] = 0;
+}
+
+// best1[i] = undecided node of largest key in {i} U N(i), or -1
+__global__ void k_mis_a(int n, const int32_t* sp, const int32_t* si, const uint64_t* key, const int8_t* state,
+                        int32_t* best1) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int best = state[i] == 0 ? i : -1;
+    for (int p = sp[i]; p < sp[i + 1]; ++p) {
+        int j = si[p];
+        if (state[j] == 0 && (best < 0 || key[j] > key[best])) best = j;
+    }
+    best1[i] = best;
+}
+
+// undecided i becomes a root when it has the largest key among undecided nodes within two hops
+__global__ void k_mis_b(int n, const int32_t* sp, const int32_t* si, const uint64_t* key, const int32_t* best1,
+                        int8_t* state) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || state[i] != 0) return;
+    int best = best1[i];
+    for (int p = sp[i]; p < sp[i + 1]; ++p) {
+        int c = best1[si[p]];
+        if (c >= 0 && (best < 0 || key[c] > key[best])) best = c;
+    }
+    if (best == i) state[i] = 1;
+}
+
+__global__ void k_mis_c(int n, const int32_t* sp, const int32_t* si, const int8_t* state, int8_t* near1) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int8_t f = state[i] == 1;
+    for (int p = sp[i]; p < sp[i + 1] && !f; ++p) f = state[si[p]] == 1;
+    near1[i] = f;
+}
+
+__global__ void k_mis_d(int n, const int32_t* sp, const int32_t* si, const int8_t* near1, int8_t* state,
+                        int32_t* undecided) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || state[i] != 0) return;
+    int8_t f = near1[i];
+    for (int p = sp[i]; p < sp[i + 1] && !f; ++p) f = near1[si[p]];
+    if (f) state[i] = 2;
+    else atomicAdd(undecided, 1);
+}
+
+__global__ void k_is_root(int n, const int8_t* state, int32_t* flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = state[i] == 1;
+}
+
+__global__ void k_phase1(int n, const int32_t* sp, const int32_t* si, const int8_t* state, const int32_t* rootscan,
+                         int32_t* phase1) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || state[i] != 1) return;
+    int id = rootscan[i];
+    phase1[i] = id;
+    for (int p = sp[i]; p < sp[i + 1]; ++p) phase1[si[p]] = id;   // root neighbourhoods are disjoint
+}
+
+__global__ void k_phase2(int n, const int32_t* sp, const int32_t* si, const double* sw2, const int32_t* phase1,
+                         int32_t* agg, int32_t* fail) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int a1 = phase1[i];
+    if (a1 >= 0) { agg[i] = a1; return; }
+    int best = -1;
+    double bw = 0.0;
+    for (int p = sp[i]; p < sp[i + 1]; ++p) {
+        int a = phase1[si[p]];
+        if (a < 0) continue;
+        double w = sw2[p];
+        if (best < 0 || w > bw || (w == bw && a < best)) { best = a; bw = w; }
+    }
+    if (best < 0) { atomicAdd(fail, 1); best = 0; }
+    agg[i] = best;
+}
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__global__ void k_count_members(int n, const int32_t* agg, int32_t* cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[agg[i]], 1);
+}
+
+__global__ void k_place_members(int n, const int32_t* agg, const int32_t* mptr, int32_t* cursor, int32_t* midx) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int k = agg[i];
+    int slot = atomicAdd(&cursor[k], 1);
+    midx[mptr[k] + slot] = i;
+}
+
+__global__ void k_sort_members(int nagg, const int32_t* mptr, int32_t* midx) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nagg) return;
+    int b = mptr[k], e = mptr[k + 1];
+    for (int a = b + 1; a < e; ++a) {
+        int v = midx[a];
+        int c = a - 1;
+        while (c >= b && midx[c] > v) { midx[c + 1] = midx[c]; --c; }
+        midx[c + 1] = v;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// tentative prolongator: q = B / ||B over the aggregate||, per component
+// ----------------------------------------------------------------------------
+__global__ void k_tentative(int nagg, int d, const int32_t* mptr, const int32_t* midx, const double* B,
+                            double* q, double* Bc) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nagg) return;
+    int b = mptr[k], e = mptr[k + 1];
+    for (int c = 0; c < d; ++c) {
+        double acc = 0.0;
+        for (int m = b; m < e; ++m) {
+            double v = B[(int64_t)midx[m] * d + c];
+            acc = acc + v * v;
+        }
+        double nrm = sqrt(acc);
+        Bc[(int64_t)k * d + c] = nrm;
+        for (int m = b; m < e; ++m) {
+            int64_t o = (int64_t)midx[m] * d + c;
+            q[o] = B[o] / nrm;
+        }
+    }
+}
+
+__global__ void k_fill_f64(double* a, int64_t n, double v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// ----------------------------------------------------------------------------
+// Galerkin product, stage 1: T = A P_g.  One thread per fine row; the row's
+// distinct column aggregates are visited in increasing order and each block
+// entry sums A_ij[r,c] * q_g[j,c] over the row's columns j in increasing order.
+// ----------------------------------------------------------------------------
+__global__ void k_rap1(int n, int br, int bc, const int32_t* rp, const int32_t* ci, const double* val,
+                       const int32_t* agg, const double* qc, int pass, int32_t* cnt, const int32_t* trp,
+                       int32_t* tci, double* tval) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int b = rp[i], e = rp[i + 1], bs = br * bc;
+    int prev = -1, out = pass ? trp[i] : 0, c = 0;
+    while (true) {
+        int l = INT_MAX;
+        for (int p = b; p < e; ++p) {
+            int a = agg[ci[p]];
+            if (a > prev && a < l) l = a;
+        }
+        if (l == INT_MAX) break;
+        if (pass) {
+            double* acc = tval + (int64_t)(out + c) * bs;
+            tci[out + c] = l;
+            for (int k = 0; k < bs; ++k) acc[k] = 0.0;
+            for (int p = b; p < e; ++p) {
+                int j = ci[p];
+                if (agg[j] != l) continue;
+                const double* a = val + (int64_t)p * bs;
+                const double* qj = qc + (int64_t)j * bc;
+                for (int r = 0; r < br; ++r)
+                    for (int cc = 0; cc < bc; ++cc) {
+                        double term = a[r * bc + cc] * qj[cc];
+                        acc[r * bc + cc] = acc[r * bc + cc] + term;
+                    }
+            }
+        }
+        ++c;
+        prev = l;
+    }
+    if (!pass) cnt[i] = c;
+}
+
+// Stage 2: A_c = P_f^T T.  One thread per coarse row k; distinct columns in
+// increasing order; each entry sums q_f[i,r] * T[i,l][r,c] over the members i
+// of aggregate k in increasing order.
+__global__ void k_rap2(int nc, int br, int bc, const int32_t* mptr, const int32_t* midx, const int32_t* trp,
+                       const int32_t* tci, const double* tval, const double* qr, int pass, int32_t* cnt,
+                       const int32_t* crp, int32_t* cci, double* cval) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nc) return;
+    const int mb = mptr[k], me = mptr[k + 1], bs = br * bc;
+    int prev = -1, out = pass ? crp[k] : 0, c = 0;
+    while (true) {
+        int l = INT_MAX;
+        for (int m = mb; m < me; ++m) {
+            int i = midx[m];
+            for (int p = trp[i]; p < trp[i + 1]; ++p) {
+                int a = tci[p];
+                if (a > prev && a < l) l = a;
+            }
+        }
+        if (l == INT_MAX) break;
+        if (pass) {
+            double* acc = cval + (int64_t)(out + c) * bs;
+            cci[out + c] = l;
+            for (int e = 0; e < bs; ++e) acc[e] = 0.0;
+            for (int m = mb; m < me; ++m) {
+                int i = midx[m];
+                for (int p = trp[i]; p < trp[i + 1]; ++p) {
+                    if (tci[p] != l) continue;
+                    const double* t = tval + (int64_t)p * bs;
+                    for (int r = 0; r < br; ++r) {
+                        double qv = qr[(int64_t)i * br + r];
+                        for (int cc = 0; cc < bc; ++cc) {
+                            double term = qv * t[r * bc + cc];
+                            acc[r * bc + cc] = acc[r * bc + cc] + term;
+                        }
+                    }
+                }
+            }
+        }
+        ++c;
+        prev = l;
+    }
+    if (!pass) cnt[k] = c;
+}
+
+// ----------------------------------------------------------------------------
+// nodal block inverses: LU with partial pivoting of the diagonal block, d <= 8
+// ----------------------------------------------------------------------------
+__global__ void k_dinv(int n, int d, const int32_t* rp, const int32_t* ci, const double* val, double* dinv,
+                       int32_t* singular) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a[64], x[64];
+    int piv[8];
+    const int bs = d * d;
+    int pd = find_col(ci, rp[i], rp[i + 1], i);
+    for (int k = 0; k < bs; ++k) a[k] = pd >= 0 ? val[(int64_t)pd * bs + k] : 0.0;
+    bool sing = false;
+    for (int k = 0; k < d; ++k) {
+        int p = k;
+        double m = fabs(a[k * d + k]);
+        for (int r = k + 1; r < d; ++r)
+            if (fabs(a[r * d + k]) > m) { m = fabs(a[r * d + k]); p = r; }
+        piv[k] = p;
+        if (m == 0.0) { sing = true; break; }
+        if (p != k)
+            for (int c = 0; c < d; ++c) { double t = a[k * d + c]; a[k * d + c] = a[p * d + c]; a[p * d + c] = t; }
+        for (int r = k + 1; r < d; ++r) {
+            double l = a[r * d + k] / a[k * d + k];
+            a[r * d + k] = l;
+            for (int c = k + 1; c < d; ++c) a[r * d + c] = a[r * d + c] - l * a[k * d + c];
+        }
+    }
+    if (sing) {
+        atomicAdd(singular, 1);
+        for (int k = 0; k < bs; ++k) dinv[(int64_t)i * bs + k] = 0.0;
+        return;
+    }
+    // solve A X = I column by column
+    for (int col = 0; col < d; ++col) {
+        double y[8];
+        for (int r = 0; r < d; ++r) y[r] = r == col ? 1.0 : 0.0;
+        for (int k = 0; k < d; ++k) { double t = y[k]; y[k] = y[piv[k]]; y[piv[k]] = t; }
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < r; ++c) y[r] = y[r] - a[r * d + c] * y[c];
+        for (int r = d - 1; r >= 0; --r) {
+            for (int c = r + 1; c < d; ++c) y[r] = y[r] - a[r * d + c] * y[c];
+            y[r] = y[r] / a[r * d + r];
+        }
+        for (int r = 0; r < d; ++r) x[r * d + col] = y[r];
+    }
+    for (int k = 0; k < bs; ++k) dinv[(int64_t)i * bs + k] = x[k];
+}
+
+// ----------------------------------------------------------------------------
+// packing into masked slices: src[slot*64 + lane] is the source block index
+// (-1 for padding); mask bit k of a slot is set when entry k is nonzero in any
+// lane's block.
+// ----------------------------------------------------------------------------
+__global__ void k_sell_mask(int64_t n_slots, int bs, const int64_t* src, const double* val, uint32_t* mask,
+                            uint32_t* slot_nz) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_slots * WAVE) return;
+    int64_t s = src[t];
+    if (s < 0) return;
+    uint32_t bits = 0;
+    for (int k = 0; k < bs; ++k)
+        if (val[s * bs + k] != 0.0) bits |= 1u << k;
+    if (bits) {
+        atomicOr(&mask[t / WAVE], bits);
+        atomicAdd(&slot_nz[t / WAVE], (uint32_t)__popc(bits));
+    }
+}
+
+__global__ void k_sell_fill(int64_t n_slots, int bs, const int64_t* src, const double* val, const uint32_t* mask,
+                            const int64_t* slot_voff, double* out) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_slots * WAVE) return;
+    int64_t slot = t / WAVE;
+    int lane = (int)(t % WAVE);
+    int64_t s = src[t];
+    uint32_t m = mask[slot];
+    int64_t g = slot_voff[slot];
+    for (int k = 0; k < bs; ++k) {
+        if (!(m & (1u << k))) continue;
+        out[g * WAVE + lane] = s >= 0 ? val[s * bs + k] : 0.0;
+        ++g;
+    }
+}
+
+__global__ void k_cast_f64_f32(const double* a, float* b, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+// ----------------------------------------------------------------------------
+// coarsest level: dense assembly and Gauss-Jordan inverse with partial pivoting
+// ----------------------------------------------------------------------------
+__global__ void k_dense_scatter(int n_rows, int br, int bc, const int32_t* rp, const int32_t* ci, const double* val,
+                                int64_t row_off, int64_t col_off, int64_t ld, double* M) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_rows) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int j = ci[p];
+        for (int r = 0; r < br; ++r)
+            for (int c = 0; c < bc; ++c)
+                M[(row_off + (int64_t)i * br + r) * ld + col_off + (int64_t)j * bc + c] =
+                    val[((int64_t)p * br + r) * bc + c];
+    }
+}
+
+__global__ void k_gj_identity(double* M, int n) {   // right half of [A | I]
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * n) return;
+    int r = (int)(t / n), c = (int)(t % n);
+    M[(int64_t)r * 2 * n + n + c] = r == c ? 1.0 : 0.0;
+}
+
+// one block: choose the pivot row for column k, swap it into row k, scale
+// row k and save column k for the elimination
+__global__ void k_gj_pivot(double* M, int n, int k, double* colk, int32_t* singular) {
+    __shared__ double bv[1024];
+    __shared__ int bi[1024];
+    const int ld = 2 * n;
+    int t = threadIdx.x;
+    double best = -1.0;
+    int bidx = -1;
+    for (int r = k + t; r < n; r += blockDim.x) {
+        double v = fabs(M[(int64_t)r * ld + k]);
+        if (v > best) { best = v; bidx = r; }
+    }
+    bv[t] = best;
+    bi[t] = bidx;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (t < off) {
+            double o = bv[t + off];
+            int oi = bi[t + off];
+            if (o > bv[t] || (o == bv[t] && oi >= 0 && (bi[t] < 0 || oi < bi[t]))) { bv[t] = o; bi[t] = oi; }
+        }
+        __syncthreads();
+    }
+    int p = bi[0];
+    double pv = bv[0];
+    if (pv <= 0.0) {
+        if (t == 0) atomicAdd(singular, 1);
+        return;
+    }
+    if (p != k)
+        for (int c = t; c < ld; c += blockDim.x) {
+            double a = M[(int64_t)k * ld + c];
+            M[(int64_t)k * ld + c] = M[(int64_t)p * ld + c];
+            M[(int64_t)p * ld + c] = a;
+        }
+    __syncthreads();
+    double inv = 1.0 / M[(int64_t)k * ld + k];
+    __syncthreads();
+    for (int c = t; c < ld; c += blockDim.x) M[(int64_t)k * ld + c] *= inv;
+    __syncthreads();
+    for (int r = t; r < n; r += blockDim.x) colk[r] = M[(int64_t)r * ld + k];
+}
+
+__global__ void k_gj_eliminate(double* M, int n, int k, const double* colk) {
+    const int ld = 2 * n;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int width = ld - k;
+    if (t >= (int64_t)n * width) return;
+    int r = (int)(t / width);
+    int c = k + (int)(t % width);
+    if (r == k) return;
+    double f = colk[r];
+    if (f == 0.0) return;
+    M[(int64_t)r * ld + c] = M[(int64_t)r * ld + c] - f * M[(int64_t)k * ld + c];
+}
+
+__global__ void k_gj_extract(const double* M, int n, double* inv) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * n) return;
+    int r = (int)(t / n), c = (int)(t % n);
+    inv[t] = M[(int64_t)r * 2 * n + n + c];
+}
+
+// ----------------------------------------------------------------------------
+// host wrappers
+// ----------------------------------------------------------------------------
+static inline unsigned grid_for(int64_t n, int threads = 256) {
+    return (unsigned)std::max<int64_t>(1, ceil_div(n, threads));
+}
+
+Strength build_strength(const SetupBsr& A, double theta, hipStream_t s) {
+    MB_CHECK(A.br == A.bc, MBAMG_E_INVALID, "A00 blocks must be square");
+    Strength S;
+    S.n = A.n_rows;
+    const int n = A.n_rows;
+    DevBuf<double> n2(std::max<int64_t>(A.nnzb, 1));
+    k_block_sqnorm<<<grid_for(A.nnzb), 256, 0, s>>>(A.val.p, A.nnzb, A.br * A.bc, n2.p);
+    MB_LAUNCH_CHECK();
+    double t4 = (theta * theta) * (theta * theta);
+    DevBuf<int32_t> cnt(std::max(n, 1)), asym(1);
+    MB_HIP(hipMemsetAsync(asym.p, 0, sizeof(int32_t), s));
+    k_strength<<<grid_for(n), 256, 0, s>>>(n, A.rp.p, A.ci.p, n2.p, t4, 0, cnt.p, nullptr, nullptr, nullptr,
+                                           asym.p);
+    MB_LAUNCH_CHECK();
+    int32_t h_asym = 0;
+    MB_HIP(hipMemcpyAsync(&h_asym, asym.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    S.ptr.alloc(n + 1);
+    int nnz = scan_exclusive(cnt.p, n, S.ptr.p, s);   // synchronises
+    MB_CHECK(h_asym == 0, MBAMG_E_INVALID, "the node pattern of A00 must be structurally symmetric");
+    S.nnz = nnz;
+    S.idx.alloc(std::max(nnz, 1));
+    S.w2.alloc(std::max(nnz, 1));
+    k_strength<<<grid_for(n), 256, 0, s>>>(n, A.rp.p, A.ci.p, n2.p, t4, 1, nullptr, S.ptr.p, S.idx.p, S.w2.p,
+                                           asym.p);
+    MB_LAUNCH_CHECK();
+    return S;
+}
+
+Aggregates build_aggregates(const Strength& S, uint64_t seed, int level, hipStream_t s) {
+    const int n = S.n;
+    Aggregates G;
+    G.n = n;
+    DevBuf<uint64_t> key(std::max(n, 1));
+    DevBuf<int8_t> state(std::max(n, 1)), near1(std::max(n, 1));
+    DevBuf<int32_t> best1(std::max(n, 1)), counter(1);
+    uint64_t mult = 0x9E3779B97F4A7C15ull * (seed * 1024ull + (uint64_t)level + 1ull);
+    k_keys<<<grid_for(n), 256, 0, s>>>(n, mult, key.p, state.p);
+    MB_LAUNCH_CHECK();
+    int rounds = 0;
+    while (true) {
+        MB_CHECK(rounds < 100000, MBAMG_E_INVALID, "aggregation did not terminate");
+        k_mis_a<<<grid_for(n), 256, 0, s>>>(n, S.ptr.p, S.idx.p, key.p, state.p, best1.p);
+        k_mis_b<<<grid_for(n), 256, 0, s>>>(n, S.ptr.p, S.idx.p, key.p, best1.p, state.p);
+        k_mis_c<<<grid_for(n), 256, 0, s>>>(n, S.ptr.p, S.idx.p, state.p, near1.p);
+        MB_HIP(hipMemsetAsync(counter.p, 0, sizeof(int32_t), s));
+        k_mis_d<<<grid_for(n), 256, 0, s>>>(n, S.ptr.p, S.idx.p, near1.p, state.p, counter.p);
+        MB_LAUNCH_CHECK();
+        int32_t und = 0;
+        MB_HIP(hipMemcpyAsync(&und, counter.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        MB_HIP(hipStreamSynchronize(s));
+        ++rounds;
+        if (und == 0) break;
+    }
+    G.mis_rounds = rounds;
+    DevBuf<int32_t> flag(std::max(n, 1)), rootscan(n + 1);
+    k_is_root<<<grid_for(n), 256, 0, s>>>(n, state.p, flag.p);
+    MB_LAUNCH_CHECK();
+    G.n_agg = scan_exclusive(flag.p, n, rootscan.p, s);
+    DevBuf<int32_t> phase1(std::max(n, 1)), fail(1);
+    k_fill_i32<<<grid_for(n), 256, 0, s>>>(phase1.p, n, -1);
+    k_phase1<<<grid_for(n), 256, 0, s>>>(n, S.ptr.p, S.idx.p, state.p, rootscan.p, phase1.p);
+    MB_HIP(hipMemsetAsync(fail.p, 0, sizeof(int32_t), s));
+    G.agg.alloc(std::max(n, 1));
+    k_phase2<<<grid_for(n), 256, 0, s>>>(n, S.ptr.p, S.idx.p, S.w2.p, phase1.p, G.agg.p, fail.p);
+    MB_LAUNCH_CHECK();
+    int32_t h_fail = 0;
+    MB_HIP(hipMemcpyAsync(&h_fail, fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    // members, increasing node order within each aggregate
+    const int na = G.n_agg;
+    DevBuf<int32_t> cnt(std::max(na, 1)), cursor(std::max(na, 1));
+    MB_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * std::max(na, 1), s));
+    MB_HIP(hipMemsetAsync(cursor.p, 0, sizeof(int32_t) * std::max(na, 1), s));
+    k_count_members<<<grid_for(n), 256, 0, s>>>(n, G.agg.p, cnt.p);
+    MB_LAUNCH_CHECK();
+    G.mptr.alloc(na + 1);
+    scan_exclusive(cnt.p, na, G.mptr.p, s);
+    MB_CHECK(h_fail == 0, MBAMG_E_INVALID, "aggregation left a node unattached");
+    G.midx.alloc(std::max(n, 1));
+    k_place_members<<<grid_for(n), 256, 0, s>>>(n, G.agg.p, G.mptr.p, cursor.p, G.midx.p);
+    k_sort_members<<<grid_for(na), 256, 0, s>>>(na, G.mptr.p, G.midx.p);
+    MB_LAUNCH_CHECK();
+    return G;
+}
+
+void build_tentative(const Aggregates& G, int d, const double* B, double* q, double* Bc, hipStream_t s) {
+    k_tentative<<<grid_for(G.n_agg), 256, 0, s>>>(G.n_agg, d, G.mptr.p, G.midx.p, B, q, Bc);
+    MB_LAUNCH_CHECK();
+}
+
+void fill_ones(double* a, int64_t n, hipStream_t s) {
+    k_fill_f64<<<grid_for(n), 256, 0, s>>>(a, n, 1.0);
+    MB_LAUNCH_CHECK();
+}
+
+SetupBsr galerkin(const SetupBsr& A, const Aggregates& G, const double* q_row, const double* q_col,
+                  hipStream_t s) {
+    const int n = A.n_rows, nc = G.n_agg, br = A.br, bc = A.bc, bs = br * bc;
+    // stage 1: T = A P_g
+    DevBuf<int32_t> cnt(std::max(n, 1)), trp(n + 1);
+    k_rap1<<<grid_for(n, 128), 128, 0, s>>>(n, br, bc, A.rp.p, A.ci.p, A.val.p, G.agg.p, q_col, 0, cnt.p, nullptr,
+                                           nullptr, nullptr);
+    MB_LAUNCH_CHECK();
+    int nt = scan_exclusive(cnt.p, n, trp.p, s);
+    DevBuf<int32_t> tci(std::max(nt, 1));
+    DevBuf<double> tval(std::max<int64_t>((int64_t)nt * bs, 1));
+    k_rap1<<<grid_for(n, 128), 128, 0, s>>>(n, br, bc, A.rp.p, A.ci.p, A.val.p, G.agg.p, q_col, 1, nullptr, trp.p,
+                                           tci.p, tval.p);
+    MB_LAUNCH_CHECK();
+    // stage 2: A_c = P_f^T T
+    SetupBsr C;
+    C.n_rows = C.n_cols = nc;
+    C.br = br;
+    C.bc = bc;
+    DevBuf<int32_t> ccnt(std::max(nc, 1));
+    C.rp.alloc(nc + 1);
+    k_rap2<<<grid_for(nc, 64), 64, 0, s>>>(nc, br, bc, G.mptr.p, G.midx.p, trp.p, tci.p, tval.p, q_row, 0, ccnt.p,
+                                          nullptr, nullptr, nullptr);
+    MB_LAUNCH_CHECK();
+    int nnzc = scan_exclusive(ccnt.p, nc, C.rp.p, s);
+    C.nnzb = nnzc;
+    C.ci.alloc(std::max(nnzc, 1));
+    C.val.alloc(std::max<int64_t>((int64_t)nnzc * bs, 1));
+    k_rap2<<<grid_for(nc, 64), 64, 0, s>>>(nc, br, bc, G.mptr.p, G.midx.p, trp.p, tci.p, tval.p, q_row, 1, nullptr,
+                                          C.rp.p, C.ci.p, C.val.p);
+    MB_LAUNCH_CHECK();
+    return C;
+}
+
+void build_dinv(const SetupBsr& A, double* dinv, hipStream_t s) {
+    MB_CHECK(A.br == A.bc && A.br <= 8, MBAMG_E_INVALID, "diagonal blocks must be square with at most 8 dofs");
+    DevBuf<int32_t> sing(1);
+    MB_HIP(hipMemsetAsync(sing.p, 0, sizeof(int32_t), s));
+    k_dinv<<<grid_for(A.n_rows, 64), 64, 0, s>>>(A.n_rows, A.br, A.rp.p, A.ci.p, A.val.p, dinv, sing.p);
+    MB_LAUNCH_CHECK();
+    int32_t h = 0;
+    MB_HIP(hipMemcpyAsync(&h, sing.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MB_HIP(hipStreamSynchronize(s));
+    MB_CHECK(h == 0, MBAMG_E_SINGULAR, "a nodal diagonal block is singular");
+}
+
+void sell_masks(int64_t n_slots, int bs, const int64_t* src, const double* val, uint32_t* mask, uint32_t* slot_nz,
+                hipStream_t s) {
+    MB_HIP(hipMemsetAsync(mask, 0, sizeof(uint32_t) * std::max<int64_t>(n_slots, 1), s));
+    if (n_slots == 0) return;
+    k_sell_mask<<<grid_for(n_slots * WAVE), 256, 0, s>>>(n_slots, bs, src, val, mask, slot_nz);
+    MB_LAUNCH_CHECK();
+}
+
+void sell_fill(int64_t n_slots, int bs, const int64_t* src, const double* val, const uint32_t* mask,
+               const int64_t* slot_voff, double* out, hipStream_t s) {
+    if (n_slots == 0) return;
+    k_sell_fill<<<grid_for(n_slots * WAVE), 256, 0, s>>>(n_slots, bs, src, val, mask, slot_voff, out);
+    MB_LAUNCH_CHECK();
+}
+
+void cast_to_f32(const double* a, float* b, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    k_cast_f64_f32<<<grid_for(n), 256, 0, s>>>(a, b, n);
+    MB_LAUNCH_CHECK();
+}
+
+void coarse_inverse(const SetupBsr (&A)[2][2], const int d[2], DevBuf<double>& inv, int& n_out, hipStream_t s) {
+    const int nn = A[0][0].n_rows;
+    const int n = nn * (d[0] + d[1]);
+    MB_CHECK(n <= 16384, MBAMG_E_INVALID, "coarsest level too large for the dense solve (raise max_levels)");
+    n_out = n;
+    DevBuf<double> M((size_t)n * 2 * n);
+    MB_HIP(hipMemsetAsync(M.p, 0, M.bytes(), s));
+    int64_t off[2] = {0, (int64_t)nn * d[0]};
+    for (int f = 0; f < 2; ++f)
+        for (int g = 0; g < 2; ++g) {
+            const SetupBsr& B = A[f][g];
+            if (B.nnzb == 0) continue;
+            k_dense_scatter<<<grid_for(nn, 64), 64, 0, s>>>(nn, B.br, B.bc, B.rp.p, B.ci.p, B.val.p, off[f], off[g],
+                                                           2 * (int64_t)n, M.p);
+            MB_LAUNCH_CHECK();
+        }
+    k_gj_identity<<<grid_for((int64_t)n * n), 256, 0, s>>>(M.p, n);
+    MB_LAUNCH_CHECK();
+    DevBuf<double> colk(n);
+    DevBuf<int32_t> sing(1);
+    MB_HIP(hipMemsetAsync(sing.p, 0, sizeof(int32_t), s));
+    for (int k = 0; k < n; ++k) {
+        k_gj_pivot<<<1, 1024, 0, s>>>(M.p, n, k, colk.p, sing.p);
+        int64_t work = (int64_t)n * (2 * n - k);
+        k_gj_eliminate<<<grid_for(work), 256, 0, s>>>(M.p, n, k, colk.p);
+    }
+    MB_LAUNCH_CHECK();
+    int32_t h = 0;
+    MB_HIP(hipMemcpyAsync(&h, sing.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MB_HIP(hipStreamSynchronize(s));
+    MB_CHECK(h == 0, MBAMG_E_SINGULAR, "the coarsest matrix is singular");
+    inv.alloc((size_t)n * n);
+    k_gj_extract<<<grid_for((int64_t)n * n), 256, 0, s>>>(M.p, n, inv.p);
+    MB_LAUNCH_CHECK();
+}
+
+}  // namespace mbamg

@@ -1,0 +1,96 @@
+// Solve-phase views and launchers (device work in solve_kernels.hip).
+#pragma once
+
+#include "common.h"
+
+namespace mbamg {
+
+// Rows of one block on one level, in smoother colour order, cut into slices
+// of at most 64 rows that never straddle two colours.
+struct SliceView {
+    const int32_t* row0;
+    const int32_t* nrow;
+};
+
+// One matrix part in masked sliced-ELL form.  Slice s has width[s] slots; slot
+// t of slice s is global slot coff[s]+t, with a column per lane in
+// col[slot*64 + lane] (-1 marks padding) and a bit mask of the block entries
+// stored for every lane of the slot.  The values of the slot's set bits follow
+// each other as groups of 64 (one per lane), the slice's first group being
+// voff[s].
+template <class T>
+struct SellView {
+    const int32_t* width;
+    const int64_t* coff;
+    const int64_t* voff;
+    const uint32_t* mask;
+    const int32_t* col;
+    const T* val;
+};
+
+template <class T>
+struct GsArgs {
+    int s_begin, s_count;      // slices of this colour
+    SliceView sl;
+    SellView<T> off, cpl, dinv;
+    const T* b;                // right-hand side of this block
+    const T* x;                // current iterate of this block (unused when starting from zero)
+    T* t;                      // undamped Gauss-Seidel iterate x + e
+    T* xn;                     // damped result x + omega e
+    const T* xg;               // iterate of the other block for the coupling term
+    int cstart;                // rows below this index already carry this sweep's update
+    T omega;
+    const T* w_row;            // per-row damping (NULL: use omega)
+    int skip_off;              // nothing processed yet and zero start: the A_ff term vanishes
+};
+
+template <class T>
+struct ResidArgs {
+    int s_count[2];
+    SliceView sl[2];
+    SellView<T> off[2], cpl[2], diag[2];
+    const T* b[2];             // NULL for a plain operator apply
+    const T* x[2];
+    T* r[2];
+};
+
+template <class T>
+struct TransferArgs {
+    int n_rows[2];             // fine rows (prolongation) or coarse rows (restriction) per block
+    const int32_t* map[2];     // prolongation: coarse row of each fine row; restriction: member pointer
+    const int32_t* idx[2];     // restriction: member rows
+    const T* q[2];
+    const T* in[2];
+    T* out[2];
+};
+
+template <class T>
+void launch_gs(int d, bool zero_x, bool has_cpl, const GsArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_resid(int d, const ResidArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_restrict(int d, const TransferArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_prolong(int d, const TransferArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_coarse(int n, const double* inv, const T* x, T* y, hipStream_t s);
+
+// Krylov helpers (FP64).  Reductions are two-pass and deterministic.
+constexpr int KMAXQ = 33;        // basis vectors + 1 slot for a norm
+constexpr int KBLOCKS = 1024;
+void launch_multidot(int64_t n, int nq, const double* V, int64_t ldv, const double* w, double* partial,
+                     int nblocks, hipStream_t s);
+void launch_update(int64_t n, int nq, const double* V, int64_t ldv, const double* h, double* w, bool norm,
+                   double* partial, int nblocks, hipStream_t s);
+void launch_reduce(const double* partial, int nblocks, int q0, int cnt, double* out, hipStream_t s);
+void launch_scale(int64_t n, const double* w, const double* nrm2, double* v, hipStream_t s);
+void launch_combine(int64_t n, int k, const double* Z, int64_t ldz, const double* y, double* x, hipStream_t s);
+void launch_combine32(int64_t n, int k, const float* Z, int64_t ldz, const double* y, double* x, hipStream_t s);
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
+int krylov_blocks(int64_t n);
+void launch_gather(int n_rows, int d, const int32_t* perm, const double* src, double* dst, hipStream_t s);
+void launch_scatter(int n_rows, int d, const int32_t* perm, const double* src, double* dst, hipStream_t s);
+void launch_cast64to32(int64_t n, const double* a, float* b, hipStream_t s);
+void launch_cast32to64(int64_t n, const float* a, double* b, hipStream_t s);
+
+}  // namespace mbamg
