@@ -1,0 +1,219 @@
+"""Benchmark: time-to-solution of the monolithic blocked AMG hot path on one GPU.
+
+One step = the whole hot path on one synthetic block system already resident
+in HBM: hierarchy setup on the GPU (strength graph, aggregation, tentative P,
+Galerkin products, smoother data, coarsest inverse) followed by the
+right-preconditioned GMRES solve to rtol 1e-8.  Forms: plain FP64, and the
+FP32 V-cycle inside FP64 flexible GMRES.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-solve (rtol 1e-8) + V-cycle HBM GB/s: FP64 vs FP32-refined vs learned"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD_LABEL = {
+    "2d-32": "2D 32x32 nodes, 6 dofs/node (6,144 unknowns), gamma 0.1",
+    "2d-256": "2D 256x256 nodes, 6 dofs/node (393,216 unknowns), gamma 0.5",
+    "3d-64": "3D 64^3 nodes, 8 dofs/node (2,097,152 unknowns), gamma 0.5",
+    "2d-512-lognormal": "2D 512x512 nodes, 6 dofs/node, lognormal kappa sigma 1, gamma 5",
+    "3d-128-lognormal": "3D 128^3 nodes, 8 dofs/node (16,777,216 unknowns), lognormal kappa sigma 1, gamma 2",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="3d-128-lognormal")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--forms", default="fp64,fp32")
+    ap.add_argument("--vcycles", type=int, default=20, help="V-cycles timed for the V-cycle bandwidth figure")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-n", type=int, default=0, help="grid size of the oracle sample (0: automatic)")
+    return ap.parse_args()
+
+
+def run_step(blocks, system, b, form, rtol, timing):
+    from paper_2103_07537_amd import mbamg
+    import torch
+    h = mbamg.Hierarchy(blocks, system.dofs, system.n_vec, precision=1 if form == "fp32" else 0)
+    if timing:
+        h.timing_enable(True)
+    x = torch.zeros_like(b)
+    info = h.solve(b, x, rtol=rtol)
+    stats = None
+    if timing:
+        stats = {k: h.timing_get(k) for k in (0, 1, 2)}
+    return h, x, info, stats
+
+
+def vcycle_rate(h, b, reps):
+    import torch
+    z = torch.empty_like(b)
+    for _ in range(3):
+        h.vcycle(b, z)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        h.vcycle(b, z)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    return ms, h.vcycle_bytes()
+
+
+def cpu_baseline(args, gpu_iters):
+    """Oracle on a bounded sample of the same workload family (smaller grid),
+    scaled to the full workload's unknowns and to the GPU's iteration count."""
+    from oracle import amg
+    from paper_2103_07537_amd.inputs import WORKLOADS, make_system
+    kw = dict(WORKLOADS[args.workload])
+    full_n = kw["n"]
+    dim = kw["dim"]
+    n_s = args.cpu_sample_n or (96 if dim == 2 else 32)
+    n_s = min(n_s, full_n)
+    kw["n"] = n_s
+    s = make_system(seed=args.seed, **kw)
+    t0 = time.perf_counter()
+    h = amg.setup(s.blocks, s.dofs, amg.Params())
+    t1 = time.perf_counter()
+    x, info = amg.gmres(h, s.b, rtol=args.rtol)
+    t2 = time.perf_counter()
+    ratio = (full_n / n_s) ** dim
+    per_it = (t2 - t1) / max(info.iterations, 1)
+    est_ms = 1e3 * ((t1 - t0) * ratio + per_it * ratio * gpu_iters)
+    return {
+        "value": est_ms, "unit": "ms", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle setup + GMRES(30) on the same generator at {n_s}^{dim} nodes "
+                   f"({s.n_dofs} unknowns, {info.iterations} iterations, {t2 - t0:.1f} s measured), "
+                   f"scaled linearly by the unknown ratio {ratio:.0f} and to the GPU's {gpu_iters} iterations"),
+        "host": platform.processor() or platform.machine(),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described in the design notes but not built)"}))
+        sys.exit(2)
+    import torch
+    from paper_2103_07537_amd import mbamg
+    from paper_2103_07537_amd.inputs import workload
+    mbamg.lib()
+    torch.cuda.set_device(0)
+    log(f"[bench] generating {args.workload} seed {args.seed}")
+    t0 = time.perf_counter()
+    system = workload(args.workload, seed=args.seed)
+    log(f"[bench] generated {system.n_dofs} unknowns in {time.perf_counter() - t0:.1f} s")
+    blocks = mbamg.to_device(system)
+    b = torch.from_numpy(system.b).cuda()
+    torch.cuda.synchronize()
+    forms = [f for f in args.forms.split(",") if f]
+    results = {}
+    xs = {}
+    for form in forms:
+        for w in range(args.warmup):
+            h, x, info, _ = run_step(blocks, system, b, form, args.rtol, False)
+            log(f"[bench] warmup {form} {w}: its {info['iterations']} setup {info['t_setup_ms']:.1f} ms "
+                f"solve {info['t_solve_ms']:.1f} ms")
+            h.close()
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        infos, stats_all = [], []
+        for k in range(args.steps):
+            h, x, info, stats = run_step(blocks, system, b, form, args.rtol, form == "fp64")
+            infos.append(info)
+            stats_all.append(stats)
+            if k < args.steps - 1:
+                h.close()
+        torch.cuda.synchronize()
+        t_total = time.perf_counter() - t_start
+        ms_step = 1e3 * t_total / args.steps
+        last = infos[-1]
+        log(f"[bench] {form}: {ms_step:.1f} ms/step, its {last['iterations']}, rel {last['rel_residual']:.2e}")
+        vc_ms, vc_bytes = vcycle_rate(h, b, args.vcycles)
+        xs[form] = x.cpu().numpy()
+        results[form] = {
+            "ms_per_step": ms_step,
+            "t_setup_ms": float(np.median([i["t_setup_ms"] for i in infos])),
+            "t_solve_ms": float(np.median([i["t_solve_ms"] for i in infos])),
+            "iterations": last["iterations"],
+            "rel_residual": last["rel_residual"],
+            "levels": last["levels"],
+            "op_complexity": last["op_complexity"],
+            "vcycle_ms": vc_ms,
+            "vcycle_alg_GBps": vc_bytes / (vc_ms * 1e-3) / 1e9,
+            "kernel_stats": stats_all[-1],
+        }
+        h.close()
+    ref = "fp64" if "fp64" in xs else forms[0]
+    for form in forms:
+        results[form]["rel_diff_vs_fp64"] = float(np.linalg.norm(xs[form] - xs[ref]) / np.linalg.norm(xs[ref]))
+
+    chosen = "fp32" if "fp32" in results else forms[0]
+    # roofline of the dominant finest-level kernel in the FP64 form (events over the timed steps)
+    roof = None
+    st = results.get("fp64", {}).get("kernel_stats")
+    if st:
+        names = {0: "block Gauss-Seidel colour pass", 1: "residual", 2: "operator apply"}
+        kind = max((0, 1, 2), key=lambda k: st[k]["total_ms"])
+        s = st[kind]
+        per_launch_bytes = s["bytes"] / max(s["launches"], 1)
+        avg_ms = s["total_ms"] / max(s["launches"], 1)
+        achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": names[kind],
+                "launches": s["launches"], "avg_us": avg_ms * 1e3, "alg_bytes_per_launch": per_launch_bytes}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle sample)")
+        cpu = cpu_baseline(args, results[chosen]["iterations"])
+    out = {
+        "metric": METRIC,
+        "value": results[chosen]["ms_per_step"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": results[chosen]["ms_per_step"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 V-cycle in f64 FGMRES" if chosen == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_LABEL.get(args.workload, args.workload), "name": args.workload,
+                   "unknowns": system.n_dofs, "rtol": args.rtol, "krylov": "GMRES(30) right-preconditioned",
+                   "form": chosen},
+        "forms": results,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

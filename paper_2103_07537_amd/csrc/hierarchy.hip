@@ -52,8 +52,16 @@ SellView<double> SellPart::view<double>() const { return {width.p, coff.p, voff.
 template <>
 SellView<float> SellPart::view<float>() const { return {width.p, coff.p, voff.p, mask.p, col.p, v32.p}; }
 
+// Structural values and stored blocks of one colour's rows (byte model).
+struct ColourStats {
+    int64_t off_nz = 0, off_bl = 0, cpl_nz = 0, cpl_bl = 0, dinv_nz = 0;
+};
+
 struct BlockLevel {
     int d = 0, n = 0, n_colours = 0, n_slices = 0;
+    int split = 1;                             // waves per slice in the smoother and residual kernels
+    std::vector<ColourStats> cstats;
+    int64_t all_nz = 0, all_bl = 0;            // off + cpl + diag over every row
     std::vector<int32_t> perm, iperm;          // colour order -> natural node, and back
     std::vector<int32_t> colour;               // natural order
     std::vector<int32_t> h_row0, h_nrow;
@@ -92,6 +100,10 @@ struct TimedLaunch {
 
 thread_local std::string g_last_error;
 
+// Krylov scalar buffer layout (device and pinned host copies)
+constexpr int KB_D1 = 0, KB_C1 = KMAXQ, KB_D2 = 2 * KMAXQ, KB_C2 = 3 * KMAXQ, KB_NU0 = 4 * KMAXQ,
+              KB_NU1 = 4 * KMAXQ + 1, KB_NU2 = 4 * KMAXQ + 2, KB_TOTAL = 4 * KMAXQ + 3;
+
 }  // namespace mbamg
 
 using namespace mbamg;
@@ -105,7 +117,11 @@ struct mbamg_hierarchy {
     int coarse_n = 0;
     // Krylov workspace
     int64_t n_fine = 0;
-    DevBuf<double> V, Z64, w, xw, bw, ztmp, partial, hbuf, ybuf;
+    DevBuf<double> V, Z64, w, xw, bw, ztmp, partial, hbuf, ybuf, sig2;
+    double* hbuf_host = nullptr;   // pinned: Krylov scalars read back each iteration
+    double* sig2_host = nullptr;
+    double* y_host = nullptr;
+    int64_t reorth_count = 0;
     DevBuf<float> Z32, vin32;
     DevBuf<double> vio;   // ABI <-> colour-order staging for vcycle/apply
     DevBuf<double> vio2;
@@ -115,6 +131,15 @@ struct mbamg_hierarchy {
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
     double t_setup_ms = 0.0;
+
+    ~mbamg_hierarchy() {
+        (void)hipDeviceSynchronize();
+        for (auto& t : timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+        for (auto e : event_pool) (void)hipEventDestroy(e);
+        if (hbuf_host) (void)hipHostFree(hbuf_host);
+        if (sig2_host) (void)hipHostFree(sig2_host);
+        if (y_host) (void)hipHostFree(y_host);
+    }
 };
 
 namespace mbamg {
@@ -311,10 +336,8 @@ static void build_part(SellPart& P, PartKind kind, const BlockLevel& B, const st
     std::vector<uint32_t> hmask = P.mask.download(s, nsl);
     P.h_slot_nz = slot_nz.download(s, nsl);
     std::vector<int64_t> slot_voff(nsl, 0);
-    std::vector<int64_t> voff(std::max(ns, 1), 0);
     int64_t g = 0;
     for (int sl = 0; sl < ns; ++sl) {
-        voff[sl] = g;
         for (int t = 0; t < P.h_width[sl]; ++t) {
             int64_t slot = P.h_coff[sl] + t;
             slot_voff[slot] = g;
@@ -322,11 +345,9 @@ static void build_part(SellPart& P, PartKind kind, const BlockLevel& B, const st
         }
     }
     P.n_groups = g;
-    P.voff.upload(voff.data(), ns, s);
-    DevBuf<int64_t> dsv;
-    dsv.upload(slot_voff, s);
+    P.voff.upload(slot_voff, s);
     P.v64.alloc(std::max<int64_t>(g, 1) * WAVE);
-    sell_fill(P.n_slots, br * bc, dsrc.p, val, P.mask.p, dsv.p, P.v64.p, s);
+    sell_fill(P.n_slots, br * bc, dsrc.p, val, P.mask.p, P.voff.p, P.v64.p, s);
     if (want32) {
         P.v32.alloc(std::max<int64_t>(g, 1) * WAVE);
         cast_to_f32(P.v64.p, P.v32.p, g * WAVE, s);
@@ -464,6 +485,26 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
                        want32, s);
             std::vector<int32_t> none;
             build_part(B.dinv, PartKind::Dinv, B, none, none, nullptr, dinv.p, df, df, want32, s);
+            B.cstats.assign(B.n_colours, ColourStats{});
+            int64_t slots = 0;
+            for (int c = 0; c < B.n_colours; ++c) {
+                ColourStats& cs = B.cstats[c];
+                int64_t nz, bl;
+                B.off.stats(B.colour_slice[c], B.colour_slice[c + 1], cs.off_nz, cs.off_bl);
+                B.cpl.stats(B.colour_slice[c], B.colour_slice[c + 1], cs.cpl_nz, cs.cpl_bl);
+                B.dinv.stats(B.colour_slice[c], B.colour_slice[c + 1], cs.dinv_nz, bl);
+                B.diag.stats(B.colour_slice[c], B.colour_slice[c + 1], nz, bl);
+                B.all_nz += cs.off_nz + cs.cpl_nz + nz;
+                B.all_bl += cs.off_bl + cs.cpl_bl + bl;
+            }
+            for (int sl = 0; sl < B.n_slices; ++sl) slots += B.off.h_width[sl] + B.cpl.h_width[sl];
+            // split each slice's slots over several waves when a colour has too few slices to
+            // fill the chip and the rows are wide enough to share
+            const double avg_width = B.n_slices ? (double)slots / B.n_slices : 0.0;
+            const double per_colour = (double)B.n_slices / std::max(1, B.n_colours);
+            B.split = 1;
+            if (per_colour < 2048 && avg_width >= 8) B.split = 2;
+            if (per_colour < 1024 && avg_width >= 16) B.split = 4;
         }
         // transfer maps between this level's and the next level's colour orders
         std::vector<int32_t> agg = Lv.G.agg.download(s, Lv.n);
@@ -514,8 +555,12 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
     h->vio.alloc(n);
     h->vio2.alloc(n);
     h->partial.alloc((size_t)KBLOCKS * KMAXQ);
-    h->hbuf.alloc(3 * KMAXQ);
+    h->hbuf.alloc(KB_TOTAL);
     h->ybuf.alloc(KMAXQ);
+    h->sig2.alloc(KMAXQ);
+    MB_HIP(hipHostMalloc((void**)&h->hbuf_host, sizeof(double) * KB_TOTAL, hipHostMallocDefault));
+    MB_HIP(hipHostMalloc((void**)&h->sig2_host, sizeof(double) * KMAXQ, hipHostMallocDefault));
+    MB_HIP(hipHostMalloc((void**)&h->y_host, sizeof(double) * KMAXQ, hipHostMallocDefault));
     MB_HIP(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
     h->t_setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -530,23 +575,14 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
 // byte model (algorithmic bytes of the finest level's kernels)
 // ----------------------------------------------------------------------------
 static double gs_bytes(const BlockLevel& B, int c, bool zero_x, bool skip_off, bool cpl, int s, int dg) {
-    int s0 = B.colour_slice[c], s1 = B.colour_slice[c + 1];
-    int64_t rows = B.colour_row[c + 1] - B.colour_row[c];
-    int64_t nz, bl, tot = 0;
+    const ColourStats& cs = B.cstats[c];
+    const int64_t rows = B.colour_row[c + 1] - B.colour_row[c];
     double bytes = 0.0;
-    if (!skip_off) {
-        B.off.stats(s0, s1, nz, bl);
-        bytes += nz * (double)s + 4.0 * bl + (double)rows * B.d * s;   // values, indices, gathered iterate
-    }
-    if (cpl) {
-        B.cpl.stats(s0, s1, nz, bl);
-        bytes += nz * (double)s + 4.0 * bl + (double)rows * dg * s;
-    }
-    B.dinv.stats(s0, s1, nz, bl);
-    bytes += nz * (double)s;
-    tot = rows * B.d;
-    bytes += 4.0 * rows;                                   // row pointer equivalent
-    bytes += (double)tot * s * (zero_x ? 3 : 4);           // b, (x), t, xn
+    if (!skip_off) bytes += cs.off_nz * (double)s + 4.0 * cs.off_bl + (double)rows * B.d * s;  // values, indices, gathered iterate
+    if (cpl) bytes += cs.cpl_nz * (double)s + 4.0 * cs.cpl_bl + (double)rows * dg * s;
+    bytes += cs.dinv_nz * (double)s;
+    bytes += 4.0 * rows;                                        // row pointer equivalent
+    bytes += (double)rows * B.d * s * (zero_x ? 3 : 4);         // b, (x), t, xn
     return bytes;
 }
 
@@ -554,12 +590,7 @@ static double resid_bytes(const Level& Lv, int s, bool with_b) {
     double bytes = 0.0;
     for (int f = 0; f < 2; ++f) {
         const BlockLevel& B = Lv.blk[f];
-        int64_t nz, bl;
-        for (const SellPart* P : {&B.off, &B.cpl, &B.diag}) {
-            P->stats(0, B.n_slices, nz, bl);
-            bytes += nz * (double)s + 4.0 * bl;
-        }
-        bytes += 4.0 * B.n;
+        bytes += B.all_nz * (double)s + 4.0 * B.all_bl + 4.0 * B.n;
         bytes += (double)B.n * B.d * s * (with_b ? 4 : 3);   // x_f, x_g gathered, (b), r
     }
     return bytes;
@@ -612,7 +643,7 @@ static void smooth_block(mbamg_hierarchy* h, int l, int f, bool zero, const T* b
             a.skip_off = (zero && k == 0 && c == 0) ? 1 : 0;
             double bytes = timed ? gs_bytes(B, c, zero, a.skip_off, has_cpl, (int)sizeof(T), Lv.d[g]) : 0.0;
             TimerScope ts(h, s, timed, 0, bytes);
-            launch_gs<T>(B.d, zero, has_cpl, a, s);
+            launch_gs<T>(B.d, B.split, zero, has_cpl, a, s);
         }
     }
 }
@@ -637,7 +668,7 @@ static void resid(mbamg_hierarchy* h, int l, const T* b, const T* x, T* r, hipSt
     const bool timed = h->timing && l == 0;
     double bytes = timed ? resid_bytes(Lv, (int)sizeof(T), b != nullptr) : 0.0;
     TimerScope ts(h, s, timed, kind, bytes);
-    launch_resid<T>(Lv.d[0], a, s);
+    launch_resid<T>(Lv.d[0], std::max(Lv.blk[0].split, Lv.blk[1].split), a, s);
 }
 
 // One V-cycle on level l from a zero guess: out = MGV(0, b).
@@ -741,16 +772,24 @@ static void apply_A(mbamg_hierarchy* h, const double* x, double* w, hipStream_t 
 // ----------------------------------------------------------------------------
 // GMRES (right preconditioned) / FGMRES, restarted
 // ----------------------------------------------------------------------------
-static double norm2_dev(mbamg_hierarchy* h, const double* v, hipStream_t s, double* dev_out) {
-    int nb = krylov_blocks(h->n_fine);
-    launch_update(h->n_fine, 0, nullptr, 0, nullptr, const_cast<double*>(v), true, h->partial.p, nb, s);
-    launch_reduce(h->partial.p, nb, 0, 1, dev_out, s);
+// ||v||^2 through the deterministic two-pass reduction (synchronous)
+static double norm2_dev(mbamg_hierarchy* h, const double* v, hipStream_t s) {
+    const int nb = krylov_blocks(h->n_fine);
+    double* kb = h->hbuf.p;
+    launch_orth(h->n_fine, 0, nullptr, 0, nullptr, v, nullptr, false, h->partial.p, nb, s);
+    launch_orth_reduce(h->partial.p, nb, 0, false, h->sig2.p, kb, kb, kb + KB_NU0, s);
     double r = 0.0;
-    MB_HIP(hipMemcpyAsync(&r, dev_out, sizeof(double), hipMemcpyDeviceToHost, s));
+    MB_HIP(hipMemcpyAsync(&r, kb + KB_NU0, sizeof(double), hipMemcpyDeviceToHost, s));
     MB_HIP(hipStreamSynchronize(s));
     return r;
 }
 
+// Restarted GMRES (FGMRES when the cycle runs in FP32), right preconditioned.
+// The Arnoldi basis is kept unnormalised: V_true[q] = sig[q] * V[q], so the
+// normalisation needs no separate pass.  Orthogonalisation is classical
+// Gram-Schmidt with one reorthogonalisation when the new vector lost more
+// than a factor 1/sqrt(2) of its norm ("twice is enough", Daniel, Gragg,
+// Kaufman & Stewart 1976; Giraud, Langou & Rozloznik 2005).
 static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, double rtol, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     const int64_t n = h->n_fine;
@@ -759,51 +798,69 @@ static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, d
     MB_CHECK(!h->L[0]->coarsest, MBAMG_E_STATE, "solve needs at least two levels");
     to_colour(h, b, h->bw.p, s);
     to_colour(h, x, h->xw.p, s);
-    double* dnorm = h->hbuf.p + 2 * KMAXQ;
-    const double bnorm = std::sqrt(norm2_dev(h, h->bw.p, s, dnorm));
+    const double bnorm = std::sqrt(norm2_dev(h, h->bw.p, s));
     int its = 0;
     double rel = 0.0;
     mbamg_status st = MBAMG_OK;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hh(3 * KMAXQ);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), sig(m + 1);
+    double* hb = h->hbuf_host;
+    double* kb = h->hbuf.p;
     const int nb = krylov_blocks(n);
     if (bnorm == 0.0) {
         MB_HIP(hipMemsetAsync(h->xw.p, 0, sizeof(double) * n, s));
         rel = 0.0;
     } else {
         while (true) {
-            // true residual
+            // true residual into V_0
             resid<double>(h, 0, h->bw.p, h->xw.p, h->V.p, s, 1);
-            const double beta = std::sqrt(norm2_dev(h, h->V.p, s, dnorm));
+            const double beta = std::sqrt(norm2_dev(h, h->V.p, s));
             rel = beta / bnorm;
             if (beta <= rtol * bnorm) break;
             if (its >= h->p.max_iters) { st = MBAMG_NOT_CONVERGED; break; }
-            launch_scale(n, h->V.p, dnorm, h->V.p, s);
+            sig[0] = 1.0 / beta;
+            h->sig2_host[0] = sig[0] * sig[0];
+            MB_HIP(hipMemcpyAsync(h->sig2.p, h->sig2_host, sizeof(double), hipMemcpyHostToDevice, s));
             std::fill(g.begin(), g.end(), 0.0);
             g[0] = beta;
             int k = 0;
             for (int j = 0; j < m; ++j) {
                 double* vj = h->V.p + (size_t)j * n;
+                double* vn = h->V.p + (size_t)(j + 1) * n;
                 double* zj64 = fp32 ? h->ztmp.p : h->Z64.p + (size_t)j * n;
                 float* zj32 = fp32 ? h->Z32.p + (size_t)j * n : nullptr;
                 apply_precond(h, vj, zj64, zj32, s);
                 apply_A(h, zj64, h->w.p, s);
-                // classical Gram-Schmidt, twice
-                double* h1 = h->hbuf.p;
-                double* h2 = h->hbuf.p + KMAXQ;
-                launch_multidot(n, j + 1, h->V.p, n, h->w.p, h->partial.p, nb, s);
-                launch_reduce(h->partial.p, nb, 0, j + 1, h1, s);
-                launch_update(n, j + 1, h->V.p, n, h1, h->w.p, false, h->partial.p, nb, s);
-                launch_multidot(n, j + 1, h->V.p, n, h->w.p, h->partial.p, nb, s);
-                launch_reduce(h->partial.p, nb, 0, j + 1, h2, s);
-                launch_update(n, j + 1, h->V.p, n, h2, h->w.p, true, h->partial.p, nb, s);
-                launch_reduce(h->partial.p, nb, j + 1, 1, dnorm, s);
-                MB_HIP(hipMemcpyAsync(hh.data(), h->hbuf.p, sizeof(double) * 3 * KMAXQ, hipMemcpyDeviceToHost, s));
+                const int nq = j + 1;
+                // pass 1: d1 = V^T w, nu0 = |w|^2
+                launch_orth(n, nq, h->V.p, n, nullptr, h->w.p, nullptr, true, h->partial.p, nb, s);
+                launch_orth_reduce(h->partial.p, nb, nq, true, h->sig2.p, kb + KB_D1, kb + KB_C1, kb + KB_NU0, s);
+                // pass 2: V_{j+1} = w - sum c1 V, d2 = V^T V_{j+1}, nu1 = |V_{j+1}|^2
+                launch_orth(n, nq, h->V.p, n, kb + KB_C1, h->w.p, vn, true, h->partial.p, nb, s);
+                launch_orth_reduce(h->partial.p, nb, nq, true, h->sig2.p, kb + KB_D2, kb + KB_C2, kb + KB_NU1, s);
+                MB_HIP(hipMemcpyAsync(hb, kb, sizeof(double) * KB_TOTAL, hipMemcpyDeviceToHost, s));
                 MB_HIP(hipStreamSynchronize(s));
                 double* col = &H[(size_t)j * (m + 1)];
-                for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[KMAXQ + i];
-                const double hn = std::sqrt(hh[2 * KMAXQ]);
+                double nu = hb[KB_NU1];
+                if (nu >= 0.5 * hb[KB_NU0]) {
+                    for (int q = 0; q <= j; ++q) col[q] = sig[j] * sig[q] * hb[KB_D1 + q];
+                } else {
+                    // pass 3: reorthogonalise in place
+                    launch_orth(n, nq, h->V.p, n, kb + KB_C2, vn, vn, false, h->partial.p, nb, s);
+                    launch_orth_reduce(h->partial.p, nb, nq, false, h->sig2.p, kb, kb, kb + KB_NU2, s);
+                    MB_HIP(hipMemcpyAsync(hb + KB_NU2, kb + KB_NU2, sizeof(double), hipMemcpyDeviceToHost, s));
+                    MB_HIP(hipStreamSynchronize(s));
+                    nu = hb[KB_NU2];
+                    for (int q = 0; q <= j; ++q) col[q] = sig[j] * sig[q] * (hb[KB_D1 + q] + hb[KB_D2 + q]);
+                    ++h->reorth_count;
+                }
+                const double hn = sig[j] * std::sqrt(nu);
                 col[j + 1] = hn;
-                if (hn != 0.0 && j + 1 < m + 1) launch_scale(n, h->w.p, dnorm, h->V.p + (size_t)(j + 1) * n, s);
+                if (nu > 0.0) {
+                    sig[j + 1] = 1.0 / std::sqrt(nu);
+                    h->sig2_host[j + 1] = sig[j + 1] * sig[j + 1];
+                    MB_HIP(hipMemcpyAsync(h->sig2.p + j + 1, h->sig2_host + j + 1, sizeof(double),
+                                          hipMemcpyHostToDevice, s));
+                }
                 for (int i = 0; i < j; ++i) {
                     double t = cs[i] * col[i] + sn[i] * col[i + 1];
                     col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
@@ -818,18 +875,18 @@ static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, d
                 g[j] = cs[j] * g[j];
                 ++its;
                 k = j + 1;
-                if (std::fabs(g[j + 1]) <= rtol * bnorm || its >= h->p.max_iters || hn == 0.0) break;
+                if (std::fabs(g[j + 1]) <= rtol * bnorm || its >= h->p.max_iters || nu == 0.0) break;
             }
-            // back substitution H[:k,:k] y = g[:k]
+            // back substitution H[:k,:k] y = g[:k]; x += sum_j y_j sig_j Z_j
             for (int i = k - 1; i >= 0; --i) {
                 double sum = g[i];
                 for (int c = i + 1; c < k; ++c) sum -= H[(size_t)c * (m + 1) + i] * y[c];
                 y[i] = sum / H[(size_t)i * (m + 1) + i];
             }
-            MB_HIP(hipMemcpyAsync(h->ybuf.p, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+            for (int i = 0; i < k; ++i) h->y_host[i] = y[i] * sig[i];
+            MB_HIP(hipMemcpyAsync(h->ybuf.p, h->y_host, sizeof(double) * k, hipMemcpyHostToDevice, s));
             if (fp32) launch_combine32(n, k, h->Z32.p, n, h->ybuf.p, h->xw.p, s);
             else launch_combine(n, k, h->Z64.p, n, h->ybuf.p, h->xw.p, s);
-            MB_HIP(hipStreamSynchronize(s));
         }
     }
     from_colour(h, h->xw.p, x, s);
@@ -963,13 +1020,7 @@ mbamg_status mbamg_get_info(const mbamg_hierarchy* h, mbamg_info* info) {
     return MBAMG_OK;
 }
 
-void mbamg_destroy(mbamg_hierarchy* h) {
-    if (!h) return;
-    (void)hipDeviceSynchronize();
-    for (auto& t : h->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
-    for (auto e : h->event_pool) (void)hipEventDestroy(e);
-    delete h;
-}
+void mbamg_destroy(mbamg_hierarchy* h) { delete h; }
 
 mbamg_status mbamg_num_levels(const mbamg_hierarchy* h, int32_t* n_levels) {
     if (!h || !n_levels) { g_last_error = "NULL argument"; return MBAMG_E_INVALID; }

@@ -16,13 +16,12 @@ struct SliceView {
 // t of slice s is global slot coff[s]+t, with a column per lane in
 // col[slot*64 + lane] (-1 marks padding) and a bit mask of the block entries
 // stored for every lane of the slot.  The values of the slot's set bits follow
-// each other as groups of 64 (one per lane), the slice's first group being
-// voff[s].
+// each other as groups of 64 (one per lane) starting at group voff[slot].
 template <class T>
 struct SellView {
     const int32_t* width;
     const int64_t* coff;
-    const int64_t* voff;
+    const int64_t* voff;       // per slot
     const uint32_t* mask;
     const int32_t* col;
     const T* val;
@@ -64,10 +63,11 @@ struct TransferArgs {
     T* out[2];
 };
 
+// P: waves per slice (1, 2 or 4); the slice's slots are split among them.
 template <class T>
-void launch_gs(int d, bool zero_x, bool has_cpl, const GsArgs<T>& a, hipStream_t s);
+void launch_gs(int d, int P, bool zero_x, bool has_cpl, const GsArgs<T>& a, hipStream_t s);
 template <class T>
-void launch_resid(int d, const ResidArgs<T>& a, hipStream_t s);
+void launch_resid(int d, int P, const ResidArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_restrict(int d, const TransferArgs<T>& a, hipStream_t s);
 template <class T>
@@ -78,12 +78,10 @@ void launch_coarse(int n, const double* inv, const T* x, T* y, hipStream_t s);
 // Krylov helpers (FP64).  Reductions are two-pass and deterministic.
 constexpr int KMAXQ = 33;        // basis vectors + 1 slot for a norm
 constexpr int KBLOCKS = 1024;
-void launch_multidot(int64_t n, int nq, const double* V, int64_t ldv, const double* w, double* partial,
-                     int nblocks, hipStream_t s);
-void launch_update(int64_t n, int nq, const double* V, int64_t ldv, const double* h, double* w, bool norm,
-                   double* partial, int nblocks, hipStream_t s);
-void launch_reduce(const double* partial, int nblocks, int q0, int cnt, double* out, hipStream_t s);
-void launch_scale(int64_t n, const double* w, const double* nrm2, double* v, hipStream_t s);
+void launch_orth(int64_t n, int nq, const double* V, int64_t ldv, const double* c, const double* w, double* out,
+                 bool dots, double* partial, int nblocks, hipStream_t s);
+void launch_orth_reduce(const double* partial, int nblocks, int nq, bool dots, const double* sig2, double* d,
+                        double* cf, double* nu, hipStream_t s);
 void launch_combine(int64_t n, int k, const double* Z, int64_t ldz, const double* y, double* x, hipStream_t s);
 void launch_combine32(int64_t n, int k, const float* Z, int64_t ldz, const double* y, double* x, hipStream_t s);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);

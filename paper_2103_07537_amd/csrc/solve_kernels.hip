@@ -17,15 +17,17 @@ constexpr int CHUNK = 2;        // slots whose loads are issued together
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous range of slices so neighbour gathers stay in its own L2.
-__device__ __forceinline__ int xcd_slice(int nslices_padded_blocks) {
-    const int per = nslices_padded_blocks >> 3;
+__device__ __forceinline__ int xcd_block(int padded_blocks) {
+    const int per = padded_blocks >> 3;
     const int bid = blockIdx.x;
-    const int logical = (bid & 7) * per + (bid >> 3);
-    return logical * WPB + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    return (bid & 7) * per + (bid >> 3);
 }
 
-static inline unsigned xcd_grid(int nslices) {
-    int blocks = (int)ceil_div(nslices, WPB);
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// grid for nslices slices with P waves per slice (4/P slices per 256-thread block)
+static inline unsigned xcd_grid(int nslices, int P) {
+    int blocks = (int)ceil_div(nslices, WPB / P);
     return (unsigned)(ceil_div(blocks, 8) * 8);
 }
 
@@ -80,30 +82,30 @@ __device__ __forceinline__ void store_vec<float, 4>(float* __restrict__ p, const
     *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
 }
 
-// acc[r] -= sum_c A[r,c] * x_col(c) over all slots of one part.
-// MODE 0: x from xa.  MODE 1: columns below cstart from xa (already updated),
-// others from xb.  MODE 2: columns below cstart from xa, others contribute 0.
-template <class T, int BR, int BC, int MODE>
-__device__ __forceinline__ void sell_sub(const SellView<T>& A, int s, int lane, const T* __restrict__ xa,
+// acc[r] -= sum_c A[r,c] * x_col(c) over the slots part, part+P, part+2P, ...
+// of one slice.  MODE 0: x from xa.  MODE 1: columns below cstart from xa
+// (already updated this sweep), others from xb.  MODE 2: columns below cstart
+// from xa, others contribute 0.
+template <class T, int BR, int BC, int MODE, int P>
+__device__ __forceinline__ void sell_sub(const SellView<T>& A, int s, int lane, int part, const T* __restrict__ xa,
                                          const T* __restrict__ xb, int cstart, T (&acc)[BR]) {
     const int w = A.width[s];
     const int64_t cb = A.coff[s];
-    int64_t vg = A.voff[s];
-    for (int t = 0; t < w; t += CHUNK) {
+    for (int t = part; t < w; t += P * CHUNK) {
         int j[CHUNK];
         uint32_t m[CHUNK];
+        int64_t vg[CHUNK];
 #pragma unroll
         for (int u = 0; u < CHUNK; ++u) {
-            const bool live = t + u < w;
-            m[u] = live ? A.mask[cb + t + u] : 0u;
-            j[u] = live ? A.col[(cb + t + u) * WAVE + lane] : -1;
+            const int tt = t + u * P;
+            const bool live = tt < w;
+            m[u] = live ? A.mask[cb + tt] : 0u;
+            vg[u] = live ? A.voff[cb + tt] : 0;
+            j[u] = live ? A.col[(cb + tt) * WAVE + lane] : -1;
         }
         T v[CHUNK][BR * BC];
 #pragma unroll
-        for (int u = 0; u < CHUNK; ++u) {
-            load_masked<T, BR * BC>(A.val + vg * WAVE + lane, m[u], v[u]);
-            vg += __builtin_popcount(m[u]);
-        }
+        for (int u = 0; u < CHUNK; ++u) load_masked<T, BR * BC>(A.val + vg[u] * WAVE + lane, m[u], v[u]);
         T xj[CHUNK][BC];
 #pragma unroll
         for (int u = 0; u < CHUNK; ++u) {
@@ -127,30 +129,59 @@ __device__ __forceinline__ void sell_sub(const SellView<T>& A, int s, int lane, 
     }
 }
 
+// Sum the P partial accumulators of one slice through LDS in a fixed order;
+// the result is valid in the slice's part-0 wave.
+template <class T, int D, int P>
+__device__ __forceinline__ void combine_parts(T (&acc)[D], int wave, int part, int lane) {
+    if constexpr (P > 1) {
+        __shared__ T red[WPB][WAVE][D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) red[wave][lane][r] = acc[r];
+        __syncthreads();
+        if (part == 0) {
+#pragma unroll
+            for (int p = 1; p < P; ++p)
+#pragma unroll
+                for (int r = 0; r < D; ++r) acc[r] += red[wave + p][lane][r];
+        }
+    }
+}
+
 // One colour of the multicolour nodal-block Gauss-Seidel sub-solve of block f
 // inside Algorithm 1: for each row i of the colour
 //   t_i  = D_i^-1 (b_i - sum_{j != i} A_ff[i,j] t_j - (A_fg x_g)_i)
 //   xn_i = x_i + omega (t_i - x_i)
 // where t_j is the updated value for rows of earlier colours and x_j otherwise;
 // t_i - x_i is the sub-solve's correction e_i for the residual b - A x.
-template <class T, int D, bool ZX, bool CPL>
+template <class T, int D, bool ZX, bool CPL, int P>
 __global__ __launch_bounds__(256) void k_gs(GsArgs<T> a, int padded_blocks) {
-    const int sidx = xcd_slice(padded_blocks);
-    if (sidx >= a.s_count) return;
-    const int s = a.s_begin + sidx;
+    const int wave = wave_id();
+    const int part = wave % P;
+    const int sidx = xcd_block(padded_blocks) * (WPB / P) + wave / P;
+    const bool valid = sidx < a.s_count;
+    if (P == 1 && !valid) return;
+    const int s = a.s_begin + (valid ? sidx : 0);
     const int lane = threadIdx.x & (WAVE - 1);
     const int row0 = a.sl.row0[s], nrow = a.sl.nrow[s];
-    const bool act = lane < nrow;
-    const int row = row0 + (act ? lane : 0);
+    const bool act = valid && lane < nrow;
+    const int row = row0 + (lane < nrow ? lane : 0);
     T acc[D];
-    load_vec<T, D>(a.b + (int64_t)row * D, acc);
-    if (!a.skip_off) {
-        if (ZX) sell_sub<T, D, D, 2>(a.off, s, lane, a.t, nullptr, a.cstart, acc);
-        else sell_sub<T, D, D, 1>(a.off, s, lane, a.t, a.x, a.cstart, acc);
+    if (part == 0) load_vec<T, D>(a.b + (int64_t)row * D, acc);
+    else {
+#pragma unroll
+        for (int r = 0; r < D; ++r) acc[r] = T(0);
     }
-    if (CPL) sell_sub<T, D, D, 0>(a.cpl, s, lane, a.xg, nullptr, 0, acc);
+    if (valid) {
+        if (!a.skip_off) {
+            if (ZX) sell_sub<T, D, D, 2, P>(a.off, s, lane, part, a.t, nullptr, a.cstart, acc);
+            else sell_sub<T, D, D, 1, P>(a.off, s, lane, part, a.t, a.x, a.cstart, acc);
+        }
+        if (CPL) sell_sub<T, D, D, 0, P>(a.cpl, s, lane, part, a.xg, nullptr, 0, acc);
+    }
+    combine_parts<T, D, P>(acc, wave, part, lane);
+    if (part != 0 || !valid) return;
     T dv[D * D];
-    load_masked<T, D * D>(a.dinv.val + a.dinv.voff[s] * WAVE + lane, a.dinv.mask[a.dinv.coff[s]], dv);
+    load_masked<T, D * D>(a.dinv.val + a.dinv.voff[a.dinv.coff[s]] * WAVE + lane, a.dinv.mask[a.dinv.coff[s]], dv);
     T tn[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) {
@@ -176,27 +207,35 @@ __global__ __launch_bounds__(256) void k_gs(GsArgs<T> a, int padded_blocks) {
 }
 
 // r = b - A x (or w = A x when b is NULL) for both block rows in one launch.
-template <class T, int D>
+template <class T, int D, int P>
 __global__ __launch_bounds__(256) void k_resid(ResidArgs<T> a, int padded_blocks) {
-    int sidx = xcd_slice(padded_blocks);
+    const int wave = wave_id();
+    const int part = wave % P;
+    int sidx = xcd_block(padded_blocks) * (WPB / P) + wave / P;
     int f = 0;
+    bool valid = true;
     if (sidx >= a.s_count[0]) {
         sidx -= a.s_count[0];
         f = 1;
-        if (sidx >= a.s_count[1]) return;
+        if (sidx >= a.s_count[1]) valid = false;
     }
+    if (P == 1 && !valid) return;
+    if (!valid) sidx = 0;
     const int g = 1 - f;
     const int lane = threadIdx.x & (WAVE - 1);
     const int row0 = a.sl[f].row0[sidx], nrow = a.sl[f].nrow[sidx];
-    const bool act = lane < nrow;
-    const int row = row0 + (act ? lane : 0);
+    const bool act = valid && lane < nrow;
+    const int row = row0 + (lane < nrow ? lane : 0);
     T acc[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) acc[r] = T(0);
-    sell_sub<T, D, D, 0>(a.diag[f], sidx, lane, a.x[f], nullptr, 0, acc);
-    sell_sub<T, D, D, 0>(a.off[f], sidx, lane, a.x[f], nullptr, 0, acc);
-    sell_sub<T, D, D, 0>(a.cpl[f], sidx, lane, a.x[g], nullptr, 0, acc);
-    if (!act) return;
+    if (valid) {
+        sell_sub<T, D, D, 0, P>(a.diag[f], sidx, lane, part, a.x[f], nullptr, 0, acc);
+        sell_sub<T, D, D, 0, P>(a.off[f], sidx, lane, part, a.x[f], nullptr, 0, acc);
+        sell_sub<T, D, D, 0, P>(a.cpl[f], sidx, lane, part, a.x[g], nullptr, 0, acc);
+    }
+    combine_parts<T, D, P>(acc, wave, part, lane);
+    if (part != 0 || !act) return;
     T out[D];
     if (a.b[f]) {
         T bb[D];
@@ -274,43 +313,63 @@ __global__ __launch_bounds__(256) void k_coarse(int n, const double* __restrict_
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <class T, int D>
+template <class T, int D, int P>
 static void gs_dispatch(bool zx, bool cpl, const GsArgs<T>& a, hipStream_t s) {
-    if (a.s_count <= 0) return;
-    unsigned grid = xcd_grid(a.s_count);
+    unsigned grid = xcd_grid(a.s_count, P);
     int pb = (int)grid;
     if (zx) {
-        if (cpl) k_gs<T, D, true, true><<<grid, 256, 0, s>>>(a, pb);
-        else k_gs<T, D, true, false><<<grid, 256, 0, s>>>(a, pb);
+        if (cpl) k_gs<T, D, true, true, P><<<grid, 256, 0, s>>>(a, pb);
+        else k_gs<T, D, true, false, P><<<grid, 256, 0, s>>>(a, pb);
     } else {
-        if (cpl) k_gs<T, D, false, true><<<grid, 256, 0, s>>>(a, pb);
-        else k_gs<T, D, false, false><<<grid, 256, 0, s>>>(a, pb);
+        if (cpl) k_gs<T, D, false, true, P><<<grid, 256, 0, s>>>(a, pb);
+        else k_gs<T, D, false, false, P><<<grid, 256, 0, s>>>(a, pb);
+    }
+}
+
+template <class T, int D>
+static void gs_dispatch_p(int P, bool zx, bool cpl, const GsArgs<T>& a, hipStream_t s) {
+    switch (P) {
+        case 1: gs_dispatch<T, D, 1>(zx, cpl, a, s); break;
+        case 2: gs_dispatch<T, D, 2>(zx, cpl, a, s); break;
+        case 4: gs_dispatch<T, D, 4>(zx, cpl, a, s); break;
+        default: throw Error(MBAMG_E_INVALID, "slot split must be 1, 2 or 4");
+    }
+}
+
+template <class T>
+void launch_gs(int d, int P, bool zero_x, bool has_cpl, const GsArgs<T>& a, hipStream_t s) {
+    if (a.s_count <= 0) return;
+    switch (d) {
+        case 1: gs_dispatch_p<T, 1>(P, zero_x, has_cpl, a, s); break;
+        case 2: gs_dispatch_p<T, 2>(P, zero_x, has_cpl, a, s); break;
+        case 3: gs_dispatch_p<T, 3>(P, zero_x, has_cpl, a, s); break;
+        case 4: gs_dispatch_p<T, 4>(P, zero_x, has_cpl, a, s); break;
+        default: throw Error(MBAMG_E_INVALID, "dofs per node must be 1..4");
     }
     MB_LAUNCH_CHECK();
 }
 
-template <class T>
-void launch_gs(int d, bool zero_x, bool has_cpl, const GsArgs<T>& a, hipStream_t s) {
-    switch (d) {
-        case 1: gs_dispatch<T, 1>(zero_x, has_cpl, a, s); break;
-        case 2: gs_dispatch<T, 2>(zero_x, has_cpl, a, s); break;
-        case 3: gs_dispatch<T, 3>(zero_x, has_cpl, a, s); break;
-        case 4: gs_dispatch<T, 4>(zero_x, has_cpl, a, s); break;
-        default: throw Error(MBAMG_E_INVALID, "dofs per node must be 1..4");
+template <class T, int D>
+static void resid_dispatch(int P, const ResidArgs<T>& a, hipStream_t s) {
+    const int total = a.s_count[0] + a.s_count[1];
+    unsigned grid = xcd_grid(total, P);
+    int pb = (int)grid;
+    switch (P) {
+        case 1: k_resid<T, D, 1><<<grid, 256, 0, s>>>(a, pb); break;
+        case 2: k_resid<T, D, 2><<<grid, 256, 0, s>>>(a, pb); break;
+        case 4: k_resid<T, D, 4><<<grid, 256, 0, s>>>(a, pb); break;
+        default: throw Error(MBAMG_E_INVALID, "slot split must be 1, 2 or 4");
     }
 }
 
 template <class T>
-void launch_resid(int d, const ResidArgs<T>& a, hipStream_t s) {
-    const int total = a.s_count[0] + a.s_count[1];
-    if (total <= 0) return;
-    unsigned grid = xcd_grid(total);
-    int pb = (int)grid;
+void launch_resid(int d, int P, const ResidArgs<T>& a, hipStream_t s) {
+    if (a.s_count[0] + a.s_count[1] <= 0) return;
     switch (d) {
-        case 1: k_resid<T, 1><<<grid, 256, 0, s>>>(a, pb); break;
-        case 2: k_resid<T, 2><<<grid, 256, 0, s>>>(a, pb); break;
-        case 3: k_resid<T, 3><<<grid, 256, 0, s>>>(a, pb); break;
-        case 4: k_resid<T, 4><<<grid, 256, 0, s>>>(a, pb); break;
+        case 1: resid_dispatch<T, 1>(P, a, s); break;
+        case 2: resid_dispatch<T, 2>(P, a, s); break;
+        case 3: resid_dispatch<T, 3>(P, a, s); break;
+        case 4: resid_dispatch<T, 4>(P, a, s); break;
         default: throw Error(MBAMG_E_INVALID, "dofs per node must be 1..4");
     }
     MB_LAUNCH_CHECK();
@@ -353,10 +412,10 @@ void launch_coarse(int n, const double* inv, const T* x, T* y, hipStream_t s) {
     MB_LAUNCH_CHECK();
 }
 
-template void launch_gs<double>(int, bool, bool, const GsArgs<double>&, hipStream_t);
-template void launch_gs<float>(int, bool, bool, const GsArgs<float>&, hipStream_t);
-template void launch_resid<double>(int, const ResidArgs<double>&, hipStream_t);
-template void launch_resid<float>(int, const ResidArgs<float>&, hipStream_t);
+template void launch_gs<double>(int, int, bool, bool, const GsArgs<double>&, hipStream_t);
+template void launch_gs<float>(int, int, bool, bool, const GsArgs<float>&, hipStream_t);
+template void launch_resid<double>(int, int, const ResidArgs<double>&, hipStream_t);
+template void launch_resid<float>(int, int, const ResidArgs<float>&, hipStream_t);
 template void launch_restrict<double>(int, const TransferArgs<double>&, hipStream_t);
 template void launch_restrict<float>(int, const TransferArgs<float>&, hipStream_t);
 template void launch_prolong<double>(int, const TransferArgs<double>&, hipStream_t);
@@ -378,69 +437,78 @@ __device__ inline double block_sum(double v, double* sh) {
     return r;
 }
 
-// partial[b*KMAXQ + q] = sum over this block's elements of V_q . w
-__global__ __launch_bounds__(256) void k_multidot(int64_t n, int nq, const double* __restrict__ V, int64_t ldv,
-                                                  const double* __restrict__ w, double* __restrict__ partial) {
+// One pass of Gram-Schmidt over the basis V_0..V_{nq-1} (stored column by
+// column, ldv apart):
+//   u = w - sum_q c_q V_q          (c == NULL: u = w)
+//   out = u                         (when out != NULL; out may alias w)
+//   partial[b*KMAXQ + q] = sum V_q . u over this block's elements (dots != 0)
+//   partial[b*KMAXQ + nq] = sum u . u
+// All loads of one element are issued before any use; NQ bounds nq.
+template <int NQ>
+__global__ __launch_bounds__(256) void k_orth(int64_t n, int nq, const double* __restrict__ V, int64_t ldv,
+                                              const double* __restrict__ c, const double* w, double* out, int dots,
+                                              double* __restrict__ partial) {
     __shared__ double sh[4];
-    double acc[KMAXQ - 1];
+    double cq[NQ], acc[NQ];
 #pragma unroll
-    for (int q = 0; q < KMAXQ - 1; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NQ; ++q) {
+        cq[q] = (c != nullptr && q < nq) ? c[q] : 0.0;
+        acc[q] = 0.0;
+    }
+    double nn = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        const double we = w[e];
+        double v[NQ];
 #pragma unroll
-        for (int q = 0; q < KMAXQ - 1; ++q)
-            if (q < nq) acc[q] += V[q * ldv + e] * we;
-    }
+        for (int q = 0; q < NQ; ++q) {
+            if (q < nq) v[q] = V[q * ldv + e];
+            else v[q] = 0.0;
+        }
+        double u = w[e];
+        if (c != nullptr) {
 #pragma unroll
-    for (int q = 0; q < KMAXQ - 1; ++q) {
-        if (q >= nq) break;
-        double r = block_sum(acc[q], sh);
-        if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * KMAXQ + q] = r;
+            for (int q = 0; q < NQ; ++q) u -= cq[q] * v[q];
+        }
+        if (out != nullptr) out[e] = u;
+        if (dots) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] += v[q] * u;
+        }
+        nn += u * u;
     }
+    if (dots) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            if (q < nq) {
+                double r = block_sum(acc[q], sh);
+                if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * KMAXQ + q] = r;
+            }
+        }
+    }
+    double r = block_sum(nn, sh);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * KMAXQ + nq] = r;
 }
 
-// w -= sum_q h_q V_q ; optionally partial norm^2 of the new w in slot nq
-__global__ __launch_bounds__(256) void k_update(int64_t n, int nq, const double* __restrict__ V, int64_t ldv,
-                                                const double* __restrict__ h, double* __restrict__ w, int norm,
-                                                double* __restrict__ partial) {
+// Final sums in a fixed order: d[q] = sum_b partial[b][q], cf[q] = sig2[q] * d[q]
+// for q < nq (when dots != 0), nu = sum_b partial[b][nq].
+__global__ void k_orth_reduce(const double* __restrict__ partial, int nb, int nq, int dots,
+                              const double* __restrict__ sig2, double* __restrict__ d, double* __restrict__ cf,
+                              double* __restrict__ nu) {
     __shared__ double sh[4];
-    double hq[KMAXQ - 1];
-#pragma unroll
-    for (int q = 0; q < KMAXQ - 1; ++q) hq[q] = q < nq ? h[q] : 0.0;
-    double acc = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        double we = w[e];
-#pragma unroll
-        for (int q = 0; q < KMAXQ - 1; ++q)
-            if (q < nq) we -= hq[q] * V[q * ldv + e];
-        w[e] = we;
-        acc += we * we;
-    }
-    if (norm) {
-        double r = block_sum(acc, sh);
-        if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * KMAXQ + nq] = r;
-    }
-}
-
-// out[q - q0] = sum_b partial[b*KMAXQ + q] for q in [q0, q0+cnt), in a fixed order
-__global__ void k_reduce(const double* __restrict__ partial, int nb, int q0, int cnt, double* __restrict__ out) {
-    __shared__ double sh[4];
-    for (int q = q0; q < q0 + cnt; ++q) {
+    for (int q = dots ? 0 : nq; q <= nq; ++q) {
         double v = 0.0;
         for (int b = threadIdx.x; b < nb; b += blockDim.x) v += partial[(int64_t)b * KMAXQ + q];
         double r = block_sum(v, sh);
-        if (threadIdx.x == 0) out[q - q0] = r;
+        if (threadIdx.x == 0) {
+            if (q < nq) {
+                d[q] = r;
+                cf[q] = sig2[q] * r;
+            } else {
+                *nu = r;
+            }
+        }
         __syncthreads();
     }
-}
-
-__global__ void k_scale(int64_t n, const double* __restrict__ w, const double* __restrict__ nrm2,
-                        double* __restrict__ v) {
-    const double inv = 1.0 / sqrt(*nrm2);
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        v[e] = w[e] * inv;
 }
 
 template <class TZ>
@@ -487,33 +555,25 @@ __global__ void k_c32to64(int64_t n, const float* __restrict__ a, double* __rest
         b[e] = (double)a[e];
 }
 
-int krylov_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(KBLOCKS, ceil_div(n, 256))); }
+int krylov_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(KBLOCKS, ceil_div(n, 1024))); }
 
 static unsigned stream_grid(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n, 256)));
 }
 
-void launch_multidot(int64_t n, int nq, const double* V, int64_t ldv, const double* w, double* partial,
-                     int nblocks, hipStream_t s) {
-    MB_CHECK(nq >= 1 && nq <= KMAXQ - 1, MBAMG_E_INVALID, "too many Krylov vectors");
-    k_multidot<<<nblocks, 256, 0, s>>>(n, nq, V, ldv, w, partial);
-    MB_LAUNCH_CHECK();
-}
-
-void launch_update(int64_t n, int nq, const double* V, int64_t ldv, const double* h, double* w, bool norm,
-                   double* partial, int nblocks, hipStream_t s) {
+void launch_orth(int64_t n, int nq, const double* V, int64_t ldv, const double* c, const double* w, double* out,
+                 bool dots, double* partial, int nblocks, hipStream_t s) {
     MB_CHECK(nq >= 0 && nq <= KMAXQ - 1, MBAMG_E_INVALID, "too many Krylov vectors");
-    k_update<<<nblocks, 256, 0, s>>>(n, nq, V, ldv, h, w, norm ? 1 : 0, partial);
+    const int d = dots ? 1 : 0;
+    if (nq <= 8) k_orth<8><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, c, w, out, d, partial);
+    else if (nq <= 16) k_orth<16><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, c, w, out, d, partial);
+    else k_orth<32><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, c, w, out, d, partial);
     MB_LAUNCH_CHECK();
 }
 
-void launch_reduce(const double* partial, int nblocks, int q0, int cnt, double* out, hipStream_t s) {
-    k_reduce<<<1, 256, 0, s>>>(partial, nblocks, q0, cnt, out);
-    MB_LAUNCH_CHECK();
-}
-
-void launch_scale(int64_t n, const double* w, const double* nrm2, double* v, hipStream_t s) {
-    k_scale<<<stream_grid(n), 256, 0, s>>>(n, w, nrm2, v);
+void launch_orth_reduce(const double* partial, int nblocks, int nq, bool dots, const double* sig2, double* d,
+                        double* cf, double* nu, hipStream_t s) {
+    k_orth_reduce<<<1, 256, 0, s>>>(partial, nblocks, nq, dots ? 1 : 0, sig2, d, cf, nu);
     MB_LAUNCH_CHECK();
 }
 
