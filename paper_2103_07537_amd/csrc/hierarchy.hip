@@ -7,6 +7,7 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <numeric>
@@ -66,7 +67,7 @@ struct BlockLevel {
     std::vector<int32_t> colour;               // natural order
     std::vector<int32_t> h_row0, h_nrow;
     std::vector<int> colour_slice, colour_row;  // per colour: first slice, first row (+ end)
-    DevBuf<int32_t> row0, nrow, d_perm;
+    DevBuf<int32_t> row0, nrow, d_perm, d_iperm;
     SellPart off, cpl, diag, dinv;
     // transfer to the next level (colour orders of both levels)
     DevBuf<int32_t> agg_p, mem_ptr, mem_idx;
@@ -177,6 +178,25 @@ struct TimerScope {
     }
 };
 
+// Setup phase timing, printed to stderr when MBAMG_VERBOSE is set (the stream
+// is synchronised at each mark only in that case).
+struct PhaseClock {
+    bool on;
+    hipStream_t s;
+    std::chrono::steady_clock::time_point last;
+    explicit PhaseClock(hipStream_t ss) : on(std::getenv("MBAMG_VERBOSE") != nullptr), s(ss) {
+        last = std::chrono::steady_clock::now();
+    }
+    void mark(const char* what, int level) {
+        if (!on) return;
+        (void)hipStreamSynchronize(s);
+        auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[mbamg setup] level %d %-22s %8.2f ms\n", level, what,
+                     std::chrono::duration<double, std::milli>(now - last).count());
+        last = now;
+    }
+};
+
 // ----------------------------------------------------------------------------
 // setup helpers
 // ----------------------------------------------------------------------------
@@ -270,88 +290,47 @@ static void order_and_slice(BlockLevel& B, int n, int ncol) {
     B.n_slices = (int)B.h_row0.size();
 }
 
-enum class PartKind { Off, Cpl, Diag, Dinv };
+enum class PartKind { Off = 0, Cpl = 1, Diag = 2, Dinv = 3 };
 
-// Pack one part of block row f into masked slices.
-// rp/ci: natural-order pattern of the source (unused for Dinv); val: device values
-// (BSR values, or the dense per-node inverse array for Dinv); col_iperm maps
-// natural column nodes to the column block's colour order.
-static void build_part(SellPart& P, PartKind kind, const BlockLevel& B, const std::vector<int32_t>& rp,
-                       const std::vector<int32_t>& ci, const std::vector<int32_t>* col_iperm, const double* val,
-                       int br, int bc, bool want32, hipStream_t s) {
+// Pack one part of block row f into masked slices on the device.  A: the
+// natural-order source block (unused for Dinv); val: its values, or the dense
+// per-node inverse array for Dinv; col_iperm: natural column node -> colour
+// order of the column block.
+static void build_part(SellPart& P, PartKind kind, const BlockLevel& B, const SetupBsr* A, const int32_t* col_iperm,
+                       const double* val, int br, int bc, bool want32, hipStream_t s) {
     P.br = br;
     P.bc = bc;
     const int ns = B.n_slices;
-    P.h_width.assign(ns, 0);
-    P.h_coff.assign(ns + 1, 0);
-    auto row_blocks = [&](int node, auto&& fn) {
-        if (kind == PartKind::Dinv) { fn(node, (int64_t)node); return; }
-        if (rp.empty()) return;
-        for (int p = rp[node]; p < rp[node + 1]; ++p) {
-            int j = ci[p];
-            if (kind == PartKind::Off && j == node) continue;
-            if (kind == PartKind::Diag && j != node) continue;
-            fn(j, (int64_t)p);
-        }
-    };
-    for (int sl = 0; sl < ns; ++sl) {
-        int w = 0;
-        for (int l = 0; l < B.h_nrow[sl]; ++l) {
-            int node = B.perm[B.h_row0[sl] + l];
-            int c = 0;
-            row_blocks(node, [&](int, int64_t) { ++c; });
-            w = std::max(w, c);
-        }
-        if (kind == PartKind::Diag || kind == PartKind::Dinv) w = 1;
-        P.h_width[sl] = w;
-        P.h_coff[sl + 1] = P.h_coff[sl] + w;
-    }
-    P.n_slots = P.h_coff[ns];
+    const int k = (int)kind;
+    const int32_t* rp = A ? A->rp.p : nullptr;
+    const int32_t* ci = A ? A->ci.p : nullptr;
+    DevBuf<int32_t> coff32;
+    part_layout(B.n, ns, k, B.d_perm.p, rp, ci, B.row0.p, B.nrow.p, P.width, coff32, P.n_slots, s);
     const int64_t nsl = std::max<int64_t>(P.n_slots, 1);
-    std::vector<int32_t> hcol(nsl * WAVE, -1);
-    std::vector<int64_t> hsrc(nsl * WAVE, -1);
-    P.h_slot_blocks.assign(nsl, 0);
-    for (int sl = 0; sl < ns; ++sl) {
-        for (int l = 0; l < B.h_nrow[sl]; ++l) {
-            int node = B.perm[B.h_row0[sl] + l];
-            int t = 0;
-            row_blocks(node, [&](int j, int64_t src) {
-                int64_t slot = P.h_coff[sl] + t;
-                hcol[slot * WAVE + l] = col_iperm ? (*col_iperm)[j] : B.iperm[j];
-                hsrc[slot * WAVE + l] = src;
-                P.h_slot_blocks[slot]++;
-                ++t;
-            });
-        }
-    }
-    P.width.upload(P.h_width, s);
-    P.coff.upload(P.h_coff.data(), ns, s);
-    P.col.upload(hcol, s);
-    DevBuf<int64_t> dsrc;
-    dsrc.upload(hsrc, s);
+    P.col.alloc(nsl * WAVE);
+    DevBuf<int64_t> src(nsl * WAVE);
+    DevBuf<int32_t> sblk(nsl);
+    part_fill_index(ns, k, B.row0.p, B.nrow.p, P.width.p, coff32.p, B.d_perm.p, rp, ci, col_iperm, P.n_slots, P.col.p,
+                    src.p, sblk.p, s);
+    P.coff.alloc(std::max(ns, 1));
+    i32_to_i64(ns, coff32.p, P.coff.p, s);
     P.mask.alloc(nsl);
     DevBuf<uint32_t> slot_nz(nsl);
     MB_HIP(hipMemsetAsync(slot_nz.p, 0, sizeof(uint32_t) * nsl, s));
-    sell_masks(P.n_slots, br * bc, dsrc.p, val, P.mask.p, slot_nz.p, s);
-    std::vector<uint32_t> hmask = P.mask.download(s, nsl);
-    P.h_slot_nz = slot_nz.download(s, nsl);
-    std::vector<int64_t> slot_voff(nsl, 0);
-    int64_t g = 0;
-    for (int sl = 0; sl < ns; ++sl) {
-        for (int t = 0; t < P.h_width[sl]; ++t) {
-            int64_t slot = P.h_coff[sl] + t;
-            slot_voff[slot] = g;
-            g += __builtin_popcount(hmask[slot]);
-        }
-    }
-    P.n_groups = g;
-    P.voff.upload(slot_voff, s);
-    P.v64.alloc(std::max<int64_t>(g, 1) * WAVE);
-    sell_fill(P.n_slots, br * bc, dsrc.p, val, P.mask.p, P.voff.p, P.v64.p, s);
+    sell_masks(P.n_slots, br * bc, src.p, val, P.mask.p, slot_nz.p, s);
+    P.n_groups = slot_offsets(P.n_slots, P.mask.p, P.voff, s);
+    P.v64.alloc(std::max<int64_t>(P.n_groups, 1) * WAVE);
+    sell_fill(P.n_slots, br * bc, src.p, val, P.mask.p, P.voff.p, P.v64.p, s);
     if (want32) {
-        P.v32.alloc(std::max<int64_t>(g, 1) * WAVE);
-        cast_to_f32(P.v64.p, P.v32.p, g * WAVE, s);
+        P.v32.alloc(std::max<int64_t>(P.n_groups, 1) * WAVE);
+        cast_to_f32(P.v64.p, P.v32.p, P.n_groups * WAVE, s);
     }
+    // host copies for the byte model
+    P.h_width = P.width.download(s, ns);
+    std::vector<int32_t> c32 = coff32.download(s, ns + 1);
+    P.h_coff.assign(c32.begin(), c32.end());
+    P.h_slot_nz = slot_nz.download(s, nsl);
+    P.h_slot_blocks = sblk.download(s, nsl);
     MB_HIP(hipStreamSynchronize(s));   // keep the temporaries alive until the kernels finish
 }
 
@@ -375,6 +354,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
     const int N = Ab[0].n_brows;
     MB_CHECK(N > 0, MBAMG_E_INVALID, "empty system");
     const bool want32 = p.precision == 1;
+    PhaseClock clk(s);
 
     // level 0 from the caller's blocks
     auto first = std::make_unique<Level>();
@@ -397,8 +377,11 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
         Level& cur = *h->L.back();
         const int64_t ndof = (int64_t)cur.n * (d0 + d1);
         if (ndof <= p.max_coarse || (int)h->L.size() >= p.max_levels) break;
+        clk.mark("start", lvl);
         Strength S = build_strength(cur.A[0][0], p.theta, s);
+        clk.mark("strength", lvl);
         Aggregates G = build_aggregates(S, p.seed, lvl, s);
+        clk.mark("aggregates", lvl);
         if ((double)G.n_agg > 0.9 * cur.n) break;
         const int nc = G.n_agg;
         DevBuf<double> q[2], Bc[2];
@@ -426,6 +409,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
                 }
                 nxt->A[f][g] = galerkin(cur.A[f][g], G, q[f].p, q[g].p, s);
             }
+        clk.mark("tentative+galerkin", lvl);
         // keep q on the fine level (natural order) for the transfer maps
         cur.blk[0].q64 = std::move(q[0]);
         cur.blk[1].q64 = std::move(q[1]);
@@ -440,7 +424,9 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
     // coarsest: dense inverse
     {
         Level& c = *h->L.back();
+        clk.mark("before coarse", (int)h->L.size() - 1);
         coarse_inverse(c.A, c.d, h->coarse_inv, h->coarse_n, s);
+        clk.mark("coarse inverse", (int)h->L.size() - 1);
         for (int f = 0; f < 2; ++f) {      // identity order
             BlockLevel& B = c.blk[f];
             B.d = c.d[f];
@@ -449,6 +435,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
             std::iota(B.perm.begin(), B.perm.end(), 0);
             B.iperm = B.perm;
             B.d_perm.upload(B.perm, s);   // used at the interface when this is the only level
+            B.d_iperm.upload(B.iperm, s);
         }
         alloc_vecs(c.v64, (int64_t)c.n * (d0 + d1));
         if (want32) alloc_vecs(c.v32, (int64_t)c.n * (d0 + d1));
@@ -458,33 +445,37 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
     for (int l = (int)h->L.size() - 2; l >= 0; --l) {
         Level& Lv = *h->L[l];
         Level& Nx = *h->L[l + 1];
+        // colouring is sequential by definition (first fit in node order): done on the host from
+        // the patterns of the diagonal blocks
         std::vector<int32_t> rp[2][2], ci[2][2];
-        for (int f = 0; f < 2; ++f)
-            for (int g = 0; g < 2; ++g) {
-                rp[f][g] = Lv.A[f][g].rp.download(s, Lv.n + 1);
-                ci[f][g] = Lv.A[f][g].ci.download(s, Lv.A[f][g].nnzb);
-            }
+        for (int f = 0; f < 2; ++f) {
+            rp[f][f] = Lv.A[f][f].rp.download(s, Lv.n + 1);
+            ci[f][f] = Lv.A[f][f].ci.download(s, Lv.A[f][f].nnzb);
+        }
         for (int f = 0; f < 2; ++f) {
             BlockLevel& B = Lv.blk[f];
             B.d = Lv.d[f];
+            if (f == 0) clk.mark("pattern download", l);
             int ncol = greedy_colour(Lv.n, rp[f][f], ci[f][f], B.colour);
             order_and_slice(B, Lv.n, ncol);
             B.row0.upload(B.h_row0, s);
             B.nrow.upload(B.h_nrow, s);
             B.d_perm.upload(B.perm, s);
+            B.d_iperm.upload(B.iperm, s);
         }
         for (int f = 0; f < 2; ++f) {
             const int g = 1 - f;
             BlockLevel& B = Lv.blk[f];
             const int df = Lv.d[f], dg = Lv.d[g];
             DevBuf<double> dinv((size_t)Lv.n * df * df);
+            if (f == 0) clk.mark("colouring", l);
             build_dinv(Lv.A[f][f], dinv.p, s);
-            build_part(B.off, PartKind::Off, B, rp[f][f], ci[f][f], nullptr, Lv.A[f][f].val.p, df, df, want32, s);
-            build_part(B.diag, PartKind::Diag, B, rp[f][f], ci[f][f], nullptr, Lv.A[f][f].val.p, df, df, want32, s);
-            build_part(B.cpl, PartKind::Cpl, B, rp[f][g], ci[f][g], &Lv.blk[g].iperm, Lv.A[f][g].val.p, df, dg,
-                       want32, s);
-            std::vector<int32_t> none;
-            build_part(B.dinv, PartKind::Dinv, B, none, none, nullptr, dinv.p, df, df, want32, s);
+            clk.mark("dinv", l);
+            build_part(B.off, PartKind::Off, B, &Lv.A[f][f], B.d_iperm.p, Lv.A[f][f].val.p, df, df, want32, s);
+            build_part(B.diag, PartKind::Diag, B, &Lv.A[f][f], B.d_iperm.p, Lv.A[f][f].val.p, df, df, want32, s);
+            build_part(B.cpl, PartKind::Cpl, B, &Lv.A[f][g], Lv.blk[g].d_iperm.p, Lv.A[f][g].val.p, df, dg, want32,
+                       s);
+            build_part(B.dinv, PartKind::Dinv, B, nullptr, nullptr, dinv.p, df, df, want32, s);
             B.cstats.assign(B.n_colours, ColourStats{});
             int64_t slots = 0;
             for (int c = 0; c < B.n_colours; ++c) {
@@ -506,24 +497,13 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
             if (per_colour < 2048 && avg_width >= 8) B.split = 2;
             if (per_colour < 1024 && avg_width >= 16) B.split = 4;
         }
+        clk.mark("sliced parts", l);
         // transfer maps between this level's and the next level's colour orders
-        std::vector<int32_t> agg = Lv.G.agg.download(s, Lv.n);
-        std::vector<int32_t> mptr = Lv.G.mptr.download(s, Nx.n + 1);
-        std::vector<int32_t> midx = Lv.G.midx.download(s, Lv.n);
         for (int f = 0; f < 2; ++f) {
             BlockLevel& B = Lv.blk[f];
             const BlockLevel& C = Nx.blk[f];
-            std::vector<int32_t> aggp(Lv.n), mp(Nx.n + 1, 0), mi(Lv.n);
-            for (int pr = 0; pr < Lv.n; ++pr) aggp[pr] = C.iperm[agg[B.perm[pr]]];
-            for (int kp = 0; kp < Nx.n; ++kp) {
-                int k = C.perm[kp];
-                mp[kp + 1] = mp[kp] + (mptr[k + 1] - mptr[k]);
-                int o = mp[kp];
-                for (int m = mptr[k]; m < mptr[k + 1]; ++m) mi[o++] = B.iperm[midx[m]];
-            }
-            B.agg_p.upload(aggp, s);
-            B.mem_ptr.upload(mp, s);
-            B.mem_idx.upload(mi, s);
+            transfer_maps(Lv.n, Nx.n, B.d_perm.p, B.d_iperm.p, Lv.G.agg.p, C.d_perm.p, C.d_iperm.p, Lv.G.mptr.p,
+                          Lv.G.midx.p, B.agg_p, B.mem_ptr, B.mem_idx, s);
             DevBuf<double> qp((size_t)Lv.n * B.d);
             launch_gather(Lv.n, B.d, B.d_perm.p, B.q64.p, qp.p, s);
             B.q64 = std::move(qp);
@@ -537,6 +517,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
         MB_HIP(hipStreamSynchronize(s));
     }
 
+    clk.mark("smoother data done", 0);
     // Krylov workspace
     h->n_fine = (int64_t)N * (d0 + d1);
     const int m = p.restart;

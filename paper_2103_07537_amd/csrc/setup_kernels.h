@@ -42,6 +42,19 @@ void sell_masks(int64_t n_slots, int bs, const int64_t* src, const double* val, 
 void sell_fill(int64_t n_slots, int bs, const int64_t* src, const double* val, const uint32_t* mask,
                const int64_t* slot_voff, double* out, hipStream_t s);
 void cast_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
+// device construction of the sliced smoother format (see hierarchy.hip)
+void part_layout(int n, int ns, int kind, const int32_t* perm, const int32_t* rp, const int32_t* ci,
+                 const int32_t* row0, const int32_t* nrow, DevBuf<int32_t>& width, DevBuf<int32_t>& coff32,
+                 int64_t& n_slots, hipStream_t s);
+void part_fill_index(int ns, int kind, const int32_t* row0, const int32_t* nrow, const int32_t* width,
+                     const int32_t* coff32, const int32_t* perm, const int32_t* rp, const int32_t* ci,
+                     const int32_t* col_iperm, int64_t n_slots, int32_t* col, int64_t* src, int32_t* slot_blocks,
+                     hipStream_t s);
+int64_t slot_offsets(int64_t n_slots, const uint32_t* mask, DevBuf<int64_t>& voff, hipStream_t s);
+void i32_to_i64(int64_t n, const int32_t* a, int64_t* b, hipStream_t s);
+void transfer_maps(int n, int nc, const int32_t* perm, const int32_t* iperm, const int32_t* agg,
+                   const int32_t* cperm, const int32_t* ciperm, const int32_t* mptr, const int32_t* midx,
+                   DevBuf<int32_t>& aggp, DevBuf<int32_t>& optr, DevBuf<int32_t>& oidx, hipStream_t s);
 void coarse_inverse(const SetupBsr (&A)[2][2], const int d[2], DevBuf<double>& inv, int& n_out, hipStream_t s);
 
 }  // namespace mbamg

@@ -474,6 +474,99 @@ __global__ void k_cast_f64_f32(const double* a, float* b, int64_t n) {
 }
 
 // ----------------------------------------------------------------------------
+// building the sliced smoother format on the device.  kind: 0 off-diagonal
+// blocks of A_ff, 1 all blocks of A_fg, 2 the diagonal block, 3 one entry per
+// node (the node index itself, for the nodal inverses).
+// ----------------------------------------------------------------------------
+__device__ inline bool part_selects(int kind, int node, int col) {
+    return kind == 1 || (kind == 0 && col != node) || (kind == 2 && col == node);
+}
+
+__global__ void k_part_rowlen(int n, int kind, const int32_t* perm, const int32_t* rp, const int32_t* ci,
+                              int32_t* rowlen) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    if (kind == 3) { rowlen[p] = 1; return; }
+    int node = perm[p], c = 0;
+    for (int q = rp[node]; q < rp[node + 1]; ++q) c += part_selects(kind, node, ci[q]);
+    rowlen[p] = c;
+}
+
+__global__ void k_part_width(int ns, int kind, const int32_t* row0, const int32_t* nrow, const int32_t* rowlen,
+                             int32_t* width) {
+    int sl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= ns) return;
+    int w = 0;
+    for (int l = 0; l < nrow[sl]; ++l) w = max(w, rowlen[row0[sl] + l]);
+    width[sl] = (kind >= 2) ? 1 : w;
+}
+
+// one thread per (slice, lane): column (in the column block's colour order) and
+// source index of each slot, -1 for padding
+__global__ void k_part_fill_index(int ns, int kind, const int32_t* row0, const int32_t* nrow, const int32_t* width,
+                                  const int32_t* coff, const int32_t* perm, const int32_t* rp, const int32_t* ci,
+                                  const int32_t* col_iperm, int32_t* col, int64_t* src, int32_t* slot_blocks) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)ns * WAVE) return;
+    int sl = (int)(t / WAVE), lane = (int)(t % WAVE);
+    int w = width[sl];
+    int64_t base = coff[sl];
+    int k = 0;
+    if (lane < nrow[sl]) {
+        int p = row0[sl] + lane;
+        int node = perm[p];
+        if (kind == 3) {
+            col[base * WAVE + lane] = p;
+            src[base * WAVE + lane] = node;
+            atomicAdd(&slot_blocks[base], 1);
+            k = 1;
+        } else {
+            for (int q = rp[node]; q < rp[node + 1] && k < w; ++q) {
+                int j = ci[q];
+                if (!part_selects(kind, node, j)) continue;
+                col[(base + k) * WAVE + lane] = col_iperm[j];
+                src[(base + k) * WAVE + lane] = q;
+                atomicAdd(&slot_blocks[base + k], 1);
+                ++k;
+            }
+        }
+    }
+    for (; k < w; ++k) {
+        col[(base + k) * WAVE + lane] = -1;
+        src[(base + k) * WAVE + lane] = -1;
+    }
+}
+
+__global__ void k_popcount(int64_t n, const uint32_t* mask, int32_t* cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) cnt[i] = __popc(mask[i]);
+}
+
+__global__ void k_i32_to_i64(int64_t n, const int32_t* a, int64_t* b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// transfer maps between colour orders: aggp[p] = ciperm[agg[perm[p]]]
+__global__ void k_map_agg(int n, const int32_t* perm, const int32_t* agg, const int32_t* ciperm, int32_t* aggp) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) aggp[p] = ciperm[agg[perm[p]]];
+}
+
+__global__ void k_map_count(int nc, const int32_t* cperm, const int32_t* mptr, int32_t* cnt) {
+    int kp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (kp < nc) { int k = cperm[kp]; cnt[kp] = mptr[k + 1] - mptr[k]; }
+}
+
+__global__ void k_map_members(int nc, const int32_t* cperm, const int32_t* mptr, const int32_t* midx,
+                              const int32_t* iperm, const int32_t* optr, int32_t* oidx) {
+    int kp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (kp >= nc) return;
+    int k = cperm[kp], o = optr[kp];
+    for (int m = mptr[k]; m < mptr[k + 1]; ++m) oidx[o++] = iperm[midx[m]];
+}
+
+// ----------------------------------------------------------------------------
 // coarsest level: dense assembly and Gauss-Jordan inverse with partial pivoting
 // ----------------------------------------------------------------------------
 __global__ void k_dense_scatter(int n_rows, int br, int bc, const int32_t* rp, const int32_t* ci, const double* val,
@@ -725,6 +818,61 @@ void sell_fill(int64_t n_slots, int bs, const int64_t* src, const double* val, c
 void cast_to_f32(const double* a, float* b, int64_t n, hipStream_t s) {
     if (n == 0) return;
     k_cast_f64_f32<<<grid_for(n), 256, 0, s>>>(a, b, n);
+    MB_LAUNCH_CHECK();
+}
+
+void part_layout(int n, int ns, int kind, const int32_t* perm, const int32_t* rp, const int32_t* ci,
+                 const int32_t* row0, const int32_t* nrow, DevBuf<int32_t>& width, DevBuf<int32_t>& coff32,
+                 int64_t& n_slots, hipStream_t s) {
+    DevBuf<int32_t> rowlen(std::max(n, 1));
+    k_part_rowlen<<<grid_for(n), 256, 0, s>>>(n, kind, perm, rp, ci, rowlen.p);
+    width.alloc(std::max(ns, 1));
+    k_part_width<<<grid_for(ns), 256, 0, s>>>(ns, kind, row0, nrow, rowlen.p, width.p);
+    MB_LAUNCH_CHECK();
+    coff32.alloc(ns + 1);
+    n_slots = scan_exclusive(width.p, ns, coff32.p, s);
+}
+
+void part_fill_index(int ns, int kind, const int32_t* row0, const int32_t* nrow, const int32_t* width,
+                     const int32_t* coff32, const int32_t* perm, const int32_t* rp, const int32_t* ci,
+                     const int32_t* col_iperm, int64_t n_slots, int32_t* col, int64_t* src, int32_t* slot_blocks,
+                     hipStream_t s) {
+    MB_HIP(hipMemsetAsync(slot_blocks, 0, sizeof(int32_t) * std::max<int64_t>(n_slots, 1), s));
+    k_part_fill_index<<<grid_for((int64_t)ns * WAVE), 256, 0, s>>>(ns, kind, row0, nrow, width, coff32, perm, rp, ci,
+                                                                   col_iperm, col, src, slot_blocks);
+    MB_LAUNCH_CHECK();
+}
+
+int64_t slot_offsets(int64_t n_slots, const uint32_t* mask, DevBuf<int64_t>& voff, hipStream_t s) {
+    DevBuf<int32_t> cnt(std::max<int64_t>(n_slots, 1)), off32(n_slots + 1);
+    k_popcount<<<grid_for(n_slots), 256, 0, s>>>(n_slots, mask, cnt.p);
+    MB_LAUNCH_CHECK();
+    int64_t groups = scan_exclusive(cnt.p, n_slots, off32.p, s);
+    voff.alloc(std::max<int64_t>(n_slots, 1));
+    k_i32_to_i64<<<grid_for(n_slots), 256, 0, s>>>(n_slots, off32.p, voff.p);
+    MB_LAUNCH_CHECK();
+    MB_HIP(hipStreamSynchronize(s));
+    return groups;
+}
+
+void i32_to_i64(int64_t n, const int32_t* a, int64_t* b, hipStream_t s) {
+    if (n <= 0) return;
+    k_i32_to_i64<<<grid_for(n), 256, 0, s>>>(n, a, b);
+    MB_LAUNCH_CHECK();
+}
+
+void transfer_maps(int n, int nc, const int32_t* perm, const int32_t* iperm, const int32_t* agg,
+                   const int32_t* cperm, const int32_t* ciperm, const int32_t* mptr, const int32_t* midx,
+                   DevBuf<int32_t>& aggp, DevBuf<int32_t>& optr, DevBuf<int32_t>& oidx, hipStream_t s) {
+    aggp.alloc(std::max(n, 1));
+    k_map_agg<<<grid_for(n), 256, 0, s>>>(n, perm, agg, ciperm, aggp.p);
+    DevBuf<int32_t> cnt(std::max(nc, 1));
+    k_map_count<<<grid_for(nc), 256, 0, s>>>(nc, cperm, mptr, cnt.p);
+    MB_LAUNCH_CHECK();
+    optr.alloc(nc + 1);
+    scan_exclusive(cnt.p, nc, optr.p, s);
+    oidx.alloc(std::max(n, 1));
+    k_map_members<<<grid_for(nc), 256, 0, s>>>(nc, cperm, mptr, midx, iperm, optr.p, oidx.p);
     MB_LAUNCH_CHECK();
 }
 
