@@ -156,10 +156,11 @@ mbamg_status mbamg_copy_colours(const mbamg_hierarchy* h, int32_t level, int32_t
 
 /* Kernel timing with HIP events on the stream the kernels run on.  While
  * enabled, every launch of the finest level's smoother and residual kernels is
- * bracketed by events.  kind 0: smoother colour pass, 1: residual,
- * 2: operator apply.  Reports launches, summed event time in ms and the
- * algorithmic bytes those launches move (structural values, indices and
- * vectors, as documented with the byte model). */
+ * bracketed by events.  kind 0: smoother colour passes from a nonzero iterate
+ * with the coupling term (the post-smoother), 1: residual, 2: operator apply,
+ * 3: the other smoother colour passes.  Reports launches, summed event time in
+ * ms and the algorithmic bytes those launches move (structural values, block
+ * indices, row pointers and vectors, each counted once per launch). */
 mbamg_status mbamg_timing_enable(mbamg_hierarchy* h, int32_t enable);
 mbamg_status mbamg_timing_get(mbamg_hierarchy* h, int32_t kind, int64_t* launches,
                               double* total_ms, double* bytes);

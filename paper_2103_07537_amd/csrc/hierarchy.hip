@@ -197,6 +197,22 @@ struct PhaseClock {
     }
 };
 
+// A second stream (default priority) with two events, released on scope exit.
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t ready = nullptr, done = nullptr;
+    SideStream() {
+        MB_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        MB_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        MB_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    }
+    ~SideStream() {
+        if (stream) { (void)hipStreamSynchronize(stream); (void)hipStreamDestroy(stream); }
+        if (ready) (void)hipEventDestroy(ready);
+        if (done) (void)hipEventDestroy(done);
+    }
+};
+
 // ----------------------------------------------------------------------------
 // setup helpers
 // ----------------------------------------------------------------------------
@@ -355,6 +371,8 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
     MB_CHECK(N > 0, MBAMG_E_INVALID, "empty system");
     const bool want32 = p.precision == 1;
     PhaseClock clk(s);
+    CoarseWork cwork;   // declared first: the side stream is drained before its buffers are freed
+    SideStream side;
 
     // level 0 from the caller's blocks
     auto first = std::make_unique<Level>();
@@ -424,9 +442,12 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
     // coarsest: dense inverse
     {
         Level& c = *h->L.back();
-        clk.mark("before coarse", (int)h->L.size() - 1);
-        coarse_inverse(c.A, c.d, h->coarse_inv, h->coarse_n, s);
-        clk.mark("coarse inverse", (int)h->L.size() - 1);
+        // the coarsest inverse runs on a second stream, overlapping the smoother data below
+        MB_HIP(hipEventRecord(side.ready, s));
+        MB_HIP(hipStreamWaitEvent(side.stream, side.ready, 0));
+        coarse_inverse_launch(c.A, c.d, h->coarse_inv, cwork, side.stream);
+        h->coarse_n = cwork.n;
+        clk.mark("coarse inverse queued", (int)h->L.size() - 1);
         for (int f = 0; f < 2; ++f) {      // identity order
             BlockLevel& B = c.blk[f];
             B.d = c.d[f];
@@ -518,6 +539,10 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
     }
 
     clk.mark("smoother data done", 0);
+    coarse_inverse_finish(cwork, side.stream);
+    MB_HIP(hipEventRecord(side.done, side.stream));
+    MB_HIP(hipStreamWaitEvent(s, side.done, 0));
+    clk.mark("coarse inverse joined", 0);
     // Krylov workspace
     h->n_fine = (int64_t)N * (d0 + d1);
     const int m = p.restart;
@@ -623,7 +648,8 @@ static void smooth_block(mbamg_hierarchy* h, int l, int f, bool zero, const T* b
             a.w_row = nullptr;
             a.skip_off = (zero && k == 0 && c == 0) ? 1 : 0;
             double bytes = timed ? gs_bytes(B, c, zero, a.skip_off, has_cpl, (int)sizeof(T), Lv.d[g]) : 0.0;
-            TimerScope ts(h, s, timed, 0, bytes);
+            // kind 0: passes from a nonzero iterate with the coupling term; kind 3: the others
+            TimerScope ts(h, s, timed, (!zero && has_cpl) ? 0 : 3, bytes);
             launch_gs<T>(B.d, B.split, zero, has_cpl, a, s);
         }
     }

@@ -55,6 +55,15 @@ void i32_to_i64(int64_t n, const int32_t* a, int64_t* b, hipStream_t s);
 void transfer_maps(int n, int nc, const int32_t* perm, const int32_t* iperm, const int32_t* agg,
                    const int32_t* cperm, const int32_t* ciperm, const int32_t* mptr, const int32_t* midx,
                    DevBuf<int32_t>& aggp, DevBuf<int32_t>& optr, DevBuf<int32_t>& oidx, hipStream_t s);
-void coarse_inverse(const SetupBsr (&A)[2][2], const int d[2], DevBuf<double>& inv, int& n_out, hipStream_t s);
+// Dense Gauss-Jordan inverse of the coarsest matrix ([block 0; block 1] order),
+// queued on stream s; coarse_inverse_finish waits for it and checks pivots.
+struct CoarseWork {
+    int n = 0;
+    DevBuf<double> M, colk;
+    DevBuf<int32_t> sing;
+};
+void coarse_inverse_launch(const SetupBsr (&A)[2][2], const int d[2], DevBuf<double>& inv, CoarseWork& w,
+                           hipStream_t s);
+void coarse_inverse_finish(CoarseWork& w, hipStream_t s);
 
 }  // namespace mbamg

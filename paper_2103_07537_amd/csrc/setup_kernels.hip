@@ -876,40 +876,46 @@ void transfer_maps(int n, int nc, const int32_t* perm, const int32_t* iperm, con
     MB_LAUNCH_CHECK();
 }
 
-void coarse_inverse(const SetupBsr (&A)[2][2], const int d[2], DevBuf<double>& inv, int& n_out, hipStream_t s) {
+void coarse_inverse_launch(const SetupBsr (&A)[2][2], const int d[2], DevBuf<double>& inv, CoarseWork& w,
+                           hipStream_t s) {
     const int nn = A[0][0].n_rows;
     const int n = nn * (d[0] + d[1]);
     MB_CHECK(n <= 16384, MBAMG_E_INVALID, "coarsest level too large for the dense solve (raise max_levels)");
-    n_out = n;
-    DevBuf<double> M((size_t)n * 2 * n);
-    MB_HIP(hipMemsetAsync(M.p, 0, M.bytes(), s));
+    w.n = n;
+    w.M.alloc((size_t)n * 2 * n);
+    w.colk.alloc(n);
+    w.sing.alloc(1);
+    inv.alloc((size_t)n * n);
+    MB_HIP(hipMemsetAsync(w.M.p, 0, w.M.bytes(), s));
     int64_t off[2] = {0, (int64_t)nn * d[0]};
     for (int f = 0; f < 2; ++f)
         for (int g = 0; g < 2; ++g) {
             const SetupBsr& B = A[f][g];
             if (B.nnzb == 0) continue;
             k_dense_scatter<<<grid_for(nn, 64), 64, 0, s>>>(nn, B.br, B.bc, B.rp.p, B.ci.p, B.val.p, off[f], off[g],
-                                                           2 * (int64_t)n, M.p);
+                                                           2 * (int64_t)n, w.M.p);
             MB_LAUNCH_CHECK();
         }
-    k_gj_identity<<<grid_for((int64_t)n * n), 256, 0, s>>>(M.p, n);
+    k_gj_identity<<<grid_for((int64_t)n * n), 256, 0, s>>>(w.M.p, n);
     MB_LAUNCH_CHECK();
-    DevBuf<double> colk(n);
-    DevBuf<int32_t> sing(1);
-    MB_HIP(hipMemsetAsync(sing.p, 0, sizeof(int32_t), s));
+    MB_HIP(hipMemsetAsync(w.sing.p, 0, sizeof(int32_t), s));
     for (int k = 0; k < n; ++k) {
-        k_gj_pivot<<<1, 1024, 0, s>>>(M.p, n, k, colk.p, sing.p);
+        k_gj_pivot<<<1, 1024, 0, s>>>(w.M.p, n, k, w.colk.p, w.sing.p);
         int64_t work = (int64_t)n * (2 * n - k);
-        k_gj_eliminate<<<grid_for(work), 256, 0, s>>>(M.p, n, k, colk.p);
+        k_gj_eliminate<<<grid_for(work), 256, 0, s>>>(w.M.p, n, k, w.colk.p);
     }
     MB_LAUNCH_CHECK();
-    int32_t h = 0;
-    MB_HIP(hipMemcpyAsync(&h, sing.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    MB_HIP(hipStreamSynchronize(s));
-    MB_CHECK(h == 0, MBAMG_E_SINGULAR, "the coarsest matrix is singular");
-    inv.alloc((size_t)n * n);
-    k_gj_extract<<<grid_for((int64_t)n * n), 256, 0, s>>>(M.p, n, inv.p);
+    k_gj_extract<<<grid_for((int64_t)n * n), 256, 0, s>>>(w.M.p, n, inv.p);
     MB_LAUNCH_CHECK();
+}
+
+void coarse_inverse_finish(CoarseWork& w, hipStream_t s) {
+    int32_t h = 0;
+    MB_HIP(hipMemcpyAsync(&h, w.sing.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MB_HIP(hipStreamSynchronize(s));
+    w.M.release();
+    w.colk.release();
+    MB_CHECK(h == 0, MBAMG_E_SINGULAR, "the coarsest matrix is singular");
 }
 
 }  // namespace mbamg
