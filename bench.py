@@ -49,7 +49,36 @@ def parse():
     ap.add_argument("--vcycles", type=int, default=20, help="V-cycles timed for the V-cycle bandwidth figure")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=0, help="grid size of the oracle sample (0: automatic)")
+    ap.add_argument("--counter-run", action="store_true",
+                    help="for hardware-counter profiling: one FP64 setup, a 1 GiB calibration copy, "
+                         "then a few V-cycles and operator applies (no solve)")
     return ap.parse_args()
+
+
+def counter_run(args):
+    """Short, fixed sequence of kernels for per-dispatch counter collection."""
+    import torch
+    from paper_2103_07537_amd import mbamg
+    from paper_2103_07537_amd.inputs import workload
+    mbamg.lib()
+    torch.cuda.set_device(0)
+    system = workload(args.workload, seed=args.seed)
+    blocks = mbamg.to_device(system)
+    b = torch.from_numpy(system.b).cuda()
+    h = mbamg.Hierarchy(blocks, system.dofs, system.n_vec, precision=0)
+    log("[counters] setup done")
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")      # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)                                                      # calibration: 1 GiB read, 1 GiB written
+    torch.cuda.synchronize()
+    z = torch.empty_like(b)
+    w = torch.empty_like(b)
+    for _ in range(3):
+        h.vcycle(b, z)
+        h.apply(z, w)
+    torch.cuda.synchronize()
+    log("[counters] done")
+    print(json.dumps({"counter_run": args.workload, "calibration_bytes": 1 << 30}), flush=True)
 
 
 def run_step(blocks, system, b, form, rtol, timing):
@@ -114,8 +143,30 @@ def cpu_baseline(args, gpu_iters):
     }
 
 
+def measured_traffic(workload_name, kind):
+    """HBM bytes per launch of the reported kernel from the committed counter
+    summaries, or None when none matches this workload and kernel source."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2103_07537_amd", "csrc", "solve_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.txt"))):
+        kv = {}
+        for line in open(path):
+            if "=" in line and not line.startswith(" "):
+                k, v = line.strip().split("=", 1)
+                kv[k] = v
+        if (kv.get("workload") == workload_name and kv.get("kind") == str(kind)
+                and kv.get("source_sha256") == sha):
+            return float(kv["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
+
+
 def main():
     args = parse()
+    if args.counter_run:
+        counter_run(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
                                    "described in the design notes but not built)"}))
@@ -187,9 +238,11 @@ def main():
         per_launch_bytes = s["bytes"] / max(s["launches"], 1)
         avg_ms = s["total_ms"] / max(s["launches"], 1)
         achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+        traffic, tsrc = measured_traffic(args.workload, kind)
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": names[kind],
-                "launches": s["launches"], "avg_us": avg_ms * 1e3, "alg_bytes_per_launch": per_launch_bytes}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": names[kind],
+                "launches": s["launches"], "avg_us": avg_ms * 1e3, "alg_bytes_per_launch": per_launch_bytes,
+                "traffic_source": tsrc}
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")

@@ -82,7 +82,7 @@ typedef struct {
     int32_t clone_aggregates; /* block 1 reuses block 0's aggregates (1; required) */
     int32_t reuse_P;          /* kept for the interface; P_11 = P_00 holds when clone is on */
     int32_t precision;        /* 0: FP64 V-cycle + GMRES; 1: FP32 V-cycle inside FP64 FGMRES */
-    int32_t restart;          /* GMRES restart length (30, at most 64) */
+    int32_t restart;          /* GMRES restart length (30, at most 31) */
     int32_t max_iters;        /* (1000) */
     int32_t learned;          /* 0 off; 1 per-aggregate weights supplied by mbamg_set_learned_weights */
     const char* mlp_weights;  /* unused by the library itself (NULL) */
