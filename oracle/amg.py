@@ -68,6 +68,12 @@ def _load():
         lib.or_rap_stage2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, i32p, i32p, i32p,
                                       i32p, f64p, f64p, i32p, i32p, f64p]
         lib.or_rap_stage2.restype = ctypes.c_int64
+        lib.or_spgemm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, i32p, i32p, f64p,
+                                  i32p, i32p, f64p, ctypes.c_int64, i32p, i32p, f64p]
+        lib.or_spgemm.restype = ctypes.c_int64
+        lib.or_sa_prolongator.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, i32p, i32p, f64p, i32p, f64p,
+                                          f64p, i32p, i32p, f64p]
+        lib.or_sa_prolongator.restype = ctypes.c_int64
         _lib = lib
     return _lib
 
@@ -85,6 +91,8 @@ class Params:
     max_levels: int = 10
     max_coarse: int = 2500      # dofs
     seed: int = 0               # aggregation priority seed
+    omega_p: float = 0.0        # uniform prolongator-smoothing weight (0: piecewise constant P)
+    weights: object = None      # callable(level, n_agg, features) -> (omega_p[n_agg], omega_s[n_agg])
 
 
 @dataclasses.dataclass
@@ -118,6 +126,9 @@ class Level:
     n_colours: list = None
     dinv: list = None           # per block (n, d, d)
     gs: list = None             # per block: list over colours of (rows, off-diag rows, Dinv)
+    omega_s: np.ndarray = None  # per-node smoother damping (None: Params.omega)
+    omega_p: np.ndarray = None  # per-aggregate prolongator-smoothing weights used for P
+    features: np.ndarray = None
 
 
 @dataclasses.dataclass
@@ -297,7 +308,54 @@ def _prepare_gs(lev: Level, f: int):
     return out
 
 
-def setup(blocks, dofs, params: Params | None = None) -> Hierarchy:
+def spgemm(A: BsrM, B: BsrM) -> BsrM:
+    """A B with the ordered sums of seq.c (columns of each row increasing)."""
+    lib = _load()
+    br, bm = A.val.shape[1], A.val.shape[2]
+    bc = B.val.shape[2]
+    cap = max(1, sum(int(B.rp[j + 1] - B.rp[j]) for j in A.ci)) if A.ci.shape[0] else 1
+    c_rp = np.zeros(A.n_rows + 1, dtype=np.int32)
+    c_ci = np.zeros(cap, dtype=np.int32)
+    c_val = np.zeros(cap * br * bc)
+    nz = lib.or_spgemm(A.n_rows, br, bm, bc, A.rp, A.ci, np.ascontiguousarray(A.val.reshape(-1)), B.rp, B.ci,
+                       np.ascontiguousarray(B.val.reshape(-1)), cap, c_rp, c_ci, c_val)
+    assert nz >= 0
+    return BsrM(A.n_rows, B.n_cols, c_rp, c_ci[:nz].copy(), c_val[:nz * br * bc].reshape(nz, br, bc).copy())
+
+
+def transpose(P: BsrM) -> BsrM:
+    """Block transpose; rows of the result list their columns in increasing order."""
+    rows = np.repeat(np.arange(P.n_rows), np.diff(P.rp))
+    order = np.lexsort((rows, P.ci))
+    cnt = np.bincount(P.ci, minlength=P.n_cols)
+    rp = np.zeros(P.n_cols + 1, dtype=np.int32)
+    np.cumsum(cnt, out=rp[1:])
+    return BsrM(P.n_cols, P.n_rows, rp, rows[order].astype(np.int32),
+                np.ascontiguousarray(P.val[order].transpose(0, 2, 1)))
+
+
+def sa_prolongator(A: BsrM, nv: int, agg: np.ndarray, q: np.ndarray, w: np.ndarray, n_agg: int) -> BsrM:
+    """P = Phat - D_vv^-1 A_vv Phat W on the vector components (seq.c)."""
+    lib = _load()
+    d = A.val.shape[1]
+    cap = max(A.ci.shape[0], 1)
+    p_rp = np.zeros(A.n_rows + 1, dtype=np.int32)
+    p_ci = np.zeros(cap, dtype=np.int32)
+    p_val = np.zeros(cap * d * d)
+    nz = lib.or_sa_prolongator(A.n_rows, d, nv, A.rp, A.ci, np.ascontiguousarray(A.val.reshape(-1)), agg,
+                               np.ascontiguousarray(q.reshape(-1)), np.ascontiguousarray(w, dtype=np.float64),
+                               p_rp, p_ci, p_val)
+    return BsrM(A.n_rows, n_agg, p_rp, p_ci[:nz].copy(), p_val[:nz * d * d].reshape(nz, d, d).copy())
+
+
+def tentative_bsr(q: np.ndarray, agg: np.ndarray, n_agg: int) -> BsrM:
+    n, d = q.shape
+    val = np.zeros((n, d, d))
+    val[:, np.arange(d), np.arange(d)] = q
+    return BsrM(n, n_agg, np.arange(n + 1, dtype=np.int32), agg.astype(np.int32), val)
+
+
+def setup(blocks, dofs, params: Params | None = None, n_vec=None) -> Hierarchy:
     """Build the hierarchy.  ``blocks`` is [[A00, A01], [A10, A11]], each an
     object with n_brows, n_bcols, row_ptr, col_idx, vals (the generator's Bsr).
 
@@ -305,6 +363,7 @@ def setup(blocks, dofs, params: Params | None = None) -> Hierarchy:
     levels exist, or when the next level would keep more than 90% of the nodes.
     """
     p = params or Params()
+    n_vec = tuple(n_vec) if n_vec is not None else (dofs[0] - 1, dofs[1] - 1)
     A = [[BsrM(b.n_brows, b.n_bcols, np.asarray(b.row_ptr, np.int32), np.asarray(b.col_idx, np.int32),
                np.asarray(b.vals, np.float64)) for b in row] for row in blocks]
     n = A[0][0].n_rows
@@ -327,8 +386,24 @@ def setup(blocks, dofs, params: Params | None = None) -> Hierarchy:
             q.append(qf)
             Bc.append(bc)
         lev.agg, lev.n_agg, lev.m_ptr, lev.m_idx, lev.q = agg, n_agg, m_ptr, m_idx, q
-        lev.P = [prolongator(q[f], agg, n_agg) for f in range(2)]
-        A = [[galerkin(A[f][g], agg, m_ptr, m_idx, n_agg, q[f], q[g]) for g in range(2)] for f in range(2)]
+        wp = None
+        if p.weights is not None:
+            from oracle import learned
+            lev.features = learned.features(lev, n_vec, lvl)
+            wp, ws = p.weights(lvl, n_agg, lev.features)
+            wp = np.asarray(wp, dtype=np.float64)
+            lev.omega_s = np.asarray(ws, dtype=np.float64)[agg]
+        elif p.omega_p != 0.0:
+            wp = np.full(n_agg, float(p.omega_p))
+        if wp is None:
+            lev.P = [prolongator(q[f], agg, n_agg) for f in range(2)]
+            A = [[galerkin(A[f][g], agg, m_ptr, m_idx, n_agg, q[f], q[g]) for g in range(2)] for f in range(2)]
+        else:
+            lev.omega_p = wp
+            Pb = [sa_prolongator(A[f][f], n_vec[f], agg, q[f], wp, n_agg) for f in range(2)]
+            lev.P = [Pb[f].csr() for f in range(2)]
+            PT = [transpose(Pb[f]) for f in range(2)]
+            A = [[spgemm(PT[f], spgemm(A[f][g], Pb[g])) for g in range(2)] for f in range(2)]
         B = Bc
         n = n_agg
         lvl += 1
@@ -379,6 +454,8 @@ def bgs(lev: Level, x0: np.ndarray, x1: np.ndarray, b0, b1, p: Params, omega=Non
     d0, d1 = lev.dofs
     x0 = x0.copy()
     x1 = x1.copy()
+    if omega is None and lev.omega_s is not None:
+        w = lev.omega_s
     for _ in range(p.bgs_sweeps):
         r0 = b0 - lev.csr[0][0] @ x0 - lev.csr[0][1] @ x1
         e0 = inner_gs(lev, 0, r0, p.inner_sweeps)

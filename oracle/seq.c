@@ -198,3 +198,114 @@ int64_t or_rap_stage2(int nc, int br, int bc, const int32_t* m_ptr, const int32_
     }
     return nz;
 }
+
+/* C = A B for block-sparse A (n rows, br x bm blocks) and B (bm x bc blocks),
+ * rows of both with increasing columns.  Row i of C lists the distinct columns
+ * reached through row i of A in increasing order; entry (r,c) of block (i,l)
+ * sums A[i,j][r][m] * B[j,l][m][c] over the columns j of row i in increasing
+ * order and, for each j, over m in increasing order.  With B the
+ * piecewise-constant prolongator this is exactly or_rap_stage1, and with A
+ * its transpose it is or_rap_stage2.  Output arrays sized by the caller
+ * (cap blocks).  Returns nnzb(C), or -1 when cap is too small. */
+int64_t or_spgemm(int n, int br, int bm, int bc, const int32_t* a_rp, const int32_t* a_ci, const double* a_val,
+                  const int32_t* b_rp, const int32_t* b_ci, const double* b_val, int64_t cap,
+                  int32_t* c_rp, int32_t* c_ci, double* c_val) {
+    int64_t nz = 0;
+    const int as = br * bm, bs = bm * bc, cs = br * bc;
+    c_rp[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        int64_t row_start = nz;
+        for (int p = a_rp[i]; p < a_rp[i + 1]; ++p) {
+            int j = a_ci[p];
+            for (int q = b_rp[j]; q < b_rp[j + 1]; ++q) {
+                int l = b_ci[q];
+                int64_t s = row_start;
+                while (s < nz && c_ci[s] < l) ++s;
+                if (s < nz && c_ci[s] == l) continue;
+                if (nz >= cap) return -1;
+                for (int64_t t = nz; t > s; --t) c_ci[t] = c_ci[t - 1];
+                c_ci[s] = l;
+                ++nz;
+            }
+        }
+        for (int64_t s = row_start; s < nz; ++s) {
+            double* acc = c_val + s * cs;
+            for (int e = 0; e < cs; ++e) acc[e] = 0.0;
+            for (int p = a_rp[i]; p < a_rp[i + 1]; ++p) {
+                int j = a_ci[p];
+                for (int q = b_rp[j]; q < b_rp[j + 1]; ++q) {
+                    if (b_ci[q] != c_ci[s]) continue;
+                    const double* a = a_val + (int64_t)p * as;
+                    const double* b = b_val + (int64_t)q * bs;
+                    for (int r = 0; r < br; ++r)
+                        for (int c = 0; c < bc; ++c)
+                            for (int m = 0; m < bm; ++m) {
+                                double term = a[r * bm + m] * b[m * bc + c];
+                                acc[r * bc + c] = acc[r * bc + c] + term;
+                            }
+                }
+            }
+        }
+        c_rp[i + 1] = (int32_t)nz;
+    }
+    return nz;
+}
+
+/* Smoothed prolongator of one block (vector components only):
+ *   P = Phat - D_vv^-1 A_vv Phat W
+ * with Phat[(i,a),(agg(i),a)] = q[i,a], D_vv the diagonal of the vector-vector
+ * part of A_ff, W = diag(w) over coarse nodes.  Row i lists, in increasing
+ * order, agg(i) and the aggregates k of its columns with w[k] != 0 (a zero
+ * weight adds nothing outside the node's own aggregate, so w = 0 gives Phat
+ * exactly, pattern included).  For vector row a and vector
+ * column c of block (i,k):
+ *   s = sum over columns j of row i in increasing order with agg(j) = k of A[i,j][a][c] * q[j,c]
+ *   P = base - w[k] * (s / A[i,i][a][a]),  base = q[i,a] if (k = agg(i), c = a) else 0
+ * other entries are base.  Returns nnzb(P); output arrays hold nnzb(A) blocks. */
+int64_t or_sa_prolongator(int n, int d, int nv, const int32_t* rp, const int32_t* ci, const double* val,
+                          const int32_t* agg, const double* q, const double* w,
+                          int32_t* p_rp, int32_t* p_ci, double* p_val) {
+    int64_t nz = 0;
+    const int bs = d * d;
+    p_rp[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        int64_t row_start = nz;
+        int pd = -1;
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+            if (ci[p] == i) pd = p;
+            int l = agg[ci[p]];
+            if (l != agg[i] && w[l] == 0.0) continue;
+            int64_t s = row_start;
+            while (s < nz && p_ci[s] < l) ++s;
+            if (s < nz && p_ci[s] == l) continue;
+            for (int64_t t = nz; t > s; --t) p_ci[t] = p_ci[t - 1];
+            p_ci[s] = l;
+            ++nz;
+        }
+        for (int64_t s = row_start; s < nz; ++s) {
+            int k = p_ci[s];
+            double* out = p_val + s * bs;
+            for (int a = 0; a < d; ++a)
+                for (int c = 0; c < d; ++c) {
+                    double base = (k == agg[i] && c == a) ? q[(int64_t)i * d + a] : 0.0;
+                    if (a < nv && c < nv) {
+                        double acc = 0.0;
+                        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+                            int j = ci[p];
+                            if (agg[j] != k) continue;
+                            double term = val[(int64_t)p * bs + a * d + c] * q[(int64_t)j * d + c];
+                            acc = acc + term;
+                        }
+                        double dg = val[(int64_t)pd * bs + a * d + a];
+                        double t = acc / dg;
+                        double u = w[k] * t;
+                        out[a * d + c] = base - u;
+                    } else {
+                        out[a * d + c] = base;
+                    }
+                }
+        }
+        p_rp[i + 1] = (int32_t)nz;
+    }
+    return nz;
+}
