@@ -72,6 +72,13 @@ typedef struct {
     int32_t n_vec[4];
 } mbamg_field_map;
 
+/* Per-aggregate weights for one level (learned == 2): given the level's
+ * n_agg x 12 features (host, row-major, as returned by mbamg_features), write
+ * omega_p[n_agg] (prolongator smoothing, >= 0) and omega_s[n_agg] (smoother
+ * damping, > 0).  Called from mbamg_setup on the calling thread. */
+typedef void (*mbamg_weight_fn)(int32_t level, int32_t n_agg, const float* features, double* omega_p,
+                                double* omega_s, void* ctx);
+
 typedef struct {
     double omega;             /* Algorithm 1 damping (default 0.8) */
     int32_t bgs_sweeps;       /* Algorithm 1 sweeps for pre- and post-smoothing (1) */
@@ -84,9 +91,15 @@ typedef struct {
     int32_t precision;        /* 0: FP64 V-cycle + GMRES; 1: FP32 V-cycle inside FP64 FGMRES */
     int32_t restart;          /* GMRES restart length (30, at most 31) */
     int32_t max_iters;        /* (1000) */
-    int32_t learned;          /* 0 off; 1 per-aggregate weights supplied by mbamg_set_learned_weights */
-    const char* mlp_weights;  /* unused by the library itself (NULL) */
+    int32_t learned;          /* 0: fixed weights; 1: network in `mlp`; 2: `weight_fn` */
+    const float* mlp;         /* learned == 1: host array of 5122 network parameters, then 12 feature
+                                 means and 12 feature standard deviations (5146 floats) */
     uint64_t seed;            /* aggregation priority seed (0) */
+    double omega_p;           /* learned == 0: uniform prolongator-smoothing weight (0: piecewise constant) */
+    int32_t judge;            /* learned != 0: also build the fixed-weight hierarchy, estimate both
+                                 convergence factors with mbamg_probe and keep the better one (1) */
+    mbamg_weight_fn weight_fn;
+    void* weight_ctx;
 } mbamg_params;
 
 typedef struct {
@@ -151,6 +164,46 @@ mbamg_status mbamg_copy_level_block(const mbamg_hierarchy* h, int32_t level, int
 /* Smoother colour of every node of block f on level l (host int32 buffer). */
 mbamg_status mbamg_copy_colours(const mbamg_hierarchy* h, int32_t level, int32_t f,
                                 int32_t* colour);
+
+/* ---- learned form -------------------------------------------------------
+ * Per aggregate k of a level, omega_P,k smooths the prolongator on the vector
+ * components, P = Phat - D_vv^-1 A_vv Phat diag(omega_P), and omega_S,k damps
+ * the block Gauss-Seidel updates of the aggregate's nodes (both blocks).  The
+ * paper uses piecewise-constant transfers and one fixed damping (Sec. 4.3.1,
+ * 4.3.2); these weights are this library's addition. */
+
+/* Raw features (n_agg x 12, host float) of level l < n_levels-1; available
+ * when the hierarchy was built with learned != 0. */
+mbamg_status mbamg_features(const mbamg_hierarchy* h, int32_t level, float* features);
+
+/* Weights used on level l (host buffers of n_agg doubles; omega_s is the
+ * uniform omega where no per-aggregate damping was set). */
+mbamg_status mbamg_level_weights(const mbamg_hierarchy* h, int32_t level, double* omega_p, double* omega_s);
+
+/* Network 12 -> 64 -> 64 -> 2 (ReLU), bfloat16 matrix-core products with FP32
+ * accumulation.  params: 5122 FP32 on the device (W1[64][12], b1, W2[64][64],
+ * b2, W3[2][64], b3); x: n x 12 normalised features; out: n x 2 =
+ * (omega_P in (0, 5/6), omega_S in (0.3, 1.3)).  Device pointers, asynchronous. */
+mbamg_status mbamg_mlp_forward(const float* params, const float* x, int64_t n, float* out, void* hip_stream);
+
+/* Mean squared error sum_c (out_c - target_c)^2 averaged over n rows, and its
+ * gradient with respect to the 5122 parameters.  grad[5122] and loss[1] are
+ * device outputs.  Asynchronous. */
+mbamg_status mbamg_mlp_loss_grad(const float* params, const float* x, const float* target, int64_t n,
+                                 float* grad, float* loss, void* hip_stream);
+
+/* One Adam step (Kingma & Ba 2015) on the 5122 parameters with moment buffers
+ * m, v (device); step counts from 1.  Asynchronous. */
+mbamg_status mbamg_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr,
+                            float beta1, float beta2, float eps, void* hip_stream);
+
+/* Asymptotic convergence factor of the stationary iteration e <- e - M A e
+ * from a seeded random start: (||e_iters|| / ||e_{iters-4}||)^(1/4).
+ * iters >= 5.  Synchronous. */
+mbamg_status mbamg_probe(mbamg_hierarchy* h, int32_t iters, uint64_t seed, double* rho, void* hip_stream);
+
+/* Change the uniform smoother damping (levels without per-aggregate damping). */
+mbamg_status mbamg_set_omega(mbamg_hierarchy* h, double omega);
 
 /* ---- measurement -------------------------------------------------------- */
 

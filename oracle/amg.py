@@ -563,3 +563,27 @@ def gmres(h: Hierarchy, b: np.ndarray, rtol: float = 1e-8, restart: int = 30,
                 break
         y = sla.solve_triangular(H[:k, :k], g[:k])
         x = x + M(V[:k].T @ y)
+
+
+def seeded_vector(n: int, seed: int) -> np.ndarray:
+    """Start vector of the convergence probe: 2 u - 1 with u the top 53 bits of
+    the SplitMix64 output finaliser of i + 0x9E3779B97F4A7C15 * (seed + 1)."""
+    mult = (0x9E3779B97F4A7C15 * (seed + 1)) & ((1 << 64) - 1)
+    with np.errstate(over="ignore"):
+        z = _mix64(np.arange(n, dtype=np.uint64) + np.uint64(mult))
+    return 2.0 * ((z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53) - 1.0
+
+
+def probe(h: Hierarchy, iters: int = 10, seed: int = 12345) -> float:
+    """Asymptotic factor of the stationary iteration e <- e - M A e:
+    (||e_iters|| / ||e_{iters-4}||)^(1/4)."""
+    lev = h.levels[0]
+    e = seeded_vector(lev.n * sum(lev.dofs), seed)
+    n4 = nk = 0.0
+    for k in range(1, iters + 1):
+        e = e - vcycle(h, apply_A(lev, e))
+        if k == iters - 4:
+            n4 = np.linalg.norm(e)
+        if k == iters:
+            nk = np.linalg.norm(e)
+    return (nk / n4) ** 0.25

@@ -66,16 +66,18 @@ def loss_grad(theta, X, T, emulate=False):
     diff = out - T
     loss = float(np.sum(diff * diff) / n)
     scale = np.array([OMEGA_P_MAX, OMEGA_S_SPAN])
+    # with emulation the backward signals enter the matrix products as bfloat16
+    # while the bias gradients sum the unrounded values, as on the GPU
     do = (2.0 / n) * diff * scale * s * (1.0 - s)
-    gW3 = do.T @ h2
+    gW3 = r(do).T @ h2
     gb3 = do.sum(axis=0)
-    dh2 = do @ r(W3)
-    dz2 = dh2 * (z2 > 0)
-    gW2 = dz2.T @ h1
+    dh2 = r(do) @ r(W3)
+    dz2 = dh2 * (h2 > 0)
+    gW2 = r(dz2).T @ h1
     gb2 = dz2.sum(axis=0)
-    dh1 = dz2 @ r(W2)
-    dz1 = dh1 * (z1 > 0)
-    gW1 = dz1.T @ Xr
+    dh1 = r(dz2) @ r(W2)
+    dz1 = dh1 * (h1 > 0)
+    gW1 = r(dz1).T @ Xr
     gb1 = dz1.sum(axis=0)
     g = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
     return loss, g

@@ -19,6 +19,7 @@ ARCH = "gfx950"
 UNITS = [
     ("setup_kernels.hip", ["-ffp-contract=off"]),
     ("solve_kernels.hip", []),
+    ("learned_kernels.hip", []),
     ("hierarchy.hip", []),
 ]
 

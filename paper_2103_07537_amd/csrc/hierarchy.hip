@@ -12,6 +12,7 @@
 #include <memory>
 #include <numeric>
 
+#include "learned_kernels.h"
 #include "setup_kernels.h"
 #include "solve_kernels.h"
 
@@ -69,6 +70,11 @@ struct BlockLevel {
     std::vector<int> colour_slice, colour_row;  // per colour: first slice, first row (+ end)
     DevBuf<int32_t> row0, nrow, d_perm, d_iperm;
     SellPart off, cpl, diag, dinv;
+    // per-row smoother damping in colour order (learned form), else empty
+    DevBuf<double> w_row64;
+    DevBuf<float> w_row32;
+    // smoothed transfers: P rows of this level, P^T rows of the next level (sliced by the next level)
+    SellPart pro, res;
     // transfer to the next level (colour orders of both levels)
     DevBuf<int32_t> agg_p, mem_ptr, mem_idx;
     DevBuf<double> q64;
@@ -88,6 +94,11 @@ struct Level {
     SetupBsr A[2][2];
     Aggregates G;
     BlockLevel blk[2];
+    // smoothed prolongators (natural order) and the weights that built them
+    bool smoothed = false, damped = false;
+    SetupBsr P[2], PT[2];
+    DevBuf<double> wp_agg, ws_agg;
+    DevBuf<float> feat;
     Vecs<double> v64;
     Vecs<float> v32;
     int64_t nnzb_total() const { return A[0][0].nnzb + A[0][1].nnzb + A[1][0].nnzb + A[1][1].nnzb; }
@@ -119,10 +130,12 @@ struct mbamg_hierarchy {
     // Krylov workspace
     int64_t n_fine = 0;
     DevBuf<double> V, Z64, w, xw, bw, ztmp, partial, hbuf, ybuf, sig2;
+    DevBuf<float> mlp;             // network parameters (5122) followed by feature mean and std (12 + 12)
     double* hbuf_host = nullptr;   // pinned: Krylov scalars read back each iteration
     double* sig2_host = nullptr;
     double* y_host = nullptr;
     int64_t reorth_count = 0;
+    double judge_rho[2] = {0.0, 0.0};   // probe factors of the learned and the fixed hierarchy
     DevBuf<float> Z32, vin32;
     DevBuf<double> vio;   // ABI <-> colour-order staging for vcycle/apply
     DevBuf<double> vio2;
@@ -363,6 +376,46 @@ static void alloc_vecs(Vecs<T>& v, int64_t n) {
 // ----------------------------------------------------------------------------
 // setup
 // ----------------------------------------------------------------------------
+// Per-aggregate weights of one level: omega_P for the smoothed prolongator and,
+// in the learned forms, omega_S for the smoother damping of the aggregate's
+// nodes.  learned 1: features -> network on the device; learned 2: features ->
+// the caller's callback; otherwise the uniform omega_p.
+static void choose_weights(mbamg_hierarchy* h, Level& cur, const Aggregates& G, int lvl, hipStream_t s) {
+    const mbamg_params& p = h->p;
+    const int nc = G.n_agg;
+    cur.wp_agg.alloc(std::max(nc, 1));
+    cur.ws_agg.alloc(std::max(nc, 1));
+    if (p.learned == 0) {
+        std::vector<double> wp(nc, p.omega_p);
+        cur.wp_agg.upload(wp, s);
+        return;
+    }
+    BsrView A[2][2];
+    for (int f = 0; f < 2; ++f)
+        for (int g = 0; g < 2; ++g) A[f][g] = {cur.A[f][g].rp.p, cur.A[f][g].ci.p, cur.A[f][g].val.p, cur.A[f][g].br};
+    cur.feat.alloc((size_t)std::max(nc, 1) * N_FEATURES);
+    aggregate_features(nc, cur.n, G.agg.p, G.mptr.p, G.midx.p, A, h->fm.n_vec[0], h->fm.n_vec[1], lvl, nullptr,
+                       nullptr, cur.feat.p, s);
+    if (p.learned == 1) {
+        DevBuf<float> xn((size_t)std::max(nc, 1) * N_FEATURES), out2((size_t)std::max(nc, 1) * 2);
+        aggregate_features(nc, cur.n, G.agg.p, G.mptr.p, G.midx.p, A, h->fm.n_vec[0], h->fm.n_vec[1], lvl,
+                           h->mlp.p + N_MLP_PARAMS, h->mlp.p + N_MLP_PARAMS + N_FEATURES, xn.p, s);
+        mlp_forward(h->mlp.p, xn.p, nc, out2.p, s);
+        split_weights(nc, out2.p, cur.wp_agg.p, cur.ws_agg.p, s);
+        MB_HIP(hipStreamSynchronize(s));
+    } else {
+        std::vector<float> F = cur.feat.download(s, (size_t)nc * N_FEATURES);
+        std::vector<double> wp(nc, 0.0), ws(nc, p.omega);
+        p.weight_fn(lvl, nc, F.data(), wp.data(), ws.data(), p.weight_ctx);
+        for (int k = 0; k < nc; ++k)
+            MB_CHECK(std::isfinite(wp[k]) && std::isfinite(ws[k]) && ws[k] > 0.0, MBAMG_E_INVALID,
+                     "weight callback returned an invalid weight");
+        cur.wp_agg.upload(wp, s);
+        cur.ws_agg.upload(ws, s);
+    }
+    cur.damped = true;
+}
+
 static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     const mbamg_params& p = h->p;
@@ -412,7 +465,20 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
         nxt->n = nc;
         nxt->d[0] = d0;
         nxt->d[1] = d1;
-        for (int f = 0; f < 2; ++f)
+        if (p.learned != 0 || p.omega_p != 0.0) {
+            choose_weights(h, cur, G, lvl, s);
+            for (int f = 0; f < 2; ++f) {
+                cur.P[f] = sa_prolongator(cur.A[f][f], h->fm.n_vec[f], G, q[f].p, cur.wp_agg.p, s);
+                cur.PT[f] = block_transpose(cur.P[f], s);
+            }
+            for (int f = 0; f < 2; ++f)
+                for (int g = 0; g < 2; ++g) {
+                    SetupBsr T = spgemm(cur.A[f][g], cur.P[g], s);
+                    nxt->A[f][g] = spgemm(cur.PT[f], T, s);
+                }
+            cur.smoothed = true;
+        }
+        for (int f = 0; f < 2 && !cur.smoothed; ++f)
             for (int g = 0; g < 2; ++g) {
                 if (cur.A[f][g].nnzb == 0) {
                     SetupBsr& Z = nxt->A[f][g];
@@ -452,9 +518,10 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
             BlockLevel& B = c.blk[f];
             B.d = c.d[f];
             B.n = c.n;
-            B.perm.resize(c.n);
-            std::iota(B.perm.begin(), B.perm.end(), 0);
-            B.iperm = B.perm;
+            B.colour.assign(c.n, 0);
+            order_and_slice(B, c.n, 1);     // one colour: identity order, slices for the transfer kernels
+            B.row0.upload(B.h_row0, s);
+            B.nrow.upload(B.h_nrow, s);
             B.d_perm.upload(B.perm, s);   // used at the interface when this is the only level
             B.d_iperm.upload(B.iperm, s);
         }
@@ -519,8 +586,23 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
             if (per_colour < 1024 && avg_width >= 16) B.split = 4;
         }
         clk.mark("sliced parts", l);
-        // transfer maps between this level's and the next level's colour orders
-        for (int f = 0; f < 2; ++f) {
+        // transfers between this level's and the next level's colour orders
+        for (int f = 0; f < 2 && Lv.smoothed; ++f) {
+            BlockLevel& B = Lv.blk[f];
+            BlockLevel& C = Nx.blk[f];
+            build_part(B.pro, PartKind::Cpl, B, &Lv.P[f], C.d_iperm.p, Lv.P[f].val.p, B.d, B.d, want32, s);
+            build_part(B.res, PartKind::Cpl, C, &Lv.PT[f], B.d_iperm.p, Lv.PT[f].val.p, B.d, B.d, want32, s);
+        }
+        for (int f = 0; f < 2 && Lv.damped; ++f) {
+            BlockLevel& B = Lv.blk[f];
+            B.w_row64.alloc(std::max(Lv.n, 1));
+            row_damping<double>(Lv.n, B.d_perm.p, Lv.G.agg.p, Lv.ws_agg.p, B.w_row64.p, s);
+            if (want32) {
+                B.w_row32.alloc(std::max(Lv.n, 1));
+                row_damping<float>(Lv.n, B.d_perm.p, Lv.G.agg.p, Lv.ws_agg.p, B.w_row32.p, s);
+            }
+        }
+        for (int f = 0; f < 2 && !Lv.smoothed; ++f) {
             BlockLevel& B = Lv.blk[f];
             const BlockLevel& C = Nx.blk[f];
             transfer_maps(Lv.n, Nx.n, B.d_perm.p, B.d_iperm.p, Lv.G.agg.p, C.d_perm.p, C.d_iperm.p, Lv.G.mptr.p,
@@ -620,6 +702,13 @@ template <>
 const float* qptr<float>(const BlockLevel& B) { return B.q32.p; }
 
 template <class T>
+static const T* wrow(const BlockLevel& B);
+template <>
+const double* wrow<double>(const BlockLevel& B) { return B.w_row64.p; }
+template <>
+const float* wrow<float>(const BlockLevel& B) { return B.w_row32.p; }
+
+template <class T>
 static void smooth_block(mbamg_hierarchy* h, int l, int f, bool zero, const T* b, const T* x, T* xn, const T* xg,
                          hipStream_t s) {
     Level& Lv = *h->L[l];
@@ -645,7 +734,7 @@ static void smooth_block(mbamg_hierarchy* h, int l, int f, bool zero, const T* b
             a.xg = xg;
             a.cstart = k == 0 ? B.colour_row[c] : INT_MAX;
             a.omega = (T)h->p.omega;
-            a.w_row = nullptr;
+            a.w_row = Lv.damped ? wrow<T>(B) : nullptr;
             a.skip_off = (zero && k == 0 && c == 0) ? 1 : 0;
             double bytes = timed ? gs_bytes(B, c, zero, a.skip_off, has_cpl, (int)sizeof(T), Lv.d[g]) : 0.0;
             // kind 0: passes from a nonzero iterate with the coupling term; kind 3: the others
@@ -672,7 +761,7 @@ static void resid(mbamg_hierarchy* h, int l, const T* b, const T* x, T* r, hipSt
         a.x[f] = x + off;
         a.r[f] = r + off;
     }
-    const bool timed = h->timing && l == 0;
+    const bool timed = h->timing && l == 0 && kind >= 0;
     double bytes = timed ? resid_bytes(Lv, (int)sizeof(T), b != nullptr) : 0.0;
     TimerScope ts(h, s, timed, kind, bytes);
     launch_resid<T>(Lv.d[0], std::max(Lv.blk[0].split, Lv.blk[1].split), a, s);
@@ -708,7 +797,18 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
     Level& Nx = *h->L[l + 1];
     Vecs<T>& C = vecs<T>(Nx);
     const int64_t nc0 = (int64_t)Nx.n * Nx.d[0];
-    {
+    if (Lv.smoothed) {
+        XferArgs<T> a{};
+        for (int f = 0; f < 2; ++f) {
+            a.s_count[f] = Nx.blk[f].n_slices;
+            a.sl[f] = Nx.blk[f].slices();
+            a.A[f] = Lv.blk[f].res.view<T>();
+            a.x[f] = V.r.p + (f ? n0 : 0);
+            a.y[f] = C.b.p + (f ? nc0 : 0);
+        }
+        a.accumulate = 0;
+        launch_xfer<T>(Lv.d[0], a, s);
+    } else {
         TransferArgs<T> a{};
         for (int f = 0; f < 2; ++f) {
             a.n_rows[f] = Nx.n;
@@ -721,7 +821,18 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
         launch_restrict<T>(Lv.d[0], a, s);
     }
     vcycle_level<T>(h, l + 1, C.b.p, C.x.p, s);
-    {
+    if (Lv.smoothed) {
+        XferArgs<T> a{};
+        for (int f = 0; f < 2; ++f) {
+            a.s_count[f] = Lv.blk[f].n_slices;
+            a.sl[f] = Lv.blk[f].slices();
+            a.A[f] = Lv.blk[f].pro.view<T>();
+            a.x[f] = C.x.p + (f ? nc0 : 0);
+            a.y[f] = buf[cur] + (f ? n0 : 0);
+        }
+        a.accumulate = 1;
+        launch_xfer<T>(Lv.d[0], a, s);
+    } else {
         TransferArgs<T> a{};
         for (int f = 0; f < 2; ++f) {
             a.n_rows[f] = Lv.n;
@@ -907,6 +1018,26 @@ static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, d
     return st;
 }
 
+// Asymptotic factor of e <- e - M A e from a seeded start (colour order).
+static double probe_impl(mbamg_hierarchy* h, int iters, uint64_t seed, hipStream_t s) {
+    MB_CHECK(iters >= 5, MBAMG_E_INVALID, "probe needs at least 5 iterations");
+    MB_CHECK(!h->L[0]->coarsest, MBAMG_E_STATE, "probe needs at least two levels");
+    const int64_t n = h->n_fine;
+    double* e = h->vio.p;
+    launch_seeded(n, seed, h->vio2.p, s);   // generated in the interface order, then reordered
+    to_colour(h, h->vio2.p, e, s);
+    double nk4 = 0.0, nk = 0.0;
+    for (int k = 1; k <= iters; ++k) {
+        apply_A(h, e, h->w.p, s, -1);
+        apply_precond(h, h->w.p, h->vio2.p, h->p.precision == 1 ? h->Z32.p : nullptr, s);
+        launch_axpby(n, -1.0, h->vio2.p, 1.0, e, s);
+        if (k == iters - 4) nk4 = norm2_dev(h, e, s);
+        if (k == iters) nk = norm2_dev(h, e, s);
+    }
+    if (nk4 <= 0.0) return 0.0;
+    return std::pow(std::sqrt(nk / nk4), 0.25);
+}
+
 }  // namespace mbamg
 
 // ----------------------------------------------------------------------------
@@ -948,8 +1079,12 @@ void mbamg_default_params(mbamg_params* p) {
     p->restart = 30;
     p->max_iters = 1000;
     p->learned = 0;
-    p->mlp_weights = nullptr;
+    p->mlp = nullptr;
     p->seed = 0;
+    p->omega_p = 0.0;
+    p->judge = 1;
+    p->weight_fn = nullptr;
+    p->weight_ctx = nullptr;
 }
 
 const char* mbamg_last_error(void) { return g_last_error.c_str(); }
@@ -967,14 +1102,46 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
                  MBAMG_E_INVALID, "invalid parameters");
         MB_CHECK(p->clone_aggregates != 0, MBAMG_E_INVALID, "separate block-1 aggregation is not built");
         MB_CHECK(p->precision == 0 || p->precision == 1, MBAMG_E_INVALID, "precision must be 0 or 1");
-        MB_CHECK(p->learned == 0, MBAMG_E_INVALID, "learned weights are set after setup, not through params");
-        auto h = std::make_unique<mbamg_hierarchy>();
-        h->p = *p;
-        h->fm = *fm;
-        h->d[0] = fm->dofs[0];
-        h->d[1] = fm->dofs[1];
+        MB_CHECK(p->learned >= 0 && p->learned <= 2, MBAMG_E_INVALID, "learned must be 0, 1 or 2");
+        MB_CHECK(p->learned != 1 || p->mlp != nullptr, MBAMG_E_INVALID, "learned == 1 needs the network parameters");
+        MB_CHECK(p->learned != 2 || p->weight_fn != nullptr, MBAMG_E_INVALID, "learned == 2 needs a weight callback");
+        MB_CHECK(p->omega_p >= 0.0 && std::isfinite(p->omega_p), MBAMG_E_INVALID, "omega_p must be >= 0");
+        for (int f = 0; f < 2; ++f)
+            MB_CHECK(fm->n_vec[f] >= 0 && fm->n_vec[f] <= fm->dofs[f], MBAMG_E_INVALID, "n_vec out of range");
         hipStream_t s = (hipStream_t)hip_stream;
-        setup_impl(h.get(), A_blocks, s);
+        auto t0 = std::chrono::steady_clock::now();
+        auto build = [&](const mbamg_params& pp) {
+            auto h = std::make_unique<mbamg_hierarchy>();
+            h->p = pp;
+            h->fm = *fm;
+            h->d[0] = fm->dofs[0];
+            h->d[1] = fm->dofs[1];
+            if (pp.learned == 1) h->mlp.upload(pp.mlp, N_MLP_PARAMS + 2 * N_FEATURES, s);
+            setup_impl(h.get(), A_blocks, s);
+            return h;
+        };
+        auto h = build(*p);
+        h->info.used_learned = p->learned != 0;
+        if (p->learned != 0 && p->judge) {
+            // the fixed-weight method is the fallback and the judge
+            mbamg_params pf = *p;
+            pf.learned = 0;
+            pf.omega_p = 0.0;
+            auto hf = build(pf);
+            const double rl = probe_impl(h.get(), 10, 12345, s);
+            const double rf = probe_impl(hf.get(), 10, 12345, s);
+            h->judge_rho[0] = hf->judge_rho[0] = rl;
+            h->judge_rho[1] = hf->judge_rho[1] = rf;
+            if (!(rl < rf)) {
+                h = std::move(hf);
+                h->info.used_learned = 0;
+            } else {
+                h->info.used_learned = 1;
+            }
+        }
+        auto t1 = std::chrono::steady_clock::now();
+        h->t_setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        h->info.t_setup_ms = h->t_setup_ms;
         *out = h.release();
         return MBAMG_OK;
     });
@@ -1149,6 +1316,75 @@ mbamg_status mbamg_vcycle_bytes(const mbamg_hierarchy* h, double* bytes) {
         *bytes = tot;
         return MBAMG_OK;
     });
+}
+
+mbamg_status mbamg_features(const mbamg_hierarchy* h, int32_t level, float* features) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(h && features && level >= 0 && level + 1 < (int)h->L.size(), MBAMG_E_INVALID, "bad argument");
+        const Level& L = *h->L[level];
+        MB_CHECK(L.feat.p != nullptr, MBAMG_E_STATE, "features are computed only for the learned forms");
+        MB_HIP(hipMemcpy(features, L.feat.p, sizeof(float) * L.G.n_agg * N_FEATURES, hipMemcpyDeviceToHost));
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_level_weights(const mbamg_hierarchy* h, int32_t level, double* omega_p, double* omega_s) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(h && omega_p && omega_s && level >= 0 && level + 1 < (int)h->L.size(), MBAMG_E_INVALID,
+                 "bad argument");
+        const Level& L = *h->L[level];
+        const int nc = L.G.n_agg;
+        if (L.smoothed) MB_HIP(hipMemcpy(omega_p, L.wp_agg.p, sizeof(double) * nc, hipMemcpyDeviceToHost));
+        else std::fill(omega_p, omega_p + nc, 0.0);
+        if (L.damped) {
+            MB_HIP(hipMemcpy(omega_s, L.ws_agg.p, sizeof(double) * nc, hipMemcpyDeviceToHost));
+        } else {
+            std::fill(omega_s, omega_s + nc, h->p.omega);
+        }
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_mlp_forward(const float* params, const float* x, int64_t n, float* out, void* hip_stream) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(params && x && out && n >= 0, MBAMG_E_INVALID, "bad argument");
+        mlp_forward(params, x, n, out, (hipStream_t)hip_stream);
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_mlp_loss_grad(const float* params, const float* x, const float* target, int64_t n, float* grad,
+                                 float* loss, void* hip_stream) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(params && x && target && grad && n > 0, MBAMG_E_INVALID, "bad argument");
+        static thread_local DevBuf<float> partial;
+        hipStream_t s = (hipStream_t)hip_stream;
+        mlp_loss_grad(params, x, target, n, grad, loss, partial, s);
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr, float beta1,
+                            float beta2, float eps, void* hip_stream) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(params && grad && m && v && step >= 1, MBAMG_E_INVALID, "bad argument");
+        mlp_adam(params, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)hip_stream);
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_probe(mbamg_hierarchy* h, int32_t iters, uint64_t seed, double* rho, void* hip_stream) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(h && rho, MBAMG_E_INVALID, "NULL argument");
+        *rho = probe_impl(h, iters, seed, (hipStream_t)hip_stream);
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_set_omega(mbamg_hierarchy* h, double omega) {
+    if (!h || !(omega > 0.0)) { g_last_error = "bad argument"; return MBAMG_E_INVALID; }
+    h->p.omega = omega;
+    return MBAMG_OK;
 }
 
 }  // extern "C"

@@ -42,6 +42,11 @@ void sell_masks(int64_t n_slots, int bs, const int64_t* src, const double* val, 
 void sell_fill(int64_t n_slots, int bs, const int64_t* src, const double* val, const uint32_t* mask,
                const int64_t* slot_voff, double* out, hipStream_t s);
 void cast_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
+// smoothed prolongator (vector components), block transpose, generic ordered block product
+SetupBsr sa_prolongator(const SetupBsr& A, int nv, const Aggregates& G, const double* q, const double* w,
+                        hipStream_t s);
+SetupBsr block_transpose(const SetupBsr& P, hipStream_t s);
+SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s);
 // device construction of the sliced smoother format (see hierarchy.hip)
 void part_layout(int n, int ns, int kind, const int32_t* perm, const int32_t* rp, const int32_t* ci,
                  const int32_t* row0, const int32_t* nrow, DevBuf<int32_t>& width, DevBuf<int32_t>& coff32,

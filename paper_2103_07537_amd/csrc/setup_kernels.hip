@@ -474,6 +474,148 @@ __global__ void k_cast_f64_f32(const double* a, float* b, int64_t n) {
 }
 
 // ----------------------------------------------------------------------------
+// smoothed prolongator, block transpose and the generic ordered block product
+// ----------------------------------------------------------------------------
+// P = Phat - D_vv^-1 A_vv Phat W on the vector components.  Row i lists agg(i)
+// and the aggregates k of its columns with w[k] != 0, in increasing order.
+// Vector entry (a,c) of block (i,k): s = sum over the row's columns j in
+// increasing order with agg(j) = k of A[i,j][a][c] * q[j,c];
+// P = base - w[k] * (s / A[i,i][a][a]) with base = q[i,a] on (k = agg(i), c = a).
+__global__ void k_sa_prolong(int n, int d, int nv, const int32_t* rp, const int32_t* ci, const double* val,
+                             const int32_t* agg, const double* q, const double* w, int pass, int32_t* cnt,
+                             const int32_t* prp, int32_t* pci, double* pval) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int b = rp[i], e = rp[i + 1], bs = d * d, ai = agg[i];
+    int pd = find_col(ci, b, e, i);
+    int prev = -1, out = pass ? prp[i] : 0, c = 0;
+    while (true) {
+        int l = INT_MAX;
+        for (int p = b; p < e; ++p) {
+            int a = agg[ci[p]];
+            if (a != ai && w[a] == 0.0) continue;
+            if (a > prev && a < l) l = a;
+        }
+        if (l == INT_MAX) break;
+        if (pass) {
+            double* blk = pval + (int64_t)(out + c) * bs;
+            pci[out + c] = l;
+            for (int ra = 0; ra < d; ++ra)
+                for (int cc = 0; cc < d; ++cc) {
+                    double base = (l == ai && cc == ra) ? q[(int64_t)i * d + ra] : 0.0;
+                    if (ra < nv && cc < nv) {
+                        double acc = 0.0;
+                        for (int p = b; p < e; ++p) {
+                            int j = ci[p];
+                            if (agg[j] != l) continue;
+                            double term = val[(int64_t)p * bs + ra * d + cc] * q[(int64_t)j * d + cc];
+                            acc = acc + term;
+                        }
+                        // a missing diagonal block gives inf here; the nodal inverses report it as singular
+                        double dg = pd >= 0 ? val[(int64_t)pd * bs + ra * d + ra] : 0.0;
+                        double t = acc / dg;
+                        double u = w[l] * t;
+                        blk[ra * d + cc] = base - u;
+                    } else {
+                        blk[ra * d + cc] = base;
+                    }
+                }
+        }
+        ++c;
+        prev = l;
+    }
+    if (!pass) cnt[i] = c;
+}
+
+__global__ void k_count_cols(int n, const int32_t* rp, const int32_t* ci, int32_t* cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) atomicAdd(&cnt[ci[p]], 1);
+}
+
+__global__ void k_place_cols(int n, const int32_t* rp, const int32_t* ci, const int32_t* trp, int32_t* cursor,
+                             int32_t* trow, int32_t* tsrc) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int c = ci[p];
+        int slot = trp[c] + atomicAdd(&cursor[c], 1);
+        trow[slot] = i;
+        tsrc[slot] = p;
+    }
+}
+
+// sort each transposed row by source row, then copy the transposed blocks
+__global__ void k_finish_transpose(int nc, int br, int bc, const int32_t* trp, int32_t* trow, int32_t* tsrc,
+                                   const double* val, double* tval) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nc) return;
+    const int b = trp[k], e = trp[k + 1];
+    for (int a = b + 1; a < e; ++a) {
+        int r = trow[a], s = tsrc[a];
+        int c = a - 1;
+        while (c >= b && trow[c] > r) { trow[c + 1] = trow[c]; tsrc[c + 1] = tsrc[c]; --c; }
+        trow[c + 1] = r;
+        tsrc[c + 1] = s;
+    }
+    for (int a = b; a < e; ++a) {
+        const double* src = val + (int64_t)tsrc[a] * br * bc;
+        double* dst = tval + (int64_t)a * br * bc;
+        for (int r = 0; r < br; ++r)
+            for (int c = 0; c < bc; ++c) dst[c * br + r] = src[r * bc + c];
+    }
+}
+
+// C = A B.  Row i of C lists the distinct columns reached through row i of A,
+// in increasing order; entry (r,c) of block (i,l) sums A[i,j][r][m]*B[j,l][m][c]
+// over the columns j of row i in increasing order and, for each, m increasing.
+__global__ void k_spgemm(int n, int br, int bm, int bc, const int32_t* arp, const int32_t* aci, const double* aval,
+                         const int32_t* brp, const int32_t* bci, const double* bval, int pass, int32_t* cnt,
+                         const int32_t* crp, int32_t* cci, double* cval) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ab = arp[i], ae = arp[i + 1];
+    int prev = -1, out = pass ? crp[i] : 0, c = 0;
+    while (true) {
+        int l = INT_MAX;
+        for (int p = ab; p < ae; ++p) {
+            int j = aci[p];
+            for (int q = brp[j]; q < brp[j + 1]; ++q) {
+                int col = bci[q];
+                if (col > prev) {
+                    if (col < l) l = col;
+                    break;     // columns of B's row increase: the first above prev is the smallest
+                }
+            }
+        }
+        if (l == INT_MAX) break;
+        if (pass) {
+            double acc[16];
+            for (int e = 0; e < br * bc; ++e) acc[e] = 0.0;
+            for (int p = ab; p < ae; ++p) {
+                int j = aci[p];
+                int q = find_col(bci, brp[j], brp[j + 1], l);
+                if (q < 0) continue;
+                const double* a = aval + (int64_t)p * br * bm;
+                const double* bb = bval + (int64_t)q * bm * bc;
+                for (int r = 0; r < br; ++r)
+                    for (int cc = 0; cc < bc; ++cc)
+                        for (int m = 0; m < bm; ++m) {
+                            double term = a[r * bm + m] * bb[m * bc + cc];
+                            acc[r * bc + cc] = acc[r * bc + cc] + term;
+                        }
+            }
+            cci[out + c] = l;
+            double* dst = cval + (int64_t)(out + c) * br * bc;
+            for (int e = 0; e < br * bc; ++e) dst[e] = acc[e];
+        }
+        ++c;
+        prev = l;
+    }
+    if (!pass) cnt[i] = c;
+}
+
+// ----------------------------------------------------------------------------
 // building the sliced smoother format on the device.  kind: 0 off-diagonal
 // blocks of A_ff, 1 all blocks of A_fg, 2 the diagonal block, 3 one entry per
 // node (the node index itself, for the nodal inverses).
@@ -819,6 +961,81 @@ void cast_to_f32(const double* a, float* b, int64_t n, hipStream_t s) {
     if (n == 0) return;
     k_cast_f64_f32<<<grid_for(n), 256, 0, s>>>(a, b, n);
     MB_LAUNCH_CHECK();
+}
+
+SetupBsr sa_prolongator(const SetupBsr& A, int nv, const Aggregates& G, const double* q, const double* w,
+                        hipStream_t s) {
+    MB_CHECK(A.br == A.bc && A.br <= 4, MBAMG_E_INVALID, "smoothed prolongator needs square blocks of at most 4");
+    const int n = A.n_rows, d = A.br;
+    SetupBsr P;
+    P.n_rows = n;
+    P.n_cols = G.n_agg;
+    P.br = P.bc = d;
+    DevBuf<int32_t> cnt(std::max(n, 1));
+    k_sa_prolong<<<grid_for(n, 128), 128, 0, s>>>(n, d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 0, cnt.p, nullptr,
+                                                 nullptr, nullptr);
+    MB_LAUNCH_CHECK();
+    P.rp.alloc(n + 1);
+    P.nnzb = scan_exclusive(cnt.p, n, P.rp.p, s);
+    P.ci.alloc(std::max<int64_t>(P.nnzb, 1));
+    P.val.alloc(std::max<int64_t>(P.nnzb * d * d, 1));
+    k_sa_prolong<<<grid_for(n, 128), 128, 0, s>>>(n, d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 1, nullptr,
+                                                 P.rp.p, P.ci.p, P.val.p);
+    MB_LAUNCH_CHECK();
+    return P;
+}
+
+SetupBsr block_transpose(const SetupBsr& P, hipStream_t s) {
+    const int n = P.n_rows, nc = P.n_cols;
+    SetupBsr T;
+    T.n_rows = nc;
+    T.n_cols = n;
+    T.br = P.bc;
+    T.bc = P.br;
+    T.nnzb = P.nnzb;
+    DevBuf<int32_t> cnt(std::max(nc, 1)), cursor(std::max(nc, 1));
+    MB_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * std::max(nc, 1), s));
+    MB_HIP(hipMemsetAsync(cursor.p, 0, sizeof(int32_t) * std::max(nc, 1), s));
+    k_count_cols<<<grid_for(n), 256, 0, s>>>(n, P.rp.p, P.ci.p, cnt.p);
+    MB_LAUNCH_CHECK();
+    T.rp.alloc(nc + 1);
+    scan_exclusive(cnt.p, nc, T.rp.p, s);
+    T.ci.alloc(std::max<int64_t>(P.nnzb, 1));
+    DevBuf<int32_t> src(std::max<int64_t>(P.nnzb, 1));
+    k_place_cols<<<grid_for(n), 256, 0, s>>>(n, P.rp.p, P.ci.p, T.rp.p, cursor.p, T.ci.p, src.p);
+    T.val.alloc(std::max<int64_t>(P.nnzb * P.br * P.bc, 1));
+    k_finish_transpose<<<grid_for(nc, 64), 64, 0, s>>>(nc, P.br, P.bc, T.rp.p, T.ci.p, src.p, P.val.p, T.val.p);
+    MB_LAUNCH_CHECK();
+    MB_HIP(hipStreamSynchronize(s));
+    return T;
+}
+
+SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s) {
+    MB_CHECK(A.bc == B.br && A.br * B.bc <= 16, MBAMG_E_INVALID, "block product shapes");
+    const int n = A.n_rows;
+    SetupBsr C;
+    C.n_rows = n;
+    C.n_cols = B.n_cols;
+    C.br = A.br;
+    C.bc = B.bc;
+    DevBuf<int32_t> cnt(std::max(n, 1));
+    C.rp.alloc(n + 1);
+    if (A.nnzb == 0 || B.nnzb == 0) {
+        MB_HIP(hipMemsetAsync(C.rp.p, 0, sizeof(int32_t) * (n + 1), s));
+        C.ci.alloc(1);
+        C.val.alloc(1);
+        return C;
+    }
+    k_spgemm<<<grid_for(n, 64), 64, 0, s>>>(n, A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, 0,
+                                           cnt.p, nullptr, nullptr, nullptr);
+    MB_LAUNCH_CHECK();
+    C.nnzb = scan_exclusive(cnt.p, n, C.rp.p, s);
+    C.ci.alloc(std::max<int64_t>(C.nnzb, 1));
+    C.val.alloc(std::max<int64_t>(C.nnzb * C.br * C.bc, 1));
+    k_spgemm<<<grid_for(n, 64), 64, 0, s>>>(n, A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, 1,
+                                           nullptr, C.rp.p, C.ci.p, C.val.p);
+    MB_LAUNCH_CHECK();
+    return C;
 }
 
 void part_layout(int n, int ns, int kind, const int32_t* perm, const int32_t* rp, const int32_t* ci,

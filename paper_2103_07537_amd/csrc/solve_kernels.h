@@ -65,6 +65,18 @@ struct TransferArgs {
 
 // P: waves per slice (1, 2 or 4); the slice's slots are split among them.
 template <class T>
+struct XferArgs {
+    int s_count[2];
+    SliceView sl[2];
+    SellView<T> A[2];
+    const T* x[2];
+    T* y[2];
+    int accumulate;
+};
+
+template <class T>
+void launch_xfer(int d, const XferArgs<T>& a, hipStream_t s);
+template <class T>
 void launch_gs(int d, int P, bool zero_x, bool has_cpl, const GsArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_resid(int d, int P, const ResidArgs<T>& a, hipStream_t s);
@@ -85,6 +97,7 @@ void launch_orth_reduce(const double* partial, int nblocks, int nq, bool dots, c
 void launch_combine(int64_t n, int k, const double* Z, int64_t ldz, const double* y, double* x, hipStream_t s);
 void launch_combine32(int64_t n, int k, const float* Z, int64_t ldz, const double* y, double* x, hipStream_t s);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
+void launch_seeded(int64_t n, uint64_t seed, double* v, hipStream_t s);
 int krylov_blocks(int64_t n);
 void launch_gather(int n_rows, int d, const int32_t* perm, const double* src, double* dst, hipStream_t s);
 void launch_scatter(int n_rows, int d, const int32_t* perm, const double* src, double* dst, hipStream_t s);

@@ -249,6 +249,39 @@ __global__ __launch_bounds__(256) void k_resid(ResidArgs<T> a, int padded_blocks
     store_vec<T, D>(a.r[f] + (int64_t)row * D, out);
 }
 
+// y = A x (or y += A x) for both blocks in one launch: the smoothed
+// prolongator (rows of the fine level) and its transpose (rows of the coarse
+// level) in masked sliced-ELL form.
+template <class T, int D>
+__global__ __launch_bounds__(256) void k_xfer(XferArgs<T> a, int padded_blocks) {
+    int sidx = xcd_block(padded_blocks) * WPB + wave_id();
+    int f = 0;
+    if (sidx >= a.s_count[0]) {
+        sidx -= a.s_count[0];
+        f = 1;
+        if (sidx >= a.s_count[1]) return;
+    }
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int row0 = a.sl[f].row0[sidx], nrow = a.sl[f].nrow[sidx];
+    const int row = row0 + (lane < nrow ? lane : 0);
+    T acc[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) acc[r] = T(0);
+    sell_sub<T, D, D, 0, 1>(a.A[f], sidx, lane, 0, a.x[f], nullptr, 0, acc);
+    if (lane >= nrow) return;
+    T out[D];
+    if (a.accumulate) {
+        T y[D];
+        load_vec<T, D>(a.y[f] + (int64_t)row * D, y);
+#pragma unroll
+        for (int r = 0; r < D; ++r) out[r] = y[r] - acc[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < D; ++r) out[r] = -acc[r];
+    }
+    store_vec<T, D>(a.y[f] + (int64_t)row * D, out);
+}
+
 // coarse b_k = sum over members i of aggregate k of q_i .* r_i (per component)
 template <class T, int D>
 __global__ void k_restrict(TransferArgs<T> a) {
@@ -374,6 +407,24 @@ void launch_resid(int d, int P, const ResidArgs<T>& a, hipStream_t s) {
     }
     MB_LAUNCH_CHECK();
 }
+
+template <class T>
+void launch_xfer(int d, const XferArgs<T>& a, hipStream_t s) {
+    const int total = a.s_count[0] + a.s_count[1];
+    if (total <= 0) return;
+    unsigned grid = xcd_grid(total, 1);
+    int pb = (int)grid;
+    switch (d) {
+        case 1: k_xfer<T, 1><<<grid, 256, 0, s>>>(a, pb); break;
+        case 2: k_xfer<T, 2><<<grid, 256, 0, s>>>(a, pb); break;
+        case 3: k_xfer<T, 3><<<grid, 256, 0, s>>>(a, pb); break;
+        case 4: k_xfer<T, 4><<<grid, 256, 0, s>>>(a, pb); break;
+        default: throw Error(MBAMG_E_INVALID, "dofs per node must be 1..4");
+    }
+    MB_LAUNCH_CHECK();
+}
+template void launch_xfer<double>(int, const XferArgs<double>&, hipStream_t);
+template void launch_xfer<float>(int, const XferArgs<float>&, hipStream_t);
 
 template <class T>
 void launch_restrict(int d, const TransferArgs<T>& a, hipStream_t s) {
@@ -555,6 +606,19 @@ __global__ void k_c32to64(int64_t n, const float* __restrict__ a, double* __rest
         b[e] = (double)a[e];
 }
 
+// seeded start vector in [-1, 1): SplitMix64 output finaliser of (i + seed * golden ratio)
+__global__ void k_seeded(int64_t n, uint64_t seed, double* v) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t z = (uint64_t)e + 0x9E3779B97F4A7C15ull * (seed + 1);
+        z ^= z >> 30;
+        z *= 0xBF58476D1CE4E5B9ull;
+        z ^= z >> 27;
+        z *= 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        v[e] = 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+    }
+}
+
 int krylov_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(KBLOCKS, ceil_div(n, 1024))); }
 
 static unsigned stream_grid(int64_t n) {
@@ -586,6 +650,11 @@ void launch_combine(int64_t n, int k, const double* Z, int64_t ldz, const double
 void launch_combine32(int64_t n, int k, const float* Z, int64_t ldz, const double* y, double* x, hipStream_t s) {
     if (k <= 0) return;
     k_combine<float><<<stream_grid(n), 256, 0, s>>>(n, k, Z, ldz, y, x);
+    MB_LAUNCH_CHECK();
+}
+
+void launch_seeded(int64_t n, uint64_t seed, double* v, hipStream_t s) {
+    k_seeded<<<stream_grid(n), 256, 0, s>>>(n, seed, v);
     MB_LAUNCH_CHECK();
 }
 

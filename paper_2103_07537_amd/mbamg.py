@@ -34,12 +34,17 @@ class FieldMap(ctypes.Structure):
     _fields_ = [("n_blocks", ctypes.c_int32), ("dofs", ctypes.c_int32 * 4), ("n_vec", ctypes.c_int32 * 4)]
 
 
+WEIGHT_FN = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+
+
 class Params(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("bgs_sweeps", ctypes.c_int32), ("inner_sweeps", ctypes.c_int32),
                 ("theta", ctypes.c_double), ("max_levels", ctypes.c_int32), ("max_coarse", ctypes.c_int32),
                 ("clone_aggregates", ctypes.c_int32), ("reuse_P", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("learned", ctypes.c_int32),
-                ("mlp_weights", ctypes.c_char_p), ("seed", ctypes.c_uint64)]
+                ("mlp", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("omega_p", ctypes.c_double),
+                ("judge", ctypes.c_int32), ("weight_fn", WEIGHT_FN), ("weight_ctx", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -75,6 +80,14 @@ SIGNATURES = [
     ("mbamg_timing_get", ctypes.c_int, [_P, _I32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]),
     ("mbamg_vcycle_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    ("mbamg_features", ctypes.c_int, [_P, _I32, _P]),
+    ("mbamg_level_weights", ctypes.c_int, [_P, _I32, _P, _P]),
+    ("mbamg_mlp_forward", ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
+    ("mbamg_mlp_loss_grad", ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P, _P]),
+    ("mbamg_mlp_adam", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_float, _P]),
+    ("mbamg_probe", ctypes.c_int, [_P, _I32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), _P]),
+    ("mbamg_set_omega", ctypes.c_int, [_P, ctypes.c_double]),
 ]
 
 _lib = None
@@ -133,13 +146,41 @@ class Hierarchy:
     either NumPy arrays (host) or torch CUDA tensors (device).
     """
 
-    def __init__(self, blocks, dofs, n_vec=None, params: Params | None = None, stream=None, **param_kw):
+    def __init__(self, blocks, dofs, n_vec=None, params: Params | None = None, stream=None, mlp=None,
+                 weights=None, **param_kw):
+        """mlp: 5146 floats (network parameters, feature means, feature stds) for learned=1;
+        weights: callable(level, n_agg, features[n_agg,12]) -> (omega_p, omega_s) for learned=2."""
         self._h = ctypes.c_void_p()
         self.dofs = tuple(int(d) for d in dofs)
         self.n_nodes = int(blocks[0][0].n_brows)
         self.n_dofs = self.n_nodes * sum(self.dofs)
         p = params if params is not None else default_params(**param_kw)
         self.params = p
+        keep_alive = []
+        if mlp is not None:
+            arr = np.ascontiguousarray(mlp, dtype=np.float32)
+            if arr.shape[0] != N_MLP_PARAMS + 24:
+                raise ValueError("mlp must hold 5122 parameters and 24 normalisation values")
+            keep_alive.append(arr)
+            p.mlp = arr.ctypes.data
+            p.learned = 1
+        if weights is not None:
+            errors = []
+
+            def _cb(level, n_agg, feat_ptr, wp_ptr, ws_ptr, ctx):
+                try:
+                    F = np.ctypeslib.as_array(feat_ptr, shape=(n_agg * 12,)).reshape(n_agg, 12).copy()
+                    wp, ws = weights(int(level), int(n_agg), F)
+                    np.ctypeslib.as_array(wp_ptr, shape=(n_agg,))[:] = np.asarray(wp, dtype=np.float64)
+                    np.ctypeslib.as_array(ws_ptr, shape=(n_agg,))[:] = np.asarray(ws, dtype=np.float64)
+                except Exception as e:          # reported after setup returns
+                    errors.append(e)
+                    np.ctypeslib.as_array(ws_ptr, shape=(n_agg,))[:] = np.nan
+
+            cb = WEIGHT_FN(_cb)
+            keep_alive.append(cb)
+            p.weight_fn = cb
+            p.learned = 2
         fm = FieldMap()
         fm.n_blocks = 2
         for f in range(2):
@@ -167,7 +208,14 @@ class Hierarchy:
                 e.nnzb = int(ci.shape[0])
                 e.row_ptr, e.col_idx, e.vals = ptrs
                 e.on_device = on_dev
-        _check(lib().mbamg_setup(arr, ctypes.byref(fm), ctypes.byref(p), _stream_ptr(stream), ctypes.byref(self._h)))
+        try:
+            _check(lib().mbamg_setup(arr, ctypes.byref(fm), ctypes.byref(p), _stream_ptr(stream),
+                                     ctypes.byref(self._h)))
+        finally:
+            p.weight_fn = WEIGHT_FN()
+            p.mlp = None
+        if weights is not None and errors:
+            raise errors[0]
         self._keep = []
 
     def close(self):
@@ -236,6 +284,29 @@ class Hierarchy:
         k = nnzb.value
         return rp, ci[:k], v[:k * self.dofs[f] * self.dofs[g]].reshape(k, self.dofs[f], self.dofs[g])
 
+    # -- learned form --------------------------------------------------------
+    def features(self, level: int) -> np.ndarray:
+        nagg = self.level_nodes(level + 1)
+        F = np.zeros((nagg, 12), dtype=np.float32)
+        _check(lib().mbamg_features(self._h, level, F.ctypes.data_as(ctypes.c_void_p)))
+        return F
+
+    def level_weights(self, level: int):
+        nagg = self.level_nodes(level + 1)
+        wp = np.zeros(nagg)
+        ws = np.zeros(nagg)
+        _check(lib().mbamg_level_weights(self._h, level, wp.ctypes.data_as(ctypes.c_void_p),
+                                         ws.ctypes.data_as(ctypes.c_void_p)))
+        return wp, ws
+
+    def probe(self, iters=10, seed=12345, stream=None) -> float:
+        r = ctypes.c_double()
+        _check(lib().mbamg_probe(self._h, iters, seed, ctypes.byref(r), _stream_ptr(stream)))
+        return r.value
+
+    def set_omega(self, omega: float):
+        _check(lib().mbamg_set_omega(self._h, float(omega)))
+
     # -- measurement ---------------------------------------------------------
     def timing_enable(self, on: bool = True):
         _check(lib().mbamg_timing_enable(self._h, 1 if on else 0))
@@ -251,6 +322,26 @@ class Hierarchy:
         b = ctypes.c_double()
         _check(lib().mbamg_vcycle_bytes(self._h, ctypes.byref(b)))
         return b.value
+
+
+N_MLP_PARAMS = 5122
+
+
+def mlp_forward(params, x, out, stream=None):
+    """out[n,2] = network(x[n,12]); torch device tensors (float32)."""
+    _check(lib().mbamg_mlp_forward(_ptr(params), _ptr(x), x.shape[0], _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def mlp_loss_grad(params, x, target, grad, loss, stream=None):
+    _check(lib().mbamg_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(target), x.shape[0], _ptr(grad), _ptr(loss),
+                                     _stream_ptr(stream)))
+    return grad, loss
+
+
+def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().mbamg_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1, beta2, eps,
+                                _stream_ptr(stream)))
 
 
 def to_device(system, device="cuda"):
