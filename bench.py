@@ -3,8 +3,11 @@
 One step = the whole hot path on one synthetic block system already resident
 in HBM: hierarchy setup on the GPU (strength graph, aggregation, tentative P,
 Galerkin products, smoother data, coarsest inverse) followed by the
-right-preconditioned GMRES solve to rtol 1e-8.  Forms: plain FP64, and the
-FP32 V-cycle inside FP64 flexible GMRES.  Prints one JSON line.
+right-preconditioned GMRES solve to rtol 1e-8.  Forms: plain FP64, the FP32
+V-cycle inside FP64 flexible GMRES, and that refined form with the trained
+per-aggregate weights (the fixed-weight hierarchy judges it and replaces it
+when its measured convergence factor is worse; both builds are inside the
+timed step).  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -45,7 +48,8 @@ def parse():
     ap.add_argument("--workload", default="3d-128-lognormal")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--forms", default="fp64,fp32")
+    ap.add_argument("--forms", default="fp64,fp32,learned")
+    ap.add_argument("--weights", default=None, help="trained network (JSON); default: the committed one")
     ap.add_argument("--vcycles", type=int, default=20, help="V-cycles timed for the V-cycle bandwidth figure")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=0, help="grid size of the oracle sample (0: automatic)")
@@ -81,10 +85,20 @@ def counter_run(args):
     print(json.dumps({"counter_run": args.workload, "calibration_bytes": 1 << 30}), flush=True)
 
 
-def run_step(blocks, system, b, form, rtol, timing):
+FORMS = {
+    # name: (precision, learned network)
+    "fp64": (0, False),
+    "fp32": (1, False),
+    "learned": (1, True),      # the full chosen form: FP32 cycle in FP64 FGMRES + learned weights, judged
+    "learned64": (0, True),
+}
+
+
+def run_step(blocks, system, b, form, rtol, timing, mlp=None):
     from paper_2103_07537_amd import mbamg
     import torch
-    h = mbamg.Hierarchy(blocks, system.dofs, system.n_vec, precision=1 if form == "fp32" else 0)
+    precision, use_mlp = FORMS[form]
+    h = mbamg.Hierarchy(blocks, system.dofs, system.n_vec, precision=precision, mlp=mlp if use_mlp else None)
     if timing:
         h.timing_enable(True)
     x = torch.zeros_like(b)
@@ -112,6 +126,29 @@ def vcycle_rate(h, b, reps):
         times.append(e0.elapsed_time(e1))
     ms = float(np.median(times))
     return ms, h.vcycle_bytes()
+
+
+def stream_copy_rate():
+    """Device-to-device copy of 1 GiB (1 GiB read + 1 GiB written): the
+    bandwidth a plain streaming kernel reaches on this GPU, reported beside
+    the 8 TB/s specification."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del src, dst
+    return 2.0 * (1 << 30) / (float(np.median(times)) * 1e-3) / 1e9
 
 
 def cpu_baseline(args, gpu_iters):
@@ -184,11 +221,23 @@ def main():
     b = torch.from_numpy(system.b).cuda()
     torch.cuda.synchronize()
     forms = [f for f in args.forms.split(",") if f]
+    for f in forms:
+        if f not in FORMS:
+            raise SystemExit(f"unknown form {f}; choose from {sorted(FORMS)}")
+    mlp = None
+    if any(FORMS[f][1] for f in forms):
+        from paper_2103_07537_amd import learned
+        wpath = args.weights or learned.DEFAULT_WEIGHTS
+        if os.path.exists(wpath):
+            mlp = learned.load(wpath)
+        else:
+            log(f"[bench] no trained network at {wpath}; skipping the learned forms")
+            forms = [f for f in forms if not FORMS[f][1]]
     results = {}
     xs = {}
     for form in forms:
         for w in range(args.warmup):
-            h, x, info, _ = run_step(blocks, system, b, form, args.rtol, False)
+            h, x, info, _ = run_step(blocks, system, b, form, args.rtol, False, mlp)
             log(f"[bench] warmup {form} {w}: its {info['iterations']} setup {info['t_setup_ms']:.1f} ms "
                 f"solve {info['t_solve_ms']:.1f} ms")
             h.close()
@@ -196,7 +245,7 @@ def main():
         t_start = time.perf_counter()
         infos, stats_all = [], []
         for k in range(args.steps):
-            h, x, info, stats = run_step(blocks, system, b, form, args.rtol, form == "fp64")
+            h, x, info, stats = run_step(blocks, system, b, form, args.rtol, form == "fp64", mlp)
             infos.append(info)
             stats_all.append(stats)
             if k < args.steps - 1:
@@ -215,9 +264,12 @@ def main():
             "iterations": last["iterations"],
             "rel_residual": last["rel_residual"],
             "levels": last["levels"],
+            "used_learned": last["used_learned"],
+            "conv_factor": last["conv_factor"],
             "op_complexity": last["op_complexity"],
             "vcycle_ms": vc_ms,
             "vcycle_alg_GBps": vc_bytes / (vc_ms * 1e-3) / 1e9,
+            "vcycle_hbm_frac": vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "kernel_stats": stats_all[-1],
         }
         h.close()
@@ -225,7 +277,7 @@ def main():
     for form in forms:
         results[form]["rel_diff_vs_fp64"] = float(np.linalg.norm(xs[form] - xs[ref]) / np.linalg.norm(xs[ref]))
 
-    chosen = "fp32" if "fp32" in results else forms[0]
+    chosen = next((f for f in ("learned", "fp32") if f in results), forms[0])
     # roofline of the dominant finest-level kernel in the FP64 form (events over the timed steps)
     roof = None
     st = results.get("fp64", {}).get("kernel_stats")
@@ -242,7 +294,7 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": names[kind],
                 "launches": s["launches"], "avg_us": avg_ms * 1e3, "alg_bytes_per_launch": per_launch_bytes,
-                "traffic_source": tsrc}
+                "traffic_source": tsrc, "stream_copy_GBps": stream_copy_rate()}
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
@@ -258,7 +310,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 V-cycle in f64 FGMRES" if chosen == "fp32" else "f64",
+        "dtype": "f32 V-cycle in f64 FGMRES" if FORMS[chosen][0] == 1 else "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_LABEL.get(args.workload, args.workload), "name": args.workload,
                    "unknowns": system.n_dofs, "rtol": args.rtol, "krylov": "GMRES(30) right-preconditioned",

@@ -467,14 +467,18 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
         nxt->d[1] = d1;
         if (p.learned != 0 || p.omega_p != 0.0) {
             choose_weights(h, cur, G, lvl, s);
+            clk.mark("weights", lvl);
             for (int f = 0; f < 2; ++f) {
                 cur.P[f] = sa_prolongator(cur.A[f][f], h->fm.n_vec[f], G, q[f].p, cur.wp_agg.p, s);
                 cur.PT[f] = block_transpose(cur.P[f], s);
             }
+            clk.mark("smoothed P, P^T", lvl);
             for (int f = 0; f < 2; ++f)
                 for (int g = 0; g < 2; ++g) {
                     SetupBsr T = spgemm(cur.A[f][g], cur.P[g], s);
+                    clk.mark("A P", lvl);
                     nxt->A[f][g] = spgemm(cur.PT[f], T, s);
+                    clk.mark("P^T (A P)", lvl);
                 }
             cur.smoothed = true;
         }
@@ -544,8 +548,23 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
             BlockLevel& B = Lv.blk[f];
             B.d = Lv.d[f];
             if (f == 0) clk.mark("pattern download", l);
-            int ncol = greedy_colour(Lv.n, rp[f][f], ci[f][f], B.colour);
-            order_and_slice(B, Lv.n, ncol);
+            if (f == 1 && rp[1][1] == rp[0][0] && ci[1][1] == ci[0][0]) {
+                // same pattern: the same first-fit colouring, order and slices
+                const BlockLevel& B0 = Lv.blk[0];
+                B.colour = B0.colour;
+                B.n = B0.n;
+                B.n_colours = B0.n_colours;
+                B.colour_row = B0.colour_row;
+                B.perm = B0.perm;
+                B.iperm = B0.iperm;
+                B.h_row0 = B0.h_row0;
+                B.h_nrow = B0.h_nrow;
+                B.colour_slice = B0.colour_slice;
+                B.n_slices = B0.n_slices;
+            } else {
+                int ncol = greedy_colour(Lv.n, rp[f][f], ci[f][f], B.colour);
+                order_and_slice(B, Lv.n, ncol);
+            }
             B.row0.upload(B.h_row0, s);
             B.nrow.upload(B.h_nrow, s);
             B.d_perm.upload(B.perm, s);
@@ -682,6 +701,16 @@ static double resid_bytes(const Level& Lv, int s, bool with_b) {
         bytes += (double)B.n * B.d * s * (with_b ? 4 : 3);   // x_f, x_g gathered, (b), r
     }
     return bytes;
+}
+
+// smoothed transfer y (+)= A x in sliced form: structural values, stored block
+// indices, one 4-byte slice-row entry per output row, the input vector once,
+// the output written (and read when accumulating)
+static double xfer_bytes(const SellPart& P, int64_t rows_out, int64_t rows_in, int d, int s, bool accumulate) {
+    int64_t nz = 0, bl = 0;
+    P.stats(0, (int)P.h_width.size(), nz, bl);
+    return nz * (double)s + 4.0 * bl + 4.0 * rows_out + (double)rows_in * d * s +
+           (double)rows_out * d * s * (accumulate ? 2 : 1);
 }
 
 // ----------------------------------------------------------------------------
@@ -1127,9 +1156,12 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
             mbamg_params pf = *p;
             pf.learned = 0;
             pf.omega_p = 0.0;
+            PhaseClock jclk(s);
             auto hf = build(pf);
+            jclk.mark("fixed hierarchy built", 0);
             const double rl = probe_impl(h.get(), 10, 12345, s);
             const double rf = probe_impl(hf.get(), 10, 12345, s);
+            jclk.mark("judge probes", 0);
             h->judge_rho[0] = hf->judge_rho[0] = rl;
             h->judge_rho[1] = hf->judge_rho[1] = rf;
             if (!(rl < rf)) {
@@ -1308,9 +1340,16 @@ mbamg_status mbamg_vcycle_bytes(const mbamg_hierarchy* h, double* bytes) {
                 }
             }
             tot += resid_bytes(Lv, s, true);
-            const int64_t nf = (int64_t)Lv.n * (Lv.d[0] + Lv.d[1]), nc = (int64_t)Nx.n * (Nx.d[0] + Nx.d[1]);
-            tot += (double)s * (2.0 * nf + nc) + 4.0 * (Lv.n + Nx.n) * 2;   // restrict: r, q, b_c, members
-            tot += (double)s * (3.0 * nf + nc) + 4.0 * Lv.n * 2;            // prolong: q, x rw, x_c, map
+            if (Lv.smoothed) {
+                for (int f = 0; f < 2; ++f) {
+                    tot += xfer_bytes(Lv.blk[f].res, Nx.n, Lv.n, Lv.d[f], s, false);
+                    tot += xfer_bytes(Lv.blk[f].pro, Lv.n, Nx.n, Lv.d[f], s, true);
+                }
+            } else {
+                const int64_t nf = (int64_t)Lv.n * (Lv.d[0] + Lv.d[1]), nc = (int64_t)Nx.n * (Nx.d[0] + Nx.d[1]);
+                tot += (double)s * (2.0 * nf + nc) + 4.0 * (Lv.n + Nx.n) * 2;   // restrict: r, q, b_c, members
+                tot += (double)s * (3.0 * nf + nc) + 4.0 * Lv.n * 2;            // prolong: q, x rw, x_c, map
+            }
         }
         tot += 8.0 * (double)h->coarse_n * h->coarse_n + 2.0 * s * h->coarse_n;
         *bytes = tot;

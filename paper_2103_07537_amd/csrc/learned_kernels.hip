@@ -377,30 +377,49 @@ __global__ void k_sum_final(const double* part, int nb, double* out) {
     }
 }
 
-__global__ void k_features(int nagg, int n, const int32_t* __restrict__ agg, const int32_t* __restrict__ mptr,
-                           const int32_t* __restrict__ midx, BsrView A00, BsrView A01, BsrView A10, BsrView A11,
-                           int nv0, int nv1, const double* __restrict__ ld, const double* __restrict__ ld_sum,
-                           float level_feature, const float* __restrict__ mean, const float* __restrict__ stdv,
-                           float* __restrict__ out) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nagg) return;
+__device__ inline double wave_sum(double v) {
+    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+    for (int off = WAVE / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ inline double wave_min(double v) {
+    for (int off = WAVE / 2; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+    return v;
+}
+
+// One 64-lane wavefront per aggregate, one lane per member (strided), sums
+// and extrema combined across the wave.
+__global__ __launch_bounds__(WAVE) void k_features(int nagg, int n, const int32_t* __restrict__ agg,
+                                                   const int32_t* __restrict__ mptr, const int32_t* __restrict__ midx,
+                                                   BsrView A00, BsrView A01, BsrView A10, BsrView A11, int nv0,
+                                                   int nv1, const double* __restrict__ ld,
+                                                   const double* __restrict__ ld_sum, float level_feature,
+                                                   const float* __restrict__ mean, const float* __restrict__ stdv,
+                                                   float* __restrict__ out) {
+    const int k = blockIdx.x, lane = threadIdx.x;
     const int b = mptr[k], e = mptr[k + 1];
     const double m = (double)(e - b);
     const double mu = *ld_sum / n;
     double sld = 0, mx = -1e300, mn = 1e300;
-    for (int q = b; q < e; ++q) {
+    for (int q = b + lane; q < e; q += WAVE) {
         double v = ld[midx[q]];
         sld += v;
         mx = fmax(mx, v);
         mn = fmin(mn, v);
     }
+    sld = wave_sum(sld);
+    mx = wave_max(mx);
+    mn = wave_min(mn);
     const double mld = sld / m;
     double var = 0;
     double cmax = -1.0, cmin = 1e300;
     double tot = 0, outw = 0, f9 = 0, f10 = 0, f11 = 0;
     double a00 = 0, a01 = 0, a10 = 0, a11 = 0;
     const int d0 = A00.d;
-    for (int q = b; q < e; ++q) {
+    for (int q = b + lane; q < e; q += WAVE) {
         const int i = midx[q];
         var += (ld[i] - mld) * (ld[i] - mld);
         const double dv0 = vdiag(A00, i, nv0), dv1 = vdiag(A11, i, nv1);
@@ -434,24 +453,37 @@ __global__ void k_features(int nagg, int n, const int32_t* __restrict__ agg, con
         if (A01.rp) a01 += row_fro2(A01, i);
         if (A10.rp) a10 += row_fro2(A10, i);
     }
-    double F[12];
-    F[0] = mld - mu;
-    F[1] = sqrt(fmax(var / m, 0.0));
-    F[2] = mx - mn;
-    F[3] = (cmax >= 0.0 && cmin > 0.0) ? log(cmax) - log(cmin) : 0.0;
-    F[4] = m / ((double)n / nagg);
-    F[5] = tot > 0 ? outw / tot : 0.0;
-    F[6] = sqrt(a01) / sqrt(a00);
-    F[7] = sqrt(a10) / sqrt(a11);
-    F[8] = f9 / m;
-    F[9] = f10 / m;
-    F[10] = f11 / m;
-    F[11] = level_feature;
-    for (int c = 0; c < 12; ++c) {
-        float v = (float)F[c];
-        if (mean) v = (v - mean[c]) / stdv[c];
-        out[(int64_t)k * 12 + c] = v;
+    var = wave_sum(var);
+    cmax = wave_max(cmax);
+    cmin = wave_min(cmin);
+    tot = wave_sum(tot);
+    outw = wave_sum(outw);
+    f9 = wave_sum(f9);
+    f10 = wave_sum(f10);
+    f11 = wave_sum(f11);
+    a00 = wave_sum(a00);
+    a01 = wave_sum(a01);
+    a10 = wave_sum(a10);
+    a11 = wave_sum(a11);
+    if (lane >= 12) return;
+    double F;
+    switch (lane) {
+        case 0: F = mld - mu; break;
+        case 1: F = sqrt(fmax(var / m, 0.0)); break;
+        case 2: F = mx - mn; break;
+        case 3: F = (cmax >= 0.0 && cmin > 0.0) ? log(cmax) - log(cmin) : 0.0; break;
+        case 4: F = m / ((double)n / nagg); break;
+        case 5: F = tot > 0 ? outw / tot : 0.0; break;
+        case 6: F = sqrt(a01) / sqrt(a00); break;
+        case 7: F = sqrt(a10) / sqrt(a11); break;
+        case 8: F = f9 / m; break;
+        case 9: F = f10 / m; break;
+        case 10: F = f11 / m; break;
+        default: F = level_feature; break;
     }
+    float v = (float)F;
+    if (mean) v = (v - mean[lane]) / stdv[lane];
+    out[(int64_t)k * 12 + lane] = v;
 }
 
 // per-aggregate weights -> per-row smoother damping in colour order
@@ -506,8 +538,9 @@ void aggregate_features(int nagg, int n, const int32_t* agg, const int32_t* mptr
     k_logdiag<<<gridn(n), 256, 0, s>>>(n, A[0][0], nv0, ld.p);
     k_sum_partial<<<256, 256, 0, s>>>(ld.p, n, part.p);
     k_sum_final<<<1, 64, 0, s>>>(part.p, 256, tot.p);
-    k_features<<<gridn(nagg, 128), 128, 0, s>>>(nagg, n, agg, mptr, midx, A[0][0], A[0][1], A[1][0], A[1][1], nv0,
-                                                 nv1, ld.p, tot.p, (float)level / 4.0f, mean, stdv, out);
+    if (nagg > 0)
+        k_features<<<nagg, WAVE, 0, s>>>(nagg, n, agg, mptr, midx, A[0][0], A[0][1], A[1][0], A[1][1], nv0, nv1, ld.p,
+                                         tot.p, (float)level / 4.0f, mean, stdv, out);
     MB_LAUNCH_CHECK();
     MB_HIP(hipStreamSynchronize(s));
 }

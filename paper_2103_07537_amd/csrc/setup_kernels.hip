@@ -545,27 +545,6 @@ __global__ void k_place_cols(int n, const int32_t* rp, const int32_t* ci, const 
     }
 }
 
-// sort each transposed row by source row, then copy the transposed blocks
-__global__ void k_finish_transpose(int nc, int br, int bc, const int32_t* trp, int32_t* trow, int32_t* tsrc,
-                                   const double* val, double* tval) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nc) return;
-    const int b = trp[k], e = trp[k + 1];
-    for (int a = b + 1; a < e; ++a) {
-        int r = trow[a], s = tsrc[a];
-        int c = a - 1;
-        while (c >= b && trow[c] > r) { trow[c + 1] = trow[c]; tsrc[c + 1] = tsrc[c]; --c; }
-        trow[c + 1] = r;
-        tsrc[c + 1] = s;
-    }
-    for (int a = b; a < e; ++a) {
-        const double* src = val + (int64_t)tsrc[a] * br * bc;
-        double* dst = tval + (int64_t)a * br * bc;
-        for (int r = 0; r < br; ++r)
-            for (int c = 0; c < bc; ++c) dst[c * br + r] = src[r * bc + c];
-    }
-}
-
 // C = A B.  Row i of C lists the distinct columns reached through row i of A,
 // in increasing order; entry (r,c) of block (i,l) sums A[i,j][r][m]*B[j,l][m][c]
 // over the columns j of row i in increasing order and, for each, m increasing.
@@ -613,6 +592,197 @@ __global__ void k_spgemm(int n, int br, int bm, int bc, const int32_t* arp, cons
         prev = l;
     }
     if (!pass) cnt[i] = c;
+}
+
+// ----------------------------------------------------------------------------
+// Wave-per-row forms of the three products above.  One 64-lane wavefront (one
+// workgroup) owns one output row: the distinct output columns are gathered in
+// an LDS hash set, ranked into increasing order, and each lane then computes
+// whole output blocks with the same summation order as the thread-per-row
+// kernels (over the row's columns in increasing order, m increasing), so the
+// results are bit-identical.  Rows with more than KS_MAX distinct columns raise
+// an overflow flag and the host reruns that product with the thread-per-row
+// kernels.
+// ----------------------------------------------------------------------------
+constexpr int KS_LOG = 10;
+constexpr int KS_TABLE = 1 << KS_LOG;   // hash slots (at most half full)
+constexpr int KS_MAX = KS_TABLE / 2;    // distinct columns per row
+
+struct KeySet {
+    int32_t table[KS_TABLE];
+    int32_t keys[KS_MAX];
+    int32_t sorted[KS_MAX];
+    int32_t count;
+    int32_t overflow;
+};
+
+__device__ inline void ks_clear(KeySet& S, int lane) {
+    for (int t = lane; t < KS_TABLE; t += WAVE) S.table[t] = -1;
+    if (lane == 0) {
+        S.count = 0;
+        S.overflow = 0;
+    }
+    __syncthreads();
+}
+
+__device__ inline void ks_insert(KeySet& S, int key) {
+    uint32_t h = ((uint32_t)key * 2654435761u) >> (32 - KS_LOG);
+    for (int probe = 0; probe < KS_TABLE; ++probe) {
+        const int prev = atomicCAS(&S.table[h], -1, key);
+        if (prev == -1) {
+            const int idx = atomicAdd(&S.count, 1);
+            if (idx < KS_MAX) S.keys[idx] = key;
+            else S.overflow = 1;
+            return;
+        }
+        if (prev == key) return;
+        h = (h + 1) & (KS_TABLE - 1);
+    }
+    S.overflow = 1;
+}
+
+// number of distinct keys after the inserts, or -1 on overflow (call after a barrier)
+__device__ inline int ks_count(const KeySet& S) { return (S.overflow || S.count > KS_MAX) ? -1 : S.count; }
+
+// sorted[0..K) = keys in increasing order (keys are distinct)
+__device__ inline void ks_sort(KeySet& S, int lane, int K) {
+    for (int t = lane; t < K; t += WAVE) {
+        const int key = S.keys[t];
+        int r = 0;
+        for (int u = 0; u < K; ++u) r += S.keys[u] < key;
+        S.sorted[r] = key;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(WAVE) void k_spgemm_w(int br, int bm, int bc, const int32_t* __restrict__ arp,
+                                                   const int32_t* __restrict__ aci, const double* __restrict__ aval,
+                                                   const int32_t* __restrict__ brp, const int32_t* __restrict__ bci,
+                                                   const double* __restrict__ bval, int pass, int32_t* cnt,
+                                                   const int32_t* crp, int32_t* cci, double* cval, int32_t* overflow) {
+    __shared__ KeySet S;
+    const int i = blockIdx.x, lane = threadIdx.x;
+    ks_clear(S, lane);
+    const int ab = arp[i], ae = arp[i + 1];
+    for (int p = ab; p < ae; ++p) {
+        const int j = aci[p];
+        for (int q = brp[j] + lane; q < brp[j + 1]; q += WAVE) ks_insert(S, bci[q]);
+    }
+    __syncthreads();
+    const int K = ks_count(S);
+    if (K < 0) {
+        if (lane == 0) {
+            atomicOr(overflow, 1);
+            if (!pass) cnt[i] = 0;
+        }
+        return;
+    }
+    if (!pass) {
+        if (lane == 0) cnt[i] = K;
+        return;
+    }
+    ks_sort(S, lane, K);
+    const int out = crp[i];
+    for (int t = lane; t < K; t += WAVE) {
+        const int l = S.sorted[t];
+        double acc[16];
+        for (int e = 0; e < br * bc; ++e) acc[e] = 0.0;
+        for (int p = ab; p < ae; ++p) {
+            const int j = aci[p];
+            const int q = find_col(bci, brp[j], brp[j + 1], l);
+            if (q < 0) continue;
+            const double* a = aval + (int64_t)p * br * bm;
+            const double* bb = bval + (int64_t)q * bm * bc;
+            for (int r = 0; r < br; ++r)
+                for (int cc = 0; cc < bc; ++cc)
+                    for (int m = 0; m < bm; ++m) {
+                        double term = a[r * bm + m] * bb[m * bc + cc];
+                        acc[r * bc + cc] = acc[r * bc + cc] + term;
+                    }
+        }
+        cci[out + t] = l;
+        double* dst = cval + (int64_t)(out + t) * br * bc;
+        for (int e = 0; e < br * bc; ++e) dst[e] = acc[e];
+    }
+}
+
+__global__ __launch_bounds__(WAVE) void k_sa_prolong_w(int d, int nv, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                       const int32_t* __restrict__ agg, const double* __restrict__ q,
+                                                       const double* __restrict__ w, int pass, int32_t* cnt,
+                                                       const int32_t* prp, int32_t* pci, double* pval,
+                                                       int32_t* overflow) {
+    __shared__ KeySet S;
+    const int i = blockIdx.x, lane = threadIdx.x;
+    ks_clear(S, lane);
+    const int b = rp[i], e = rp[i + 1], bs = d * d, ai = agg[i];
+    for (int p = b + lane; p < e; p += WAVE) {
+        const int a = agg[ci[p]];
+        if (a == ai || w[a] != 0.0) ks_insert(S, a);
+    }
+    __syncthreads();
+    const int K = ks_count(S);
+    if (K < 0) {
+        if (lane == 0) {
+            atomicOr(overflow, 1);
+            if (!pass) cnt[i] = 0;
+        }
+        return;
+    }
+    if (!pass) {
+        if (lane == 0) cnt[i] = K;
+        return;
+    }
+    ks_sort(S, lane, K);
+    const int pd = find_col(ci, b, e, i);
+    const int out = prp[i];
+    for (int t = lane; t < K; t += WAVE) {
+        const int l = S.sorted[t];
+        double* blk = pval + (int64_t)(out + t) * bs;
+        pci[out + t] = l;
+        for (int ra = 0; ra < d; ++ra)
+            for (int cc = 0; cc < d; ++cc) {
+                double base = (l == ai && cc == ra) ? q[(int64_t)i * d + ra] : 0.0;
+                if (ra < nv && cc < nv) {
+                    double acc = 0.0;
+                    for (int p = b; p < e; ++p) {
+                        const int j = ci[p];
+                        if (agg[j] != l) continue;
+                        double term = val[(int64_t)p * bs + ra * d + cc] * q[(int64_t)j * d + cc];
+                        acc = acc + term;
+                    }
+                    double dg = pd >= 0 ? val[(int64_t)pd * bs + ra * d + ra] : 0.0;
+                    double tq = acc / dg;
+                    double u = w[l] * tq;
+                    blk[ra * d + cc] = base - u;
+                } else {
+                    blk[ra * d + cc] = base;
+                }
+            }
+    }
+}
+
+// transposed row k: entries placed in arbitrary order (trow = source row,
+// tsrc = source block) are ranked by source row (distinct within a row) and
+// written in increasing order with the blocks transposed
+__global__ __launch_bounds__(WAVE) void k_transpose_rank(int br, int bc, const int32_t* __restrict__ trp,
+                                                         const int32_t* __restrict__ trow,
+                                                         const int32_t* __restrict__ tsrc,
+                                                         const double* __restrict__ val, int32_t* __restrict__ tci,
+                                                         double* __restrict__ tval) {
+    const int k = blockIdx.x, lane = threadIdx.x;
+    const int b = trp[k], e = trp[k + 1];
+    for (int a = b + lane; a < e; a += WAVE) {
+        const int r = trow[a];
+        int rank = 0;
+        for (int u = b; u < e; ++u) rank += trow[u] < r;
+        const int dp = b + rank;
+        tci[dp] = r;
+        const double* src = val + (int64_t)tsrc[a] * br * bc;
+        double* dst = tval + (int64_t)dp * br * bc;
+        for (int r2 = 0; r2 < br; ++r2)
+            for (int c = 0; c < bc; ++c) dst[c * br + r2] = src[r2 * bc + c];
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -971,16 +1141,30 @@ SetupBsr sa_prolongator(const SetupBsr& A, int nv, const Aggregates& G, const do
     P.n_rows = n;
     P.n_cols = G.n_agg;
     P.br = P.bc = d;
-    DevBuf<int32_t> cnt(std::max(n, 1));
-    k_sa_prolong<<<grid_for(n, 128), 128, 0, s>>>(n, d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 0, cnt.p, nullptr,
-                                                 nullptr, nullptr);
-    MB_LAUNCH_CHECK();
+    DevBuf<int32_t> cnt(std::max(n, 1)), ovf(1);
+    MB_HIP(hipMemsetAsync(ovf.p, 0, sizeof(int32_t), s));
+    if (n > 0) {
+        k_sa_prolong_w<<<n, WAVE, 0, s>>>(d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 0, cnt.p, nullptr, nullptr,
+                                          nullptr, ovf.p);
+        MB_LAUNCH_CHECK();
+    }
+    const bool wide = ovf.download(s, 1)[0] != 0;
+    if (wide) {
+        k_sa_prolong<<<grid_for(n, 128), 128, 0, s>>>(n, d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 0, cnt.p,
+                                                     nullptr, nullptr, nullptr);
+        MB_LAUNCH_CHECK();
+    }
     P.rp.alloc(n + 1);
     P.nnzb = scan_exclusive(cnt.p, n, P.rp.p, s);
     P.ci.alloc(std::max<int64_t>(P.nnzb, 1));
     P.val.alloc(std::max<int64_t>(P.nnzb * d * d, 1));
-    k_sa_prolong<<<grid_for(n, 128), 128, 0, s>>>(n, d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 1, nullptr,
-                                                 P.rp.p, P.ci.p, P.val.p);
+    if (wide) {
+        k_sa_prolong<<<grid_for(n, 128), 128, 0, s>>>(n, d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 1, nullptr,
+                                                     P.rp.p, P.ci.p, P.val.p);
+    } else if (n > 0) {
+        k_sa_prolong_w<<<n, WAVE, 0, s>>>(d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 1, nullptr, P.rp.p, P.ci.p,
+                                          P.val.p, ovf.p);
+    }
     MB_LAUNCH_CHECK();
     return P;
 }
@@ -1004,8 +1188,13 @@ SetupBsr block_transpose(const SetupBsr& P, hipStream_t s) {
     DevBuf<int32_t> src(std::max<int64_t>(P.nnzb, 1));
     k_place_cols<<<grid_for(n), 256, 0, s>>>(n, P.rp.p, P.ci.p, T.rp.p, cursor.p, T.ci.p, src.p);
     T.val.alloc(std::max<int64_t>(P.nnzb * P.br * P.bc, 1));
-    k_finish_transpose<<<grid_for(nc, 64), 64, 0, s>>>(nc, P.br, P.bc, T.rp.p, T.ci.p, src.p, P.val.p, T.val.p);
-    MB_LAUNCH_CHECK();
+    if (nc > 0) {
+        DevBuf<int32_t> sorted_ci(std::max<int64_t>(P.nnzb, 1));
+        k_transpose_rank<<<nc, WAVE, 0, s>>>(P.br, P.bc, T.rp.p, T.ci.p, src.p, P.val.p, sorted_ci.p, T.val.p);
+        MB_LAUNCH_CHECK();
+        MB_HIP(hipStreamSynchronize(s));
+        T.ci = std::move(sorted_ci);
+    }
     MB_HIP(hipStreamSynchronize(s));
     return T;
 }
@@ -1018,7 +1207,7 @@ SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s) {
     C.n_cols = B.n_cols;
     C.br = A.br;
     C.bc = B.bc;
-    DevBuf<int32_t> cnt(std::max(n, 1));
+    DevBuf<int32_t> cnt(std::max(n, 1)), ovf(1);
     C.rp.alloc(n + 1);
     if (A.nnzb == 0 || B.nnzb == 0) {
         MB_HIP(hipMemsetAsync(C.rp.p, 0, sizeof(int32_t) * (n + 1), s));
@@ -1026,14 +1215,25 @@ SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s) {
         C.val.alloc(1);
         return C;
     }
-    k_spgemm<<<grid_for(n, 64), 64, 0, s>>>(n, A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, 0,
-                                           cnt.p, nullptr, nullptr, nullptr);
+    MB_HIP(hipMemsetAsync(ovf.p, 0, sizeof(int32_t), s));
+    k_spgemm_w<<<n, WAVE, 0, s>>>(A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, 0, cnt.p,
+                                  nullptr, nullptr, nullptr, ovf.p);
     MB_LAUNCH_CHECK();
+    const bool wide = ovf.download(s, 1)[0] != 0;
+    if (wide) {
+        k_spgemm<<<grid_for(n, 64), 64, 0, s>>>(n, A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p,
+                                               B.val.p, 0, cnt.p, nullptr, nullptr, nullptr);
+        MB_LAUNCH_CHECK();
+    }
     C.nnzb = scan_exclusive(cnt.p, n, C.rp.p, s);
     C.ci.alloc(std::max<int64_t>(C.nnzb, 1));
     C.val.alloc(std::max<int64_t>(C.nnzb * C.br * C.bc, 1));
-    k_spgemm<<<grid_for(n, 64), 64, 0, s>>>(n, A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, 1,
-                                           nullptr, C.rp.p, C.ci.p, C.val.p);
+    if (wide)
+        k_spgemm<<<grid_for(n, 64), 64, 0, s>>>(n, A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p,
+                                               B.val.p, 1, nullptr, C.rp.p, C.ci.p, C.val.p);
+    else
+        k_spgemm_w<<<n, WAVE, 0, s>>>(A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, 1, nullptr,
+                                      C.rp.p, C.ci.p, C.val.p, ovf.p);
     MB_LAUNCH_CHECK();
     return C;
 }
