@@ -98,11 +98,15 @@ def run_step(blocks, system, b, form, rtol, timing, mlp=None):
     from paper_2103_07537_amd import mbamg
     import torch
     precision, use_mlp = FORMS[form]
+    t0 = time.perf_counter()
     h = mbamg.Hierarchy(blocks, system.dofs, system.n_vec, precision=precision, mlp=mlp if use_mlp else None)
+    t1 = time.perf_counter()
     if timing:
         h.timing_enable(True)
     x = torch.zeros_like(b)
     info = h.solve(b, x, rtol=rtol)
+    t2 = time.perf_counter()
+    log(f"[bench]   {form}: hierarchy {1e3 * (t1 - t0):.1f} ms, solve {1e3 * (t2 - t1):.1f} ms (wall)")
     stats = None
     if timing:
         stats = {k: h.timing_get(k) for k in (0, 1, 2, 3)}
@@ -249,7 +253,9 @@ def main():
             infos.append(info)
             stats_all.append(stats)
             if k < args.steps - 1:
+                tc = time.perf_counter()
                 h.close()
+                log(f"[bench]   {form}: release {1e3 * (time.perf_counter() - tc):.1f} ms (wall)")
         torch.cuda.synchronize()
         t_total = time.perf_counter() - t_start
         ms_step = 1e3 * t_total / args.steps

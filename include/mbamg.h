@@ -23,6 +23,10 @@
  *   mbamg_setup deep-copies the blocks (host or device memory), so the caller
  *   may free them on return.  The hierarchy owns all of its device memory
  *   until mbamg_destroy.  Vector arguments are caller-owned device buffers.
+ *   Device memory the library releases (at mbamg_destroy, and the
+ *   temporaries of mbamg_setup) stays cached in the process for reuse by
+ *   later setups on the same device; mbamg_setup and mbamg_destroy
+ *   synchronise the device before cached memory is reused.
  *
  * Streams
  *   hip_stream may be NULL (the default stream).  mbamg_vcycle is

@@ -21,6 +21,7 @@ UNITS = [
     ("solve_kernels.hip", []),
     ("learned_kernels.hip", []),
     ("hierarchy.hip", []),
+    ("memory.hip", []),
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

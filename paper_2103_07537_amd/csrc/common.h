@@ -37,6 +37,17 @@ struct Error : std::runtime_error {
 
 constexpr int WAVE = 64;
 
+// Device memory comes from a process-wide cache (memory.hip): a freed block
+// is parked as pending in a per-thread list and becomes reusable only at a
+// point where the caller has made the whole device idle (pool_device_idle),
+// so a block is never handed out while a kernel may still use it.  Cached
+// blocks stay mapped, which keeps the large allocations of repeated setups
+// off the driver's map/unmap path.
+void* dev_alloc(size_t bytes);
+void dev_free(void* p, size_t bytes);
+// Call right after hipDeviceSynchronize(): this thread's pending blocks become reusable.
+void pool_device_idle();
+
 // Owning device buffer.
 template <class T>
 struct DevBuf {
@@ -54,19 +65,13 @@ struct DevBuf {
     ~DevBuf() { release(); }
     void alloc(size_t count) {
         release();
-        n = count;
         if (count) {
-            hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
-            if (e != hipSuccess) {
-                p = nullptr;
-                n = 0;
-                (void)hipGetLastError();
-                throw Error(MBAMG_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-            }
+            p = static_cast<T*>(dev_alloc(count * sizeof(T)));
+            n = count;
         }
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) dev_free(p, n * sizeof(T));
         p = nullptr;
         n = 0;
     }

@@ -75,6 +75,7 @@ struct BlockLevel {
     DevBuf<float> w_row32;
     // smoothed transfers: P rows of this level, P^T rows of the next level (sliced by the next level)
     SellPart pro, res;
+    int pro_split = 1, res_split = 1;          // waves per slice in the transfer kernels
     // transfer to the next level (colour orders of both levels)
     DevBuf<int32_t> agg_p, mem_ptr, mem_idx;
     DevBuf<double> q64;
@@ -321,6 +322,22 @@ static void order_and_slice(BlockLevel& B, int n, int ncol) {
 
 enum class PartKind { Off = 0, Cpl = 1, Diag = 2, Dinv = 3 };
 
+// Waves per slice (1..16) for a launch over `slices` slices of `width` slots
+// on average: wide slices are shared by more waves until the launch has
+// about 2048 waves, keeping at least 4 slots per wave.
+static int slot_split(double slices, double width) {
+    int P = 1;
+    while (P < 16 && slices * P < 2048 && width >= 8.0 * P) P *= 2;
+    return P;
+}
+
+static int transfer_split(const SellPart& P, int n_slices) {
+    int64_t slots = 0;
+    for (int w : P.h_width) slots += w;
+    const double avg = n_slices ? (double)slots / n_slices : 0.0;
+    return slot_split(n_slices, avg);
+}
+
 // Pack one part of block row f into masked slices on the device.  A: the
 // natural-order source block (unused for Dinv); val: its values, or the dense
 // per-node inverse array for Dinv; col_iperm: natural column node -> colour
@@ -398,8 +415,7 @@ static void choose_weights(mbamg_hierarchy* h, Level& cur, const Aggregates& G, 
                        nullptr, cur.feat.p, s);
     if (p.learned == 1) {
         DevBuf<float> xn((size_t)std::max(nc, 1) * N_FEATURES), out2((size_t)std::max(nc, 1) * 2);
-        aggregate_features(nc, cur.n, G.agg.p, G.mptr.p, G.midx.p, A, h->fm.n_vec[0], h->fm.n_vec[1], lvl,
-                           h->mlp.p + N_MLP_PARAMS, h->mlp.p + N_MLP_PARAMS + N_FEATURES, xn.p, s);
+        normalize_features(nc, cur.feat.p, h->mlp.p + N_MLP_PARAMS, h->mlp.p + N_MLP_PARAMS + N_FEATURES, xn.p, s);
         mlp_forward(h->mlp.p, xn.p, nc, out2.p, s);
         split_weights(nc, out2.p, cur.wp_agg.p, cur.ws_agg.p, s);
         MB_HIP(hipStreamSynchronize(s));
@@ -465,6 +481,21 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
         nxt->n = nc;
         nxt->d[0] = d0;
         nxt->d[1] = d1;
+        // A_c[f][g] = P_f^T A_fg P_g.  The four block pairs usually share one
+        // pattern; the symbolic phase then runs once and the rest reuse it.
+        auto galerkin_all = [&](const SetupBsr (&P)[2], const SetupBsr (&PT)[2]) {
+            const bool sameP = same_pattern(P[0], P[1], s);
+            SetupBsr T00;
+            for (int f = 0; f < 2; ++f)
+                for (int g = 0; g < 2; ++g) {
+                    const bool first = f == 0 && g == 0;
+                    const bool reuse = !first && (g == 0 || sameP) && (f == 0 || sameP) &&
+                                       same_pattern(cur.A[f][g], cur.A[0][0], s);
+                    SetupBsr T = spgemm(cur.A[f][g], P[g], s, reuse ? &T00 : nullptr);
+                    nxt->A[f][g] = spgemm(PT[f], T, s, reuse ? &nxt->A[0][0] : nullptr);
+                    if (first) T00 = std::move(T);
+                }
+        };
         if (p.learned != 0 || p.omega_p != 0.0) {
             choose_weights(h, cur, G, lvl, s);
             clk.mark("weights", lvl);
@@ -473,30 +504,16 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
                 cur.PT[f] = block_transpose(cur.P[f], s);
             }
             clk.mark("smoothed P, P^T", lvl);
-            for (int f = 0; f < 2; ++f)
-                for (int g = 0; g < 2; ++g) {
-                    SetupBsr T = spgemm(cur.A[f][g], cur.P[g], s);
-                    clk.mark("A P", lvl);
-                    nxt->A[f][g] = spgemm(cur.PT[f], T, s);
-                    clk.mark("P^T (A P)", lvl);
-                }
+            galerkin_all(cur.P, cur.PT);
             cur.smoothed = true;
-        }
-        for (int f = 0; f < 2 && !cur.smoothed; ++f)
-            for (int g = 0; g < 2; ++g) {
-                if (cur.A[f][g].nnzb == 0) {
-                    SetupBsr& Z = nxt->A[f][g];
-                    Z.n_rows = Z.n_cols = nc;
-                    Z.br = h->d[f];
-                    Z.bc = h->d[g];
-                    Z.rp.alloc(nc + 1);
-                    MB_HIP(hipMemsetAsync(Z.rp.p, 0, sizeof(int32_t) * (nc + 1), s));
-                    Z.ci.alloc(1);
-                    Z.val.alloc(1);
-                    continue;
-                }
-                nxt->A[f][g] = galerkin(cur.A[f][g], G, q[f].p, q[g].p, s);
+        } else {
+            SetupBsr P[2], PT[2];
+            for (int f = 0; f < 2; ++f) {
+                P[f] = tentative_bsr(G, h->d[f], q[f].p, s);
+                PT[f] = block_transpose(P[f], s);
             }
+            galerkin_all(P, PT);
+        }
         clk.mark("tentative+galerkin", lvl);
         // keep q on the fine level (natural order) for the transfer maps
         cur.blk[0].q64 = std::move(q[0]);
@@ -600,9 +617,10 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
             // fill the chip and the rows are wide enough to share
             const double avg_width = B.n_slices ? (double)slots / B.n_slices : 0.0;
             const double per_colour = (double)B.n_slices / std::max(1, B.n_colours);
-            B.split = 1;
-            if (per_colour < 2048 && avg_width >= 8) B.split = 2;
-            if (per_colour < 1024 && avg_width >= 16) B.split = 4;
+            B.split = slot_split(per_colour, avg_width);
+            if (clk.on)
+                std::fprintf(stderr, "[mbamg setup] level %d block %d: %d nodes, %d colours, %d slices, %.1f slots/slice, "
+                             "split %d\n", l, f, Lv.n, B.n_colours, B.n_slices, avg_width, B.split);
         }
         clk.mark("sliced parts", l);
         // transfers between this level's and the next level's colour orders
@@ -611,6 +629,8 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
             BlockLevel& C = Nx.blk[f];
             build_part(B.pro, PartKind::Cpl, B, &Lv.P[f], C.d_iperm.p, Lv.P[f].val.p, B.d, B.d, want32, s);
             build_part(B.res, PartKind::Cpl, C, &Lv.PT[f], B.d_iperm.p, Lv.PT[f].val.p, B.d, B.d, want32, s);
+            B.pro_split = transfer_split(B.pro, B.n_slices);
+            B.res_split = transfer_split(B.res, C.n_slices);
         }
         for (int f = 0; f < 2 && Lv.damped; ++f) {
             BlockLevel& B = Lv.blk[f];
@@ -836,7 +856,7 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
             a.y[f] = C.b.p + (f ? nc0 : 0);
         }
         a.accumulate = 0;
-        launch_xfer<T>(Lv.d[0], a, s);
+        launch_xfer<T>(Lv.d[0], Lv.blk[0].res_split, a, s);
     } else {
         TransferArgs<T> a{};
         for (int f = 0; f < 2; ++f) {
@@ -860,7 +880,7 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
             a.y[f] = buf[cur] + (f ? n0 : 0);
         }
         a.accumulate = 1;
-        launch_xfer<T>(Lv.d[0], a, s);
+        launch_xfer<T>(Lv.d[0], Lv.blk[0].pro_split, a, s);
     } else {
         TransferArgs<T> a{};
         for (int f = 0; f < 2; ++f) {
@@ -1147,6 +1167,9 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
             h->d[1] = fm->dofs[1];
             if (pp.learned == 1) h->mlp.upload(pp.mlp, N_MLP_PARAMS + 2 * N_FEATURES, s);
             setup_impl(h.get(), A_blocks, s);
+            // the build's temporaries are idle now and can serve the next allocations
+            MB_HIP(hipDeviceSynchronize());
+            pool_device_idle();
             return h;
         };
         auto h = build(*p);
@@ -1171,6 +1194,8 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
                 h->info.used_learned = 1;
             }
         }
+        MB_HIP(hipDeviceSynchronize());
+        pool_device_idle();
         auto t1 = std::chrono::steady_clock::now();
         h->t_setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
         h->info.t_setup_ms = h->t_setup_ms;
@@ -1226,7 +1251,10 @@ mbamg_status mbamg_get_info(const mbamg_hierarchy* h, mbamg_info* info) {
     return MBAMG_OK;
 }
 
-void mbamg_destroy(mbamg_hierarchy* h) { delete h; }
+void mbamg_destroy(mbamg_hierarchy* h) {
+    delete h;   // the destructor synchronises the device before its buffers are released
+    pool_device_idle();
+}
 
 mbamg_status mbamg_num_levels(const mbamg_hierarchy* h, int32_t* n_levels) {
     if (!h || !n_levels) { g_last_error = "NULL argument"; return MBAMG_E_INVALID; }

@@ -27,6 +27,8 @@ void mlp_adam(float* th, const float* g, float* m, float* v, int64_t step, float
 void aggregate_features(int nagg, int n, const int32_t* agg, const int32_t* mptr, const int32_t* midx,
                         const BsrView (&A)[2][2], int nv0, int nv1, int level, const float* mean, const float* stdv,
                         float* out, hipStream_t s);
+// out = (raw - mean) / stdv per feature column, in FP32 (the normalisation aggregate_features applies)
+void normalize_features(int nagg, const float* raw, const float* mean, const float* stdv, float* out, hipStream_t s);
 void split_weights(int nagg, const float* out2, double* wp, double* ws, hipStream_t s);
 template <class T>
 void row_damping(int n, const int32_t* perm, const int32_t* agg, const double* ws, T* w_row, hipStream_t s);

@@ -545,6 +545,20 @@ void aggregate_features(int nagg, int n, const int32_t* agg, const int32_t* mptr
     MB_HIP(hipStreamSynchronize(s));
 }
 
+__global__ void k_normalize_features(int64_t n, const float* raw, const float* mean, const float* stdv, float* out) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int c = (int)(t % N_FEATURES);
+    out[t] = (raw[t] - mean[c]) / stdv[c];
+}
+
+void normalize_features(int nagg, const float* raw, const float* mean, const float* stdv, float* out, hipStream_t s) {
+    const int64_t n = (int64_t)nagg * N_FEATURES;
+    if (n == 0) return;
+    k_normalize_features<<<gridn(n), 256, 0, s>>>(n, raw, mean, stdv, out);
+    MB_LAUNCH_CHECK();
+}
+
 void split_weights(int nagg, const float* out2, double* wp, double* ws, hipStream_t s) {
     k_split_weights<<<gridn(nagg), 256, 0, s>>>(nagg, out2, wp, ws);
     MB_LAUNCH_CHECK();

@@ -1,0 +1,105 @@
+// Caching device allocator behind DevBuf.
+//
+// Blocks are rounded up to 1/8-octave size classes (at least 4 KiB) and kept
+// per device in free lists keyed by their rounded size.  A freed block first
+// goes to the freeing thread's pending list: the library only knows that the
+// block is idle once the device has been synchronised, so pending blocks are
+// moved to the free lists by pool_device_idle(), which the library calls right
+// after hipDeviceSynchronize().  When hipMalloc fails, the cached free blocks
+// are released and the allocation is retried once.
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+
+namespace mbamg {
+namespace {
+
+struct Block {
+    int dev;
+    size_t bytes;
+    void* p;
+};
+
+struct Pool {
+    std::mutex m;
+    std::unordered_map<int, std::multimap<size_t, void*>> free_lists;   // device -> (size class -> block)
+};
+
+Pool& pool() {
+    static Pool* p = new Pool;   // never destroyed: blocks may be freed during process teardown
+    return *p;
+}
+
+thread_local std::vector<Block> t_pending;
+
+size_t size_class(size_t b) {
+    if (b <= 4096) return 4096;
+    int e = 63 - __builtin_clzll((unsigned long long)b);
+    size_t step = (size_t)1 << (e > 3 ? e - 3 : 0);
+    if (step < 4096) step = 4096;
+    return (b + step - 1) / step * step;
+}
+
+int current_device() {
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess) {
+        (void)hipGetLastError();
+        d = 0;
+    }
+    return d;
+}
+
+void release_cached(int dev) {
+    std::multimap<size_t, void*> drop;
+    {
+        std::lock_guard<std::mutex> g(pool().m);
+        drop.swap(pool().free_lists[dev]);
+    }
+    for (auto& kv : drop) (void)hipFree(kv.second);
+}
+
+}  // namespace
+
+void* dev_alloc(size_t bytes) {
+    const size_t r = size_class(bytes);
+    const int dev = current_device();
+    {
+        std::lock_guard<std::mutex> g(pool().m);
+        auto& fl = pool().free_lists[dev];
+        auto it = fl.find(r);
+        if (it != fl.end()) {
+            void* p = it->second;
+            fl.erase(it);
+            return p;
+        }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, r);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        release_cached(dev);
+        e = hipMalloc(&p, r);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(MBAMG_E_NOMEM, "hipMalloc of " + std::to_string(r) + " bytes failed");
+        }
+    }
+    return p;
+}
+
+void dev_free(void* p, size_t bytes) {
+    if (!p) return;
+    t_pending.push_back({current_device(), size_class(bytes), p});
+}
+
+void pool_device_idle() {
+    if (t_pending.empty()) return;
+    std::lock_guard<std::mutex> g(pool().m);
+    for (const Block& b : t_pending) pool().free_lists[b.dev].emplace(b.bytes, b.p);
+    t_pending.clear();
+}
+
+}  // namespace mbamg

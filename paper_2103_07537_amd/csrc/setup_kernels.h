@@ -34,8 +34,8 @@ Strength build_strength(const SetupBsr& A, double theta, hipStream_t s);
 Aggregates build_aggregates(const Strength& S, uint64_t seed, int level, hipStream_t s);
 void fill_ones(double* a, int64_t n, hipStream_t s);
 void build_tentative(const Aggregates& G, int d, const double* B, double* q, double* Bc, hipStream_t s);
-SetupBsr galerkin(const SetupBsr& A, const Aggregates& G, const double* q_row, const double* q_col,
-                  hipStream_t s);
+// the tentative prolongator as a block matrix: row i holds diag(q_i) in column agg(i)
+SetupBsr tentative_bsr(const Aggregates& G, int d, const double* q, hipStream_t s);
 void build_dinv(const SetupBsr& A, double* dinv, hipStream_t s);
 void sell_masks(int64_t n_slots, int bs, const int64_t* src, const double* val, uint32_t* mask, uint32_t* slot_nz,
                 hipStream_t s);
@@ -46,7 +46,11 @@ void cast_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
 SetupBsr sa_prolongator(const SetupBsr& A, int nv, const Aggregates& G, const double* q, const double* w,
                         hipStream_t s);
 SetupBsr block_transpose(const SetupBsr& P, hipStream_t s);
-SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s);
+// C = A B; `like`, when given, is a product whose operands had the same
+// patterns as A and B: its pattern is reused and only the values are computed
+SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s, const SetupBsr* like = nullptr);
+// true when X and Y have identical block patterns (synchronous)
+bool same_pattern(const SetupBsr& X, const SetupBsr& Y, hipStream_t s);
 // device construction of the sliced smoother format (see hierarchy.hip)
 void part_layout(int n, int ns, int kind, const int32_t* perm, const int32_t* rp, const int32_t* ci,
                  const int32_t* row0, const int32_t* nrow, DevBuf<int32_t>& width, DevBuf<int32_t>& coff32,

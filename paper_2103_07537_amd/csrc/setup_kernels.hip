@@ -292,96 +292,24 @@ __global__ void k_tentative(int nagg, int d, const int32_t* mptr, const int32_t*
     }
 }
 
+// the tentative prolongator as a block matrix: row i holds one block, in
+// column agg(i), equal to diag(q_i)
+__global__ void k_tentative_bsr(int n, int d, const int32_t* agg, const double* q, int32_t* rp, int32_t* ci,
+                                double* val) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    rp[i] = i;
+    if (i == n) return;
+    ci[i] = agg[i];
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) val[(int64_t)i * d * d + r * d + c] = r == c ? q[(int64_t)i * d + r] : 0.0;
+}
+
 __global__ void k_fill_f64(double* a, int64_t n, double v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = v;
 }
 
-// ----------------------------------------------------------------------------
-// Galerkin product, stage 1: T = A P_g.  One thread per fine row; the row's
-// distinct column aggregates are visited in increasing order and each block
-// entry sums A_ij[r,c] * q_g[j,c] over the row's columns j in increasing order.
-// ----------------------------------------------------------------------------
-__global__ void k_rap1(int n, int br, int bc, const int32_t* rp, const int32_t* ci, const double* val,
-                       const int32_t* agg, const double* qc, int pass, int32_t* cnt, const int32_t* trp,
-                       int32_t* tci, double* tval) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int b = rp[i], e = rp[i + 1], bs = br * bc;
-    int prev = -1, out = pass ? trp[i] : 0, c = 0;
-    while (true) {
-        int l = INT_MAX;
-        for (int p = b; p < e; ++p) {
-            int a = agg[ci[p]];
-            if (a > prev && a < l) l = a;
-        }
-        if (l == INT_MAX) break;
-        if (pass) {
-            double* acc = tval + (int64_t)(out + c) * bs;
-            tci[out + c] = l;
-            for (int k = 0; k < bs; ++k) acc[k] = 0.0;
-            for (int p = b; p < e; ++p) {
-                int j = ci[p];
-                if (agg[j] != l) continue;
-                const double* a = val + (int64_t)p * bs;
-                const double* qj = qc + (int64_t)j * bc;
-                for (int r = 0; r < br; ++r)
-                    for (int cc = 0; cc < bc; ++cc) {
-                        double term = a[r * bc + cc] * qj[cc];
-                        acc[r * bc + cc] = acc[r * bc + cc] + term;
-                    }
-            }
-        }
-        ++c;
-        prev = l;
-    }
-    if (!pass) cnt[i] = c;
-}
-
-// Stage 2: A_c = P_f^T T.  One thread per coarse row k; distinct columns in
-// increasing order; each entry sums q_f[i,r] * T[i,l][r,c] over the members i
-// of aggregate k in increasing order.
-__global__ void k_rap2(int nc, int br, int bc, const int32_t* mptr, const int32_t* midx, const int32_t* trp,
-                       const int32_t* tci, const double* tval, const double* qr, int pass, int32_t* cnt,
-                       const int32_t* crp, int32_t* cci, double* cval) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nc) return;
-    const int mb = mptr[k], me = mptr[k + 1], bs = br * bc;
-    int prev = -1, out = pass ? crp[k] : 0, c = 0;
-    while (true) {
-        int l = INT_MAX;
-        for (int m = mb; m < me; ++m) {
-            int i = midx[m];
-            for (int p = trp[i]; p < trp[i + 1]; ++p) {
-                int a = tci[p];
-                if (a > prev && a < l) l = a;
-            }
-        }
-        if (l == INT_MAX) break;
-        if (pass) {
-            double* acc = cval + (int64_t)(out + c) * bs;
-            cci[out + c] = l;
-            for (int e = 0; e < bs; ++e) acc[e] = 0.0;
-            for (int m = mb; m < me; ++m) {
-                int i = midx[m];
-                for (int p = trp[i]; p < trp[i + 1]; ++p) {
-                    if (tci[p] != l) continue;
-                    const double* t = tval + (int64_t)p * bs;
-                    for (int r = 0; r < br; ++r) {
-                        double qv = qr[(int64_t)i * br + r];
-                        for (int cc = 0; cc < bc; ++cc) {
-                            double term = qv * t[r * bc + cc];
-                            acc[r * bc + cc] = acc[r * bc + cc] + term;
-                        }
-                    }
-                }
-            }
-        }
-        ++c;
-        prev = l;
-    }
-    if (!pass) cnt[k] = c;
-}
 
 // ----------------------------------------------------------------------------
 // nodal block inverses: LU with partial pivoting of the diagonal block, d <= 8
@@ -595,13 +523,13 @@ __global__ void k_spgemm(int n, int br, int bm, int bc, const int32_t* arp, cons
 }
 
 // ----------------------------------------------------------------------------
-// Wave-per-row forms of the three products above.  One 64-lane wavefront (one
-// workgroup) owns one output row: the distinct output columns are gathered in
-// an LDS hash set, ranked into increasing order, and each lane then computes
-// whole output blocks with the same summation order as the thread-per-row
-// kernels (over the row's columns in increasing order, m increasing), so the
-// results are bit-identical.  Rows with more than KS_MAX distinct columns raise
-// an overflow flag and the host reruns that product with the thread-per-row
+// Wave-per-row forms of the products above.  One 64-lane wavefront (one
+// workgroup) owns one output row: its distinct output columns are gathered in
+// an LDS hash set and ranked into increasing order.  Values are computed with
+// the same summation order as the thread-per-row kernels (over the row's
+// columns in increasing order, m increasing), so the results are
+// bit-identical.  Rows with more than KS_MAX distinct columns raise an
+// overflow flag and the host reruns that product with the thread-per-row
 // kernels.
 // ----------------------------------------------------------------------------
 constexpr int KS_LOG = 10;
@@ -614,29 +542,36 @@ struct KeySet {
     int32_t sorted[KS_MAX];
     int32_t count;
     int32_t overflow;
+    int32_t tlog;
 };
 
-__device__ inline void ks_clear(KeySet& S, int lane) {
-    for (int t = lane; t < KS_TABLE; t += WAVE) S.table[t] = -1;
+// a table of 2^tlog slots, sized so that `cand` insertions fill at most half
+__device__ inline void ks_clear(KeySet& S, int lane, int64_t cand) {
+    int tlog = 6;
+    while (tlog < KS_LOG && ((int64_t)1 << (tlog - 1)) < cand) ++tlog;
+    for (int t = lane; t < (1 << tlog); t += WAVE) S.table[t] = -1;
     if (lane == 0) {
         S.count = 0;
         S.overflow = 0;
+        S.tlog = tlog;
     }
     __syncthreads();
 }
 
 __device__ inline void ks_insert(KeySet& S, int key) {
-    uint32_t h = ((uint32_t)key * 2654435761u) >> (32 - KS_LOG);
-    for (int probe = 0; probe < KS_TABLE; ++probe) {
+    const int tlog = S.tlog;
+    const uint32_t mask = (1u << tlog) - 1;
+    uint32_t h = ((uint32_t)key * 2654435761u) >> (32 - tlog);
+    for (int probe = 0; probe <= (int)mask; ++probe) {
         const int prev = atomicCAS(&S.table[h], -1, key);
         if (prev == -1) {
             const int idx = atomicAdd(&S.count, 1);
-            if (idx < KS_MAX) S.keys[idx] = key;
+            if (idx < (1 << (tlog - 1))) S.keys[idx] = key;
             else S.overflow = 1;
             return;
         }
         if (prev == key) return;
-        h = (h + 1) & (KS_TABLE - 1);
+        h = (h + 1) & mask;
     }
     S.overflow = 1;
 }
@@ -655,15 +590,21 @@ __device__ inline void ks_sort(KeySet& S, int lane, int K) {
     __syncthreads();
 }
 
-__global__ __launch_bounds__(WAVE) void k_spgemm_w(int br, int bm, int bc, const int32_t* __restrict__ arp,
-                                                   const int32_t* __restrict__ aci, const double* __restrict__ aval,
-                                                   const int32_t* __restrict__ brp, const int32_t* __restrict__ bci,
-                                                   const double* __restrict__ bval, int pass, int32_t* cnt,
-                                                   const int32_t* crp, int32_t* cci, double* cval, int32_t* overflow) {
+// Pattern of C = A B: pass 0 counts each row's distinct columns, pass 1
+// writes them in increasing order.
+__global__ __launch_bounds__(WAVE) void k_spgemm_sym(const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                                                     const int32_t* __restrict__ brp, const int32_t* __restrict__ bci,
+                                                     int pass, int32_t* cnt, const int32_t* crp, int32_t* cci,
+                                                     int32_t* overflow) {
     __shared__ KeySet S;
     const int i = blockIdx.x, lane = threadIdx.x;
-    ks_clear(S, lane);
     const int ab = arp[i], ae = arp[i + 1];
+    int64_t cand = 0;
+    for (int p = ab; p < ae; ++p) {
+        const int j = aci[p];
+        cand += brp[j + 1] - brp[j];
+    }
+    ks_clear(S, lane, cand);
     for (int p = ab; p < ae; ++p) {
         const int j = aci[p];
         for (int q = brp[j] + lane; q < brp[j + 1]; q += WAVE) ks_insert(S, bci[q]);
@@ -683,27 +624,91 @@ __global__ __launch_bounds__(WAVE) void k_spgemm_w(int br, int bm, int bc, const
     }
     ks_sort(S, lane, K);
     const int out = crp[i];
-    for (int t = lane; t < K; t += WAVE) {
-        const int l = S.sorted[t];
-        double acc[16];
-        for (int e = 0; e < br * bc; ++e) acc[e] = 0.0;
-        for (int p = ab; p < ae; ++p) {
-            const int j = aci[p];
-            const int q = find_col(bci, brp[j], brp[j + 1], l);
-            if (q < 0) continue;
-            const double* a = aval + (int64_t)p * br * bm;
-            const double* bb = bval + (int64_t)q * bm * bc;
-            for (int r = 0; r < br; ++r)
-                for (int cc = 0; cc < bc; ++cc)
-                    for (int m = 0; m < bm; ++m) {
-                        double term = a[r * bm + m] * bb[m * bc + cc];
-                        acc[r * bc + cc] = acc[r * bc + cc] + term;
-                    }
-        }
-        cci[out + t] = l;
-        double* dst = cval + (int64_t)(out + t) * br * bc;
-        for (int e = 0; e < br * bc; ++e) dst[e] = acc[e];
+    for (int t = lane; t < K; t += WAVE) cci[out + t] = S.sorted[t];
+}
+
+__global__ void k_row_of(int n, const int32_t* __restrict__ rp, int32_t* __restrict__ row) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) row[p] = i;
+}
+
+// Values of C = A B on a known pattern, one thread per output block (i, l):
+// the sum over the columns j of row i of A in increasing order and, for each,
+// m increasing -- the order of the thread-per-row kernel.
+template <int BR, int BM, int BC>
+__global__ void k_spgemm_num(int64_t nnz, const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                             const double* __restrict__ aval, const int32_t* __restrict__ brp,
+                             const int32_t* __restrict__ bci, const double* __restrict__ bval,
+                             const int32_t* __restrict__ crow, const int32_t* __restrict__ cci,
+                             double* __restrict__ cval) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnz) return;
+    const int i = crow[k], l = cci[k];
+    double acc[BR * BC];
+#pragma unroll
+    for (int e = 0; e < BR * BC; ++e) acc[e] = 0.0;
+    for (int p = arp[i]; p < arp[i + 1]; ++p) {
+        const int j = aci[p];
+        const int q = find_col(bci, brp[j], brp[j + 1], l);
+        if (q < 0) continue;
+        double a[BR * BM], bb[BM * BC];
+#pragma unroll
+        for (int e = 0; e < BR * BM; ++e) a[e] = aval[(int64_t)p * BR * BM + e];
+#pragma unroll
+        for (int e = 0; e < BM * BC; ++e) bb[e] = bval[(int64_t)q * BM * BC + e];
+#pragma unroll
+        for (int r = 0; r < BR; ++r)
+#pragma unroll
+            for (int cc = 0; cc < BC; ++cc)
+#pragma unroll
+                for (int m = 0; m < BM; ++m) {
+                    double term = a[r * BM + m] * bb[m * BC + cc];
+                    acc[r * BC + cc] = acc[r * BC + cc] + term;
+                }
     }
+    double* dst = cval + k * BR * BC;
+#pragma unroll
+    for (int e = 0; e < BR * BC; ++e) dst[e] = acc[e];
+}
+
+// the same for any block shape with at most 16 entries per output block
+__global__ void k_spgemm_num_any(int64_t nnz, int br, int bm, int bc, const int32_t* __restrict__ arp,
+                                 const int32_t* __restrict__ aci, const double* __restrict__ aval,
+                                 const int32_t* __restrict__ brp, const int32_t* __restrict__ bci,
+                                 const double* __restrict__ bval, const int32_t* __restrict__ crow,
+                                 const int32_t* __restrict__ cci, double* __restrict__ cval) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnz) return;
+    const int i = crow[k], l = cci[k];
+    double acc[16];
+    for (int e = 0; e < br * bc; ++e) acc[e] = 0.0;
+    for (int p = arp[i]; p < arp[i + 1]; ++p) {
+        const int j = aci[p];
+        const int q = find_col(bci, brp[j], brp[j + 1], l);
+        if (q < 0) continue;
+        const double* a = aval + (int64_t)p * br * bm;
+        const double* bb = bval + (int64_t)q * bm * bc;
+        for (int r = 0; r < br; ++r)
+            for (int cc = 0; cc < bc; ++cc)
+                for (int m = 0; m < bm; ++m) {
+                    double term = a[r * bm + m] * bb[m * bc + cc];
+                    acc[r * bc + cc] = acc[r * bc + cc] + term;
+                }
+    }
+    double* dst = cval + k * br * bc;
+    for (int e = 0; e < br * bc; ++e) dst[e] = acc[e];
+}
+
+// flag (initially 1) is cleared when the two patterns differ in any row
+__global__ void k_same_pattern(int n, const int32_t* __restrict__ rpa, const int32_t* __restrict__ cia,
+                               const int32_t* __restrict__ rpb, const int32_t* __restrict__ cib, int32_t* flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a0 = rpa[i], a1 = rpa[i + 1];
+    bool same = a0 == rpb[i] && a1 == rpb[i + 1];
+    for (int p = a0; same && p < a1; ++p) same = cia[p] == cib[p];
+    if (!same) atomicAnd(flag, 0);
 }
 
 __global__ __launch_bounds__(WAVE) void k_sa_prolong_w(int d, int nv, const int32_t* __restrict__ rp,
@@ -714,8 +719,8 @@ __global__ __launch_bounds__(WAVE) void k_sa_prolong_w(int d, int nv, const int3
                                                        int32_t* overflow) {
     __shared__ KeySet S;
     const int i = blockIdx.x, lane = threadIdx.x;
-    ks_clear(S, lane);
     const int b = rp[i], e = rp[i + 1], bs = d * d, ai = agg[i];
+    ks_clear(S, lane, e - b);
     for (int p = b + lane; p < e; p += WAVE) {
         const int a = agg[ci[p]];
         if (a == ai || w[a] != 0.0) ks_insert(S, a);
@@ -1066,38 +1071,19 @@ void fill_ones(double* a, int64_t n, hipStream_t s) {
     MB_LAUNCH_CHECK();
 }
 
-SetupBsr galerkin(const SetupBsr& A, const Aggregates& G, const double* q_row, const double* q_col,
-                  hipStream_t s) {
-    const int n = A.n_rows, nc = G.n_agg, br = A.br, bc = A.bc, bs = br * bc;
-    // stage 1: T = A P_g
-    DevBuf<int32_t> cnt(std::max(n, 1)), trp(n + 1);
-    k_rap1<<<grid_for(n, 128), 128, 0, s>>>(n, br, bc, A.rp.p, A.ci.p, A.val.p, G.agg.p, q_col, 0, cnt.p, nullptr,
-                                           nullptr, nullptr);
+SetupBsr tentative_bsr(const Aggregates& G, int d, const double* q, hipStream_t s) {
+    const int n = G.n;
+    SetupBsr P;
+    P.n_rows = n;
+    P.n_cols = G.n_agg;
+    P.br = P.bc = d;
+    P.nnzb = n;
+    P.rp.alloc(n + 1);
+    P.ci.alloc(std::max(n, 1));
+    P.val.alloc(std::max<int64_t>((int64_t)n * d * d, 1));
+    k_tentative_bsr<<<grid_for(n + 1), 256, 0, s>>>(n, d, G.agg.p, q, P.rp.p, P.ci.p, P.val.p);
     MB_LAUNCH_CHECK();
-    int nt = scan_exclusive(cnt.p, n, trp.p, s);
-    DevBuf<int32_t> tci(std::max(nt, 1));
-    DevBuf<double> tval(std::max<int64_t>((int64_t)nt * bs, 1));
-    k_rap1<<<grid_for(n, 128), 128, 0, s>>>(n, br, bc, A.rp.p, A.ci.p, A.val.p, G.agg.p, q_col, 1, nullptr, trp.p,
-                                           tci.p, tval.p);
-    MB_LAUNCH_CHECK();
-    // stage 2: A_c = P_f^T T
-    SetupBsr C;
-    C.n_rows = C.n_cols = nc;
-    C.br = br;
-    C.bc = bc;
-    DevBuf<int32_t> ccnt(std::max(nc, 1));
-    C.rp.alloc(nc + 1);
-    k_rap2<<<grid_for(nc, 64), 64, 0, s>>>(nc, br, bc, G.mptr.p, G.midx.p, trp.p, tci.p, tval.p, q_row, 0, ccnt.p,
-                                          nullptr, nullptr, nullptr);
-    MB_LAUNCH_CHECK();
-    int nnzc = scan_exclusive(ccnt.p, nc, C.rp.p, s);
-    C.nnzb = nnzc;
-    C.ci.alloc(std::max(nnzc, 1));
-    C.val.alloc(std::max<int64_t>((int64_t)nnzc * bs, 1));
-    k_rap2<<<grid_for(nc, 64), 64, 0, s>>>(nc, br, bc, G.mptr.p, G.midx.p, trp.p, tci.p, tval.p, q_row, 1, nullptr,
-                                          C.rp.p, C.ci.p, C.val.p);
-    MB_LAUNCH_CHECK();
-    return C;
+    return P;
 }
 
 void build_dinv(const SetupBsr& A, double* dinv, hipStream_t s) {
@@ -1143,13 +1129,15 @@ SetupBsr sa_prolongator(const SetupBsr& A, int nv, const Aggregates& G, const do
     P.br = P.bc = d;
     DevBuf<int32_t> cnt(std::max(n, 1)), ovf(1);
     MB_HIP(hipMemsetAsync(ovf.p, 0, sizeof(int32_t), s));
-    if (n > 0) {
+    // short rows: one thread per row; long rows: one wavefront per row
+    bool per_thread = n > 0 && A.nnzb <= (int64_t)16 * n;
+    if (n > 0 && !per_thread) {
         k_sa_prolong_w<<<n, WAVE, 0, s>>>(d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 0, cnt.p, nullptr, nullptr,
                                           nullptr, ovf.p);
         MB_LAUNCH_CHECK();
+        per_thread = ovf.download(s, 1)[0] != 0;
     }
-    const bool wide = ovf.download(s, 1)[0] != 0;
-    if (wide) {
+    if (per_thread) {
         k_sa_prolong<<<grid_for(n, 128), 128, 0, s>>>(n, d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 0, cnt.p,
                                                      nullptr, nullptr, nullptr);
         MB_LAUNCH_CHECK();
@@ -1158,7 +1146,7 @@ SetupBsr sa_prolongator(const SetupBsr& A, int nv, const Aggregates& G, const do
     P.nnzb = scan_exclusive(cnt.p, n, P.rp.p, s);
     P.ci.alloc(std::max<int64_t>(P.nnzb, 1));
     P.val.alloc(std::max<int64_t>(P.nnzb * d * d, 1));
-    if (wide) {
+    if (per_thread) {
         k_sa_prolong<<<grid_for(n, 128), 128, 0, s>>>(n, d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 1, nullptr,
                                                      P.rp.p, P.ci.p, P.val.p);
     } else if (n > 0) {
@@ -1199,7 +1187,34 @@ SetupBsr block_transpose(const SetupBsr& P, hipStream_t s) {
     return T;
 }
 
-SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s) {
+bool same_pattern(const SetupBsr& X, const SetupBsr& Y, hipStream_t s) {
+    if (X.n_rows != Y.n_rows || X.n_cols != Y.n_cols || X.nnzb != Y.nnzb) return false;
+    if (X.n_rows == 0 || X.nnzb == 0) return true;
+    DevBuf<int32_t> flag(1);
+    const std::vector<int32_t> one(1, 1);
+    flag.upload(one, s);
+    k_same_pattern<<<grid_for(X.n_rows), 256, 0, s>>>(X.n_rows, X.rp.p, X.ci.p, Y.rp.p, Y.ci.p, flag.p);
+    MB_LAUNCH_CHECK();
+    return flag.download(s, 1)[0] != 0;
+}
+
+static void spgemm_values(const SetupBsr& A, const SetupBsr& B, SetupBsr& C, const int32_t* crow, hipStream_t s) {
+    if (C.nnzb == 0) return;
+    const unsigned g = grid_for(C.nnzb, 128);
+    const int64_t z = C.nnzb;
+    if (A.br == 4 && A.bc == 4 && B.bc == 4)
+        k_spgemm_num<4, 4, 4><<<g, 128, 0, s>>>(z, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, crow, C.ci.p,
+                                                C.val.p);
+    else if (A.br == 3 && A.bc == 3 && B.bc == 3)
+        k_spgemm_num<3, 3, 3><<<g, 128, 0, s>>>(z, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, crow, C.ci.p,
+                                                C.val.p);
+    else
+        k_spgemm_num_any<<<g, 128, 0, s>>>(z, A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p,
+                                           crow, C.ci.p, C.val.p);
+    MB_LAUNCH_CHECK();
+}
+
+SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s, const SetupBsr* like) {
     MB_CHECK(A.bc == B.br && A.br * B.bc <= 16, MBAMG_E_INVALID, "block product shapes");
     const int n = A.n_rows;
     SetupBsr C;
@@ -1207,7 +1222,6 @@ SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s) {
     C.n_cols = B.n_cols;
     C.br = A.br;
     C.bc = B.bc;
-    DevBuf<int32_t> cnt(std::max(n, 1)), ovf(1);
     C.rp.alloc(n + 1);
     if (A.nnzb == 0 || B.nnzb == 0) {
         MB_HIP(hipMemsetAsync(C.rp.p, 0, sizeof(int32_t) * (n + 1), s));
@@ -1215,26 +1229,45 @@ SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s) {
         C.val.alloc(1);
         return C;
     }
-    MB_HIP(hipMemsetAsync(ovf.p, 0, sizeof(int32_t), s));
-    k_spgemm_w<<<n, WAVE, 0, s>>>(A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, 0, cnt.p,
-                                  nullptr, nullptr, nullptr, ovf.p);
-    MB_LAUNCH_CHECK();
-    const bool wide = ovf.download(s, 1)[0] != 0;
-    if (wide) {
-        k_spgemm<<<grid_for(n, 64), 64, 0, s>>>(n, A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p,
-                                               B.val.p, 0, cnt.p, nullptr, nullptr, nullptr);
+    if (like) {
+        // the caller guarantees that A and B have the patterns that produced `like`
+        MB_CHECK(like->n_rows == n && like->n_cols == B.n_cols, MBAMG_E_STATE, "internal: reused pattern shape");
+        C.nnzb = like->nnzb;
+        C.ci.alloc(std::max<int64_t>(C.nnzb, 1));
+        MB_HIP(hipMemcpyAsync(C.rp.p, like->rp.p, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+        if (C.nnzb)
+            MB_HIP(hipMemcpyAsync(C.ci.p, like->ci.p, sizeof(int32_t) * C.nnzb, hipMemcpyDeviceToDevice, s));
+    } else {
+        DevBuf<int32_t> cnt(std::max(n, 1)), ovf(1);
+        MB_HIP(hipMemsetAsync(ovf.p, 0, sizeof(int32_t), s));
+        k_spgemm_sym<<<n, WAVE, 0, s>>>(A.rp.p, A.ci.p, B.rp.p, B.ci.p, 0, cnt.p, nullptr, nullptr, ovf.p);
         MB_LAUNCH_CHECK();
+        if (ovf.download(s, 1)[0] != 0) {
+            // a row has too many distinct columns for the LDS set: thread-per-row product
+            k_spgemm<<<grid_for(n, 64), 64, 0, s>>>(n, A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p,
+                                                   B.val.p, 0, cnt.p, nullptr, nullptr, nullptr);
+            MB_LAUNCH_CHECK();
+            C.nnzb = scan_exclusive(cnt.p, n, C.rp.p, s);
+            C.ci.alloc(std::max<int64_t>(C.nnzb, 1));
+            C.val.alloc(std::max<int64_t>(C.nnzb * C.br * C.bc, 1));
+            k_spgemm<<<grid_for(n, 64), 64, 0, s>>>(n, A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p,
+                                                   B.val.p, 1, nullptr, C.rp.p, C.ci.p, C.val.p);
+            MB_LAUNCH_CHECK();
+            MB_HIP(hipStreamSynchronize(s));
+            return C;
+        }
+        C.nnzb = scan_exclusive(cnt.p, n, C.rp.p, s);
+        C.ci.alloc(std::max<int64_t>(C.nnzb, 1));
+        k_spgemm_sym<<<n, WAVE, 0, s>>>(A.rp.p, A.ci.p, B.rp.p, B.ci.p, 1, nullptr, C.rp.p, C.ci.p, ovf.p);
+        MB_LAUNCH_CHECK();
+        MB_HIP(hipStreamSynchronize(s));   // cnt and ovf are released on leaving this block
     }
-    C.nnzb = scan_exclusive(cnt.p, n, C.rp.p, s);
-    C.ci.alloc(std::max<int64_t>(C.nnzb, 1));
     C.val.alloc(std::max<int64_t>(C.nnzb * C.br * C.bc, 1));
-    if (wide)
-        k_spgemm<<<grid_for(n, 64), 64, 0, s>>>(n, A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p,
-                                               B.val.p, 1, nullptr, C.rp.p, C.ci.p, C.val.p);
-    else
-        k_spgemm_w<<<n, WAVE, 0, s>>>(A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, 1, nullptr,
-                                      C.rp.p, C.ci.p, C.val.p, ovf.p);
+    DevBuf<int32_t> crow(std::max<int64_t>(C.nnzb, 1));
+    k_row_of<<<grid_for(n), 256, 0, s>>>(n, C.rp.p, crow.p);
     MB_LAUNCH_CHECK();
+    spgemm_values(A, B, C, crow.p, s);
+    MB_HIP(hipStreamSynchronize(s));   // crow is released on return
     return C;
 }
 

@@ -74,12 +74,14 @@ struct XferArgs {
     int accumulate;
 };
 
+// P waves share each slice's slots (1, 2 or 4)
 template <class T>
-void launch_xfer(int d, const XferArgs<T>& a, hipStream_t s);
+void launch_xfer(int d, int P, const XferArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_gs(int d, int P, bool zero_x, bool has_cpl, const GsArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_resid(int d, int P, const ResidArgs<T>& a, hipStream_t s);
+
 template <class T>
 void launch_restrict(int d, const TransferArgs<T>& a, hipStream_t s);
 template <class T>

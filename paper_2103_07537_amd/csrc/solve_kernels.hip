@@ -12,7 +12,11 @@
 
 namespace mbamg {
 
-constexpr int WPB = 4;          // waves per 256-thread block
+constexpr int WPB = 4;          // waves per block when a slice has at most 4 waves
+
+// P waves share each slice; a block holds max(P, WPB) waves
+template <int P>
+constexpr int waves_per_block() { return P > WPB ? P : WPB; }
 constexpr int CHUNK = 2;        // slots whose loads are issued together
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
@@ -27,7 +31,7 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 
 // grid for nslices slices with P waves per slice (4/P slices per 256-thread block)
 static inline unsigned xcd_grid(int nslices, int P) {
-    int blocks = (int)ceil_div(nslices, WPB / P);
+    int blocks = (int)ceil_div(nslices, std::max(WPB, P) / P);
     return (unsigned)(ceil_div(blocks, 8) * 8);
 }
 
@@ -134,7 +138,7 @@ __device__ __forceinline__ void sell_sub(const SellView<T>& A, int s, int lane, 
 template <class T, int D, int P>
 __device__ __forceinline__ void combine_parts(T (&acc)[D], int wave, int part, int lane) {
     if constexpr (P > 1) {
-        __shared__ T red[WPB][WAVE][D];
+        __shared__ T red[waves_per_block<P>()][WAVE][D];
 #pragma unroll
         for (int r = 0; r < D; ++r) red[wave][lane][r] = acc[r];
         __syncthreads();
@@ -154,10 +158,10 @@ __device__ __forceinline__ void combine_parts(T (&acc)[D], int wave, int part, i
 // where t_j is the updated value for rows of earlier colours and x_j otherwise;
 // t_i - x_i is the sub-solve's correction e_i for the residual b - A x.
 template <class T, int D, bool ZX, bool CPL, int P>
-__global__ __launch_bounds__(256) void k_gs(GsArgs<T> a, int padded_blocks) {
+__global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_gs(GsArgs<T> a, int padded_blocks) {
     const int wave = wave_id();
     const int part = wave % P;
-    const int sidx = xcd_block(padded_blocks) * (WPB / P) + wave / P;
+    const int sidx = xcd_block(padded_blocks) * (waves_per_block<P>() / P) + wave / P;
     const bool valid = sidx < a.s_count;
     if (P == 1 && !valid) return;
     const int s = a.s_begin + (valid ? sidx : 0);
@@ -208,10 +212,10 @@ __global__ __launch_bounds__(256) void k_gs(GsArgs<T> a, int padded_blocks) {
 
 // r = b - A x (or w = A x when b is NULL) for both block rows in one launch.
 template <class T, int D, int P>
-__global__ __launch_bounds__(256) void k_resid(ResidArgs<T> a, int padded_blocks) {
+__global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_resid(ResidArgs<T> a, int padded_blocks) {
     const int wave = wave_id();
     const int part = wave % P;
-    int sidx = xcd_block(padded_blocks) * (WPB / P) + wave / P;
+    int sidx = xcd_block(padded_blocks) * (waves_per_block<P>() / P) + wave / P;
     int f = 0;
     bool valid = true;
     if (sidx >= a.s_count[0]) {
@@ -220,7 +224,10 @@ __global__ __launch_bounds__(256) void k_resid(ResidArgs<T> a, int padded_blocks
         if (sidx >= a.s_count[1]) valid = false;
     }
     if (P == 1 && !valid) return;
-    if (!valid) sidx = 0;
+    if (!valid) {   // padding wave of a split slice: read any existing slice, write nothing
+        f = a.s_count[0] > 0 ? 0 : 1;
+        sidx = 0;
+    }
     const int g = 1 - f;
     const int lane = threadIdx.x & (WAVE - 1);
     const int row0 = a.sl[f].row0[sidx], nrow = a.sl[f].nrow[sidx];
@@ -252,14 +259,22 @@ __global__ __launch_bounds__(256) void k_resid(ResidArgs<T> a, int padded_blocks
 // y = A x (or y += A x) for both blocks in one launch: the smoothed
 // prolongator (rows of the fine level) and its transpose (rows of the coarse
 // level) in masked sliced-ELL form.
-template <class T, int D>
-__global__ __launch_bounds__(256) void k_xfer(XferArgs<T> a, int padded_blocks) {
-    int sidx = xcd_block(padded_blocks) * WPB + wave_id();
+template <class T, int D, int P>
+__global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_xfer(XferArgs<T> a, int padded_blocks) {
+    const int wave = wave_id();
+    const int part = wave % P;
+    int sidx = xcd_block(padded_blocks) * (waves_per_block<P>() / P) + wave / P;
     int f = 0;
+    bool valid = true;
     if (sidx >= a.s_count[0]) {
         sidx -= a.s_count[0];
         f = 1;
-        if (sidx >= a.s_count[1]) return;
+        if (sidx >= a.s_count[1]) valid = false;
+    }
+    if (P == 1 && !valid) return;
+    if (!valid) {   // padding wave of a split slice: read any existing slice, write nothing
+        f = a.s_count[0] > 0 ? 0 : 1;
+        sidx = 0;
     }
     const int lane = threadIdx.x & (WAVE - 1);
     const int row0 = a.sl[f].row0[sidx], nrow = a.sl[f].nrow[sidx];
@@ -267,8 +282,9 @@ __global__ __launch_bounds__(256) void k_xfer(XferArgs<T> a, int padded_blocks) 
     T acc[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) acc[r] = T(0);
-    sell_sub<T, D, D, 0, 1>(a.A[f], sidx, lane, 0, a.x[f], nullptr, 0, acc);
-    if (lane >= nrow) return;
+    if (valid) sell_sub<T, D, D, 0, P>(a.A[f], sidx, lane, part, a.x[f], nullptr, 0, acc);
+    combine_parts<T, D, P>(acc, wave, part, lane);
+    if (part != 0 || !valid || lane >= nrow) return;
     T out[D];
     if (a.accumulate) {
         T y[D];
@@ -350,12 +366,13 @@ template <class T, int D, int P>
 static void gs_dispatch(bool zx, bool cpl, const GsArgs<T>& a, hipStream_t s) {
     unsigned grid = xcd_grid(a.s_count, P);
     int pb = (int)grid;
+    constexpr int TPB = waves_per_block<P>() * WAVE;
     if (zx) {
-        if (cpl) k_gs<T, D, true, true, P><<<grid, 256, 0, s>>>(a, pb);
-        else k_gs<T, D, true, false, P><<<grid, 256, 0, s>>>(a, pb);
+        if (cpl) k_gs<T, D, true, true, P><<<grid, TPB, 0, s>>>(a, pb);
+        else k_gs<T, D, true, false, P><<<grid, TPB, 0, s>>>(a, pb);
     } else {
-        if (cpl) k_gs<T, D, false, true, P><<<grid, 256, 0, s>>>(a, pb);
-        else k_gs<T, D, false, false, P><<<grid, 256, 0, s>>>(a, pb);
+        if (cpl) k_gs<T, D, false, true, P><<<grid, TPB, 0, s>>>(a, pb);
+        else k_gs<T, D, false, false, P><<<grid, TPB, 0, s>>>(a, pb);
     }
 }
 
@@ -365,7 +382,9 @@ static void gs_dispatch_p(int P, bool zx, bool cpl, const GsArgs<T>& a, hipStrea
         case 1: gs_dispatch<T, D, 1>(zx, cpl, a, s); break;
         case 2: gs_dispatch<T, D, 2>(zx, cpl, a, s); break;
         case 4: gs_dispatch<T, D, 4>(zx, cpl, a, s); break;
-        default: throw Error(MBAMG_E_INVALID, "slot split must be 1, 2 or 4");
+        case 8: gs_dispatch<T, D, 8>(zx, cpl, a, s); break;
+        case 16: gs_dispatch<T, D, 16>(zx, cpl, a, s); break;
+        default: throw Error(MBAMG_E_INVALID, "slot split must be 1, 2, 4, 8 or 16");
     }
 }
 
@@ -391,7 +410,9 @@ static void resid_dispatch(int P, const ResidArgs<T>& a, hipStream_t s) {
         case 1: k_resid<T, D, 1><<<grid, 256, 0, s>>>(a, pb); break;
         case 2: k_resid<T, D, 2><<<grid, 256, 0, s>>>(a, pb); break;
         case 4: k_resid<T, D, 4><<<grid, 256, 0, s>>>(a, pb); break;
-        default: throw Error(MBAMG_E_INVALID, "slot split must be 1, 2 or 4");
+        case 8: k_resid<T, D, 8><<<grid, 512, 0, s>>>(a, pb); break;
+        case 16: k_resid<T, D, 16><<<grid, 1024, 0, s>>>(a, pb); break;
+        default: throw Error(MBAMG_E_INVALID, "slot split must be 1, 2, 4, 8 or 16");
     }
 }
 
@@ -408,23 +429,35 @@ void launch_resid(int d, int P, const ResidArgs<T>& a, hipStream_t s) {
     MB_LAUNCH_CHECK();
 }
 
-template <class T>
-void launch_xfer(int d, const XferArgs<T>& a, hipStream_t s) {
+template <class T, int D>
+static void xfer_dispatch(int P, const XferArgs<T>& a, hipStream_t s) {
     const int total = a.s_count[0] + a.s_count[1];
-    if (total <= 0) return;
-    unsigned grid = xcd_grid(total, 1);
+    unsigned grid = xcd_grid(total, P);
     int pb = (int)grid;
+    switch (P) {
+        case 1: k_xfer<T, D, 1><<<grid, 256, 0, s>>>(a, pb); break;
+        case 2: k_xfer<T, D, 2><<<grid, 256, 0, s>>>(a, pb); break;
+        case 4: k_xfer<T, D, 4><<<grid, 256, 0, s>>>(a, pb); break;
+        case 8: k_xfer<T, D, 8><<<grid, 512, 0, s>>>(a, pb); break;
+        case 16: k_xfer<T, D, 16><<<grid, 1024, 0, s>>>(a, pb); break;
+        default: throw Error(MBAMG_E_INVALID, "slot split must be 1, 2, 4, 8 or 16");
+    }
+}
+
+template <class T>
+void launch_xfer(int d, int P, const XferArgs<T>& a, hipStream_t s) {
+    if (a.s_count[0] + a.s_count[1] <= 0) return;
     switch (d) {
-        case 1: k_xfer<T, 1><<<grid, 256, 0, s>>>(a, pb); break;
-        case 2: k_xfer<T, 2><<<grid, 256, 0, s>>>(a, pb); break;
-        case 3: k_xfer<T, 3><<<grid, 256, 0, s>>>(a, pb); break;
-        case 4: k_xfer<T, 4><<<grid, 256, 0, s>>>(a, pb); break;
+        case 1: xfer_dispatch<T, 1>(P, a, s); break;
+        case 2: xfer_dispatch<T, 2>(P, a, s); break;
+        case 3: xfer_dispatch<T, 3>(P, a, s); break;
+        case 4: xfer_dispatch<T, 4>(P, a, s); break;
         default: throw Error(MBAMG_E_INVALID, "dofs per node must be 1..4");
     }
     MB_LAUNCH_CHECK();
 }
-template void launch_xfer<double>(int, const XferArgs<double>&, hipStream_t);
-template void launch_xfer<float>(int, const XferArgs<float>&, hipStream_t);
+template void launch_xfer<double>(int, int, const XferArgs<double>&, hipStream_t);
+template void launch_xfer<float>(int, int, const XferArgs<float>&, hipStream_t);
 
 template <class T>
 void launch_restrict(int d, const TransferArgs<T>& a, hipStream_t s) {
