@@ -432,7 +432,62 @@ static void choose_weights(mbamg_hierarchy* h, Level& cur, const Aggregates& G, 
     cur.damped = true;
 }
 
-static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
+template <class T>
+static void clone_buf(DevBuf<T>& dst, const DevBuf<T>& src, hipStream_t s) {
+    dst.alloc(src.n);
+    if (src.n) MB_HIP(hipMemcpyAsync(dst.p, src.p, src.bytes(), hipMemcpyDeviceToDevice, s));
+}
+
+static void clone_part(SellPart& d, const SellPart& p, hipStream_t s) {
+    d.br = p.br;
+    d.bc = p.bc;
+    d.n_slots = p.n_slots;
+    d.n_groups = p.n_groups;
+    clone_buf(d.width, p.width, s);
+    clone_buf(d.coff, p.coff, s);
+    clone_buf(d.voff, p.voff, s);
+    clone_buf(d.mask, p.mask, s);
+    clone_buf(d.col, p.col, s);
+    clone_buf(d.v64, p.v64, s);
+    clone_buf(d.v32, p.v32, s);
+    d.h_coff = p.h_coff;
+    d.h_width = p.h_width;
+    d.h_slot_nz = p.h_slot_nz;
+    d.h_slot_blocks = p.h_slot_blocks;
+}
+
+// The colour order, slices and smoother parts of a block row: they depend on
+// A and the colouring alone, not on the transfers or weights.
+static void clone_smoother(BlockLevel& d, const BlockLevel& b, hipStream_t s) {
+    d.d = b.d;
+    d.n = b.n;
+    d.n_colours = b.n_colours;
+    d.n_slices = b.n_slices;
+    d.split = b.split;
+    d.cstats = b.cstats;
+    d.all_nz = b.all_nz;
+    d.all_bl = b.all_bl;
+    d.perm = b.perm;
+    d.iperm = b.iperm;
+    d.colour = b.colour;
+    d.h_row0 = b.h_row0;
+    d.h_nrow = b.h_nrow;
+    d.colour_slice = b.colour_slice;
+    d.colour_row = b.colour_row;
+    clone_buf(d.row0, b.row0, s);
+    clone_buf(d.nrow, b.nrow, s);
+    clone_buf(d.d_perm, b.d_perm, s);
+    clone_buf(d.d_iperm, b.d_iperm, s);
+    clone_part(d.off, b.off, s);
+    clone_part(d.cpl, b.cpl, s);
+    clone_part(d.diag, b.diag, s);
+    clone_part(d.dinv, b.dinv, s);
+}
+
+// donor: a hierarchy built from the same blocks with the same level-0
+// parameters (aggregation, precision); its level-0 aggregates and smoother
+// data are copied instead of recomputed.
+static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, const mbamg_hierarchy* donor) {
     auto t0 = std::chrono::steady_clock::now();
     const mbamg_params& p = h->p;
     const int d0 = h->d[0], d1 = h->d[1];
@@ -465,9 +520,20 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
         const int64_t ndof = (int64_t)cur.n * (d0 + d1);
         if (ndof <= p.max_coarse || (int)h->L.size() >= p.max_levels) break;
         clk.mark("start", lvl);
-        Strength S = build_strength(cur.A[0][0], p.theta, s);
-        clk.mark("strength", lvl);
-        Aggregates G = build_aggregates(S, p.seed, lvl, s);
+        Aggregates G;
+        if (lvl == 0 && donor && donor->L.size() > 1 && donor->L[0]->n == cur.n) {
+            const Aggregates& D = donor->L[0]->G;
+            G.n = D.n;
+            G.n_agg = D.n_agg;
+            G.mis_rounds = D.mis_rounds;
+            clone_buf(G.agg, D.agg, s);
+            clone_buf(G.mptr, D.mptr, s);
+            clone_buf(G.midx, D.midx, s);
+        } else {
+            Strength S = build_strength(cur.A[0][0], p.theta, s);
+            clk.mark("strength", lvl);
+            G = build_aggregates(S, p.seed, lvl, s);
+        }
         clk.mark("aggregates", lvl);
         if ((double)G.n_agg > 0.9 * cur.n) break;
         const int nc = G.n_agg;
@@ -485,15 +551,21 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
         // pattern; the symbolic phase then runs once and the rest reuse it.
         auto galerkin_all = [&](const SetupBsr (&P)[2], const SetupBsr (&PT)[2]) {
             const bool sameP = same_pattern(P[0], P[1], s);
-            SetupBsr T00;
+            SetupBsr T[2][2];
             for (int f = 0; f < 2; ++f)
                 for (int g = 0; g < 2; ++g) {
-                    const bool first = f == 0 && g == 0;
-                    const bool reuse = !first && (g == 0 || sameP) && (f == 0 || sameP) &&
-                                       same_pattern(cur.A[f][g], cur.A[0][0], s);
-                    SetupBsr T = spgemm(cur.A[f][g], P[g], s, reuse ? &T00 : nullptr);
-                    nxt->A[f][g] = spgemm(PT[f], T, s, reuse ? &nxt->A[0][0] : nullptr);
-                    if (first) T00 = std::move(T);
+                    // an earlier pair (f', g') whose A block and prolongators have the same patterns
+                    int src = -1;
+                    for (int k = 0; k < f * 2 + g && src < 0; ++k) {
+                        const int f2 = k / 2, g2 = k % 2;
+                        if ((f2 == f || sameP) && (g2 == g || sameP) && cur.A[f2][g2].nnzb > 0 &&
+                            same_pattern(cur.A[f][g], cur.A[f2][g2], s))
+                            src = k;
+                    }
+                    const SetupBsr* likeT = src >= 0 ? &T[src / 2][src % 2] : nullptr;
+                    const SetupBsr* likeC = src >= 0 ? &nxt->A[src / 2][src % 2] : nullptr;
+                    T[f][g] = spgemm(cur.A[f][g], P[g], s, likeT);
+                    nxt->A[f][g] = spgemm(PT[f], T[f][g], s, likeC);
                 }
         };
         if (p.learned != 0 || p.omega_p != 0.0) {
@@ -554,14 +626,19 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
     for (int l = (int)h->L.size() - 2; l >= 0; --l) {
         Level& Lv = *h->L[l];
         Level& Nx = *h->L[l + 1];
+        const bool shared = l == 0 && donor && donor->L.size() > 1 && donor->L[0]->n == Lv.n;
+        if (shared) {
+            for (int f = 0; f < 2; ++f) clone_smoother(Lv.blk[f], donor->L[0]->blk[f], s);
+            clk.mark("smoother data copied", l);
+        }
         // colouring is sequential by definition (first fit in node order): done on the host from
         // the patterns of the diagonal blocks
         std::vector<int32_t> rp[2][2], ci[2][2];
-        for (int f = 0; f < 2; ++f) {
+        for (int f = 0; f < 2 && !shared; ++f) {
             rp[f][f] = Lv.A[f][f].rp.download(s, Lv.n + 1);
             ci[f][f] = Lv.A[f][f].ci.download(s, Lv.A[f][f].nnzb);
         }
-        for (int f = 0; f < 2; ++f) {
+        for (int f = 0; f < 2 && !shared; ++f) {
             BlockLevel& B = Lv.blk[f];
             B.d = Lv.d[f];
             if (f == 0) clk.mark("pattern download", l);
@@ -587,7 +664,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
             B.d_perm.upload(B.perm, s);
             B.d_iperm.upload(B.iperm, s);
         }
-        for (int f = 0; f < 2; ++f) {
+        for (int f = 0; f < 2 && !shared; ++f) {
             const int g = 1 - f;
             BlockLevel& B = Lv.blk[f];
             const int df = Lv.d[f], dg = Lv.d[g];
@@ -1159,20 +1236,20 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
             MB_CHECK(fm->n_vec[f] >= 0 && fm->n_vec[f] <= fm->dofs[f], MBAMG_E_INVALID, "n_vec out of range");
         hipStream_t s = (hipStream_t)hip_stream;
         auto t0 = std::chrono::steady_clock::now();
-        auto build = [&](const mbamg_params& pp) {
+        auto build = [&](const mbamg_params& pp, const mbamg_hierarchy* donor) {
             auto h = std::make_unique<mbamg_hierarchy>();
             h->p = pp;
             h->fm = *fm;
             h->d[0] = fm->dofs[0];
             h->d[1] = fm->dofs[1];
             if (pp.learned == 1) h->mlp.upload(pp.mlp, N_MLP_PARAMS + 2 * N_FEATURES, s);
-            setup_impl(h.get(), A_blocks, s);
+            setup_impl(h.get(), A_blocks, s, donor);
             // the build's temporaries are idle now and can serve the next allocations
             MB_HIP(hipDeviceSynchronize());
             pool_device_idle();
             return h;
         };
-        auto h = build(*p);
+        auto h = build(*p, nullptr);
         h->info.used_learned = p->learned != 0;
         if (p->learned != 0 && p->judge) {
             // the fixed-weight method is the fallback and the judge
@@ -1180,7 +1257,7 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
             pf.learned = 0;
             pf.omega_p = 0.0;
             PhaseClock jclk(s);
-            auto hf = build(pf);
+            auto hf = build(pf, h.get());   // shares the level-0 aggregates and smoother data
             jclk.mark("fixed hierarchy built", 0);
             const double rl = probe_impl(h.get(), 10, 12345, s);
             const double rf = probe_impl(hf.get(), 10, 12345, s);
