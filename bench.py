@@ -155,29 +155,49 @@ def stream_copy_rate():
     return 2.0 * (1 << 30) / (float(np.median(times)) * 1e-3) / 1e9
 
 
-def cpu_baseline(args, gpu_iters):
-    """Oracle on a bounded sample of the same workload family (smaller grid),
-    scaled to the full workload's unknowns and to the GPU's iteration count."""
+def cpu_baseline(args, form, gpu_iters, mlp):
+    """The oracle, single-threaded, on a bounded sample of the same workload
+    family (a smaller grid of the same generator) doing the same work as the
+    reported form: for the learned form the oracle runs the same network
+    (bfloat16-emulated) on its own features, builds the fixed hierarchy too and
+    lets the two probes judge.  The measured time is scaled linearly by the
+    unknown ratio and, for the solve, to the GPU's iteration count."""
+    from threadpoolctl import threadpool_limits
     from oracle import amg
     from paper_2103_07537_amd.inputs import WORKLOADS, make_system
     kw = dict(WORKLOADS[args.workload])
     full_n = kw["n"]
     dim = kw["dim"]
-    n_s = args.cpu_sample_n or (96 if dim == 2 else 32)
-    n_s = min(n_s, full_n)
+    n_s = min(args.cpu_sample_n or (40 if dim == 3 else 256), full_n)
     kw["n"] = n_s
     s = make_system(seed=args.seed, **kw)
-    t0 = time.perf_counter()
-    h = amg.setup(s.blocks, s.dofs, amg.Params())
-    t1 = time.perf_counter()
-    x, info = amg.gmres(h, s.b, rtol=args.rtol)
-    t2 = time.perf_counter()
+    learned_form = FORMS[form][1] and mlp is not None
+    weights = None
+    if learned_form:
+        from oracle import learned as ol
+        theta = np.asarray(mlp[:5122], dtype=np.float64)
+        mean, std = mlp[5122:5134], mlp[5134:5146]
+
+        def weights(level, n_agg, F):
+            out, _ = ol.forward(theta, ((F.astype(np.float32) - mean) / std).astype(np.float64), emulate=True)
+            return out[:, 0], out[:, 1]
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        h = amg.setup(s.blocks, s.dofs, amg.Params(weights=weights), n_vec=s.n_vec)
+        if learned_form:
+            hf = amg.setup(s.blocks, s.dofs, amg.Params(), n_vec=s.n_vec)
+            if not amg.probe(h, 10, 12345) < amg.probe(hf, 10, 12345):
+                h = hf
+        t1 = time.perf_counter()
+        x, info = amg.gmres(h, s.b, rtol=args.rtol)
+        t2 = time.perf_counter()
     ratio = (full_n / n_s) ** dim
     per_it = (t2 - t1) / max(info.iterations, 1)
     est_ms = 1e3 * ((t1 - t0) * ratio + per_it * ratio * gpu_iters)
+    what = ("learned and fixed setups, both probes, " if learned_form else "setup, ") + "GMRES(30)"
     return {
         "value": est_ms, "unit": "ms", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle setup + GMRES(30) on the same generator at {n_s}^{dim} nodes "
+        "sample": (f"oracle ({what}, FP64, one thread) on the same generator at {n_s}^{dim} nodes "
                    f"({s.n_dofs} unknowns, {info.iterations} iterations, {t2 - t0:.1f} s measured), "
                    f"scaled linearly by the unknown ratio {ratio:.0f} and to the GPU's {gpu_iters} iterations"),
         "host": platform.processor() or platform.machine(),
@@ -304,7 +324,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
-        cpu = cpu_baseline(args, results[chosen]["iterations"])
+        cpu = cpu_baseline(args, chosen, results[chosen]["iterations"], mlp)
     out = {
         "metric": METRIC,
         "value": results[chosen]["ms_per_step"],
