@@ -5,6 +5,8 @@
 // GMRES / flexible GMRES, and the C-ABI declared in include/mbamg.h.
 #include <algorithm>
 #include <chrono>
+#include <future>
+#include <map>
 #include <climits>
 #include <cmath>
 #include <cstdlib>
@@ -432,6 +434,55 @@ static void choose_weights(mbamg_hierarchy* h, Level& cur, const Aggregates& G, 
     cur.damped = true;
 }
 
+// First-fit colouring, colour order and slices of both block rows of one level
+// (host work on the diagonal blocks' patterns).  `ready` marks the point on
+// the setup stream after which the level's blocks are complete; the patterns
+// are copied on a stream of the calling thread.
+static void colour_level(Level& Lv, hipEvent_t ready, int device) {
+    MB_HIP(hipSetDevice(device));   // the calling thread may be a fresh one
+    hipStream_t cs = nullptr;
+    MB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    std::vector<int32_t> rp[2], ci[2];
+    try {
+        MB_HIP(hipStreamWaitEvent(cs, ready, 0));
+        for (int f = 0; f < 2; ++f) {
+            rp[f].resize((size_t)Lv.n + 1);
+            ci[f].resize((size_t)Lv.A[f][f].nnzb);
+            MB_HIP(hipMemcpyAsync(rp[f].data(), Lv.A[f][f].rp.p, sizeof(int32_t) * rp[f].size(),
+                                  hipMemcpyDeviceToHost, cs));
+            if (!ci[f].empty())
+                MB_HIP(hipMemcpyAsync(ci[f].data(), Lv.A[f][f].ci.p, sizeof(int32_t) * ci[f].size(),
+                                      hipMemcpyDeviceToHost, cs));
+        }
+        MB_HIP(hipStreamSynchronize(cs));
+    } catch (...) {
+        (void)hipStreamDestroy(cs);
+        throw;
+    }
+    (void)hipStreamDestroy(cs);
+    for (int f = 0; f < 2; ++f) {
+        BlockLevel& B = Lv.blk[f];
+        B.d = Lv.d[f];
+        if (f == 1 && rp[1] == rp[0] && ci[1] == ci[0]) {
+            // same pattern: the same first-fit colouring, order and slices
+            const BlockLevel& B0 = Lv.blk[0];
+            B.colour = B0.colour;
+            B.n = B0.n;
+            B.n_colours = B0.n_colours;
+            B.colour_row = B0.colour_row;
+            B.perm = B0.perm;
+            B.iperm = B0.iperm;
+            B.h_row0 = B0.h_row0;
+            B.h_nrow = B0.h_nrow;
+            B.colour_slice = B0.colour_slice;
+            B.n_slices = B0.n_slices;
+        } else {
+            int ncol = greedy_colour(Lv.n, rp[f], ci[f], B.colour);
+            order_and_slice(B, Lv.n, ncol);
+        }
+    }
+}
+
 template <class T>
 static void clone_buf(DevBuf<T>& dst, const DevBuf<T>& src, hipStream_t s) {
     dst.alloc(src.n);
@@ -497,6 +548,16 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
     PhaseClock clk(s);
     CoarseWork cwork;   // declared first: the side stream is drained before its buffers are freed
     SideStream side;
+    // host colouring jobs per level; joined before their level's smoother data is built
+    // (and, on an error, waited for when the futures go out of scope, before the events)
+    std::vector<hipEvent_t> colour_events;
+    struct EventList {
+        std::vector<hipEvent_t>& e;
+        ~EventList() { for (auto ev : e) (void)hipEventDestroy(ev); }
+    } colour_events_guard{colour_events};
+    std::map<int, std::future<void>> colour_jobs;
+    int device = 0;
+    MB_HIP(hipGetDevice(&device));
 
     // level 0 from the caller's blocks
     auto first = std::make_unique<Level>();
@@ -536,6 +597,16 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
         }
         clk.mark("aggregates", lvl);
         if ((double)G.n_agg > 0.9 * cur.n) break;
+        // this level is not the coarsest: colour it on a host thread while the GPU
+        // builds the next level (the level-0 colouring comes with the donor's copy)
+        if (!(lvl == 0 && donor && donor->L.size() > 1 && donor->L[0]->n == cur.n)) {
+            hipEvent_t ev = nullptr;
+            MB_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            colour_events.push_back(ev);
+            MB_HIP(hipEventRecord(ev, s));
+            Level* lp = &cur;
+            colour_jobs[lvl] = std::async(std::launch::async, [lp, ev, device] { colour_level(*lp, ev, device); });
+        }
         const int nc = G.n_agg;
         DevBuf<double> q[2], Bc[2];
         for (int f = 0; f < 2; ++f) {     // block 1 reuses block 0's aggregates
@@ -632,33 +703,22 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
             clk.mark("smoother data copied", l);
         }
         // colouring is sequential by definition (first fit in node order): done on the host from
-        // the patterns of the diagonal blocks
-        std::vector<int32_t> rp[2][2], ci[2][2];
-        for (int f = 0; f < 2 && !shared; ++f) {
-            rp[f][f] = Lv.A[f][f].rp.download(s, Lv.n + 1);
-            ci[f][f] = Lv.A[f][f].ci.download(s, Lv.A[f][f].nnzb);
+        // the patterns of the diagonal blocks, by the job started when the level was built
+        if (!shared) {
+            auto job = colour_jobs.find(l);
+            if (job != colour_jobs.end()) {
+                job->second.get();
+            } else {
+                hipEvent_t ev = nullptr;
+                MB_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+                colour_events.push_back(ev);
+                MB_HIP(hipEventRecord(ev, s));
+                colour_level(Lv, ev, device);
+            }
+            clk.mark("colouring joined", l);
         }
         for (int f = 0; f < 2 && !shared; ++f) {
             BlockLevel& B = Lv.blk[f];
-            B.d = Lv.d[f];
-            if (f == 0) clk.mark("pattern download", l);
-            if (f == 1 && rp[1][1] == rp[0][0] && ci[1][1] == ci[0][0]) {
-                // same pattern: the same first-fit colouring, order and slices
-                const BlockLevel& B0 = Lv.blk[0];
-                B.colour = B0.colour;
-                B.n = B0.n;
-                B.n_colours = B0.n_colours;
-                B.colour_row = B0.colour_row;
-                B.perm = B0.perm;
-                B.iperm = B0.iperm;
-                B.h_row0 = B0.h_row0;
-                B.h_nrow = B0.h_nrow;
-                B.colour_slice = B0.colour_slice;
-                B.n_slices = B0.n_slices;
-            } else {
-                int ncol = greedy_colour(Lv.n, rp[f][f], ci[f][f], B.colour);
-                order_and_slice(B, Lv.n, ncol);
-            }
             B.row0.upload(B.h_row0, s);
             B.nrow.upload(B.h_nrow, s);
             B.d_perm.upload(B.perm, s);

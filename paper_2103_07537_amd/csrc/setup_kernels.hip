@@ -365,18 +365,26 @@ __global__ void k_dinv(int n, int d, const int32_t* rp, const int32_t* ci, const
 // (-1 for padding); mask bit k of a slot is set when entry k is nonzero in any
 // lane's block.
 // ----------------------------------------------------------------------------
+// One wavefront per slot (one lane per row): the slot's mask is the OR of the
+// lanes' nonzero patterns and slot_nz the sum of their nonzero counts.
 __global__ void k_sell_mask(int64_t n_slots, int bs, const int64_t* src, const double* val, uint32_t* mask,
                             uint32_t* slot_nz) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_slots * WAVE) return;
-    int64_t s = src[t];
-    if (s < 0) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t slot = t / WAVE;
+    if (slot >= n_slots) return;   // whole wavefronts
+    const int64_t s = src[t];
     uint32_t bits = 0;
+    if (s >= 0)
+        for (int k = 0; k < bs; ++k)
+            if (val[s * bs + k] != 0.0) bits |= 1u << k;
+    uint32_t m = 0;
     for (int k = 0; k < bs; ++k)
-        if (val[s * bs + k] != 0.0) bits |= 1u << k;
-    if (bits) {
-        atomicOr(&mask[t / WAVE], bits);
-        atomicAdd(&slot_nz[t / WAVE], (uint32_t)__popc(bits));
+        if (__ballot((bits >> k) & 1u)) m |= 1u << k;
+    int nz = __popc(bits);
+    for (int off = WAVE / 2; off > 0; off >>= 1) nz += __shfl_xor(nz, off);
+    if ((t & (WAVE - 1)) == 0) {
+        mask[slot] = m;
+        slot_nz[slot] = (uint32_t)nz;
     }
 }
 
