@@ -90,30 +90,53 @@ __device__ __forceinline__ void store_vec<float, 4>(float* __restrict__ p, const
 // of one slice.  MODE 0: x from xa.  MODE 1: columns below cstart from xa
 // (already updated this sweep), others from xb.  MODE 2: columns below cstart
 // from xa, others contribute 0.
+// When P waves share a slice (coarse levels: few wide slices, so each wave's
+// chain of dependent loads is what the launch waits for), the column indices,
+// masks and value offsets of the next chunk are fetched while the current
+// chunk's values and gathers are in flight, and FP32 chunks are 4 slots wide.
+template <class T, int P>
+constexpr int sell_chunk() { return P >= 4 && sizeof(T) == 4 ? 4 : CHUNK; }
+
 template <class T, int BR, int BC, int MODE, int P>
 __device__ __forceinline__ void sell_sub(const SellView<T>& A, int s, int lane, int part, const T* __restrict__ xa,
                                          const T* __restrict__ xb, int cstart, T (&acc)[BR]) {
+    constexpr int CH = sell_chunk<T, P>();
+    constexpr bool PF = P >= 4;
     const int w = A.width[s];
     const int64_t cb = A.coff[s];
-    for (int t = part; t < w; t += P * CHUNK) {
-        int j[CHUNK];
-        uint32_t m[CHUNK];
-        int64_t vg[CHUNK];
+    int j[CH];
+    uint32_t m[CH];
+    int64_t vg[CH];
+    auto fetch = [&](int t0) {
 #pragma unroll
-        for (int u = 0; u < CHUNK; ++u) {
-            const int tt = t + u * P;
+        for (int u = 0; u < CH; ++u) {
+            const int tt = t0 + u * P;
             const bool live = tt < w;
             m[u] = live ? A.mask[cb + tt] : 0u;
             vg[u] = live ? A.voff[cb + tt] : 0;
             j[u] = live ? A.col[(cb + tt) * WAVE + lane] : -1;
         }
-        T v[CHUNK][BR * BC];
+    };
+    if (PF) fetch(part);
+    for (int t = part; t < w; t += P * CH) {
+        if (!PF) fetch(t);
+        int jc[CH];
+        uint32_t mc[CH];
+        int64_t gc[CH];
 #pragma unroll
-        for (int u = 0; u < CHUNK; ++u) load_masked<T, BR * BC>(A.val + vg[u] * WAVE + lane, m[u], v[u]);
-        T xj[CHUNK][BC];
+        for (int u = 0; u < CH; ++u) {
+            jc[u] = j[u];
+            mc[u] = m[u];
+            gc[u] = vg[u];
+        }
+        if (PF) fetch(t + P * CH);
+        T v[CH][BR * BC];
 #pragma unroll
-        for (int u = 0; u < CHUNK; ++u) {
-            const int jj = j[u];
+        for (int u = 0; u < CH; ++u) load_masked<T, BR * BC>(A.val + gc[u] * WAVE + lane, mc[u], v[u]);
+        T xj[CH][BC];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int jj = jc[u];
             const T* src = nullptr;
             if (MODE == 0) src = xa;
             else if (MODE == 1) src = jj < cstart ? xa : xb;
@@ -125,7 +148,7 @@ __device__ __forceinline__ void sell_sub(const SellView<T>& A, int s, int lane, 
             }
         }
 #pragma unroll
-        for (int u = 0; u < CHUNK; ++u)
+        for (int u = 0; u < CH; ++u)
 #pragma unroll
             for (int r = 0; r < BR; ++r)
 #pragma unroll
