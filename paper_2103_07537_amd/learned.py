@@ -26,6 +26,9 @@ from .inputs import WORKLOADS, make_system
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "mlp_2d64_lognormal.json")
+# trained on 2000 fields of varying contrast and coupling (2d-64-mixed); adapts
+# per field on 2D systems but does not carry over to 3D coarse levels
+MIXED_WEIGHTS = os.path.join(HERE, "weights", "mlp_2d64_mixed.json")
 OMEGA_P_GRID = (0.0, 1.0 / 3.0, 0.5, 2.0 / 3.0, 5.0 / 6.0)
 OMEGA_S_GRID = (0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1)
 TRAIN_FAMILY = "2d-64-lognormal"
@@ -35,10 +38,22 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def family_kwargs(family: str, seed: int) -> dict:
+    """Generator arguments of one sampled field.  "2d-64-mixed" (64^2 nodes)
+    draws the lognormal contrast sigma in [0.25, 2] and the coupling strength
+    gamma log-uniformly in [0.3, 10] per field (from the field's seed); any
+    other name is a fixed workload."""
+    if family == "2d-64-mixed":
+        u = np.random.default_rng([int(seed), 7]).random(2)
+        return dict(n=64, dim=2, kappa="lognormal", sigma=float(0.25 + 1.75 * u[0]),
+                    gamma=float(np.exp(np.log(0.3) + (np.log(10.0) - np.log(0.3)) * u[1])))
+    return dict(WORKLOADS[family])
+
+
 def label_field(seed: int, family: str = TRAIN_FAMILY, probe_iters: int = 10):
     """Best uniform (omega_P, omega_S) of one field by probe, and the feature
     rows of the hierarchy built with it."""
-    kw = dict(WORKLOADS[family])
+    kw = family_kwargs(family, seed)
     s = make_system(seed=seed, **kw)
     blocks = mbamg.to_device(s)
     best = (np.inf, 0.0, 0.8)
@@ -77,11 +92,11 @@ def load_data(path):
     return X, T, d["tables"], d["seeds"]
 
 
-def collect(seeds, out_path=None, progress_every=50):
+def collect(seeds, out_path=None, progress_every=50, family=TRAIN_FAMILY):
     Xs, Ts, tables = [], [], []
     t0 = time.time()
     for k, seed in enumerate(seeds):
-        X, T, table = label_field(int(seed))
+        X, T, table = label_field(int(seed), family)
         Xs.append(X)
         Ts.append(T)
         tables.append(table)
@@ -159,23 +174,30 @@ def main(argv=None):
     ap.add_argument("--fields", type=int, default=2000)
     ap.add_argument("--seed0", type=int, default=1000)
     ap.add_argument("--epochs", type=int, default=40)
-    ap.add_argument("--data", default=None, help="npz of labelled rows to reuse or write")
+    ap.add_argument("--data", default=None, help="npz of labelled rows to write, or comma-separated npz files to reuse")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--family", default=TRAIN_FAMILY, help="field family: a workload name or 2d-64-mixed")
     a = ap.parse_args(argv)
     import torch
     mbamg.lib()
     torch.cuda.set_device(0)
     seeds = list(range(a.seed0, a.seed0 + a.fields))
-    if a.data and os.path.exists(a.data):
-        X, T, tables, _ = load_data(a.data)
+    if a.data and all(os.path.exists(d) for d in a.data.split(",")):
+        parts = [load_data(d) for d in a.data.split(",")]
+        X = np.concatenate([p[0] for p in parts])
+        T = np.concatenate([p[1] for p in parts])
+        tables = np.concatenate([p[2] for p in parts])
+        sets = [{"data": os.path.basename(d), "fields": int(len(p[3])), "seeds": [int(p[3].min()), int(p[3].max())]}
+                for d, p in zip(a.data.split(","), parts)]
         _log(f"[learned] reusing {X.shape[0]} rows from {a.data}")
     else:
-        X, T, tables = collect(seeds, a.data)
+        X, T, tables = collect(seeds, a.data, family=a.family)
+        sets = [{"family": a.family, "fields": len(seeds), "seeds": [seeds[0], seeds[-1]]}]
     params, mean, std, hist = train(X, T, epochs=a.epochs)
     best = [(OMEGA_P_GRID[int(i) // len(OMEGA_S_GRID)], OMEGA_S_GRID[int(i) % len(OMEGA_S_GRID)])
             for i in np.argmin(tables.reshape(tables.shape[0], -1), axis=1)]
     save(a.out, params, mean, std, {
-        "train_family": TRAIN_FAMILY, "train_seeds": [seeds[0], seeds[0] + tables.shape[0] - 1],
+        "train_family": a.family, "train_sets": sets,
         "rows": int(X.shape[0]), "omega_p_grid": list(OMEGA_P_GRID), "omega_s_grid": list(OMEGA_S_GRID),
         "probe_iters": 10, "epochs": a.epochs, "loss_history": hist,
         "target_counts": {f"{wp:.3f},{ws:.2f}": best.count((wp, ws)) for wp, ws in sorted(set(best))}})

@@ -107,3 +107,34 @@ def test_trained_form_matches_oracle():
     assert info["converged"]
     assert np.linalg.norm(s.b - A @ xg) <= 1e-8 * np.linalg.norm(s.b) * (1 + 1e-6)
     assert abs(info["iterations"] - io.iterations) <= 1
+
+
+def test_mixed_network_adapts_per_field():
+    """The network trained on fields of varying contrast and coupling
+    (2d-64-mixed, seeds 1000-2999) on held-out fields of that family: it
+    converges on every field, including high-contrast ones where the fixed
+    method and the best single (omega_P, omega_S) pair of the training grid
+    stall, and stays close to that pair where both work."""
+    from paper_2103_07537_amd import learned
+    if not os.path.exists(learned.MIXED_WEIGHTS):
+        pytest.skip("no mixed-family network committed")
+    mlp = learned.load(learned.MIXED_WEIGHTS)
+    fixed, const, net = [], [], []
+    for seed in range(6000, 6012):
+        kw = learned.family_kwargs("2d-64-mixed", seed)
+        s = make_system(seed=seed, **kw)
+        i_f, _ = _solve(s)
+        i_c, _ = _solve(s, omega_p=5.0 / 6.0, omega=0.9)
+        i_n, r_n = _solve(s, mlp=mlp, judge=0)
+        log(f"  seed {seed} sigma {kw['sigma']:.2f} gamma {kw['gamma']:.2f}: fixed {i_f['iterations']}"
+            f"{'' if i_f['converged'] else '*'} pair {i_c['iterations']}{'' if i_c['converged'] else '*'}"
+            f" network {i_n['iterations']}{'' if i_n['converged'] else '*'}")
+        assert i_n["converged"] and r_n <= 1e-8 * (1 + 1e-6)
+        fixed.append(i_f["iterations"] if i_f["converged"] else None)
+        const.append(i_c["iterations"] if i_c["converged"] else None)
+        net.append(i_n["iterations"])
+    stalled = sum(c is None for c in const)
+    log(f"  the best grid pair stalls on {stalled} of 12 fields, the fixed method on {sum(f is None for f in fixed)}")
+    assert stalled >= 2
+    both = [(n, c) for n, c in zip(net, const) if c is not None]
+    assert np.median([n for n, _ in both]) <= 1.25 * np.median([c for _, c in both])
