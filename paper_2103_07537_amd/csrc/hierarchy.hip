@@ -113,6 +113,31 @@ struct TimedLaunch {
     double bytes;
 };
 
+// A second stream (default priority) with two events, released on scope exit.
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t ready = nullptr, done = nullptr;
+    SideStream() {
+        MB_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        MB_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        MB_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    }
+    ~SideStream() {
+        if (stream) { (void)hipStreamSynchronize(stream); (void)hipStreamDestroy(stream); }
+        if (ready) (void)hipEventDestroy(ready);
+        if (done) (void)hipEventDestroy(done);
+    }
+};
+
+// The coarsest inverse of a build while it is still running on its own stream:
+// members are released job first (its launches are all issued), then the
+// stream (drained), then the buffers.
+struct PendingCoarse {
+    CoarseWork w;
+    SideStream side;
+    std::future<void> job;
+};
+
 thread_local std::string g_last_error;
 
 // Krylov scalar buffer layout (device and pinned host copies)
@@ -148,6 +173,8 @@ struct mbamg_hierarchy {
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
     double t_setup_ms = 0.0;
+    // last member, so it is released first: a coarsest inverse still in flight
+    std::unique_ptr<PendingCoarse> coarse_pending;
 
     ~mbamg_hierarchy() {
         (void)hipDeviceSynchronize();
@@ -210,22 +237,6 @@ struct PhaseClock {
         std::fprintf(stderr, "[mbamg setup] level %d %-22s %8.2f ms\n", level, what,
                      std::chrono::duration<double, std::milli>(now - last).count());
         last = now;
-    }
-};
-
-// A second stream (default priority) with two events, released on scope exit.
-struct SideStream {
-    hipStream_t stream = nullptr;
-    hipEvent_t ready = nullptr, done = nullptr;
-    SideStream() {
-        MB_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
-        MB_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-        MB_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
-    }
-    ~SideStream() {
-        if (stream) { (void)hipStreamSynchronize(stream); (void)hipStreamDestroy(stream); }
-        if (ready) (void)hipEventDestroy(ready);
-        if (done) (void)hipEventDestroy(done);
     }
 };
 
@@ -538,7 +549,21 @@ static void clone_smoother(BlockLevel& d, const BlockLevel& b, hipStream_t s) {
 // donor: a hierarchy built from the same blocks with the same level-0
 // parameters (aggregation, precision); its level-0 aggregates and smoother
 // data are copied instead of recomputed.
-static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, const mbamg_hierarchy* donor) {
+// Join a build's coarsest inverse: the launches are issued, the inverse is
+// checked, and stream s waits for it.
+static void finish_coarse(mbamg_hierarchy* h, hipStream_t s) {
+    if (!h->coarse_pending) return;
+    PendingCoarse& pc = *h->coarse_pending;
+    pc.job.get();
+    MB_CHECK(pc.w.n == h->coarse_n, MBAMG_E_STATE, "internal: coarsest size");
+    coarse_inverse_finish(pc.w, pc.side.stream);
+    MB_HIP(hipEventRecord(pc.side.done, pc.side.stream));
+    MB_HIP(hipStreamWaitEvent(s, pc.side.done, 0));
+    h->coarse_pending.reset();
+}
+
+static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, const mbamg_hierarchy* donor,
+                       bool defer_coarse) {
     auto t0 = std::chrono::steady_clock::now();
     const mbamg_params& p = h->p;
     const int d0 = h->d[0], d1 = h->d[1];
@@ -546,8 +571,9 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
     MB_CHECK(N > 0, MBAMG_E_INVALID, "empty system");
     const bool want32 = p.precision == 1;
     PhaseClock clk(s);
-    CoarseWork cwork;   // declared first: the side stream is drained before its buffers are freed
-    SideStream side;
+    h->coarse_pending = std::make_unique<PendingCoarse>();
+    CoarseWork& cwork = h->coarse_pending->w;
+    SideStream& side = h->coarse_pending->side;
     // host colouring jobs per level; joined before their level's smoother data is built
     // (and, on an error, waited for when the futures go out of scope, before the events)
     std::vector<hipEvent_t> colour_events;
@@ -558,6 +584,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
     std::map<int, std::future<void>> colour_jobs;
     int device = 0;
     MB_HIP(hipGetDevice(&device));
+    std::future<void>& coarse_job = h->coarse_pending->job;
 
     // level 0 from the caller's blocks
     auto first = std::make_unique<Level>();
@@ -675,8 +702,14 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
         // the coarsest inverse runs on a second stream, overlapping the smoother data below
         MB_HIP(hipEventRecord(side.ready, s));
         MB_HIP(hipStreamWaitEvent(side.stream, side.ready, 0));
-        coarse_inverse_launch(c.A, c.d, h->coarse_inv, cwork, side.stream);
-        h->coarse_n = cwork.n;
+        // its thousands of small launches are issued from a host thread of their own, so this
+        // thread goes on queueing the smoother data at once
+        h->coarse_n = c.n * (c.d[0] + c.d[1]);
+        Level* cp = &c;
+        coarse_job = std::async(std::launch::async, [h, cp, &cwork, &side, device] {
+            MB_HIP(hipSetDevice(device));
+            coarse_inverse_launch(cp->A, cp->d, h->coarse_inv, cwork, side.stream);
+        });
         clk.mark("coarse inverse queued", (int)h->L.size() - 1);
         for (int f = 0; f < 2; ++f) {      // identity order
             BlockLevel& B = c.blk[f];
@@ -797,10 +830,10 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
     }
 
     clk.mark("smoother data done", 0);
-    coarse_inverse_finish(cwork, side.stream);
-    MB_HIP(hipEventRecord(side.done, side.stream));
-    MB_HIP(hipStreamWaitEvent(s, side.done, 0));
-    clk.mark("coarse inverse joined", 0);
+    if (!defer_coarse) {
+        finish_coarse(h, s);
+        clk.mark("coarse inverse joined", 0);
+    }
     // Krylov workspace
     h->n_fine = (int64_t)N * (d0 + d1);
     const int m = p.restart;
@@ -1296,20 +1329,22 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
             MB_CHECK(fm->n_vec[f] >= 0 && fm->n_vec[f] <= fm->dofs[f], MBAMG_E_INVALID, "n_vec out of range");
         hipStream_t s = (hipStream_t)hip_stream;
         auto t0 = std::chrono::steady_clock::now();
-        auto build = [&](const mbamg_params& pp, const mbamg_hierarchy* donor) {
+        auto build = [&](const mbamg_params& pp, const mbamg_hierarchy* donor, bool defer_coarse) {
             auto h = std::make_unique<mbamg_hierarchy>();
             h->p = pp;
             h->fm = *fm;
             h->d[0] = fm->dofs[0];
             h->d[1] = fm->dofs[1];
             if (pp.learned == 1) h->mlp.upload(pp.mlp, N_MLP_PARAMS + 2 * N_FEATURES, s);
-            setup_impl(h.get(), A_blocks, s, donor);
-            // the build's temporaries are idle now and can serve the next allocations
-            MB_HIP(hipDeviceSynchronize());
-            pool_device_idle();
+            setup_impl(h.get(), A_blocks, s, donor, defer_coarse);
+            if (!defer_coarse) {
+                // the build's temporaries are idle now and can serve the next allocations
+                MB_HIP(hipDeviceSynchronize());
+                pool_device_idle();
+            }
             return h;
         };
-        auto h = build(*p, nullptr);
+        auto h = build(*p, nullptr, false);
         h->info.used_learned = p->learned != 0;
         if (p->learned != 0 && p->judge) {
             // the fixed-weight method is the fallback and the judge
@@ -1317,9 +1352,12 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
             pf.learned = 0;
             pf.omega_p = 0.0;
             PhaseClock jclk(s);
-            auto hf = build(pf, h.get());   // shares the level-0 aggregates and smoother data
+            // shares the level-0 aggregates and smoother data; its coarsest inverse keeps running on
+            // its own stream while the learned hierarchy is probed
+            auto hf = build(pf, h.get(), true);
             jclk.mark("fixed hierarchy built", 0);
             const double rl = probe_impl(h.get(), 10, 12345, s);
+            finish_coarse(hf.get(), s);
             const double rf = probe_impl(hf.get(), 10, 12345, s);
             jclk.mark("judge probes", 0);
             h->judge_rho[0] = hf->judge_rho[0] = rl;
