@@ -1344,18 +1344,19 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
             }
             return h;
         };
-        auto h = build(*p, nullptr, false);
-        h->info.used_learned = p->learned != 0;
+        std::unique_ptr<mbamg_hierarchy> h;
         if (p->learned != 0 && p->judge) {
-            // the fixed-weight method is the fallback and the judge
+            // the fixed-weight method is the fallback and the judge.  It is built first: its
+            // coarsest inverse then runs on its own stream during the learned build, which
+            // copies the fixed build's level-0 aggregates and smoother data
             mbamg_params pf = *p;
             pf.learned = 0;
             pf.omega_p = 0.0;
             PhaseClock jclk(s);
-            // shares the level-0 aggregates and smoother data; its coarsest inverse keeps running on
-            // its own stream while the learned hierarchy is probed
-            auto hf = build(pf, h.get(), true);
+            auto hf = build(pf, nullptr, true);
             jclk.mark("fixed hierarchy built", 0);
+            h = build(*p, hf.get(), false);
+            jclk.mark("learned hierarchy built", 0);
             const double rl = probe_impl(h.get(), 10, 12345, s);
             finish_coarse(hf.get(), s);
             const double rf = probe_impl(hf.get(), 10, 12345, s);
@@ -1368,6 +1369,9 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
             } else {
                 h->info.used_learned = 1;
             }
+        } else {
+            h = build(*p, nullptr, false);
+            h->info.used_learned = p->learned != 0;
         }
         MB_HIP(hipDeviceSynchronize());
         pool_device_idle();
