@@ -907,75 +907,121 @@ __global__ void k_dense_scatter(int n_rows, int br, int bc, const int32_t* rp, c
     }
 }
 
-__global__ void k_gj_identity(double* M, int n) {   // right half of [A | I]
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)n * n) return;
-    int r = (int)(t / n), c = (int)(t % n);
-    M[(int64_t)r * 2 * n + n + c] = r == c ? 1.0 : 0.0;
+// ----------------------------------------------------------------------------
+// Coarsest inverse: Gauss-Jordan with partial (row) pivoting, in place on an
+// n x n matrix, one launch per column.  Step k reads the matrix of step k-1
+// (Ain) and writes the next one (Aout), so no thread reads what another writes
+// in the same launch.  With p the pivot row of column k and piv = Ain[p][k]:
+//   row k of Aout  = (Ain[p] with 1 in column k) / piv
+//   row r != k     = (Ain[s] with 0 in column k) - Ain[s][k] * (row k of Aout),
+//                    s = k for r == p (the row swapped out), else s = r
+// which leaves the inverse of the column-interchanged matrix; the interchanges
+// are undone in reverse order at the end.  One extra block of each launch
+// recomputes column k+1 of Aout by the same expressions (bit-identical: no
+// contraction in this unit) and chooses the next pivot (largest magnitude,
+// ties to the smaller row), so the pivot search needs no launch of its own.
+// ----------------------------------------------------------------------------
+struct GjPivot {
+    int p;
+    double piv;
+};
+
+__device__ inline double gj_value(const double* Ain, int n, int k, int p, double piv, int r, int c) {
+    const double prow = (c == k ? 1.0 : Ain[(int64_t)p * n + c]) / piv;
+    if (r == k) return prow;
+    const int src = r == p ? k : r;
+    const double f = Ain[(int64_t)src * n + k];
+    const double base = c == k ? 0.0 : Ain[(int64_t)src * n + c];
+    return base - f * prow;
 }
 
-// one block: choose the pivot row for column k, swap it into row k, scale
-// row k and save column k for the elimination
-__global__ void k_gj_pivot(double* M, int n, int k, double* colk, int32_t* singular) {
+// the pivot of `col` among rows >= k0 (one block of 1024 threads)
+__device__ inline void gj_argmax(double v, int r, int k0, int n, GjPivot* out, int32_t* perm_slot,
+                                 int32_t* singular) {
     __shared__ double bv[1024];
     __shared__ int bi[1024];
-    const int ld = 2 * n;
-    int t = threadIdx.x;
-    double best = -1.0;
-    int bidx = -1;
-    for (int r = k + t; r < n; r += blockDim.x) {
-        double v = fabs(M[(int64_t)r * ld + k]);
-        if (v > best) { best = v; bidx = r; }
-    }
-    bv[t] = best;
-    bi[t] = bidx;
+    __shared__ double bval[1024];
+    (void)n;
+    const int t = threadIdx.x;
+    bv[t] = (r >= k0) ? fabs(v) : -1.0;
+    bi[t] = (r >= k0) ? r : INT_MAX;
+    bval[t] = v;
     __syncthreads();
     for (int off = blockDim.x / 2; off > 0; off >>= 1) {
         if (t < off) {
-            double o = bv[t + off];
-            int oi = bi[t + off];
-            if (o > bv[t] || (o == bv[t] && oi >= 0 && (bi[t] < 0 || oi < bi[t]))) { bv[t] = o; bi[t] = oi; }
+            const double o = bv[t + off];
+            const int oi = bi[t + off];
+            if (o > bv[t] || (o == bv[t] && oi < bi[t])) {
+                bv[t] = o;
+                bi[t] = oi;
+                bval[t] = bval[t + off];
+            }
         }
         __syncthreads();
     }
-    int p = bi[0];
-    double pv = bv[0];
-    if (pv <= 0.0) {
-        if (t == 0) atomicAdd(singular, 1);
+    if (t == 0) {
+        // no finite candidate (a column of NaN after an earlier zero pivot): keep a valid row index
+        const int p = bi[0] == INT_MAX ? k0 : bi[0];
+        out->p = p;
+        out->piv = bi[0] == INT_MAX ? 0.0 : bval[0];
+        *perm_slot = p;
+        if (!(bv[0] > 0.0) || bi[0] == INT_MAX) atomicAdd(singular, 1);
+    }
+}
+
+// block-level argmax over a column whose rows are visited in strides
+__device__ inline void gj_column_pivot(const double* Ain, int n, int k, int p, double piv, int col, bool first,
+                                       GjPivot* out, int32_t* perm_slot, int32_t* singular) {
+    double best = -1.0, bestv = 0.0;
+    int bidx = INT_MAX;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        const double v = first ? Ain[(int64_t)r * n + col] : gj_value(Ain, n, k, p, piv, r, col);
+        if (r >= col && (fabs(v) > best || (fabs(v) == best && r < bidx))) {
+            best = fabs(v);
+            bestv = v;
+            bidx = r;
+        }
+    }
+    gj_argmax(bestv, bidx == INT_MAX ? -1 : bidx, col, n, out, perm_slot, singular);
+}
+
+__global__ __launch_bounds__(1024) void k_gj_first(const double* A, int n, GjPivot* st, int32_t* perm,
+                                                   int32_t* singular) {
+    gj_column_pivot(A, n, 0, 0, 1.0, 0, true, st, perm, singular);
+}
+
+__global__ __launch_bounds__(1024) void k_gj_step(const double* __restrict__ Ain, double* __restrict__ Aout, int n,
+                                                  int k, const GjPivot* cur, GjPivot* nxt, int32_t* perm,
+                                                  int32_t* singular, int bulk_blocks) {
+    const int p = cur->p;
+    const double piv = cur->piv;
+    if ((int)blockIdx.x == bulk_blocks) {   // the next column's pivot
+        if (k + 1 < n) gj_column_pivot(Ain, n, k, p, piv, k + 1, false, nxt, perm + k + 1, singular);
         return;
     }
-    if (p != k)
-        for (int c = t; c < ld; c += blockDim.x) {
-            double a = M[(int64_t)k * ld + c];
-            M[(int64_t)k * ld + c] = M[(int64_t)p * ld + c];
-            M[(int64_t)p * ld + c] = a;
-        }
-    __syncthreads();
-    double inv = 1.0 / M[(int64_t)k * ld + k];
-    __syncthreads();
-    for (int c = t; c < ld; c += blockDim.x) M[(int64_t)k * ld + c] *= inv;
-    __syncthreads();
-    for (int r = t; r < n; r += blockDim.x) colk[r] = M[(int64_t)r * ld + k];
-}
-
-__global__ void k_gj_eliminate(double* M, int n, int k, const double* colk) {
-    const int ld = 2 * n;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int width = ld - k;
-    if (t >= (int64_t)n * width) return;
-    int r = (int)(t / width);
-    int c = k + (int)(t % width);
-    if (r == k) return;
-    double f = colk[r];
-    if (f == 0.0) return;
-    M[(int64_t)r * ld + c] = M[(int64_t)r * ld + c] - f * M[(int64_t)k * ld + c];
-}
-
-__global__ void k_gj_extract(const double* M, int n, double* inv) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n * n) return;
-    int r = (int)(t / n), c = (int)(t % n);
-    inv[t] = M[(int64_t)r * 2 * n + n + c];
+    const int r = (int)(t / n), c = (int)(t % n);
+    Aout[t] = gj_value(Ain, n, k, p, piv, r, c);
+}
+
+// undo the column interchanges in reverse order: inv[:, c] = X[:, src[c]]
+__global__ void k_gj_unscramble(const int32_t* perm, int n, int32_t* src) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int c = 0; c < n; ++c) src[c] = c;
+    for (int k = n - 1; k >= 0; --k) {
+        const int q = perm[k];
+        const int a = src[k];
+        src[k] = src[q];
+        src[q] = a;
+    }
+}
+
+__global__ void k_gj_extract(const double* X, int n, const int32_t* src, double* inv) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * n) return;
+    const int r = (int)(t / n), c = (int)(t % n);
+    inv[t] = X[(int64_t)r * n + src[c]];
 }
 
 // ----------------------------------------------------------------------------
@@ -1340,30 +1386,39 @@ void coarse_inverse_launch(const SetupBsr (&A)[2][2], const int d[2], DevBuf<dou
     const int n = nn * (d[0] + d[1]);
     MB_CHECK(n <= 16384, MBAMG_E_INVALID, "coarsest level too large for the dense solve (raise max_levels)");
     w.n = n;
-    w.M.alloc((size_t)n * 2 * n);
-    w.colk.alloc(n);
+    w.M.alloc((size_t)2 * n * n);         // two n x n matrices, read and written alternately
+    w.colk.alloc(4);                      // two pivot records
     w.sing.alloc(1);
+    w.perm.alloc(std::max(n, 1));
+    w.src.alloc(std::max(n, 1));
     inv.alloc((size_t)n * n);
-    MB_HIP(hipMemsetAsync(w.M.p, 0, w.M.bytes(), s));
+    double* M0 = w.M.p;
+    double* M1 = w.M.p + (int64_t)n * n;
+    GjPivot* st = reinterpret_cast<GjPivot*>(w.colk.p);
+    MB_HIP(hipMemsetAsync(M0, 0, sizeof(double) * (size_t)n * n, s));
     int64_t off[2] = {0, (int64_t)nn * d[0]};
     for (int f = 0; f < 2; ++f)
         for (int g = 0; g < 2; ++g) {
             const SetupBsr& B = A[f][g];
             if (B.nnzb == 0) continue;
             k_dense_scatter<<<grid_for(nn, 64), 64, 0, s>>>(nn, B.br, B.bc, B.rp.p, B.ci.p, B.val.p, off[f], off[g],
-                                                           2 * (int64_t)n, w.M.p);
+                                                           (int64_t)n, M0);
             MB_LAUNCH_CHECK();
         }
-    k_gj_identity<<<grid_for((int64_t)n * n), 256, 0, s>>>(w.M.p, n);
-    MB_LAUNCH_CHECK();
     MB_HIP(hipMemsetAsync(w.sing.p, 0, sizeof(int32_t), s));
+    k_gj_first<<<1, 1024, 0, s>>>(M0, n, st, w.perm.p, w.sing.p);
+    MB_LAUNCH_CHECK();
+    const int bulk = (int)grid_for((int64_t)n * n, 1024);
     for (int k = 0; k < n; ++k) {
-        k_gj_pivot<<<1, 1024, 0, s>>>(w.M.p, n, k, w.colk.p, w.sing.p);
-        int64_t work = (int64_t)n * (2 * n - k);
-        k_gj_eliminate<<<grid_for(work), 256, 0, s>>>(w.M.p, n, k, w.colk.p);
+        const double* in = (k % 2 == 0) ? M0 : M1;
+        double* out = (k % 2 == 0) ? M1 : M0;
+        k_gj_step<<<bulk + 1, 1024, 0, s>>>(in, out, n, k, st + (k % 2), st + ((k + 1) % 2), w.perm.p, w.sing.p,
+                                           bulk);
     }
     MB_LAUNCH_CHECK();
-    k_gj_extract<<<grid_for((int64_t)n * n), 256, 0, s>>>(w.M.p, n, inv.p);
+    const double* X = (n % 2 == 0) ? M0 : M1;
+    k_gj_unscramble<<<1, 1, 0, s>>>(w.perm.p, n, w.src.p);
+    k_gj_extract<<<grid_for((int64_t)n * n), 256, 0, s>>>(X, n, w.src.p, inv.p);
     MB_LAUNCH_CHECK();
 }
 
@@ -1373,6 +1428,8 @@ void coarse_inverse_finish(CoarseWork& w, hipStream_t s) {
     MB_HIP(hipStreamSynchronize(s));
     w.M.release();
     w.colk.release();
+    w.perm.release();
+    w.src.release();
     MB_CHECK(h == 0, MBAMG_E_SINGULAR, "the coarsest matrix is singular");
 }
 
