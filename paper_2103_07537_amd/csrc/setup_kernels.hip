@@ -920,6 +920,7 @@ __global__ void k_dense_scatter(int n_rows, int br, int bc, const int32_t* rp, c
 // recomputes column k+1 of Aout by the same expressions (bit-identical: no
 // contraction in this unit) and chooses the next pivot (largest magnitude,
 // ties to the smaller row), so the pivot search needs no launch of its own.
+// That block is block 0, so it is dispatched before the bulk and overlaps it.
 // ----------------------------------------------------------------------------
 struct GjPivot {
     int p;
@@ -995,11 +996,13 @@ __global__ __launch_bounds__(1024) void k_gj_step(const double* __restrict__ Ain
                                                   int32_t* singular, int bulk_blocks) {
     const int p = cur->p;
     const double piv = cur->piv;
-    if ((int)blockIdx.x == bulk_blocks) {   // the next column's pivot
+    // block 0 (dispatched first, so it overlaps the bulk) chooses the next column's pivot
+    if (blockIdx.x == 0) {
         if (k + 1 < n) gj_column_pivot(Ain, n, k, p, piv, k + 1, false, nxt, perm + k + 1, singular);
         return;
     }
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    (void)bulk_blocks;
+    const int64_t t = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n * n) return;
     const int r = (int)(t / n), c = (int)(t % n);
     Aout[t] = gj_value(Ain, n, k, p, piv, r, c);
