@@ -12,8 +12,8 @@ NumPy/SciPy written to follow the paper's definitions:
 * Coarse operators by the Galerkin product of Sec. 3 with R = P^T and block
   diagonal transfers P = diag(P00, P11) (Sec. 4.3.1, eq. blocktransfers).
 * Aggregates built from the graph of A00 and cloned for block 1 (Sec. 4.3.1,
-  "cloning the Navier-Stokes aggregation"), piecewise-constant interpolation
-  for each solution component over each aggregate.
+  the aggregate-cloning figure), piecewise-constant interpolation for each
+  solution component over each aggregate.
 * Smoother: the damped block Gauss-Seidel of Algorithm 1 (Sec. 4.3.2); the
   approximate sub-block solves are multicolour nodal-block Gauss-Seidel sweeps
   started from zero.
@@ -470,6 +470,30 @@ def apply_A(lev: Level, x: np.ndarray) -> np.ndarray:
     x0, x1 = _split(lev, x)
     return np.concatenate([lev.csr[0][0] @ x0 + lev.csr[0][1] @ x1,
                            lev.csr[1][0] @ x0 + lev.csr[1][1] @ x1])
+
+
+def apply_rows(blocks, dofs, x: np.ndarray, nodes: np.ndarray, absolute: bool = False) -> np.ndarray:
+    """(A x) on the given nodes' rows of both fields, straight from the
+    definition of the 2x2 block system (Sec. 4.2, eq. 2x2system): for node i
+    of field f, sum over g and over the blocks A_fg[i, j] of row i of
+    A_fg[i, j] x_g[j].  With ``absolute`` the same sums of |A| |x| (the scale
+    of the rounding error of any evaluation order).  Returns an array
+    (len(nodes), dofs[0] + dofs[1])."""
+    N = blocks[0][0].n_brows
+    xs = [x[:N * dofs[0]].reshape(N, dofs[0]), x[N * dofs[0]:].reshape(N, dofs[1])]
+    out = np.zeros((len(nodes), dofs[0] + dofs[1]))
+    for k, i in enumerate(np.asarray(nodes)):
+        for f in range(2):
+            acc = np.zeros(dofs[f])
+            for g in range(2):
+                B = blocks[f][g]
+                for p in range(B.row_ptr[i], B.row_ptr[i + 1]):
+                    if absolute:
+                        acc += np.abs(B.vals[p]) @ np.abs(xs[g][B.col_idx[p]])
+                    else:
+                        acc += B.vals[p] @ xs[g][B.col_idx[p]]
+            out[k, (0 if f == 0 else dofs[0]):(dofs[0] if f == 0 else dofs[0] + dofs[1])] = acc
+    return out
 
 
 def mgv(h: Hierarchy, lvl: int, b: np.ndarray) -> np.ndarray:

@@ -368,3 +368,17 @@ def test_gmres_restarts_and_reports_true_residual():
     rel = np.linalg.norm(s.b - A @ x) / np.linalg.norm(s.b)
     assert info.converged and info.iterations > 5 and rel <= 1e-9
     assert info.rel_residual == pytest.approx(rel, rel=1e-6)
+
+
+def test_apply_rows_equals_dense_product():
+    """The row-by-row apply is the block system's matrix-vector product."""
+    from oracle import amg
+    s = make_system(7, 2, 0.8, seed=4, kappa="lognormal", blk1_scale=2.0, a10_scale=0.5)
+    x = np.random.default_rng(3).standard_normal(s.n_dofs)
+    ref = s.to_scipy().toarray() @ x
+    nodes = np.array([0, 3, 17, 48])
+    got = amg.apply_rows(s.blocks, s.dofs, x, nodes)
+    N = s.N
+    for k, i in enumerate(nodes):
+        want = np.concatenate([ref[i * 3:(i + 1) * 3], ref[N * 3 + i * 3:N * 3 + (i + 1) * 3]])
+        assert np.allclose(got[k], want, rtol=1e-13, atol=1e-13)
