@@ -78,6 +78,11 @@ struct BlockLevel {
     // smoothed transfers: P rows of this level, P^T rows of the next level (sliced by the next level)
     SellPart pro, res;
     int pro_split = 1, res_split = 1;          // waves per slice in the transfer kernels
+    // coarse levels with long rows: the smoother and residual run on the row form
+    bool rows = false;
+    RowPart raff, rafg;
+    DevBuf<double> rdinv64;
+    DevBuf<float> rdinv32;
     // transfer to the next level (colour orders of both levels)
     DevBuf<int32_t> agg_p, mem_ptr, mem_idx;
     DevBuf<double> q64;
@@ -788,9 +793,23 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
             const double avg_width = B.n_slices ? (double)slots / B.n_slices : 0.0;
             const double per_colour = (double)B.n_slices / std::max(1, B.n_colours);
             B.split = slot_split(per_colour, avg_width);
+            // long rows (dense coarse stencils): one wavefront per row instead
+            B.rows = l > 0 && Lv.A[f][f].nnzb >= (int64_t)32 * Lv.n;
+            if (B.rows) {
+                build_rows(B.raff, Lv.n, B.d_perm.p, Lv.A[f][f], B.d_iperm.p, want32, s);
+                build_rows(B.rafg, Lv.n, B.d_perm.p, Lv.A[f][g], Lv.blk[g].d_iperm.p, want32, s);
+                B.rdinv64.alloc((size_t)Lv.n * df * df);
+                gather_blocks(Lv.n, df * df, B.d_perm.p, dinv.p, B.rdinv64.p, s);
+                if (want32) {
+                    B.rdinv32.alloc((size_t)Lv.n * df * df);
+                    cast_to_f32(B.rdinv64.p, B.rdinv32.p, (int64_t)Lv.n * df * df, s);
+                }
+                MB_HIP(hipStreamSynchronize(s));   // dinv is released at the end of this iteration
+            }
             if (clk.on)
                 std::fprintf(stderr, "[mbamg setup] level %d block %d: %d nodes, %d colours, %d slices, %.1f slots/slice, "
-                             "split %d\n", l, f, Lv.n, B.n_colours, B.n_slices, avg_width, B.split);
+                             "split %d%s\n", l, f, Lv.n, B.n_colours, B.n_slices, avg_width, B.split,
+                             B.rows ? ", row form" : "");
         }
         clk.mark("sliced parts", l);
         // transfers between this level's and the next level's colour orders
@@ -914,6 +933,19 @@ template <>
 Vecs<float>& vecs<float>(Level& L) { return L.v32; }
 
 template <class T>
+static RowView<T> rview(const RowPart& R);
+template <>
+RowView<double> rview<double>(const RowPart& R) { return {R.rp.p, R.col.p, R.v64.p}; }
+template <>
+RowView<float> rview<float>(const RowPart& R) { return {R.rp.p, R.col.p, R.v32.p}; }
+template <class T>
+static const T* rdinv(const BlockLevel& B);
+template <>
+const double* rdinv<double>(const BlockLevel& B) { return B.rdinv64.p; }
+template <>
+const float* rdinv<float>(const BlockLevel& B) { return B.rdinv32.p; }
+
+template <class T>
 static const T* qptr(const BlockLevel& B);
 template <>
 const double* qptr<double>(const BlockLevel& B) { return B.q64.p; }
@@ -937,6 +969,28 @@ static void smooth_block(mbamg_hierarchy* h, int l, int f, bool zero, const T* b
     T* tbuf = vecs<T>(Lv).t.p + off;
     const bool has_cpl = xg != nullptr;
     const bool timed = h->timing && l == 0;
+    if (B.rows) {
+        for (int k = 0; k < h->p.inner_sweeps; ++k)
+            for (int c = 0; c < B.n_colours; ++c) {
+                GsRowArgs<T> a{};
+                a.r_begin = B.colour_row[c];
+                a.r_count = B.colour_row[c + 1] - B.colour_row[c];
+                a.aff = rview<T>(B.raff);
+                a.afg = rview<T>(B.rafg);
+                a.dinv = rdinv<T>(B);
+                a.b = b;
+                a.x = x;
+                a.t = tbuf;
+                a.xn = xn;
+                a.xg = xg;
+                a.cstart = k == 0 ? B.colour_row[c] : INT_MAX;
+                a.omega = (T)h->p.omega;
+                a.w_row = Lv.damped ? wrow<T>(B) : nullptr;
+                a.skip_off = (zero && k == 0 && c == 0) ? 1 : 0;
+                launch_gs_rows<T>(B.d, zero, has_cpl, a, s);
+            }
+        return;
+    }
     for (int k = 0; k < h->p.inner_sweeps; ++k) {
         for (int c = 0; c < B.n_colours; ++c) {
             GsArgs<T> a{};
@@ -983,6 +1037,19 @@ static void resid(mbamg_hierarchy* h, int l, const T* b, const T* x, T* r, hipSt
     const bool timed = h->timing && l == 0 && kind >= 0;
     double bytes = timed ? resid_bytes(Lv, (int)sizeof(T), b != nullptr) : 0.0;
     TimerScope ts(h, s, timed, kind, bytes);
+    if (Lv.blk[0].rows && Lv.blk[1].rows) {
+        ResidRowArgs<T> ra{};
+        for (int f = 0; f < 2; ++f) {
+            ra.n[f] = Lv.n;
+            ra.aff[f] = rview<T>(Lv.blk[f].raff);
+            ra.afg[f] = rview<T>(Lv.blk[f].rafg);
+            ra.b[f] = a.b[f];
+            ra.x[f] = a.x[f];
+            ra.r[f] = a.r[f];
+        }
+        launch_resid_rows<T>(Lv.d[0], ra, s);
+        return;
+    }
     launch_resid<T>(Lv.d[0], std::max(Lv.blk[0].split, Lv.blk[1].split), a, s);
 }
 

@@ -49,6 +49,21 @@ SetupBsr block_transpose(const SetupBsr& P, hipStream_t s);
 // C = A B; `like`, when given, is a product whose operands had the same
 // patterns as A and B: its pattern is reused and only the values are computed
 SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s, const SetupBsr* like = nullptr);
+// A block row in row form (see RowView): rows in the colour order `perm`
+// (colour position -> natural node), columns mapped through `col_iperm`
+// (natural node -> colour position of the column block).
+struct RowPart {
+    int br = 0, bc = 0;
+    int64_t nnzb = 0;
+    DevBuf<int32_t> rp, col;
+    DevBuf<double> v64;
+    DevBuf<float> v32;
+};
+void build_rows(RowPart& R, int n, const int32_t* perm, const SetupBsr& A, const int32_t* col_iperm, bool want32,
+                hipStream_t s);
+// dst[p] = src[perm[p]] for blocks of bs values
+void gather_blocks(int n, int bs, const int32_t* perm, const double* src, double* dst, hipStream_t s);
+
 // true when X and Y have identical block patterns (synchronous)
 bool same_pattern(const SetupBsr& X, const SetupBsr& Y, hipStream_t s);
 // device construction of the sliced smoother format (see hierarchy.hip)

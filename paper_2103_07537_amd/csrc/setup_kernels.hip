@@ -1244,6 +1244,69 @@ SetupBsr block_transpose(const SetupBsr& P, hipStream_t s) {
     return T;
 }
 
+__global__ void k_rows_count(int n, const int32_t* perm, const int32_t* rp, int32_t* cnt) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int node = perm[p];
+    cnt[p] = rp[node + 1] - rp[node];
+}
+
+__global__ void k_rows_fill(int n, int bs, const int32_t* perm, const int32_t* rp, const int32_t* ci,
+                            const double* val, const int32_t* col_iperm, const int32_t* rrp, int32_t* rcol,
+                            double* rval) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int node = perm[p];
+    int q = rrp[p];
+    for (int k = rp[node]; k < rp[node + 1]; ++k, ++q) {
+        rcol[q] = col_iperm[ci[k]];
+        for (int e = 0; e < bs; ++e) rval[(int64_t)q * bs + e] = val[(int64_t)k * bs + e];
+    }
+}
+
+__global__ void k_gather_blocks(int n, int bs, const int32_t* perm, const double* src, double* dst) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * bs) return;
+    const int p = (int)(t / bs), e = (int)(t % bs);
+    dst[t] = src[(int64_t)perm[p] * bs + e];
+}
+
+void build_rows(RowPart& R, int n, const int32_t* perm, const SetupBsr& A, const int32_t* col_iperm, bool want32,
+                hipStream_t s) {
+    R.br = A.br;
+    R.bc = A.bc;
+    const int bs = A.br * A.bc;
+    R.rp.alloc(n + 1);
+    if (A.nnzb == 0 || n == 0) {
+        MB_HIP(hipMemsetAsync(R.rp.p, 0, sizeof(int32_t) * (n + 1), s));
+        R.nnzb = 0;
+        R.col.alloc(1);
+        R.v64.alloc(1);
+        if (want32) R.v32.alloc(1);
+        return;
+    }
+    DevBuf<int32_t> cnt(n);
+    k_rows_count<<<grid_for(n), 256, 0, s>>>(n, perm, A.rp.p, cnt.p);
+    MB_LAUNCH_CHECK();
+    R.nnzb = scan_exclusive(cnt.p, n, R.rp.p, s);
+    R.col.alloc(std::max<int64_t>(R.nnzb, 1));
+    R.v64.alloc(std::max<int64_t>(R.nnzb * bs, 1));
+    k_rows_fill<<<grid_for(n), 256, 0, s>>>(n, bs, perm, A.rp.p, A.ci.p, A.val.p, col_iperm, R.rp.p, R.col.p,
+                                            R.v64.p);
+    MB_LAUNCH_CHECK();
+    if (want32) {
+        R.v32.alloc(std::max<int64_t>(R.nnzb * bs, 1));
+        cast_to_f32(R.v64.p, R.v32.p, R.nnzb * bs, s);
+    }
+    MB_HIP(hipStreamSynchronize(s));   // cnt is released on return
+}
+
+void gather_blocks(int n, int bs, const int32_t* perm, const double* src, double* dst, hipStream_t s) {
+    if (n == 0) return;
+    k_gather_blocks<<<grid_for((int64_t)n * bs), 256, 0, s>>>(n, bs, perm, src, dst);
+    MB_LAUNCH_CHECK();
+}
+
 bool same_pattern(const SetupBsr& X, const SetupBsr& Y, hipStream_t s) {
     if (X.n_rows != Y.n_rows || X.n_cols != Y.n_cols || X.nnzb != Y.nnzb) return false;
     if (X.n_rows == 0 || X.nnzb == 0) return true;

@@ -43,6 +43,42 @@ struct GsArgs {
     int skip_off;              // nothing processed yet and zero start: the A_ff term vanishes
 };
 
+// A block row of a coarse level in row form: rows in colour order, each row's
+// blocks contiguous (row-major br x bc) with columns in the column block's
+// colour order.  Used where rows are long (dense coarse stencils): one
+// wavefront per row, its lanes over the row's blocks.
+template <class T>
+struct RowView {
+    const int32_t* rp;         // rows + 1
+    const int32_t* col;
+    const T* val;
+};
+
+template <class T>
+struct GsRowArgs {
+    int r_begin, r_count;      // rows of this colour
+    RowView<T> aff, afg;       // A_ff with its diagonal block (skipped here), A_fg
+    const T* dinv;             // d x d per row, colour order
+    const T* b;
+    const T* x;
+    T* t;
+    T* xn;
+    const T* xg;
+    int cstart;
+    T omega;
+    const T* w_row;
+    int skip_off;
+};
+
+template <class T>
+struct ResidRowArgs {
+    int n[2];
+    RowView<T> aff[2], afg[2];
+    const T* b[2];             // NULL for a plain operator apply
+    const T* x[2];
+    T* r[2];
+};
+
 template <class T>
 struct ResidArgs {
     int s_count[2];
@@ -81,6 +117,10 @@ template <class T>
 void launch_gs(int d, int P, bool zero_x, bool has_cpl, const GsArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_resid(int d, int P, const ResidArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_gs_rows(int d, bool zero_x, bool has_cpl, const GsRowArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_resid_rows(int d, const ResidRowArgs<T>& a, hipStream_t s);
 
 template <class T>
 void launch_restrict(int d, const TransferArgs<T>& a, hipStream_t s);

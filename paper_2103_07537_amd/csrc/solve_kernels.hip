@@ -233,6 +233,139 @@ __global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_gs(GsArgs<T> a,
     store_vec<T, D>(a.xn + (int64_t)row * D, xn);
 }
 
+// ---------------------------------------------------------------------------
+// Row-form kernels for coarse levels: one wavefront per row, lanes over the
+// row's blocks, partial sums combined across the wavefront.
+// ---------------------------------------------------------------------------
+// a dense block of N values, with 16-byte loads where the size allows (blocks
+// are stored back to back, so a block of 4 or 16 entries is 16-byte aligned)
+template <class T, int N>
+__device__ __forceinline__ void load_block(const T* __restrict__ p, T (&v)[N]) {
+    if constexpr (sizeof(T) == 4 && N % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < N / 4; ++k) {
+            const float4 q = reinterpret_cast<const float4*>(p)[k];
+            v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
+        }
+    } else if constexpr (sizeof(T) == 8 && N % 2 == 0) {
+#pragma unroll
+        for (int k = 0; k < N / 2; ++k) {
+            const double2 q = reinterpret_cast<const double2*>(p)[k];
+            v[2 * k] = q.x; v[2 * k + 1] = q.y;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = p[k];
+    }
+}
+
+template <class T, int D, int DG, int MODE, bool SKIP_DIAG>
+__device__ __forceinline__ void row_sub(const RowView<T>& A, int row, int lane, const T* __restrict__ xa,
+                                        const T* __restrict__ xb, int cstart, T (&acc)[D]) {
+    const int e = A.rp[row + 1];
+    for (int p = A.rp[row] + lane; p < e; p += WAVE) {
+        const int j = A.col[p];
+        if (SKIP_DIAG && j == row) continue;
+        const T* src;
+        if (MODE == 0) src = xa;
+        else if (MODE == 1) src = j < cstart ? xa : xb;
+        else src = j < cstart ? xa : nullptr;
+        if (!src) continue;
+        T xj[DG];
+        load_vec<T, DG>(src + (int64_t)j * DG, xj);
+        T blk[D * DG];
+        load_block<T, D * DG>(A.val + (int64_t)p * D * DG, blk);
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < DG; ++c) acc[r] -= blk[r * DG + c] * xj[c];
+    }
+}
+
+template <class T, int D>
+__device__ __forceinline__ void wave_sum_vec(T (&acc)[D]) {
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+        for (int off = WAVE / 2; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
+}
+
+// One colour of the block row's Gauss-Seidel sub-solve (the arithmetic of k_gs).
+template <class T, int D, bool ZX, bool CPL>
+__global__ __launch_bounds__(256) void k_gs_rows(GsRowArgs<T> a) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = blockIdx.x * WPB + wave_id();
+    if (w >= a.r_count) return;   // whole wavefront
+    const int row = a.r_begin + w;
+    T acc[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) acc[r] = T(0);
+    if (!a.skip_off) {
+        if (ZX) row_sub<T, D, D, 2, true>(a.aff, row, lane, a.t, nullptr, a.cstart, acc);
+        else row_sub<T, D, D, 1, true>(a.aff, row, lane, a.t, a.x, a.cstart, acc);
+    }
+    if (CPL) row_sub<T, D, D, 0, false>(a.afg, row, lane, a.xg, nullptr, 0, acc);
+    wave_sum_vec<T, D>(acc);
+    if (lane != 0) return;
+    T bb[D];
+    load_vec<T, D>(a.b + (int64_t)row * D, bb);
+#pragma unroll
+    for (int r = 0; r < D; ++r) acc[r] += bb[r];
+    const T* dv = a.dinv + (int64_t)row * D * D;
+    T tn[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        T sum = T(0);
+#pragma unroll
+        for (int c = 0; c < D; ++c) sum += dv[r * D + c] * acc[c];
+        tn[r] = sum;
+    }
+    const T wgt = a.w_row ? a.w_row[row] : a.omega;
+    T xn[D];
+    if (ZX) {
+#pragma unroll
+        for (int r = 0; r < D; ++r) xn[r] = wgt * tn[r];
+    } else {
+        T xo[D];
+        load_vec<T, D>(a.x + (int64_t)row * D, xo);
+#pragma unroll
+        for (int r = 0; r < D; ++r) xn[r] = xo[r] + wgt * (tn[r] - xo[r]);
+    }
+    store_vec<T, D>(a.t + (int64_t)row * D, tn);
+    store_vec<T, D>(a.xn + (int64_t)row * D, xn);
+}
+
+// r = b - A x (or w = A x when b is NULL), rows of block 0 then block 1
+template <class T, int D>
+__global__ __launch_bounds__(256) void k_resid_rows(ResidRowArgs<T> a) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    int row = blockIdx.x * WPB + wave_id();
+    int f = 0;
+    if (row >= a.n[0]) {
+        row -= a.n[0];
+        f = 1;
+        if (row >= a.n[1]) return;   // whole wavefront
+    }
+    const int g = 1 - f;
+    T acc[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) acc[r] = T(0);
+    row_sub<T, D, D, 0, false>(a.aff[f], row, lane, a.x[f], nullptr, 0, acc);
+    row_sub<T, D, D, 0, false>(a.afg[f], row, lane, a.x[g], nullptr, 0, acc);
+    wave_sum_vec<T, D>(acc);
+    if (lane != 0) return;
+    T out[D];
+    if (a.b[f]) {
+        T bb[D];
+        load_vec<T, D>(a.b[f] + (int64_t)row * D, bb);
+#pragma unroll
+        for (int r = 0; r < D; ++r) out[r] = bb[r] + acc[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < D; ++r) out[r] = -acc[r];
+    }
+    store_vec<T, D>(a.r[f] + (int64_t)row * D, out);
+}
+
 // r = b - A x (or w = A x when b is NULL) for both block rows in one launch.
 template <class T, int D, int P>
 __global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_resid(ResidArgs<T> a, int padded_blocks) {
@@ -423,6 +556,50 @@ void launch_gs(int d, int P, bool zero_x, bool has_cpl, const GsArgs<T>& a, hipS
     }
     MB_LAUNCH_CHECK();
 }
+
+template <class T, int D>
+static void gs_rows_dispatch(bool zx, bool cpl, const GsRowArgs<T>& a, hipStream_t s) {
+    const unsigned grid = (unsigned)ceil_div(a.r_count, WPB);
+    if (zx) {
+        if (cpl) k_gs_rows<T, D, true, true><<<grid, 256, 0, s>>>(a);
+        else k_gs_rows<T, D, true, false><<<grid, 256, 0, s>>>(a);
+    } else {
+        if (cpl) k_gs_rows<T, D, false, true><<<grid, 256, 0, s>>>(a);
+        else k_gs_rows<T, D, false, false><<<grid, 256, 0, s>>>(a);
+    }
+}
+
+template <class T>
+void launch_gs_rows(int d, bool zero_x, bool has_cpl, const GsRowArgs<T>& a, hipStream_t s) {
+    if (a.r_count <= 0) return;
+    switch (d) {
+        case 1: gs_rows_dispatch<T, 1>(zero_x, has_cpl, a, s); break;
+        case 2: gs_rows_dispatch<T, 2>(zero_x, has_cpl, a, s); break;
+        case 3: gs_rows_dispatch<T, 3>(zero_x, has_cpl, a, s); break;
+        case 4: gs_rows_dispatch<T, 4>(zero_x, has_cpl, a, s); break;
+        default: throw Error(MBAMG_E_INVALID, "dofs per node must be 1..4");
+    }
+    MB_LAUNCH_CHECK();
+}
+template void launch_gs_rows<double>(int, bool, bool, const GsRowArgs<double>&, hipStream_t);
+template void launch_gs_rows<float>(int, bool, bool, const GsRowArgs<float>&, hipStream_t);
+
+template <class T>
+void launch_resid_rows(int d, const ResidRowArgs<T>& a, hipStream_t s) {
+    const int total = a.n[0] + a.n[1];
+    if (total <= 0) return;
+    const unsigned grid = (unsigned)ceil_div(total, WPB);
+    switch (d) {
+        case 1: k_resid_rows<T, 1><<<grid, 256, 0, s>>>(a); break;
+        case 2: k_resid_rows<T, 2><<<grid, 256, 0, s>>>(a); break;
+        case 3: k_resid_rows<T, 3><<<grid, 256, 0, s>>>(a); break;
+        case 4: k_resid_rows<T, 4><<<grid, 256, 0, s>>>(a); break;
+        default: throw Error(MBAMG_E_INVALID, "dofs per node must be 1..4");
+    }
+    MB_LAUNCH_CHECK();
+}
+template void launch_resid_rows<double>(int, const ResidRowArgs<double>&, hipStream_t);
+template void launch_resid_rows<float>(int, const ResidRowArgs<float>&, hipStream_t);
 
 template <class T, int D>
 static void resid_dispatch(int P, const ResidArgs<T>& a, hipStream_t s) {
