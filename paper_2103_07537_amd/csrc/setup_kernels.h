@@ -83,8 +83,8 @@ void transfer_maps(int n, int nc, const int32_t* perm, const int32_t* iperm, con
 // queued on stream s; coarse_inverse_finish waits for it and checks pivots.
 struct CoarseWork {
     int n = 0;
-    DevBuf<double> M, colk;            // two n x n matrices; two pivot records
-    DevBuf<int32_t> sing, perm, src;   // singular flag; row interchanges; column source map
+    DevBuf<double> M;                    // two n x n matrices (ping-pong)
+    DevBuf<int32_t> sing, rowsrc, ord;   // singular flag; a panel's row sources; row order (two copies)
 };
 void coarse_inverse_launch(const SetupBsr (&A)[2][2], const int d[2], DevBuf<double>& inv, CoarseWork& w,
                            hipStream_t s);

@@ -9,6 +9,8 @@
 // (which compare those numbers) reproducible.
 #include "setup_kernels.h"
 
+#include <utility>
+
 namespace mbamg {
 
 // ----------------------------------------------------------------------------
@@ -908,123 +910,196 @@ __global__ void k_dense_scatter(int n_rows, int br, int bc, const int32_t* rp, c
 }
 
 // ----------------------------------------------------------------------------
-// Coarsest inverse: Gauss-Jordan with partial (row) pivoting, in place on an
-// n x n matrix, one launch per column.  Step k reads the matrix of step k-1
-// (Ain) and writes the next one (Aout), so no thread reads what another writes
-// in the same launch.  With p the pivot row of column k and piv = Ain[p][k]:
-//   row k of Aout  = (Ain[p] with 1 in column k) / piv
-//   row r != k     = (Ain[s] with 0 in column k) - Ain[s][k] * (row k of Aout),
-//                    s = k for r == p (the row swapped out), else s = r
-// which leaves the inverse of the column-interchanged matrix; the interchanges
-// are undone in reverse order at the end.  One extra block of each launch
-// recomputes column k+1 of Aout by the same expressions (bit-identical: no
-// contraction in this unit) and chooses the next pivot (largest magnitude,
-// ties to the smaller row), so the pivot search needs no launch of its own.
-// That block is block 0, so it is dispatched before the bulk and overlaps it.
+// Coarsest inverse: blocked Gauss-Jordan with partial (row) pivoting.
+//
+// One Gauss-Jordan step on column k with pivot row p and piv = M[p][k] trades
+// rows p and k, scales the new row k by 1/piv (1/piv in column k), and
+// subtracts M[r][k] times it from every other row r (which then holds
+// -M[r][k]/piv in column k).  Panels of B columns: one workgroup holds the
+// panel's n x B entries in registers and runs its B steps on them alone,
+// recording for every row the row whose data it now holds (rowsrc).  The
+// panel then holds the columns in which the composite transformation T of its
+// steps differs from the identity, so every other column x (the inverse built
+// so far on the left, the untouched matrix on the right) becomes
+//   T P x = P x + (G - E) (P x)[panel rows],   (P x)[r] = x[rowsrc[r]],
+// G the panel and E the panel's columns of the identity: one tiled rank-B
+// update, written to the other half of a ping-pong pair so that reads of
+// x[rowsrc[r]] never see updated values.  The product of the row interchanges
+// (ord) is carried along; the columns of the result are finally scattered to
+// ord, which undoes the column interchanges that in-place Gauss-Jordan
+// inversion leaves (Quintana-Orti, Quintana-Orti, van de Geijn & Remon, "A
+// note on parallel matrix inversion", SIAM J. Sci. Comput. 22, 2001).
 // ----------------------------------------------------------------------------
-struct GjPivot {
-    int p;
-    double piv;
+constexpr int GJ_TILE = 64;
+
+template <int T, int B>
+struct GjShared {
+    double wbest[T / WAVE];
+    int widx[T / WAVE];
+    double rowk[B];
 };
 
-__device__ inline double gj_value(const double* Ain, int n, int k, int p, double piv, int r, int c) {
-    const double prow = (c == k ? 1.0 : Ain[(int64_t)p * n + c]) / piv;
-    if (r == k) return prow;
-    const int src = r == p ? k : r;
-    const double f = Ain[(int64_t)src * n + k];
-    const double base = c == k ? 0.0 : Ain[(int64_t)src * n + c];
-    return base - f * prow;
-}
-
-// the pivot of `col` among rows >= k0 (one block of 1024 threads)
-__device__ inline void gj_argmax(double v, int r, int k0, int n, GjPivot* out, int32_t* perm_slot,
-                                 int32_t* singular) {
-    __shared__ double bv[1024];
-    __shared__ int bi[1024];
-    __shared__ double bval[1024];
-    (void)n;
-    const int t = threadIdx.x;
-    bv[t] = (r >= k0) ? fabs(v) : -1.0;
-    bi[t] = (r >= k0) ? r : INT_MAX;
-    bval[t] = v;
+// Step KK of a panel (KK a compile-time index, so that v stays in registers).
+// Rows are never moved inside the panel: lab[j] is the position that the
+// thread's j-th row holds in the row order so far, and a row interchange
+// exchanges two labels.
+template <int T, int R, int B, int KK>
+__device__ __forceinline__ void gj_panel_step(double (&v)[R][B], int (&lab)[R], int n, int k0, GjShared<T, B>& sh,
+                                              int32_t* singular) {
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
+    const int k = k0 + KK;
+    // pivot: largest magnitude in column k at position k or below, ties to the smaller position
+    double best = -1.0;
+    int bi = INT_MAX;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const double a = fabs(v[j][KK]);
+        if (lab[j] >= k && lab[j] < n && (a > best || (a == best && lab[j] < bi))) {
+            best = a;
+            bi = lab[j];
+        }
+    }
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    if (lane == 0) {
+        sh.wbest[wv] = best;
+        sh.widx[wv] = bi;
+    }
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if (t < off) {
-            const double o = bv[t + off];
-            const int oi = bi[t + off];
-            if (o > bv[t] || (o == bv[t] && oi < bi[t])) {
-                bv[t] = o;
-                bi[t] = oi;
-                bval[t] = bval[t + off];
-            }
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-        // no finite candidate (a column of NaN after an earlier zero pivot): keep a valid row index
-        const int p = bi[0] == INT_MAX ? k0 : bi[0];
-        out->p = p;
-        out->piv = bi[0] == INT_MAX ? 0.0 : bval[0];
-        *perm_slot = p;
-        if (!(bv[0] > 0.0) || bi[0] == INT_MAX) atomicAdd(singular, 1);
-    }
-}
-
-// block-level argmax over a column whose rows are visited in strides
-__device__ inline void gj_column_pivot(const double* Ain, int n, int k, int p, double piv, int col, bool first,
-                                       GjPivot* out, int32_t* perm_slot, int32_t* singular) {
-    double best = -1.0, bestv = 0.0;
-    int bidx = INT_MAX;
-    for (int r = threadIdx.x; r < n; r += blockDim.x) {
-        const double v = first ? Ain[(int64_t)r * n + col] : gj_value(Ain, n, k, p, piv, r, col);
-        if (r >= col && (fabs(v) > best || (fabs(v) == best && r < bidx))) {
-            best = fabs(v);
-            bestv = v;
-            bidx = r;
+    best = sh.wbest[0];
+    bi = sh.widx[0];
+#pragma unroll
+    for (int w = 1; w < T / WAVE; ++w) {
+        const double ob = sh.wbest[w];
+        const int oi = sh.widx[w];
+        if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
         }
     }
-    gj_argmax(bestv, bidx == INT_MAX ? -1 : bidx, col, n, out, perm_slot, singular);
-}
-
-__global__ __launch_bounds__(1024) void k_gj_first(const double* A, int n, GjPivot* st, int32_t* perm,
-                                                   int32_t* singular) {
-    gj_column_pivot(A, n, 0, 0, 1.0, 0, true, st, perm, singular);
-}
-
-__global__ __launch_bounds__(1024) void k_gj_step(const double* __restrict__ Ain, double* __restrict__ Aout, int n,
-                                                  int k, const GjPivot* cur, GjPivot* nxt, int32_t* perm,
-                                                  int32_t* singular, int bulk_blocks) {
-    const int p = cur->p;
-    const double piv = cur->piv;
-    // block 0 (dispatched first, so it overlaps the bulk) chooses the next column's pivot
-    if (blockIdx.x == 0) {
-        if (k + 1 < n) gj_column_pivot(Ain, n, k, p, piv, k + 1, false, nxt, perm + k + 1, singular);
-        return;
+    // no finite candidate (NaN after an earlier zero pivot): keep a valid row
+    const int lp = bi == INT_MAX ? k : bi;
+    if (t == 0 && (!(best > 0.0) || bi == INT_MAX)) atomicAdd(singular, 1);
+    // the owner of the pivot row publishes the new row k
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (__any(lab[j] == lp) && lab[j] == lp) {
+            const double inv = 1.0 / v[j][KK];
+#pragma unroll
+            for (int c = 0; c < B; ++c) sh.rowk[c] = c == KK ? inv : v[j][c] * inv;
+        }
     }
-    (void)bulk_blocks;
-    const int64_t t = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)n * n) return;
-    const int r = (int)(t / n), c = (int)(t % n);
-    Aout[t] = gj_value(Ain, n, k, p, piv, r, c);
-}
-
-// undo the column interchanges in reverse order: inv[:, c] = X[:, src[c]]
-__global__ void k_gj_unscramble(const int32_t* perm, int n, int32_t* src) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    for (int c = 0; c < n; ++c) src[c] = c;
-    for (int k = n - 1; k >= 0; --k) {
-        const int q = perm[k];
-        const int a = src[k];
-        src[k] = src[q];
-        src[q] = a;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const bool piv = lab[j] == lp;
+        const double f = v[j][KK];
+#pragma unroll
+        for (int c = 0; c < B; ++c) v[j][c] = fma(-f, sh.rowk[c], c == KK ? 0.0 : v[j][c]);
+        // one lane of one wave holds the pivot row: the others skip its copy
+        if (__any(piv)) {
+#pragma unroll
+            for (int c = 0; c < B; ++c) v[j][c] = piv ? sh.rowk[c] : v[j][c];
+        }
+        lab[j] = piv ? k : (lab[j] == k ? lp : lab[j]);
     }
 }
 
-__global__ void k_gj_extract(const double* X, int n, const int32_t* src, double* inv) {
+template <int T, int R, int B, int... KK>
+__device__ __forceinline__ void gj_panel_steps(std::integer_sequence<int, KK...>, double (&v)[R][B], int (&lab)[R],
+                                               int n, int k0, int b, GjShared<T, B>& sh, int32_t* singular) {
+    ((KK < b ? gj_panel_step<T, R, B, KK>(v, lab, n, k0, sh, singular) : void()), ...);
+}
+
+// Panel [k0, k0 + b), b <= B; thread t of T owns rows t + j * T, j < R.  Each
+// row is written back at the position it ends in; rowsrc[pos] = its old row.
+template <int T, int R, int B>
+__global__ __launch_bounds__(T) void k_gj_panel(double* M, int n, int k0, int b, int32_t* rowsrc, int32_t* singular) {
+    __shared__ GjShared<T, B> sh;
+    const int t = threadIdx.x;
+    double v[R][B];
+    int lab[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int r = t + j * T;
+        lab[j] = r;
+#pragma unroll
+        for (int c = 0; c < B; ++c) v[j][c] = (r < n && c < b) ? M[(int64_t)r * n + k0 + c] : 0.0;
+    }
+    gj_panel_steps<T, R, B>(std::make_integer_sequence<int, B>{}, v, lab, n, k0, b, sh, singular);
+    // every thread's loads were consumed before the last barrier: rows may now land anywhere
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int r = t + j * T;
+        if (r >= n) continue;
+#pragma unroll
+        for (int c = 0; c < B; ++c)
+            if (c < b) M[(int64_t)lab[j] * n + k0 + c] = v[j][c];
+        rowsrc[lab[j]] = r;
+    }
+}
+
+// Out = P In + (G - E) (P In)[panel rows] outside the panel, Out = In inside it;
+// GJ_TILE x GJ_TILE tiles, 256 threads, each thread one column and 16 rows.
+// Column-tile 0 also carries the row order: ord_out[r] = ord_in[rowsrc[r]]
+// (ord_in null: the identity).
+template <int B>
+__global__ __launch_bounds__(256) void k_gj_update(const double* __restrict__ Min, double* __restrict__ Mout, int n,
+                                                   int k0, int b, const int32_t* __restrict__ rowsrc,
+                                                   const int32_t* __restrict__ ord_in, int32_t* __restrict__ ord_out) {
+    __shared__ double G[B][GJ_TILE];
+    __shared__ int rsrc[GJ_TILE];
+    const int t = threadIdx.x, tx = t % GJ_TILE, ty = t / GJ_TILE;
+    const int row0 = blockIdx.y * GJ_TILE;
+    const int c = blockIdx.x * GJ_TILE + tx;
+    for (int e = t; e < GJ_TILE * B; e += 256) {
+        const int rr = e / B, q = e % B;
+        const int r = row0 + rr;
+        double g = 0.0;
+        if (r < n && q < b) g = Min[(int64_t)r * n + k0 + q] - (r == k0 + q ? 1.0 : 0.0);
+        G[q][rr] = g;
+    }
+    if (t < GJ_TILE) {
+        const int r = row0 + t;
+        const int sr = r < n ? rowsrc[r] : 0;
+        rsrc[t] = sr;
+        if (blockIdx.x == 0 && r < n) ord_out[r] = ord_in ? ord_in[sr] : sr;
+    }
+    __syncthreads();
+    if (c >= n) return;
+    const bool in_panel = c >= k0 && c < k0 + b;
+    double x[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) x[q] = (q < b && !in_panel) ? Min[(int64_t)rowsrc[k0 + q] * n + c] : 0.0;
+#pragma unroll 4
+    for (int i = 0; i < GJ_TILE / 4; ++i) {
+        const int rr = ty * (GJ_TILE / 4) + i;
+        const int r = row0 + rr;
+        if (r >= n) break;
+        double out;
+        if (in_panel) {
+            out = Min[(int64_t)r * n + c];
+        } else {
+            out = Min[(int64_t)rsrc[rr] * n + c];
+#pragma unroll
+            for (int q = 0; q < B; ++q) out = fma(G[q][rr], x[q], out);
+        }
+        Mout[(int64_t)r * n + c] = out;
+    }
+}
+
+// inv[:, ord[i]] = X[:, i]
+__global__ void k_gj_extract(const double* X, int n, const int32_t* ord, double* inv) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n * n) return;
-    const int r = (int)(t / n), c = (int)(t % n);
-    inv[t] = X[(int64_t)r * n + src[c]];
+    const int r = (int)(t / n), i = (int)(t % n);
+    inv[(int64_t)r * n + ord[i]] = X[t];
 }
 
 // ----------------------------------------------------------------------------
@@ -1446,45 +1521,65 @@ void transfer_maps(int n, int nc, const int32_t* perm, const int32_t* iperm, con
     MB_LAUNCH_CHECK();
 }
 
+template <int T, int R, int B>
+static void gj_run(CoarseWork& w, int n, hipStream_t s, double** result, const int32_t** order) {
+    double* cur = w.M.p;
+    double* nxt = w.M.p + (size_t)n * n;
+    const int32_t* ord_in = nullptr;
+    int which = 0;
+    for (int k0 = 0; k0 < n; k0 += B) {
+        const int b = std::min(B, n - k0);
+        k_gj_panel<T, R, B><<<1, T, 0, s>>>(cur, n, k0, b, w.rowsrc.p, w.sing.p);
+        if (b == n) {   // one panel: nothing outside it
+            ord_in = w.rowsrc.p;
+            break;
+        }
+        int32_t* ord_out = w.ord.p + (size_t)which * n;
+        const dim3 grid((n + GJ_TILE - 1) / GJ_TILE, (n + GJ_TILE - 1) / GJ_TILE);
+        k_gj_update<B><<<grid, 256, 0, s>>>(cur, nxt, n, k0, b, w.rowsrc.p, ord_in, ord_out);
+        ord_in = ord_out;
+        which ^= 1;
+        std::swap(cur, nxt);
+    }
+    MB_LAUNCH_CHECK();
+    *result = cur;
+    *order = ord_in;
+}
+
 void coarse_inverse_launch(const SetupBsr (&A)[2][2], const int d[2], DevBuf<double>& inv, CoarseWork& w,
                            hipStream_t s) {
     const int nn = A[0][0].n_rows;
     const int n = nn * (d[0] + d[1]);
     MB_CHECK(n <= 16384, MBAMG_E_INVALID, "coarsest level too large for the dense solve (raise max_levels)");
     w.n = n;
-    w.M.alloc((size_t)2 * n * n);         // two n x n matrices, read and written alternately
-    w.colk.alloc(4);                      // two pivot records
+    w.M.alloc((size_t)2 * n * n);
     w.sing.alloc(1);
-    w.perm.alloc(std::max(n, 1));
-    w.src.alloc(std::max(n, 1));
+    w.rowsrc.alloc(std::max(n, 1));
+    w.ord.alloc((size_t)2 * std::max(n, 1));
     inv.alloc((size_t)n * n);
-    double* M0 = w.M.p;
-    double* M1 = w.M.p + (int64_t)n * n;
-    GjPivot* st = reinterpret_cast<GjPivot*>(w.colk.p);
-    MB_HIP(hipMemsetAsync(M0, 0, sizeof(double) * (size_t)n * n, s));
+    MB_HIP(hipMemsetAsync(w.sing.p, 0, sizeof(int32_t), s));
+    if (n == 0) return;
+    MB_HIP(hipMemsetAsync(w.M.p, 0, sizeof(double) * (size_t)n * n, s));
     int64_t off[2] = {0, (int64_t)nn * d[0]};
     for (int f = 0; f < 2; ++f)
         for (int g = 0; g < 2; ++g) {
             const SetupBsr& B = A[f][g];
             if (B.nnzb == 0) continue;
             k_dense_scatter<<<grid_for(nn, 64), 64, 0, s>>>(nn, B.br, B.bc, B.rp.p, B.ci.p, B.val.p, off[f], off[g],
-                                                           (int64_t)n, M0);
+                                                           (int64_t)n, w.M.p);
             MB_LAUNCH_CHECK();
         }
-    MB_HIP(hipMemsetAsync(w.sing.p, 0, sizeof(int32_t), s));
-    k_gj_first<<<1, 1024, 0, s>>>(M0, n, st, w.perm.p, w.sing.p);
-    MB_LAUNCH_CHECK();
-    const int bulk = (int)grid_for((int64_t)n * n, 1024);
-    for (int k = 0; k < n; ++k) {
-        const double* in = (k % 2 == 0) ? M0 : M1;
-        double* out = (k % 2 == 0) ? M1 : M0;
-        k_gj_step<<<bulk + 1, 1024, 0, s>>>(in, out, n, k, st + (k % 2), st + ((k + 1) % 2), w.perm.p, w.sing.p,
-                                           bulk);
-    }
-    MB_LAUNCH_CHECK();
-    const double* X = (n % 2 == 0) ? M0 : M1;
-    k_gj_unscramble<<<1, 1, 0, s>>>(w.perm.p, n, w.src.p);
-    k_gj_extract<<<grid_for((int64_t)n * n), 256, 0, s>>>(X, n, w.src.p, inv.p);
+    // threads T and rows per thread R set the panel width B: R * B doubles stay in registers
+    double* X = nullptr;
+    const int32_t* ord = nullptr;
+    if (n <= 512) gj_run<512, 1, 32>(w, n, s, &X, &ord);
+    else if (n <= 1024) gj_run<512, 2, 32>(w, n, s, &X, &ord);
+    else if (n <= 2048) gj_run<512, 4, 16>(w, n, s, &X, &ord);
+    else if (n <= 3072) gj_run<512, 6, 16>(w, n, s, &X, &ord);
+    else if (n <= 4096) gj_run<1024, 4, 8>(w, n, s, &X, &ord);
+    else if (n <= 8192) gj_run<512, 16, 4>(w, n, s, &X, &ord);
+    else gj_run<1024, 16, 2>(w, n, s, &X, &ord);
+    k_gj_extract<<<grid_for((int64_t)n * n), 256, 0, s>>>(X, n, ord, inv.p);
     MB_LAUNCH_CHECK();
 }
 
@@ -1493,9 +1588,8 @@ void coarse_inverse_finish(CoarseWork& w, hipStream_t s) {
     MB_HIP(hipMemcpyAsync(&h, w.sing.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     MB_HIP(hipStreamSynchronize(s));
     w.M.release();
-    w.colk.release();
-    w.perm.release();
-    w.src.release();
+    w.rowsrc.release();
+    w.ord.release();
     MB_CHECK(h == 0, MBAMG_E_SINGULAR, "the coarsest matrix is singular");
 }
 
