@@ -932,116 +932,148 @@ __global__ void k_dense_scatter(int n_rows, int br, int bc, const int32_t* rp, c
 // ----------------------------------------------------------------------------
 constexpr int GJ_TILE = 64;
 
-template <int T, int B>
-struct GjShared {
-    double wbest[T / WAVE];
-    int widx[T / WAVE];
-    double rowk[B];
-};
-
-// Step KK of a panel (KK a compile-time index, so that v stays in registers).
-// Rows are never moved inside the panel: lab[j] is the position that the
-// thread's j-th row holds in the row order so far, and a row interchange
-// exchanges two labels.
-template <int T, int R, int B, int KK>
-__device__ __forceinline__ void gj_panel_step(double (&v)[R][B], int (&lab)[R], int n, int k0, GjShared<T, B>& sh,
-                                              int32_t* singular) {
-    const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
-    const int k = k0 + KK;
-    // pivot: largest magnitude in column k at position k or below, ties to the smaller position
-    double best = -1.0;
-    int bi = INT_MAX;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const double a = fabs(v[j][KK]);
-        if (lab[j] >= k && lab[j] < n && (a > best || (a == best && lab[j] < bi))) {
-            best = a;
-            bi = lab[j];
-        }
-    }
-    for (int off = WAVE / 2; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
-        }
-    }
-    if (lane == 0) {
-        sh.wbest[wv] = best;
-        sh.widx[wv] = bi;
-    }
-    __syncthreads();
-    best = sh.wbest[0];
-    bi = sh.widx[0];
-#pragma unroll
-    for (int w = 1; w < T / WAVE; ++w) {
-        const double ob = sh.wbest[w];
-        const int oi = sh.widx[w];
-        if (ob > best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
-        }
-    }
-    // no finite candidate (NaN after an earlier zero pivot): keep a valid row
-    const int lp = bi == INT_MAX ? k : bi;
-    if (t == 0 && (!(best > 0.0) || bi == INT_MAX)) atomicAdd(singular, 1);
-    // the owner of the pivot row publishes the new row k
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        if (__any(lab[j] == lp) && lab[j] == lp) {
-            const double inv = 1.0 / v[j][KK];
-#pragma unroll
-            for (int c = 0; c < B; ++c) sh.rowk[c] = c == KK ? inv : v[j][c] * inv;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const bool piv = lab[j] == lp;
-        const double f = v[j][KK];
-#pragma unroll
-        for (int c = 0; c < B; ++c) v[j][c] = fma(-f, sh.rowk[c], c == KK ? 0.0 : v[j][c]);
-        // one lane of one wave holds the pivot row: the others skip its copy
-        if (__any(piv)) {
-#pragma unroll
-            for (int c = 0; c < B; ++c) v[j][c] = piv ? sh.rowk[c] : v[j][c];
-        }
-        lab[j] = piv ? k : (lab[j] == k ? lp : lab[j]);
+// larger magnitude wins, ties to the smaller position
+__device__ __forceinline__ void gj_take(double& best, int& bi, double ob, int oi) {
+    if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
     }
 }
-
-template <int T, int R, int B, int... KK>
-__device__ __forceinline__ void gj_panel_steps(std::integer_sequence<int, KK...>, double (&v)[R][B], int (&lab)[R],
-                                               int n, int k0, int b, GjShared<T, B>& sh, int32_t* singular) {
-    ((KK < b ? gj_panel_step<T, R, B, KK>(v, lab, n, k0, sh, singular) : void()), ...);
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void gj_dpp_take(double& best, int& bi) {
+    const int lo = __double2loint(best), hi = __double2hiint(best);
+    const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+    const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+    const int oi = __builtin_amdgcn_update_dpp(bi, bi, CTRL, ROWS, 0xF, false);
+    gj_take(best, bi, __hiloint2double(ohi, olo), oi);
+}
+// arg-max over the wave, returned to every lane: exchanges inside quads and
+// half-rows and rows of 16 lanes, then row broadcasts carry the total to lane 63
+__device__ __forceinline__ void gj_wave_argmax(double& best, int& bi) {
+    gj_dpp_take<0xB1, 0xF>(best, bi);    // quad_perm [1,0,3,2]
+    gj_dpp_take<0x4E, 0xF>(best, bi);    // quad_perm [2,3,0,1]
+    gj_dpp_take<0x141, 0xF>(best, bi);   // row_half_mirror
+    gj_dpp_take<0x140, 0xF>(best, bi);   // row_mirror
+    gj_dpp_take<0x142, 0xA>(best, bi);   // row_bcast:15 into rows 1 and 3
+    gj_dpp_take<0x143, 0xC>(best, bi);   // row_bcast:31 into rows 2 and 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(best), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(best), 63);
+    bi = __builtin_amdgcn_readlane(bi, 63);
+    best = __hiloint2double(hi, lo);
 }
 
-// Panel [k0, k0 + b), b <= B; thread t of T owns rows t + j * T, j < R.  Each
-// row is written back at the position it ends in; rowsrc[pos] = its old row.
+// Panel [k0, k0 + b), b <= B; thread t of T owns rows t + j * T, j < R, in
+// registers.  Rows are never moved inside the panel: lab[j] is the position
+// that the thread's j-th row holds in the row order so far, and a row
+// interchange exchanges two labels.  The columns sit in a rotating frame so
+// that the step loop indexes registers with constants: at step kk, v[j][c]
+// holds panel column (c + kk) mod B, the pivot column is v[j][0].  Global
+// memory is read and written in coalesced order and redistributed through
+// LDS one slot (T rows) at a time.  Each row ends at position lab[j];
+// rowsrc[position] = the row it came from.
 template <int T, int R, int B>
 __global__ __launch_bounds__(T) void k_gj_panel(double* M, int n, int k0, int b, int32_t* rowsrc, int32_t* singular) {
-    __shared__ GjShared<T, B> sh;
-    const int t = threadIdx.x;
+    __shared__ double stage[T][B + 1];
+    __shared__ int slab[T];
+    __shared__ double wbest[T / WAVE];
+    __shared__ int widx[T / WAVE];
+    __shared__ double rowk[B];
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
     double v[R][B];
     int lab[R];
+    {
+        // every load in flight at once
+        double u[R][B];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int r = t + j * T;
-        lab[j] = r;
+        for (int j = 0; j < R; ++j)
 #pragma unroll
-        for (int c = 0; c < B; ++c) v[j][c] = (r < n && c < b) ? M[(int64_t)r * n + k0 + c] : 0.0;
+            for (int q = 0; q < B; ++q) {
+                const int e = t + q * T, rr = e / B, c = e % B, r = j * T + rr;
+                u[j][q] = (r < n && c < b) ? M[(int64_t)r * n + k0 + c] : 0.0;
+            }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            lab[j] = t + j * T;
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const int e = t + q * T;
+                stage[e / B][e % B] = u[j][q];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < B; ++c) v[j][c] = stage[t][c];
+            __syncthreads();
+        }
     }
-    gj_panel_steps<T, R, B>(std::make_integer_sequence<int, B>{}, v, lab, n, k0, b, sh, singular);
-    // every thread's loads were consumed before the last barrier: rows may now land anywhere
+    for (int kk = 0; kk < b; ++kk) {
+        const int k = k0 + kk;
+        // pivot: largest magnitude in column k at position k or below, ties to the smaller position
+        double best = -1.0;
+        int bi = INT_MAX;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const double a = fabs(v[j][0]);
+            if (lab[j] >= k && lab[j] < n && (a > best || (a == best && lab[j] < bi))) {
+                best = a;
+                bi = lab[j];
+            }
+        }
+        gj_wave_argmax(best, bi);
+        if (lane == 0) {
+            wbest[wv] = best;
+            widx[wv] = bi;
+        }
+        __syncthreads();
+        best = wbest[0];
+        bi = widx[0];
+#pragma unroll
+        for (int w = 1; w < T / WAVE; ++w) gj_take(best, bi, wbest[w], widx[w]);
+        // no finite candidate (NaN after an earlier zero pivot): keep a valid row
+        const int lp = bi == INT_MAX ? k : bi;
+        if (t == 0 && (!(best > 0.0) || bi == INT_MAX)) atomicAdd(singular, 1);
+        // the owner of the pivot row publishes the new row k (rotated frame)
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (__any(lab[j] == lp) && lab[j] == lp) {
+                const double inv = 1.0 / v[j][0];
+                rowk[0] = inv;
+#pragma unroll
+                for (int c = 1; c < B; ++c) rowk[c] = v[j][c] * inv;
+            }
+        }
+        __syncthreads();
+        // eliminate column k from every row and rotate the frame by one
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const bool piv = lab[j] == lp;
+            const double f = v[j][0];
+#pragma unroll
+            for (int c = 1; c < B; ++c) v[j][c - 1] = fma(-f, rowk[c], v[j][c]);
+            v[j][B - 1] = -f * rowk[0];
+            // one lane of one wave holds the pivot row: the others skip its copy
+            if (__any(piv)) {
+#pragma unroll
+                for (int c = 1; c < B; ++c) v[j][c - 1] = piv ? rowk[c] : v[j][c - 1];
+                v[j][B - 1] = piv ? rowk[0] : v[j][B - 1];
+            }
+            lab[j] = piv ? k : (lab[j] == k ? lp : lab[j]);
+        }
+    }
+    // after b steps, frame column c holds panel column (c + b) mod B
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const int r = t + j * T;
-        if (r >= n) continue;
 #pragma unroll
-        for (int c = 0; c < B; ++c)
-            if (c < b) M[(int64_t)lab[j] * n + k0 + c] = v[j][c];
-        rowsrc[lab[j]] = r;
+        for (int c = 0; c < B; ++c) stage[t][c] = v[j][c];
+        slab[t] = lab[j];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const int e = t + q * T, rr = e / B, c = e % B, r = j * T + rr;
+            const int pc = (c + b) % B;
+            if (r < n && pc < b) M[(int64_t)slab[rr] * n + k0 + pc] = stage[rr][c];
+        }
+        if (t + j * T < n) rowsrc[lab[j]] = t + j * T;
+        __syncthreads();
     }
 }
 
@@ -1572,13 +1604,13 @@ void coarse_inverse_launch(const SetupBsr (&A)[2][2], const int d[2], DevBuf<dou
     // threads T and rows per thread R set the panel width B: R * B doubles stay in registers
     double* X = nullptr;
     const int32_t* ord = nullptr;
-    if (n <= 512) gj_run<512, 1, 32>(w, n, s, &X, &ord);
-    else if (n <= 1024) gj_run<512, 2, 32>(w, n, s, &X, &ord);
+    if (n <= 512) gj_run<512, 1, 16>(w, n, s, &X, &ord);
+    else if (n <= 1024) gj_run<512, 2, 16>(w, n, s, &X, &ord);
     else if (n <= 2048) gj_run<512, 4, 16>(w, n, s, &X, &ord);
     else if (n <= 3072) gj_run<512, 6, 16>(w, n, s, &X, &ord);
-    else if (n <= 4096) gj_run<1024, 4, 8>(w, n, s, &X, &ord);
+    else if (n <= 4096) gj_run<512, 8, 8>(w, n, s, &X, &ord);
     else if (n <= 8192) gj_run<512, 16, 4>(w, n, s, &X, &ord);
-    else gj_run<1024, 16, 2>(w, n, s, &X, &ord);
+    else gj_run<512, 32, 2>(w, n, s, &X, &ord);
     k_gj_extract<<<grid_for((int64_t)n * n), 256, 0, s>>>(X, n, ord, inv.p);
     MB_LAUNCH_CHECK();
 }
