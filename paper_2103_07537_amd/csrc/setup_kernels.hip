@@ -10,6 +10,8 @@
 #include "setup_kernels.h"
 
 #include <utility>
+#include <cstdlib>
+#include <cstring>
 
 namespace mbamg {
 
@@ -98,6 +100,16 @@ int scan_exclusive(const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
 // ----------------------------------------------------------------------------
 // strength graph
 // ----------------------------------------------------------------------------
+// Kernel-form overrides for tests: every form computes the same sums in the
+// same order, so a hierarchy must come out bit-identical under each.
+//   MBAMG_SA_FORM     = thread | wave | generic   (smoothed prolongator)
+//   MBAMG_SPGEMM_FORM = block | entry              (numeric Galerkin product)
+//   MBAMG_SORT_FORM   = thread | wave              (aggregate member lists)
+static const char* form_override(const char* var) {
+    const char* v = std::getenv(var);
+    return (v && *v) ? v : nullptr;
+}
+
 __device__ inline int find_col(const int32_t* ci, int lo, int hi, int key) {
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
@@ -271,6 +283,37 @@ __global__ void k_sort_members(int nagg, const int32_t* mptr, int32_t* midx) {
     }
 }
 
+// the same with one wavefront per aggregate (large aggregates on coarse
+// levels): members ranked in LDS; longer lists than the LDS copy holds take
+// the one-lane insertion sort
+constexpr int SORT_LDS = 2048;
+__global__ __launch_bounds__(WAVE) void k_sort_members_w(int nagg, const int32_t* mptr, int32_t* midx) {
+    __shared__ int32_t v[SORT_LDS];
+    const int k = blockIdx.x, lane = threadIdx.x;
+    const int b = mptr[k], e = mptr[k + 1], m = e - b;
+    if (m > SORT_LDS) {
+        if (lane == 0)
+            for (int a = b + 1; a < e; ++a) {
+                const int x = midx[a];
+                int c = a - 1;
+                while (c >= b && midx[c] > x) {
+                    midx[c + 1] = midx[c];
+                    --c;
+                }
+                midx[c + 1] = x;
+            }
+        return;
+    }
+    for (int t = lane; t < m; t += WAVE) v[t] = midx[b + t];
+    __syncthreads();
+    for (int t = lane; t < m; t += WAVE) {
+        const int key = v[t];
+        int r = 0;
+        for (int u = 0; u < m; ++u) r += v[u] < key;
+        midx[b + r] = key;
+    }
+}
+
 // ----------------------------------------------------------------------------
 // tentative prolongator: q = B / ||B over the aggregate||, per component
 // ----------------------------------------------------------------------------
@@ -419,11 +462,13 @@ __global__ void k_cast_f64_f32(const double* a, float* b, int64_t n) {
 // Vector entry (a,c) of block (i,k): s = sum over the row's columns j in
 // increasing order with agg(j) = k of A[i,j][a][c] * q[j,c];
 // P = base - w[k] * (s / A[i,i][a][a]) with base = q[i,a] on (k = agg(i), c = a).
-__global__ void k_sa_prolong(int n, int d, int nv, const int32_t* rp, const int32_t* ci, const double* val,
-                             const int32_t* agg, const double* q, const double* w, int pass, int32_t* cnt,
-                             const int32_t* prp, int32_t* pci, double* pval) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Smoothed prolongator row i: the distinct kept aggregates l of row i in
+// increasing order; block (i,l) = [l == agg(i)] diag(q_i) - w_l D_i^-1 sum over
+// the row's entries p with agg(col p) == l, in increasing p, of A_p diag(q_col).
+// Any row length, one thread, no local storage.
+__device__ void sa_row_generic(int i, int d, int nv, const int32_t* rp, const int32_t* ci, const double* val,
+                               const int32_t* agg, const double* q, const double* w, int pass, int32_t* cnt,
+                               const int32_t* prp, int32_t* pci, double* pval) {
     const int b = rp[i], e = rp[i + 1], bs = d * d, ai = agg[i];
     int pd = find_col(ci, b, e, i);
     int prev = -1, out = pass ? prp[i] : 0, c = 0;
@@ -456,6 +501,88 @@ __global__ void k_sa_prolong(int n, int d, int nv, const int32_t* rp, const int3
                         blk[ra * d + cc] = base - u;
                     } else {
                         blk[ra * d + cc] = base;
+                    }
+                }
+        }
+        ++c;
+        prev = l;
+    }
+    if (!pass) cnt[i] = c;
+}
+
+// One thread per row: rows of at most SA_REG entries keep their columns and
+// aggregates in registers and read each block of A once; longer rows take
+// the generic form.  Same sums in the same order.
+constexpr int SA_REG = 16;
+template <int D>
+__global__ __launch_bounds__(128) void k_sa_prolong_t(int n, int nv, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                               const double* __restrict__ val, const int32_t* __restrict__ agg,
+                               const double* __restrict__ q, const double* __restrict__ w, int pass, int32_t* cnt,
+                               const int32_t* prp, int32_t* pci, double* pval, int generic_only) {
+    constexpr int BS = D * D;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int b = rp[i], e = rp[i + 1], ai = agg[i];
+    if (e - b > SA_REG || generic_only) {
+        sa_row_generic(i, D, nv, rp, ci, val, agg, q, w, pass, cnt, prp, pci, pval);
+        return;
+    }
+    int jj[SA_REG], ag[SA_REG];   // ag = INT_MAX: no entry, or an aggregate that is not kept
+#pragma unroll
+    for (int u = 0; u < SA_REG; ++u) {
+        jj[u] = 0;
+        ag[u] = INT_MAX;
+        if (b + u < e) {
+            jj[u] = ci[b + u];
+            const int a = agg[jj[u]];
+            if (a == ai || w[a] != 0.0) ag[u] = a;
+        }
+    }
+    double dg[D];
+    if (pass) {
+        const int pd = find_col(ci, b, e, i);
+#pragma unroll
+        for (int r = 0; r < D; ++r) dg[r] = pd >= 0 ? val[(int64_t)pd * BS + r * D + r] : 0.0;
+    }
+    int prev = -1, c = 0;
+    const int out = pass ? prp[i] : 0;
+    while (true) {
+        int l = INT_MAX;
+#pragma unroll
+        for (int u = 0; u < SA_REG; ++u)
+            if (ag[u] > prev && ag[u] < l) l = ag[u];
+        if (l == INT_MAX) break;
+        if (pass) {
+            double acc[BS];
+#pragma unroll
+            for (int x = 0; x < BS; ++x) acc[x] = 0.0;
+#pragma unroll
+            for (int u = 0; u < SA_REG; ++u) {
+                if (ag[u] != l) continue;
+                const double* vb = val + (int64_t)(b + u) * BS;
+                double qj[D];
+#pragma unroll
+                for (int cc = 0; cc < D; ++cc) qj[cc] = q[(int64_t)jj[u] * D + cc];
+#pragma unroll
+                for (int x = 0; x < BS; ++x) {
+                    const double term = vb[x] * qj[x % D];
+                    acc[x] = acc[x] + term;
+                }
+            }
+            double* blk = pval + (int64_t)(out + c) * BS;
+            pci[out + c] = l;
+            const double wl = w[l];
+#pragma unroll
+            for (int ra = 0; ra < D; ++ra)
+#pragma unroll
+                for (int cc = 0; cc < D; ++cc) {
+                    const double base = (l == ai && cc == ra) ? q[(int64_t)i * D + ra] : 0.0;
+                    if (ra < nv && cc < nv) {
+                        const double t = acc[ra * D + cc] / dg[ra];
+                        const double u = wl * t;
+                        blk[ra * D + cc] = base - u;
+                    } else {
+                        blk[ra * D + cc] = base;
                     }
                 }
         }
@@ -682,6 +809,40 @@ __global__ void k_spgemm_num(int64_t nnz, const int32_t* __restrict__ arp, const
     for (int e = 0; e < BR * BC; ++e) dst[e] = acc[e];
 }
 
+// the same with one lane per output entry and 16 lanes per output block, for
+// outputs too small to fill the GPU one block per thread; each entry's sum
+// runs in the same order
+template <int BR, int BM, int BC>
+__global__ __launch_bounds__(256) void k_spgemm_num_e(int64_t nnz, const int32_t* __restrict__ arp,
+                                                      const int32_t* __restrict__ aci,
+                                                      const double* __restrict__ aval,
+                                                      const int32_t* __restrict__ brp,
+                                                      const int32_t* __restrict__ bci,
+                                                      const double* __restrict__ bval,
+                                                      const int32_t* __restrict__ crow,
+                                                      const int32_t* __restrict__ cci, double* __restrict__ cval) {
+    static_assert(BR * BC <= 16, "at most 16 entries per output block");
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = tid / 16;
+    const int ent = (int)(tid % 16);
+    if (k >= nnz) return;
+    const int r = ent / BC, cc = ent % BC;
+    const bool live = ent < BR * BC;
+    const int i = crow[k], l = cci[k];
+    double acc = 0.0;
+    for (int p = arp[i]; p < arp[i + 1]; ++p) {
+        const int j = aci[p];
+        const int q = find_col(bci, brp[j], brp[j + 1], l);
+        if (q < 0 || !live) continue;
+#pragma unroll
+        for (int m = 0; m < BM; ++m) {
+            const double term = aval[(int64_t)p * BR * BM + r * BM + m] * bval[(int64_t)q * BM * BC + m * BC + cc];
+            acc = acc + term;
+        }
+    }
+    if (live) cval[k * BR * BC + ent] = acc;
+}
+
 // the same for any block shape with at most 16 entries per output block
 __global__ void k_spgemm_num_any(int64_t nnz, int br, int bm, int bc, const int32_t* __restrict__ arp,
                                  const int32_t* __restrict__ aci, const double* __restrict__ aval,
@@ -721,19 +882,39 @@ __global__ void k_same_pattern(int n, const int32_t* __restrict__ rpa, const int
     if (!same) atomicAnd(flag, 0);
 }
 
-__global__ __launch_bounds__(WAVE) void k_sa_prolong_w(int d, int nv, const int32_t* __restrict__ rp,
+// One wavefront per row (long rows, at most SA_WROW entries and KS_MAX
+// distinct aggregates, else *overflow is set): the distinct kept aggregates
+// are collected and sorted in LDS, every entry is tagged with its output
+// block, and 16 lanes per output block (one per entry) sum over the row's
+// entries in increasing order -- the sums of the generic form, in its order.
+constexpr int SA_WROW = 1024;
+template <int D>
+__global__ __launch_bounds__(WAVE) void k_sa_prolong_w(int nv, const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci, const double* __restrict__ val,
                                                        const int32_t* __restrict__ agg, const double* __restrict__ q,
                                                        const double* __restrict__ w, int pass, int32_t* cnt,
                                                        const int32_t* prp, int32_t* pci, double* pval,
                                                        int32_t* overflow) {
+    constexpr int BS = D * D;
     __shared__ KeySet S;
+    __shared__ int32_t slot[SA_WROW], sj[SA_WROW];
     const int i = blockIdx.x, lane = threadIdx.x;
-    const int b = rp[i], e = rp[i + 1], bs = d * d, ai = agg[i];
-    ks_clear(S, lane, e - b);
-    for (int p = b + lane; p < e; p += WAVE) {
-        const int a = agg[ci[p]];
-        if (a == ai || w[a] != 0.0) ks_insert(S, a);
+    const int b = rp[i], e = rp[i + 1], ai = agg[i], len = e - b;
+    if (len > SA_WROW) {
+        if (lane == 0) {
+            atomicOr(overflow, 1);
+            if (!pass) cnt[i] = 0;
+        }
+        return;
+    }
+    ks_clear(S, lane, len);
+    for (int p = lane; p < len; p += WAVE) {
+        const int j = ci[b + p];
+        const int a = agg[j];
+        const bool keep = a == ai || w[a] != 0.0;
+        if (keep) ks_insert(S, a);
+        sj[p] = j;
+        slot[p] = keep ? a : -1;
     }
     __syncthreads();
     const int K = ks_count(S);
@@ -749,31 +930,44 @@ __global__ __launch_bounds__(WAVE) void k_sa_prolong_w(int d, int nv, const int3
         return;
     }
     ks_sort(S, lane, K);
+    // output block of each entry: the rank of its aggregate among the sorted ones
+    for (int p = lane; p < len; p += WAVE) {
+        const int a = slot[p];
+        if (a < 0) continue;
+        int lo = 0, hi = K - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (S.sorted[mid] < a) lo = mid + 1;
+            else hi = mid;
+        }
+        slot[p] = lo;
+    }
+    __syncthreads();
     const int pd = find_col(ci, b, e, i);
     const int out = prp[i];
-    for (int t = lane; t < K; t += WAVE) {
-        const int l = S.sorted[t];
-        double* blk = pval + (int64_t)(out + t) * bs;
-        pci[out + t] = l;
-        for (int ra = 0; ra < d; ++ra)
-            for (int cc = 0; cc < d; ++cc) {
-                double base = (l == ai && cc == ra) ? q[(int64_t)i * d + ra] : 0.0;
-                if (ra < nv && cc < nv) {
-                    double acc = 0.0;
-                    for (int p = b; p < e; ++p) {
-                        const int j = ci[p];
-                        if (agg[j] != l) continue;
-                        double term = val[(int64_t)p * bs + ra * d + cc] * q[(int64_t)j * d + cc];
-                        acc = acc + term;
-                    }
-                    double dg = pd >= 0 ? val[(int64_t)pd * bs + ra * d + ra] : 0.0;
-                    double tq = acc / dg;
-                    double u = w[l] * tq;
-                    blk[ra * d + cc] = base - u;
-                } else {
-                    blk[ra * d + cc] = base;
-                }
+    const int sub = lane / 16, ent = lane % 16, ra = ent / D, cc = ent % D;
+    const bool live = ent < BS;
+    const double dg = (live && pd >= 0) ? val[(int64_t)pd * BS + ra * D + ra] : 0.0;
+    for (int t0 = 0; t0 < K; t0 += WAVE / 16) {
+        const int t = t0 + sub;
+        double acc = 0.0;
+        for (int p = 0; p < len; ++p) {
+            if (slot[p] != t || !live) continue;
+            const double term = val[(int64_t)(b + p) * BS + ent] * q[(int64_t)sj[p] * D + cc];
+            acc = acc + term;
+        }
+        if (t < K && live) {
+            const int l = S.sorted[t];
+            const double base = (l == ai && cc == ra) ? q[(int64_t)i * D + ra] : 0.0;
+            double r = base;
+            if (ra < nv && cc < nv) {
+                const double tq = acc / dg;
+                const double u = w[l] * tq;
+                r = base - u;
             }
+            pval[(int64_t)(out + t) * BS + ent] = r;
+            if (ent == 0) pci[out + t] = l;
+        }
     }
 }
 
@@ -1220,7 +1414,10 @@ Aggregates build_aggregates(const Strength& S, uint64_t seed, int level, hipStre
     MB_CHECK(h_fail == 0, MBAMG_E_INVALID, "aggregation left a node unattached");
     G.midx.alloc(std::max(n, 1));
     k_place_members<<<grid_for(n), 256, 0, s>>>(n, G.agg.p, G.mptr.p, cursor.p, G.midx.p);
-    k_sort_members<<<grid_for(na), 256, 0, s>>>(na, G.mptr.p, G.midx.p);
+    bool wave_sort = n >= 16 * (int64_t)na;
+    if (const char* f = form_override("MBAMG_SORT_FORM")) wave_sort = std::strcmp(f, "wave") == 0;
+    if (na > 0 && wave_sort) k_sort_members_w<<<na, WAVE, 0, s>>>(na, G.mptr.p, G.midx.p);
+    else k_sort_members<<<grid_for(na), 256, 0, s>>>(na, G.mptr.p, G.midx.p);
     MB_LAUNCH_CHECK();
     return G;
 }
@@ -1283,9 +1480,36 @@ void cast_to_f32(const double* a, float* b, int64_t n, hipStream_t s) {
     MB_LAUNCH_CHECK();
 }
 
+template <int D>
+static void sa_launch(const SetupBsr& A, int nv, const Aggregates& G, const double* q, const double* w, bool wave,
+                      bool generic, int pass, int32_t* cnt, SetupBsr* P, int32_t* ovf, hipStream_t s) {
+    const int n = A.n_rows;
+    int32_t* prp = P ? P->rp.p : nullptr;
+    int32_t* pci = P ? P->ci.p : nullptr;
+    double* pval = P ? P->val.p : nullptr;
+    if (wave)
+        k_sa_prolong_w<D><<<n, WAVE, 0, s>>>(nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, pass, cnt, prp, pci, pval,
+                                             ovf);
+    else
+        k_sa_prolong_t<D><<<grid_for(n, 128), 128, 0, s>>>(n, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, pass, cnt,
+                                                            prp, pci, pval, generic ? 1 : 0);
+    MB_LAUNCH_CHECK();
+}
+
+static void sa_dispatch(int d, const SetupBsr& A, int nv, const Aggregates& G, const double* q, const double* w,
+                        bool wave, bool generic, int pass, int32_t* cnt, SetupBsr* P, int32_t* ovf, hipStream_t s) {
+    switch (d) {
+        case 1: sa_launch<1>(A, nv, G, q, w, wave, generic, pass, cnt, P, ovf, s); break;
+        case 2: sa_launch<2>(A, nv, G, q, w, wave, generic, pass, cnt, P, ovf, s); break;
+        case 3: sa_launch<3>(A, nv, G, q, w, wave, generic, pass, cnt, P, ovf, s); break;
+        default: sa_launch<4>(A, nv, G, q, w, wave, generic, pass, cnt, P, ovf, s); break;
+    }
+}
+
 SetupBsr sa_prolongator(const SetupBsr& A, int nv, const Aggregates& G, const double* q, const double* w,
                         hipStream_t s) {
-    MB_CHECK(A.br == A.bc && A.br <= 4, MBAMG_E_INVALID, "smoothed prolongator needs square blocks of at most 4");
+    MB_CHECK(A.br == A.bc && A.br >= 1 && A.br <= 4, MBAMG_E_INVALID,
+             "smoothed prolongator needs square blocks of at most 4");
     const int n = A.n_rows, d = A.br;
     SetupBsr P;
     P.n_rows = n;
@@ -1293,31 +1517,24 @@ SetupBsr sa_prolongator(const SetupBsr& A, int nv, const Aggregates& G, const do
     P.br = P.bc = d;
     DevBuf<int32_t> cnt(std::max(n, 1)), ovf(1);
     MB_HIP(hipMemsetAsync(ovf.p, 0, sizeof(int32_t), s));
-    // short rows: one thread per row; long rows: one wavefront per row
-    bool per_thread = n > 0 && A.nnzb <= (int64_t)16 * n;
-    if (n > 0 && !per_thread) {
-        k_sa_prolong_w<<<n, WAVE, 0, s>>>(d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 0, cnt.p, nullptr, nullptr,
-                                          nullptr, ovf.p);
-        MB_LAUNCH_CHECK();
-        per_thread = ovf.download(s, 1)[0] != 0;
+    // short rows: one thread per row; long rows: one wavefront per row, or
+    // one thread per row when some row does not fit the wavefront form
+    bool wave = n > 0 && A.nnzb > (int64_t)16 * n;
+    bool generic = false;
+    if (const char* f = form_override("MBAMG_SA_FORM")) {
+        wave = n > 0 && std::strcmp(f, "wave") == 0;
+        generic = std::strcmp(f, "generic") == 0;
     }
-    if (per_thread) {
-        k_sa_prolong<<<grid_for(n, 128), 128, 0, s>>>(n, d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 0, cnt.p,
-                                                     nullptr, nullptr, nullptr);
-        MB_LAUNCH_CHECK();
+    if (wave) {
+        sa_dispatch(d, A, nv, G, q, w, true, false, 0, cnt.p, nullptr, ovf.p, s);
+        wave = ovf.download(s, 1)[0] == 0;
     }
+    if (n > 0 && !wave) sa_dispatch(d, A, nv, G, q, w, false, generic, 0, cnt.p, nullptr, ovf.p, s);
     P.rp.alloc(n + 1);
     P.nnzb = scan_exclusive(cnt.p, n, P.rp.p, s);
     P.ci.alloc(std::max<int64_t>(P.nnzb, 1));
     P.val.alloc(std::max<int64_t>(P.nnzb * d * d, 1));
-    if (per_thread) {
-        k_sa_prolong<<<grid_for(n, 128), 128, 0, s>>>(n, d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 1, nullptr,
-                                                     P.rp.p, P.ci.p, P.val.p);
-    } else if (n > 0) {
-        k_sa_prolong_w<<<n, WAVE, 0, s>>>(d, nv, A.rp.p, A.ci.p, A.val.p, G.agg.p, q, w, 1, nullptr, P.rp.p, P.ci.p,
-                                          P.val.p, ovf.p);
-    }
-    MB_LAUNCH_CHECK();
+    if (n > 0) sa_dispatch(d, A, nv, G, q, w, wave, generic, 1, nullptr, &P, ovf.p, s);
     return P;
 }
 
@@ -1425,11 +1642,23 @@ bool same_pattern(const SetupBsr& X, const SetupBsr& Y, hipStream_t s) {
     return flag.download(s, 1)[0] != 0;
 }
 
+// outputs with fewer blocks than this take one lane per output entry
+constexpr int64_t SPGEMM_ENTRY_MAX = (int64_t)1 << 21;
+
 static void spgemm_values(const SetupBsr& A, const SetupBsr& B, SetupBsr& C, const int32_t* crow, hipStream_t s) {
     if (C.nnzb == 0) return;
     const unsigned g = grid_for(C.nnzb, 128);
     const int64_t z = C.nnzb;
-    if (A.br == 4 && A.bc == 4 && B.bc == 4)
+    bool entry = z < SPGEMM_ENTRY_MAX;
+    if (const char* f = form_override("MBAMG_SPGEMM_FORM")) entry = std::strcmp(f, "entry") == 0;
+    const unsigned ge = grid_for(z * 16, 256);
+    if (entry && A.br == 4 && A.bc == 4 && B.bc == 4)
+        k_spgemm_num_e<4, 4, 4><<<ge, 256, 0, s>>>(z, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, crow, C.ci.p,
+                                                  C.val.p);
+    else if (entry && A.br == 3 && A.bc == 3 && B.bc == 3)
+        k_spgemm_num_e<3, 3, 3><<<ge, 256, 0, s>>>(z, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, crow, C.ci.p,
+                                                  C.val.p);
+    else if (A.br == 4 && A.bc == 4 && B.bc == 4)
         k_spgemm_num<4, 4, 4><<<g, 128, 0, s>>>(z, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, crow, C.ci.p,
                                                 C.val.p);
     else if (A.br == 3 && A.bc == 3 && B.bc == 3)

@@ -1,0 +1,68 @@
+"""Every kernel form of the setup computes the same sums in the same order, so
+hierarchies built under each forced form are bit-identical to the default
+choice (which the oracle tests pin):
+
+- smoothed prolongator: one thread per row with the row in registers, the
+  generic one-thread form, one wavefront per row;
+- numeric Galerkin product: one thread per output block, one lane per entry;
+- aggregate member lists: one lane per aggregate, one wavefront per aggregate.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import gpu_hierarchy, log
+from paper_2103_07537_amd.inputs import make_system
+
+pytestmark = pytest.mark.gpu
+
+
+def weights_fn(level, n_agg, F):
+    k = np.arange(n_agg)
+    return 0.1 + 0.6 * ((k * 37 + level) % 11) / 10.0, 0.5 + 0.5 * ((k * 13 + 3 * level) % 7) / 6.0
+
+
+CASES = {
+    "3d-20-lognormal": lambda: make_system(20, 3, 2.0, seed=21, kappa="lognormal"),
+    "2d-96-lognormal": lambda: make_system(96, 2, 5.0, seed=22, kappa="lognormal"),
+}
+
+FORMS = [("MBAMG_SA_FORM", "thread"), ("MBAMG_SA_FORM", "wave"), ("MBAMG_SA_FORM", "generic"),
+         ("MBAMG_SPGEMM_FORM", "block"), ("MBAMG_SPGEMM_FORM", "entry"),
+         ("MBAMG_SORT_FORM", "thread"), ("MBAMG_SORT_FORM", "wave")]
+
+
+def _snapshot(h):
+    out = []
+    L = h.num_levels()
+    for l in range(L):
+        if l + 1 < L:
+            out.append(h.aggregates(l))
+        for f in range(2):
+            for g in range(2):
+                out.extend(h.level_block(l, f, g))
+    return out
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def ref(request):
+    s = CASES[request.param]()
+    log(f"case={request.param} N={s.N}")
+    h = gpu_hierarchy(s, weights=weights_fn, judge=0, max_coarse=60)
+    snap = _snapshot(h)
+    log(f"  {h.num_levels()} levels")
+    h.close()
+    return s, snap
+
+
+@pytest.mark.parametrize("var,form", FORMS)
+def test_kernel_form_is_bit_identical(ref, var, form, monkeypatch):
+    s, snap = ref
+    monkeypatch.setenv(var, form)
+    log(f"  {var}={form}")
+    h = gpu_hierarchy(s, weights=weights_fn, judge=0, max_coarse=60)
+    got = _snapshot(h)
+    h.close()
+    assert len(got) == len(snap)
+    for a, b in zip(got, snap):
+        assert a.dtype == b.dtype and a.shape == b.shape
+        assert a.tobytes() == b.tobytes()
