@@ -105,6 +105,7 @@ int scan_exclusive(const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
 //   MBAMG_SA_FORM     = thread | wave | generic   (smoothed prolongator)
 //   MBAMG_SPGEMM_FORM = block | entry              (numeric Galerkin product)
 //   MBAMG_SORT_FORM   = thread | wave              (aggregate member lists)
+//   MBAMG_SYM_FORM    = thread | wave              (product pattern)
 static const char* form_override(const char* var) {
     const char* v = std::getenv(var);
     return (v && *v) ? v : nullptr;
@@ -725,6 +726,56 @@ __device__ inline void ks_sort(KeySet& S, int lane, int K) {
         S.sorted[r] = key;
     }
     __syncthreads();
+}
+
+// Pattern of C = A B, one thread per row: the row's distinct columns kept
+// sorted in registers (at most SYM_REG; more sets *overflow and the caller
+// takes the wavefront form).  Pass 0 counts, pass 1 writes.
+constexpr int SYM_REG = 32;
+__global__ __launch_bounds__(128) void k_spgemm_sym_t(int n, const int32_t* __restrict__ arp,
+                                                      const int32_t* __restrict__ aci,
+                                                      const int32_t* __restrict__ brp,
+                                                      const int32_t* __restrict__ bci, int pass, int32_t* cnt,
+                                                      const int32_t* crp, int32_t* cci, int32_t* overflow) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cols[SYM_REG];
+#pragma unroll
+    for (int u = 0; u < SYM_REG; ++u) cols[u] = INT_MAX;
+    int k = 0;
+    for (int p = arp[i]; p < arp[i + 1]; ++p) {
+        const int j = aci[p];
+        for (int q = brp[j]; q < brp[j + 1]; ++q) {
+            const int c = bci[q];
+            int pos = 0;
+            bool present = false;
+#pragma unroll
+            for (int u = 0; u < SYM_REG; ++u) {
+                pos += cols[u] < c;
+                present |= cols[u] == c;
+            }
+            if (present) continue;
+            if (k == SYM_REG) {
+                atomicOr(overflow, 1);
+                return;
+            }
+#pragma unroll
+            for (int u = SYM_REG - 1; u > 0; --u)
+                if (u > pos) cols[u] = cols[u - 1];
+#pragma unroll
+            for (int u = 0; u < SYM_REG; ++u)
+                if (u == pos) cols[u] = c;
+            ++k;
+        }
+    }
+    if (!pass) {
+        cnt[i] = k;
+        return;
+    }
+    const int out = crp[i];
+#pragma unroll
+    for (int u = 0; u < SYM_REG; ++u)
+        if (u < k) cci[out + u] = cols[u];
 }
 
 // Pattern of C = A B: pass 0 counts each row's distinct columns, pass 1
@@ -1642,8 +1693,10 @@ bool same_pattern(const SetupBsr& X, const SetupBsr& Y, hipStream_t s) {
     return flag.download(s, 1)[0] != 0;
 }
 
-// outputs with fewer blocks than this take one lane per output entry
-constexpr int64_t SPGEMM_ENTRY_MAX = (int64_t)1 << 21;
+// outputs with fewer blocks than this take one lane per output entry (above
+// it, one thread per block is faster: the lanes of a block repeat its
+// column searches)
+constexpr int64_t SPGEMM_ENTRY_MAX = (int64_t)1 << 15;
 
 static void spgemm_values(const SetupBsr& A, const SetupBsr& B, SetupBsr& C, const int32_t* crow, hipStream_t s) {
     if (C.nnzb == 0) return;
@@ -1696,9 +1749,23 @@ SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s, const Setup
     } else {
         DevBuf<int32_t> cnt(std::max(n, 1)), ovf(1);
         MB_HIP(hipMemsetAsync(ovf.p, 0, sizeof(int32_t), s));
-        k_spgemm_sym<<<n, WAVE, 0, s>>>(A.rp.p, A.ci.p, B.rp.p, B.ci.p, 0, cnt.p, nullptr, nullptr, ovf.p);
-        MB_LAUNCH_CHECK();
-        if (ovf.download(s, 1)[0] != 0) {
+        // short rows of A: one thread per row while the distinct columns fit in registers
+        bool per_thread = A.nnzb <= (int64_t)16 * n;
+        if (const char* f = form_override("MBAMG_SYM_FORM")) per_thread = std::strcmp(f, "thread") == 0;
+        if (per_thread) {
+            k_spgemm_sym_t<<<grid_for(n, 128), 128, 0, s>>>(n, A.rp.p, A.ci.p, B.rp.p, B.ci.p, 0, cnt.p, nullptr,
+                                                          nullptr, ovf.p);
+            MB_LAUNCH_CHECK();
+            if (ovf.download(s, 1)[0] != 0) {
+                per_thread = false;
+                MB_HIP(hipMemsetAsync(ovf.p, 0, sizeof(int32_t), s));
+            }
+        }
+        if (!per_thread) {
+            k_spgemm_sym<<<n, WAVE, 0, s>>>(A.rp.p, A.ci.p, B.rp.p, B.ci.p, 0, cnt.p, nullptr, nullptr, ovf.p);
+            MB_LAUNCH_CHECK();
+        }
+        if (!per_thread && ovf.download(s, 1)[0] != 0) {
             // a row has too many distinct columns for the LDS set: thread-per-row product
             k_spgemm<<<grid_for(n, 64), 64, 0, s>>>(n, A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p,
                                                    B.val.p, 0, cnt.p, nullptr, nullptr, nullptr);
@@ -1714,7 +1781,11 @@ SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s, const Setup
         }
         C.nnzb = scan_exclusive(cnt.p, n, C.rp.p, s);
         C.ci.alloc(std::max<int64_t>(C.nnzb, 1));
-        k_spgemm_sym<<<n, WAVE, 0, s>>>(A.rp.p, A.ci.p, B.rp.p, B.ci.p, 1, nullptr, C.rp.p, C.ci.p, ovf.p);
+        if (per_thread)
+            k_spgemm_sym_t<<<grid_for(n, 128), 128, 0, s>>>(n, A.rp.p, A.ci.p, B.rp.p, B.ci.p, 1, nullptr, C.rp.p,
+                                                          C.ci.p, ovf.p);
+        else
+            k_spgemm_sym<<<n, WAVE, 0, s>>>(A.rp.p, A.ci.p, B.rp.p, B.ci.p, 1, nullptr, C.rp.p, C.ci.p, ovf.p);
         MB_LAUNCH_CHECK();
         MB_HIP(hipStreamSynchronize(s));   // cnt and ovf are released on leaving this block
     }

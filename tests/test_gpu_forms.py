@@ -5,7 +5,9 @@ choice (which the oracle tests pin):
 - smoothed prolongator: one thread per row with the row in registers, the
   generic one-thread form, one wavefront per row;
 - numeric Galerkin product: one thread per output block, one lane per entry;
-- aggregate member lists: one lane per aggregate, one wavefront per aggregate.
+- aggregate member lists: one lane per aggregate, one wavefront per aggregate;
+- product pattern: one thread per row (registers), one wavefront per row (LDS
+  hash set); a forced thread form falls back where a row overflows.
 """
 import numpy as np
 import pytest
@@ -28,7 +30,8 @@ CASES = {
 
 FORMS = [("MBAMG_SA_FORM", "thread"), ("MBAMG_SA_FORM", "wave"), ("MBAMG_SA_FORM", "generic"),
          ("MBAMG_SPGEMM_FORM", "block"), ("MBAMG_SPGEMM_FORM", "entry"),
-         ("MBAMG_SORT_FORM", "thread"), ("MBAMG_SORT_FORM", "wave")]
+         ("MBAMG_SORT_FORM", "thread"), ("MBAMG_SORT_FORM", "wave"),
+         ("MBAMG_SYM_FORM", "thread"), ("MBAMG_SYM_FORM", "wave")]
 
 
 def _snapshot(h):
