@@ -459,9 +459,12 @@ static void colour_level(Level& Lv, hipEvent_t ready, int device) {
     hipStream_t cs = nullptr;
     MB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     std::vector<int32_t> rp[2], ci[2];
+    bool same = false;
     try {
         MB_HIP(hipStreamWaitEvent(cs, ready, 0));
-        for (int f = 0; f < 2; ++f) {
+        // block 1's pattern is compared on the device and copied only when it differs
+        same = same_pattern(Lv.A[0][0], Lv.A[1][1], cs);
+        for (int f = 0; f < (same ? 1 : 2); ++f) {
             rp[f].resize((size_t)Lv.n + 1);
             ci[f].resize((size_t)Lv.A[f][f].nnzb);
             MB_HIP(hipMemcpyAsync(rp[f].data(), Lv.A[f][f].rp.p, sizeof(int32_t) * rp[f].size(),
@@ -479,7 +482,7 @@ static void colour_level(Level& Lv, hipEvent_t ready, int device) {
     for (int f = 0; f < 2; ++f) {
         BlockLevel& B = Lv.blk[f];
         B.d = Lv.d[f];
-        if (f == 1 && rp[1] == rp[0] && ci[1] == ci[0]) {
+        if (f == 1 && same) {
             // same pattern: the same first-fit colouring, order and slices
             const BlockLevel& B0 = Lv.blk[0];
             B.colour = B0.colour;
@@ -613,8 +616,19 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
         const int64_t ndof = (int64_t)cur.n * (d0 + d1);
         if (ndof <= p.max_coarse || (int)h->L.size() >= p.max_levels) break;
         clk.mark("start", lvl);
+        const bool donor_level = lvl == 0 && donor && donor->L.size() > 1 && donor->L[0]->n == cur.n;
+        // level 0's pattern is final now: its colouring starts before aggregation (the job
+        // is simply not used if level 0 turns out to be the coarsest)
+        if (lvl == 0 && !donor_level) {
+            hipEvent_t ev = nullptr;
+            MB_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            colour_events.push_back(ev);
+            MB_HIP(hipEventRecord(ev, s));
+            Level* lp = &cur;
+            colour_jobs[lvl] = std::async(std::launch::async, [lp, ev, device] { colour_level(*lp, ev, device); });
+        }
         Aggregates G;
-        if (lvl == 0 && donor && donor->L.size() > 1 && donor->L[0]->n == cur.n) {
+        if (donor_level) {
             const Aggregates& D = donor->L[0]->G;
             G.n = D.n;
             G.n_agg = D.n_agg;
@@ -631,7 +645,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
         if ((double)G.n_agg > 0.9 * cur.n) break;
         // this level is not the coarsest: colour it on a host thread while the GPU
         // builds the next level (the level-0 colouring comes with the donor's copy)
-        if (!(lvl == 0 && donor && donor->L.size() > 1 && donor->L[0]->n == cur.n)) {
+        if (!donor_level && !colour_jobs.count(lvl)) {
             hipEvent_t ev = nullptr;
             MB_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
             colour_events.push_back(ev);

@@ -5,8 +5,10 @@
 // goes to the freeing thread's pending list: the library only knows that the
 // block is idle once the device has been synchronised, so pending blocks are
 // moved to the free lists by pool_device_idle(), which the library calls right
-// after hipDeviceSynchronize().  When hipMalloc fails, the cached free blocks
-// are released and the allocation is retried once.
+// after hipDeviceSynchronize().  A thread that ends hands its pending blocks
+// to a shared list that the next pool_device_idle() promotes as well.  When
+// hipMalloc fails, the cached free blocks are released and the allocation is
+// retried once.
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -33,7 +35,20 @@ Pool& pool() {
     return *p;
 }
 
-thread_local std::vector<Block> t_pending;
+// blocks freed by threads that have ended, promoted by the next idle point
+std::vector<Block>& orphans() {
+    static auto* v = new std::vector<Block>;   // guarded by pool().m
+    return *v;
+}
+struct Pending {
+    std::vector<Block> v;
+    ~Pending() {
+        if (v.empty()) return;
+        std::lock_guard<std::mutex> g(pool().m);
+        orphans().insert(orphans().end(), v.begin(), v.end());
+    }
+};
+thread_local Pending t_pending;
 
 size_t size_class(size_t b) {
     if (b <= 4096) return 4096;
@@ -92,14 +107,23 @@ void* dev_alloc(size_t bytes) {
 
 void dev_free(void* p, size_t bytes) {
     if (!p) return;
-    t_pending.push_back({current_device(), size_class(bytes), p});
+    t_pending.v.push_back({current_device(), size_class(bytes), p});
 }
 
+// the current device has been synchronised: its pending blocks are idle
 void pool_device_idle() {
-    if (t_pending.empty()) return;
+    const int dev = current_device();
     std::lock_guard<std::mutex> g(pool().m);
-    for (const Block& b : t_pending) pool().free_lists[b.dev].emplace(b.bytes, b.p);
-    t_pending.clear();
+    auto promote = [dev](std::vector<Block>& list) {
+        size_t keep = 0;
+        for (const Block& b : list) {
+            if (b.dev == dev) pool().free_lists[dev].emplace(b.bytes, b.p);
+            else list[keep++] = b;
+        }
+        list.resize(keep);
+    };
+    promote(t_pending.v);
+    promote(orphans());
 }
 
 }  // namespace mbamg
