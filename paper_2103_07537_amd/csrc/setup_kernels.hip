@@ -413,39 +413,52 @@ __global__ void k_dinv(int n, int d, const int32_t* rp, const int32_t* ci, const
 // ----------------------------------------------------------------------------
 // One wavefront per slot (one lane per row): the slot's mask is the OR of the
 // lanes' nonzero patterns and slot_nz the sum of their nonzero counts.
-__global__ void k_sell_mask(int64_t n_slots, int bs, const int64_t* src, const double* val, uint32_t* mask,
-                            uint32_t* slot_nz) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t slot = t / WAVE;
+// One wavefront per slot of 64 rows; the 64 source blocks (bs <= 16 entries,
+// src < 0: padding) are read 4 at a time, 16 lanes per block, so every load
+// is a contiguous block.  mask = entries nonzero in any row of the slot,
+// slot_nz = nonzero entries over the slot.
+__global__ __launch_bounds__(256) void k_sell_mask(int64_t n_slots, int bs, const int64_t* __restrict__ src,
+                                                   const double* __restrict__ val, uint32_t* mask,
+                                                   uint32_t* slot_nz) {
+    const int64_t slot = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     if (slot >= n_slots) return;   // whole wavefronts
-    const int64_t s = src[t];
-    uint32_t bits = 0;
-    if (s >= 0)
-        for (int k = 0; k < bs; ++k)
-            if (val[s * bs + k] != 0.0) bits |= 1u << k;
-    uint32_t m = 0;
-    for (int k = 0; k < bs; ++k)
-        if (__ballot((bits >> k) & 1u)) m |= 1u << k;
-    int nz = __popc(bits);
-    for (int off = WAVE / 2; off > 0; off >>= 1) nz += __shfl_xor(nz, off);
-    if ((t & (WAVE - 1)) == 0) {
+    const int lane = threadIdx.x & (WAVE - 1), k = lane & 15, sub = lane >> 4;
+    uint32_t m = 0, nz = 0;
+    for (int it = 0; it < WAVE / 4; ++it) {
+        const int64_t sb = src[slot * WAVE + it * 4 + sub];
+        const bool on = sb >= 0 && k < bs && val[sb * bs + k] != 0.0;
+        const uint64_t bal = __ballot(on);
+        nz += (uint32_t)__popcll(bal);
+        m |= (uint32_t)((bal | (bal >> 16) | (bal >> 32) | (bal >> 48)) & 0xFFFFu);
+    }
+    if (lane == 0) {
         mask[slot] = m;
-        slot_nz[slot] = (uint32_t)nz;
+        slot_nz[slot] = nz;
     }
 }
 
-__global__ void k_sell_fill(int64_t n_slots, int bs, const int64_t* src, const double* val, const uint32_t* mask,
-                            const int64_t* slot_voff, double* out) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_slots * WAVE) return;
-    int64_t slot = t / WAVE;
-    int lane = (int)(t % WAVE);
-    int64_t s = src[t];
-    uint32_t m = mask[slot];
+// The slot's blocks are staged through LDS (read as in k_sell_mask) and
+// written entry by entry of the mask, 64 rows per entry.
+__global__ __launch_bounds__(256) void k_sell_fill(int64_t n_slots, int bs, const int64_t* __restrict__ src,
+                                                   const double* __restrict__ val, const uint32_t* __restrict__ mask,
+                                                   const int64_t* __restrict__ slot_voff, double* out) {
+    __shared__ double tile[256 / WAVE][WAVE][17];
+    const int64_t slot = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (slot >= n_slots) return;   // whole wavefronts; no block-wide barrier below
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1), k = lane & 15, sub = lane >> 4;
+    for (int it = 0; it < WAVE / 4; ++it) {
+        const int row = it * 4 + sub;
+        const int64_t sb = src[slot * WAVE + row];
+        tile[w][row][k] = (sb >= 0 && k < bs) ? val[sb * bs + k] : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t m = mask[slot];
     int64_t g = slot_voff[slot];
-    for (int k = 0; k < bs; ++k) {
-        if (!(m & (1u << k))) continue;
-        out[g * WAVE + lane] = s >= 0 ? val[s * bs + k] : 0.0;
+    for (int e = 0; e < bs; ++e) {
+        if (!(m & (1u << e))) continue;
+        out[g * WAVE + lane] = tile[w][lane][e];
         ++g;
     }
 }
@@ -1090,7 +1103,6 @@ __global__ void k_part_fill_index(int ns, int kind, const int32_t* row0, const i
         if (kind == 3) {
             col[base * WAVE + lane] = p;
             src[base * WAVE + lane] = node;
-            atomicAdd(&slot_blocks[base], 1);
             k = 1;
         } else {
             for (int q = rp[node]; q < rp[node + 1] && k < w; ++q) {
@@ -1098,14 +1110,19 @@ __global__ void k_part_fill_index(int ns, int kind, const int32_t* row0, const i
                 if (!part_selects(kind, node, j)) continue;
                 col[(base + k) * WAVE + lane] = col_iperm[j];
                 src[(base + k) * WAVE + lane] = q;
-                atomicAdd(&slot_blocks[base + k], 1);
                 ++k;
             }
         }
     }
+    const int placed = k;
     for (; k < w; ++k) {
         col[(base + k) * WAVE + lane] = -1;
         src[(base + k) * WAVE + lane] = -1;
+    }
+    // blocks per slot: the slots of a slice belong to its wavefront alone
+    for (int kk = 0; kk < w; ++kk) {
+        const int c = (int)__popcll(__ballot(kk < placed));
+        if (lane == 0) slot_blocks[base + kk] = c;
     }
 }
 
@@ -1512,6 +1529,7 @@ void build_dinv(const SetupBsr& A, double* dinv, hipStream_t s) {
 
 void sell_masks(int64_t n_slots, int bs, const int64_t* src, const double* val, uint32_t* mask, uint32_t* slot_nz,
                 hipStream_t s) {
+    MB_CHECK(bs >= 1 && bs <= 16, MBAMG_E_INVALID, "sliced format: blocks of at most 16 entries");
     MB_HIP(hipMemsetAsync(mask, 0, sizeof(uint32_t) * std::max<int64_t>(n_slots, 1), s));
     if (n_slots == 0) return;
     k_sell_mask<<<grid_for(n_slots * WAVE), 256, 0, s>>>(n_slots, bs, src, val, mask, slot_nz);
@@ -1626,17 +1644,24 @@ __global__ void k_rows_count(int n, const int32_t* perm, const int32_t* rp, int3
     cnt[p] = rp[node + 1] - rp[node];
 }
 
-__global__ void k_rows_fill(int n, int bs, const int32_t* perm, const int32_t* rp, const int32_t* ci,
-                            const double* val, const int32_t* col_iperm, const int32_t* rrp, int32_t* rcol,
-                            double* rval) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
+// one wavefront per row: the row's blocks are contiguous at both ends
+__global__ __launch_bounds__(256) void k_rows_fill(int n, int bs, const int32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                   const double* __restrict__ val,
+                                                   const int32_t* __restrict__ col_iperm,
+                                                   const int32_t* __restrict__ rrp, int32_t* __restrict__ rcol,
+                                                   double* __restrict__ rval) {
+    const int p = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
     if (p >= n) return;
+    const int lane = threadIdx.x & (WAVE - 1);
     const int node = perm[p];
-    int q = rrp[p];
-    for (int k = rp[node]; k < rp[node + 1]; ++k, ++q) {
-        rcol[q] = col_iperm[ci[k]];
-        for (int e = 0; e < bs; ++e) rval[(int64_t)q * bs + e] = val[(int64_t)k * bs + e];
-    }
+    const int k0 = rp[node], len = rp[node + 1] - k0;
+    const int q0 = rrp[p];
+    for (int u = lane; u < len; u += WAVE) rcol[q0 + u] = col_iperm[ci[k0 + u]];
+    const int64_t nv = (int64_t)len * bs;
+    const double* a = val + (int64_t)k0 * bs;
+    double* b = rval + (int64_t)q0 * bs;
+    for (int64_t u = lane; u < nv; u += WAVE) b[u] = a[u];
 }
 
 __global__ void k_gather_blocks(int n, int bs, const int32_t* perm, const double* src, double* dst) {
@@ -1666,8 +1691,8 @@ void build_rows(RowPart& R, int n, const int32_t* perm, const SetupBsr& A, const
     R.nnzb = scan_exclusive(cnt.p, n, R.rp.p, s);
     R.col.alloc(std::max<int64_t>(R.nnzb, 1));
     R.v64.alloc(std::max<int64_t>(R.nnzb * bs, 1));
-    k_rows_fill<<<grid_for(n), 256, 0, s>>>(n, bs, perm, A.rp.p, A.ci.p, A.val.p, col_iperm, R.rp.p, R.col.p,
-                                            R.v64.p);
+    k_rows_fill<<<grid_for((int64_t)n * WAVE), 256, 0, s>>>(n, bs, perm, A.rp.p, A.ci.p, A.val.p, col_iperm, R.rp.p,
+                                                           R.col.p, R.v64.p);
     MB_LAUNCH_CHECK();
     if (want32) {
         R.v32.alloc(std::max<int64_t>(R.nnzb * bs, 1));
