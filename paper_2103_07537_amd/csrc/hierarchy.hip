@@ -809,6 +809,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
             B.split = slot_split(per_colour, avg_width);
             // long rows (dense coarse stencils): one wavefront per row instead
             B.rows = l > 0 && Lv.A[f][f].nnzb >= (int64_t)32 * Lv.n;
+            if (const char* fo = form_override("MBAMG_ROWS_FORM")) B.rows = l > 0 && std::strcmp(fo, "rows") == 0;
             if (B.rows) {
                 build_rows(B.raff, Lv.n, B.d_perm.p, Lv.A[f][f], B.d_iperm.p, want32, s);
                 build_rows(B.rafg, Lv.n, B.d_perm.p, Lv.A[f][g], Lv.blk[g].d_iperm.p, want32, s);

@@ -66,6 +66,10 @@ void gather_blocks(int n, int bs, const int32_t* perm, const double* src, double
 
 // true when X and Y have identical block patterns (synchronous)
 bool same_pattern(const SetupBsr& X, const SetupBsr& Y, hipStream_t s);
+
+// Test-only choice between equivalent kernel forms: the value of environment
+// variable `var`, or null when it is unset or empty.
+const char* form_override(const char* var);
 // device construction of the sliced smoother format (see hierarchy.hip)
 void part_layout(int n, int ns, int kind, const int32_t* perm, const int32_t* rp, const int32_t* ci,
                  const int32_t* row0, const int32_t* nrow, DevBuf<int32_t>& width, DevBuf<int32_t>& coff32,

@@ -106,7 +106,9 @@ int scan_exclusive(const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
 //   MBAMG_SPGEMM_FORM = block | entry              (numeric Galerkin product)
 //   MBAMG_SORT_FORM   = thread | wave              (aggregate member lists)
 //   MBAMG_SYM_FORM    = thread | wave              (product pattern)
-static const char* form_override(const char* var) {
+//   MBAMG_ROWS_FORM   = rows | sliced              (coarse-level smoother layout;
+//                                                   changes the summation order)
+const char* form_override(const char* var) {
     const char* v = std::getenv(var);
     return (v && *v) ? v : nullptr;
 }

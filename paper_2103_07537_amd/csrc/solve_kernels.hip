@@ -282,11 +282,35 @@ __device__ __forceinline__ void row_sub(const RowView<T>& A, int row, int lane, 
     }
 }
 
+// v from lane src (by the DPP control CTRL, in the rows of ROWMASK; 0 where
+// the source lane is out of range or the row is masked)
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_in(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, true));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_in(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the wavefront, valid in lane WAVE - 1: shifts by 1, 2, 4 and 8
+// inside each row of 16 lanes leave every row's sum in its last lane, then
+// the row broadcasts 15 and 31 add the rows up.
 template <class T, int D>
 __device__ __forceinline__ void wave_sum_vec(T (&acc)[D]) {
 #pragma unroll
-    for (int r = 0; r < D; ++r)
-        for (int off = WAVE / 2; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
+    for (int r = 0; r < D; ++r) {
+        T v = acc[r];
+        v += dpp_in<0x111, 0xF>(v);   // row_shr:1
+        v += dpp_in<0x112, 0xF>(v);   // row_shr:2
+        v += dpp_in<0x114, 0xF>(v);   // row_shr:4
+        v += dpp_in<0x118, 0xF>(v);   // row_shr:8
+        v += dpp_in<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+        v += dpp_in<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+        acc[r] = v;
+    }
 }
 
 // One colour of the block row's Gauss-Seidel sub-solve (the arithmetic of k_gs).
@@ -305,7 +329,7 @@ __global__ __launch_bounds__(256) void k_gs_rows(GsRowArgs<T> a) {
     }
     if (CPL) row_sub<T, D, D, 0, false>(a.afg, row, lane, a.xg, nullptr, 0, acc);
     wave_sum_vec<T, D>(acc);
-    if (lane != 0) return;
+    if (lane != WAVE - 1) return;
     T bb[D];
     load_vec<T, D>(a.b + (int64_t)row * D, bb);
 #pragma unroll
@@ -352,7 +376,7 @@ __global__ __launch_bounds__(256) void k_resid_rows(ResidRowArgs<T> a) {
     row_sub<T, D, D, 0, false>(a.aff[f], row, lane, a.x[f], nullptr, 0, acc);
     row_sub<T, D, D, 0, false>(a.afg[f], row, lane, a.x[g], nullptr, 0, acc);
     wave_sum_vec<T, D>(acc);
-    if (lane != 0) return;
+    if (lane != WAVE - 1) return;
     T out[D];
     if (a.b[f]) {
         T bb[D];
