@@ -839,6 +839,22 @@ __global__ void k_row_of(int n, const int32_t* __restrict__ rp, int32_t* __restr
 // Values of C = A B on a known pattern, one thread per output block (i, l):
 // the sum over the columns j of row i of A in increasing order and, for each,
 // m increasing -- the order of the thread-per-row kernel.
+// find_col for the short sorted rows of the product's right operand: up to
+// 16 columns are loaded at once (no chain of dependent loads), longer rows
+// are searched by bisection
+__device__ __forceinline__ int find_col_short(const int32_t* __restrict__ ci, int lo, int hi, int key) {
+    const int len = hi - lo;
+    if (len > 16) return find_col(ci, lo, hi, key);
+    int c[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) c[u] = u < len ? ci[lo + u] : -1;
+    int pos = -1;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+        if (c[u] == key) pos = lo + u;
+    return pos;
+}
+
 template <int BR, int BM, int BC>
 __global__ void k_spgemm_num(int64_t nnz, const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
                              const double* __restrict__ aval, const int32_t* __restrict__ brp,
@@ -853,7 +869,7 @@ __global__ void k_spgemm_num(int64_t nnz, const int32_t* __restrict__ arp, const
     for (int e = 0; e < BR * BC; ++e) acc[e] = 0.0;
     for (int p = arp[i]; p < arp[i + 1]; ++p) {
         const int j = aci[p];
-        const int q = find_col(bci, brp[j], brp[j + 1], l);
+        const int q = find_col_short(bci, brp[j], brp[j + 1], l);
         if (q < 0) continue;
         double a[BR * BM], bb[BM * BC];
 #pragma unroll
@@ -898,7 +914,7 @@ __global__ __launch_bounds__(256) void k_spgemm_num_e(int64_t nnz, const int32_t
     double acc = 0.0;
     for (int p = arp[i]; p < arp[i + 1]; ++p) {
         const int j = aci[p];
-        const int q = find_col(bci, brp[j], brp[j + 1], l);
+        const int q = find_col_short(bci, brp[j], brp[j + 1], l);
         if (q < 0 || !live) continue;
 #pragma unroll
         for (int m = 0; m < BM; ++m) {
