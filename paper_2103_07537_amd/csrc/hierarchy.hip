@@ -1429,18 +1429,18 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
         std::unique_ptr<mbamg_hierarchy> h;
         if (p->learned != 0 && p->judge) {
             // the fixed-weight method is the fallback and the judge.  It is built first: its
-            // coarsest inverse then runs on its own stream during the learned build, which
-            // copies the fixed build's level-0 aggregates and smoother data
+            // coarsest inverse and then its probe run on their own stream during the learned
+            // build, which copies the fixed build's level-0 aggregates and smoother data
             mbamg_params pf = *p;
             pf.learned = 0;
             pf.omega_p = 0.0;
             PhaseClock jclk(s);
             auto hf = build(pf, nullptr, true);
             jclk.mark("fixed hierarchy built", 0);
-            h = build(*p, hf.get(), false);
-            jclk.mark("learned hierarchy built", 0);
-            // the two probes run at the same time, the fixed one on a stream and host thread of
-            // its own (the hierarchies share no buffers)
+            // the fixed hierarchy is probed on a stream and host thread of its own while the
+            // learned one is built (the learned build only reads the fixed one's level-0 data;
+            // the hierarchies share no buffers).  Declared after hf: on an exception the probe
+            // is waited for before hf goes away.
             int device = 0;
             MB_HIP(hipGetDevice(&device));
             SideStream s2;
@@ -1450,6 +1450,8 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
                 finish_coarse(fixed, s2.stream);
                 return probe_impl(fixed, 10, 12345, s2.stream);
             });
+            h = build(*p, hf.get(), false);
+            jclk.mark("learned hierarchy built", 0);
             const double rl = probe_impl(h.get(), 10, 12345, s);
             const double rf = fixed_probe.get();
             jclk.mark("judge probes", 0);
