@@ -668,22 +668,44 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
         // pattern; the symbolic phase then runs once and the rest reuse it.
         auto galerkin_all = [&](const SetupBsr (&P)[2], const SetupBsr (&PT)[2]) {
             const bool sameP = same_pattern(P[0], P[1], s);
-            SetupBsr T[2][2];
-            for (int f = 0; f < 2; ++f)
-                for (int g = 0; g < 2; ++g) {
-                    // an earlier pair (f', g') whose A block and prolongators have the same patterns
-                    int src = -1;
-                    for (int k = 0; k < f * 2 + g && src < 0; ++k) {
-                        const int f2 = k / 2, g2 = k % 2;
-                        if ((f2 == f || sameP) && (g2 == g || sameP) && cur.A[f2][g2].nnzb > 0 &&
-                            same_pattern(cur.A[f][g], cur.A[f2][g2], s))
-                            src = k;
+            // block pairs whose A block and prolongators have the same patterns form one group:
+            // its products T = A_fg P_g and P_f^T T share their patterns and one launch each
+            std::vector<std::vector<int>> groups;
+            for (int k = 0; k < 4; ++k) {
+                const int f = k / 2, g = k % 2;
+                bool placed = false;
+                for (auto& grp : groups) {
+                    const int f2 = grp[0] / 2, g2 = grp[0] % 2;
+                    if ((f2 == f || sameP) && (g2 == g || sameP) && cur.A[f2][g2].nnzb > 0 &&
+                        same_pattern(cur.A[f][g], cur.A[f2][g2], s)) {
+                        grp.push_back(k);
+                        placed = true;
+                        break;
                     }
-                    const SetupBsr* likeT = src >= 0 ? &T[src / 2][src % 2] : nullptr;
-                    const SetupBsr* likeC = src >= 0 ? &nxt->A[src / 2][src % 2] : nullptr;
-                    T[f][g] = spgemm(cur.A[f][g], P[g], s, likeT);
-                    nxt->A[f][g] = spgemm(PT[f], T[f][g], s, likeC);
                 }
+                if (!placed) groups.push_back({k});
+            }
+            SetupBsr T[2][2];
+            for (const auto& grp : groups) {
+                const SetupBsr* Aa[4];
+                const SetupBsr* Pb[4];
+                const SetupBsr* PTa[4];
+                const SetupBsr* Tb[4];
+                SetupBsr* Tc[4];
+                SetupBsr* Cc[4];
+                const int K = (int)grp.size();
+                for (int u = 0; u < K; ++u) {
+                    const int f = grp[u] / 2, g = grp[u] % 2;
+                    Aa[u] = &cur.A[f][g];
+                    Pb[u] = &P[g];
+                    PTa[u] = &PT[f];
+                    Tb[u] = &T[f][g];
+                    Tc[u] = &T[f][g];
+                    Cc[u] = &nxt->A[f][g];
+                }
+                spgemm_multi(Aa, Pb, K, Tc, s);
+                spgemm_multi(PTa, Tb, K, Cc, s);
+            }
         };
         if (p.learned != 0 || p.omega_p != 0.0) {
             choose_weights(h, cur, G, lvl, s);

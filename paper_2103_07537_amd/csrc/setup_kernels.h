@@ -49,6 +49,11 @@ SetupBsr block_transpose(const SetupBsr& P, hipStream_t s);
 // C = A B; `like`, when given, is a product whose operands had the same
 // patterns as A and B: its pattern is reused and only the values are computed
 SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s, const SetupBsr* like = nullptr);
+// C_k = A_k B_k for k < K <= 4 where the A_k share one pattern and the B_k
+// share one pattern: the pattern is found once (or taken from `like`) and the
+// values come from one launch; bit-identical to K separate products.
+void spgemm_multi(const SetupBsr* const* A, const SetupBsr* const* B, int K, SetupBsr* const* C, hipStream_t s,
+                  const SetupBsr* like = nullptr);
 // A block row in row form (see RowView): rows in the colour order `perm`
 // (colour position -> natural node), columns mapped through `col_iperm`
 // (natural node -> colour position of the column block).

@@ -103,7 +103,8 @@ int scan_exclusive(const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
 // Kernel-form overrides for tests: every form computes the same sums in the
 // same order, so a hierarchy must come out bit-identical under each.
 //   MBAMG_SA_FORM     = thread | wave | generic   (smoothed prolongator)
-//   MBAMG_SPGEMM_FORM = block | entry              (numeric Galerkin product)
+//   MBAMG_SPGEMM_FORM = block | entry | fused      (numeric Galerkin product; fused:
+//                                                   one launch for every group of pairs)
 //   MBAMG_SORT_FORM   = thread | wave              (aggregate member lists)
 //   MBAMG_SYM_FORM    = thread | wave              (product pattern)
 //   MBAMG_ROWS_FORM   = rows | sliced              (coarse-level smoother layout;
@@ -889,6 +890,60 @@ __global__ void k_spgemm_num(int64_t nnz, const int32_t* __restrict__ arp, const
     double* dst = cval + k * BR * BC;
 #pragma unroll
     for (int e = 0; e < BR * BC; ++e) dst[e] = acc[e];
+}
+
+// K products C_k = A_k B_k with one pattern (A_k share one, B_k share one):
+// every output block's column lookups are done once for all K; each entry's
+// sum runs in the same order as one product alone.
+template <int K>
+struct SpgemmVals {
+    const double* a[K];
+    const double* b[K];
+    double* c[K];
+};
+template <int BR, int BM, int BC, int K>
+__global__ __launch_bounds__(128) void k_spgemm_num_k(int64_t nnz, const int32_t* __restrict__ arp,
+                                                      const int32_t* __restrict__ aci,
+                                                      const int32_t* __restrict__ brp,
+                                                      const int32_t* __restrict__ bci,
+                                                      const int32_t* __restrict__ crow,
+                                                      const int32_t* __restrict__ cci, SpgemmVals<K> v) {
+    const int64_t kk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (kk >= nnz) return;
+    const int i = crow[kk], l = cci[kk];
+    double acc[K][BR * BC];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int e = 0; e < BR * BC; ++e) acc[k][e] = 0.0;
+    for (int p = arp[i]; p < arp[i + 1]; ++p) {
+        const int j = aci[p];
+        const int q = find_col_short(bci, brp[j], brp[j + 1], l);
+        if (q < 0) continue;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double a[BR * BM], bb[BM * BC];
+#pragma unroll
+            for (int e = 0; e < BR * BM; ++e) a[e] = v.a[k][(int64_t)p * BR * BM + e];
+#pragma unroll
+            for (int e = 0; e < BM * BC; ++e) bb[e] = v.b[k][(int64_t)q * BM * BC + e];
+#pragma unroll
+            for (int r = 0; r < BR; ++r)
+#pragma unroll
+                for (int cc = 0; cc < BC; ++cc)
+#pragma unroll
+                    for (int m = 0; m < BM; ++m) {
+                        const double term = a[r * BM + m] * bb[m * BC + cc];
+                        acc[k][r * BC + cc] = acc[k][r * BC + cc] + term;
+                    }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double* dst = v.c[k] + kk * BR * BC;
+#pragma unroll
+        for (int e = 0; e < BR * BC; ++e) dst[e] = acc[k][e];
+    }
 }
 
 // the same with one lane per output entry and 16 lanes per output block, for
@@ -1766,10 +1821,14 @@ static void spgemm_values(const SetupBsr& A, const SetupBsr& B, SetupBsr& C, con
     MB_LAUNCH_CHECK();
 }
 
-SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s, const SetupBsr* like) {
+// The pattern of C = A B (rows of C list their columns in increasing order),
+// found or taken from `like`; C.val is allocated.  Returns false when a row
+// was too long for the symbolic kernels and the one-thread-per-row product
+// has filled the values as well.
+static bool spgemm_pattern(const SetupBsr& A, const SetupBsr& B, SetupBsr& C, hipStream_t s, const SetupBsr* like) {
     MB_CHECK(A.bc == B.br && A.br * B.bc <= 16, MBAMG_E_INVALID, "block product shapes");
     const int n = A.n_rows;
-    SetupBsr C;
+    C = SetupBsr();
     C.n_rows = n;
     C.n_cols = B.n_cols;
     C.br = A.br;
@@ -1779,7 +1838,7 @@ SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s, const Setup
         MB_HIP(hipMemsetAsync(C.rp.p, 0, sizeof(int32_t) * (n + 1), s));
         C.ci.alloc(1);
         C.val.alloc(1);
-        return C;
+        return false;
     }
     if (like) {
         // the caller guarantees that A and B have the patterns that produced `like`
@@ -1820,7 +1879,7 @@ SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s, const Setup
                                                    B.val.p, 1, nullptr, C.rp.p, C.ci.p, C.val.p);
             MB_LAUNCH_CHECK();
             MB_HIP(hipStreamSynchronize(s));
-            return C;
+            return false;
         }
         C.nnzb = scan_exclusive(cnt.p, n, C.rp.p, s);
         C.ci.alloc(std::max<int64_t>(C.nnzb, 1));
@@ -1833,12 +1892,88 @@ SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s, const Setup
         MB_HIP(hipStreamSynchronize(s));   // cnt and ovf are released on leaving this block
     }
     C.val.alloc(std::max<int64_t>(C.nnzb * C.br * C.bc, 1));
+    return true;
+}
+
+SetupBsr spgemm(const SetupBsr& A, const SetupBsr& B, hipStream_t s, const SetupBsr* like) {
+    SetupBsr C;
+    if (!spgemm_pattern(A, B, C, s, like)) return C;
     DevBuf<int32_t> crow(std::max<int64_t>(C.nnzb, 1));
-    k_row_of<<<grid_for(n), 256, 0, s>>>(n, C.rp.p, crow.p);
+    k_row_of<<<grid_for(C.n_rows), 256, 0, s>>>(C.n_rows, C.rp.p, crow.p);
     MB_LAUNCH_CHECK();
     spgemm_values(A, B, C, crow.p, s);
     MB_HIP(hipStreamSynchronize(s));   // crow is released on return
     return C;
+}
+
+template <int BR, int BM, int BC, int K>
+static void launch_num_k(const SetupBsr* const* A, const SetupBsr* const* B, SetupBsr* const* C,
+                         const int32_t* crow, hipStream_t s) {
+    SpgemmVals<K> v;
+    for (int k = 0; k < K; ++k) {
+        v.a[k] = A[k]->val.p;
+        v.b[k] = B[k]->val.p;
+        v.c[k] = C[k]->val.p;
+    }
+    const SetupBsr& A0 = *A[0];
+    const SetupBsr& B0 = *B[0];
+    k_spgemm_num_k<BR, BM, BC, K><<<grid_for(C[0]->nnzb, 128), 128, 0, s>>>(C[0]->nnzb, A0.rp.p, A0.ci.p, B0.rp.p,
+                                                                           B0.ci.p, crow, C[0]->ci.p, v);
+    MB_LAUNCH_CHECK();
+}
+
+void spgemm_multi(const SetupBsr* const* A, const SetupBsr* const* B, int K, SetupBsr* const* C, hipStream_t s,
+                  const SetupBsr* like) {
+    MB_CHECK(K >= 1 && K <= 4, MBAMG_E_INVALID, "internal: 1..4 products at once");
+    for (int k = 1; k < K; ++k)
+        MB_CHECK(A[k]->n_rows == A[0]->n_rows && A[k]->nnzb == A[0]->nnzb && B[k]->nnzb == B[0]->nnzb &&
+                     A[k]->br == A[0]->br && A[k]->bc == A[0]->bc && B[k]->bc == B[0]->bc,
+                 MBAMG_E_STATE, "internal: products grouped with different shapes");
+    if (!spgemm_pattern(*A[0], *B[0], *C[0], s, like)) {
+        for (int k = 1; k < K; ++k) *C[k] = spgemm(*A[k], *B[k], s, C[0]);
+        return;
+    }
+    for (int k = 1; k < K; ++k) {
+        SetupBsr& Ck = *C[k];
+        Ck = SetupBsr();
+        Ck.n_rows = C[0]->n_rows;
+        Ck.n_cols = C[0]->n_cols;
+        Ck.br = C[0]->br;
+        Ck.bc = C[0]->bc;
+        Ck.nnzb = C[0]->nnzb;
+        Ck.rp.alloc(Ck.n_rows + 1);
+        Ck.ci.alloc(std::max<int64_t>(Ck.nnzb, 1));
+        Ck.val.alloc(std::max<int64_t>(Ck.nnzb * Ck.br * Ck.bc, 1));
+        MB_HIP(hipMemcpyAsync(Ck.rp.p, C[0]->rp.p, sizeof(int32_t) * (Ck.n_rows + 1), hipMemcpyDeviceToDevice, s));
+        if (Ck.nnzb)
+            MB_HIP(hipMemcpyAsync(Ck.ci.p, C[0]->ci.p, sizeof(int32_t) * Ck.nnzb, hipMemcpyDeviceToDevice, s));
+    }
+    const int64_t z = C[0]->nnzb;
+    if (z == 0) return;
+    DevBuf<int32_t> crow(std::max<int64_t>(z, 1));
+    k_row_of<<<grid_for(C[0]->n_rows), 256, 0, s>>>(C[0]->n_rows, C[0]->rp.p, crow.p);
+    MB_LAUNCH_CHECK();
+    const SetupBsr& A0 = *A[0];
+    const SetupBsr& B0 = *B[0];
+    const bool shape4 = A0.br == 4 && A0.bc == 4 && B0.bc == 4, shape3 = A0.br == 3 && A0.bc == 3 && B0.bc == 3;
+    // one launch for the group, one lookup per output block and row entry (measured: pays
+    // for groups of three or four, where the lookups dominate; pairs are faster apart); the
+    // forced single-product forms and tiny outputs take one launch per product
+    const char* fo = form_override("MBAMG_SPGEMM_FORM");
+    const bool fuse = (shape4 || shape3) && (fo ? std::strcmp(fo, "fused") == 0 && K >= 2
+                                                : K >= 3 && z >= SPGEMM_ENTRY_MAX);
+    if (!fuse) {
+        for (int k = 0; k < K; ++k) spgemm_values(*A[k], *B[k], *C[k], crow.p, s);
+    } else if (shape4) {
+        if (K == 2) launch_num_k<4, 4, 4, 2>(A, B, C, crow.p, s);
+        else if (K == 3) launch_num_k<4, 4, 4, 3>(A, B, C, crow.p, s);
+        else launch_num_k<4, 4, 4, 4>(A, B, C, crow.p, s);
+    } else {
+        if (K == 2) launch_num_k<3, 3, 3, 2>(A, B, C, crow.p, s);
+        else if (K == 3) launch_num_k<3, 3, 3, 3>(A, B, C, crow.p, s);
+        else launch_num_k<3, 3, 3, 4>(A, B, C, crow.p, s);
+    }
+    MB_HIP(hipStreamSynchronize(s));   // crow is released on return
 }
 
 void part_layout(int n, int ns, int kind, const int32_t* perm, const int32_t* rp, const int32_t* ci,

@@ -4,7 +4,8 @@ choice (which the oracle tests pin):
 
 - smoothed prolongator: one thread per row with the row in registers, the
   generic one-thread form, one wavefront per row;
-- numeric Galerkin product: one thread per output block, one lane per entry;
+- numeric Galerkin product: one thread per output block, one lane per entry,
+  one launch for the block pairs that share their patterns;
 - aggregate member lists: one lane per aggregate, one wavefront per aggregate;
 - product pattern: one thread per row (registers), one wavefront per row (LDS
   hash set); a forced thread form falls back where a row overflows.
@@ -29,7 +30,7 @@ CASES = {
 }
 
 FORMS = [("MBAMG_SA_FORM", "thread"), ("MBAMG_SA_FORM", "wave"), ("MBAMG_SA_FORM", "generic"),
-         ("MBAMG_SPGEMM_FORM", "block"), ("MBAMG_SPGEMM_FORM", "entry"),
+         ("MBAMG_SPGEMM_FORM", "block"), ("MBAMG_SPGEMM_FORM", "entry"), ("MBAMG_SPGEMM_FORM", "fused"),
          ("MBAMG_SORT_FORM", "thread"), ("MBAMG_SORT_FORM", "wave"),
          ("MBAMG_SYM_FORM", "thread"), ("MBAMG_SYM_FORM", "wave")]
 
