@@ -198,6 +198,12 @@ __global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_gs(GsArgs<T> a,
 #pragma unroll
         for (int r = 0; r < D; ++r) acc[r] = T(0);
     }
+    // small levels (split slices): the row's own data is fetched before the sums, so its
+    // latency overlaps theirs instead of following them
+    T dv[D * D];
+    if (P > 1 && part == 0 && valid)
+        load_masked<T, D * D>(a.dinv.val + a.dinv.voff[a.dinv.coff[s]] * WAVE + lane, a.dinv.mask[a.dinv.coff[s]],
+                              dv);
     if (valid) {
         if (!a.skip_off) {
             if (ZX) sell_sub<T, D, D, 2, P>(a.off, s, lane, part, a.t, nullptr, a.cstart, acc);
@@ -207,8 +213,9 @@ __global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_gs(GsArgs<T> a,
     }
     combine_parts<T, D, P>(acc, wave, part, lane);
     if (part != 0 || !valid) return;
-    T dv[D * D];
-    load_masked<T, D * D>(a.dinv.val + a.dinv.voff[a.dinv.coff[s]] * WAVE + lane, a.dinv.mask[a.dinv.coff[s]], dv);
+    if (P == 1)
+        load_masked<T, D * D>(a.dinv.val + a.dinv.voff[a.dinv.coff[s]] * WAVE + lane, a.dinv.mask[a.dinv.coff[s]],
+                              dv);
     T tn[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) {
@@ -320,6 +327,12 @@ __global__ __launch_bounds__(256) void k_gs_rows(GsRowArgs<T> a) {
     const int w = blockIdx.x * WPB + wave_id();
     if (w >= a.r_count) return;   // whole wavefront
     const int row = a.r_begin + w;
+    // the row's own data first: its latency overlaps the row sums'
+    T bb[D], dv[D * D], xo[D];
+    load_vec<T, D>(a.b + (int64_t)row * D, bb);
+    load_block<T, D * D>(a.dinv + (int64_t)row * D * D, dv);
+    if (!ZX) load_vec<T, D>(a.x + (int64_t)row * D, xo);
+    const T wgt = a.w_row ? a.w_row[row] : a.omega;
     T acc[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) acc[r] = T(0);
@@ -330,11 +343,8 @@ __global__ __launch_bounds__(256) void k_gs_rows(GsRowArgs<T> a) {
     if (CPL) row_sub<T, D, D, 0, false>(a.afg, row, lane, a.xg, nullptr, 0, acc);
     wave_sum_vec<T, D>(acc);
     if (lane != WAVE - 1) return;
-    T bb[D];
-    load_vec<T, D>(a.b + (int64_t)row * D, bb);
 #pragma unroll
     for (int r = 0; r < D; ++r) acc[r] += bb[r];
-    const T* dv = a.dinv + (int64_t)row * D * D;
     T tn[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) {
@@ -343,14 +353,11 @@ __global__ __launch_bounds__(256) void k_gs_rows(GsRowArgs<T> a) {
         for (int c = 0; c < D; ++c) sum += dv[r * D + c] * acc[c];
         tn[r] = sum;
     }
-    const T wgt = a.w_row ? a.w_row[row] : a.omega;
     T xn[D];
     if (ZX) {
 #pragma unroll
         for (int r = 0; r < D; ++r) xn[r] = wgt * tn[r];
     } else {
-        T xo[D];
-        load_vec<T, D>(a.x + (int64_t)row * D, xo);
 #pragma unroll
         for (int r = 0; r < D; ++r) xn[r] = xo[r] + wgt * (tn[r] - xo[r]);
     }
@@ -370,6 +377,8 @@ __global__ __launch_bounds__(256) void k_resid_rows(ResidRowArgs<T> a) {
         if (row >= a.n[1]) return;   // whole wavefront
     }
     const int g = 1 - f;
+    T bb[D];   // fetched first: its latency overlaps the row sums'
+    if (a.b[f]) load_vec<T, D>(a.b[f] + (int64_t)row * D, bb);
     T acc[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) acc[r] = T(0);
@@ -379,8 +388,6 @@ __global__ __launch_bounds__(256) void k_resid_rows(ResidRowArgs<T> a) {
     if (lane != WAVE - 1) return;
     T out[D];
     if (a.b[f]) {
-        T bb[D];
-        load_vec<T, D>(a.b[f] + (int64_t)row * D, bb);
 #pragma unroll
         for (int r = 0; r < D; ++r) out[r] = bb[r] + acc[r];
     } else {
