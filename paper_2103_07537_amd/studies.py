@@ -1,0 +1,105 @@
+"""Smoother parameter studies on the synthetic workloads.
+
+The paper studies two knobs of the block Gauss-Seidel smoother on its MHD
+generator problem: the damping omega of Algorithm 1, and one against two
+smoothing sweeps (more sweeps cut the iterations but not the time).  This
+module repeats both on the synthetic systems with the library's own
+hierarchy: every point is a fresh setup plus GMRES(30) to rtol 1e-8 on one
+GPU, timed with the device synchronised on both sides.
+
+    python -m paper_2103_07537_amd.studies omega  --workload 2d-256
+    python -m paper_2103_07537_amd.studies sweeps --workload 2d-512-lognormal --precision 1
+
+Each point prints one JSON line; a markdown table follows on stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import statistics
+import sys
+import time
+
+OMEGAS = (0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1)
+# (BGS sweeps for pre- and post-smoothing, inner multicolour sweeps per block)
+SWEEPS = ((1, 1), (2, 1), (1, 2), (2, 2))
+
+
+def run_point(blocks, system, b, *, repeats: int = 3, rtol: float = 1e-8, **params) -> dict:
+    """Setup + solve `repeats` times with `params`; medians of the timings."""
+    import torch
+    from . import mbamg
+    setups, solves, its, rels = [], [], None, None
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = mbamg.Hierarchy(blocks, system.dofs, system.n_vec, **params)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        info = h.solve(b, x, rtol=rtol)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        setups.append(1e3 * (t1 - t0))
+        solves.append(1e3 * (t3 - t2))
+        its, rels, conv = info["iterations"], info["rel_residual"], info["converged"]
+        h.close()
+    setup, solve = statistics.median(setups), statistics.median(solves)
+    return dict(params=params, iterations=its, rel_residual=rels, converged=bool(conv), setup_ms=setup,
+                solve_ms=solve, total_ms=setup + solve, ms_per_iteration=solve / max(its, 1))
+
+
+def study(kind: str, name: str, *, seed: int = 1, precision: int = 0, repeats: int = 3, points=None) -> list:
+    import torch
+    from . import mbamg
+    from .inputs import workload
+    mbamg.lib()
+    s = workload(name, seed=seed)
+    blocks = mbamg.to_device(s)
+    b = torch.from_numpy(s.b).cuda()
+    out = []
+    if kind == "omega":
+        for w in (points or OMEGAS):
+            out.append(run_point(blocks, s, b, repeats=repeats, precision=precision, omega=w))
+    elif kind == "sweeps":
+        for bgs, inner in (points or SWEEPS):
+            out.append(run_point(blocks, s, b, repeats=repeats, precision=precision, bgs_sweeps=bgs,
+                                 inner_sweeps=inner))
+    else:
+        raise ValueError(kind)
+    for r in out:
+        r["workload"] = name
+        r["unknowns"] = s.n_dofs
+    return out
+
+
+def table(rows: list) -> str:
+    lines = ["| parameters | iterations | setup ms | solve ms | total ms | ms/iteration |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        p = ", ".join(f"{k}={v}" for k, v in r["params"].items() if k != "precision")
+        its = str(r["iterations"]) if r["converged"] else f"{r['iterations']} (not converged)"
+        lines.append(f"| {p} | {its} | {r['setup_ms']:.1f} | {r['solve_ms']:.1f} | "
+                     f"{r['total_ms']:.1f} | {r['ms_per_iteration']:.2f} |")
+    return "\n".join(lines)
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("kind", choices=["omega", "sweeps"])
+    ap.add_argument("--workload", default="2d-256")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--precision", type=int, default=0, choices=[0, 1])
+    ap.add_argument("--repeats", type=int, default=3)
+    a = ap.parse_args(argv)
+    rows = study(a.kind, a.workload, seed=a.seed, precision=a.precision, repeats=a.repeats)
+    for r in rows:
+        print(json.dumps(r), flush=True)
+    print(table(rows), file=sys.stderr)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -57,3 +57,14 @@ def test_coupling_field_is_normalised():
     h = 1.0 / 9
     Z = s.blocks[0][1].vals
     assert np.abs(Z).max() == pytest.approx(1.0 / (2 * h), rel=1e-12)
+
+
+def test_study_table_marks_unconverged_points():
+    from paper_2103_07537_amd import studies
+    rows = [dict(params=dict(precision=1, omega=0.8), iterations=12, converged=True, setup_ms=1.0, solve_ms=2.0,
+                 total_ms=3.0, ms_per_iteration=0.1667),
+            dict(params=dict(precision=1, omega=1.1), iterations=1000, converged=False, setup_ms=1.0,
+                 solve_ms=9.0, total_ms=10.0, ms_per_iteration=0.009)]
+    t = studies.table(rows).splitlines()
+    assert t[2].startswith("| omega=0.8 | 12 |") and "precision" not in t[2]
+    assert "1000 (not converged)" in t[3]
