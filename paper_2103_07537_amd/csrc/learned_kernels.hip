@@ -324,6 +324,21 @@ __device__ inline int find_block(const int32_t* ci, int lo, int hi, int key) {
 }
 
 // mean vector-diagonal entry of the diagonal block of row i
+// a block of n <= 16 doubles into registers (16-byte loads for 4x4 blocks)
+__device__ __forceinline__ void load_block_n(const double* __restrict__ p, int n, double (&v)[16]) {
+    if (n == 16) {
+#pragma unroll
+        for (int x = 0; x < 16; x += 2) {
+            const double2 t = *reinterpret_cast<const double2*>(p + x);
+            v[x] = t.x;
+            v[x + 1] = t.y;
+        }
+    } else {
+#pragma unroll
+        for (int x = 0; x < 16; ++x) v[x] = x < n ? p[x] : 0.0;
+    }
+}
+
 __device__ inline double vdiag(const BsrView& A, int i, int nv) {
     int p = find_block(A.ci, A.rp[i], A.rp[i + 1], i);
     if (p < 0) return 0.0;
@@ -419,22 +434,34 @@ __global__ __launch_bounds__(WAVE) void k_features(int nagg, int n, const int32_
     double tot = 0, outw = 0, f9 = 0, f10 = 0, f11 = 0;
     double a00 = 0, a01 = 0, a10 = 0, a11 = 0;
     const int d0 = A00.d;
+    const int d1 = A11.d;
     for (int q = b + lane; q < e; q += WAVE) {
         const int i = midx[q];
         var += (ld[i] - mld) * (ld[i] - mld);
-        const double dv0 = vdiag(A00, i, nv0), dv1 = vdiag(A11, i, nv1);
+        // every block of the member's A00 and A11 rows is read once, into registers;
+        // the sums run in the order of vdiag, cvv and row_fro2
+        double dv0 = 0.0, dv1 = 0.0, fro00 = 0.0, fro11 = 0.0;
         double off0 = 0, off1 = 0, g2 = 0, cpp = 0;
         for (int p = A00.rp[i]; p < A00.rp[i + 1]; ++p) {
             const int jn = A00.ci[p];
-            const double* blk = A00.val + (int64_t)p * d0 * d0;
+            double blk[16];
+            load_block_n(A00.val + (int64_t)p * d0 * d0, d0 * d0, blk);
+#pragma unroll
+            for (int x = 0; x < 16; ++x)
+                if (x < d0 * d0) fro00 += blk[x] * blk[x];
             if (d0 > nv0)
                 for (int a = 0; a < nv0; ++a)
                     for (int c = nv0; c < d0; ++c) g2 += blk[a * d0 + c] * blk[a * d0 + c];
             if (jn == i) {
                 if (d0 > nv0) cpp = fabs(blk[nv0 * d0 + nv0]);
+                double sd = 0.0;
+                for (int a = 0; a < nv0; ++a) sd += blk[a * d0 + a];
+                dv0 = sd / nv0;
                 continue;
             }
-            const double c = cvv(A00, p, nv0);
+            double sc = 0.0;
+            for (int a = 0; a < nv0; ++a) sc += fabs(blk[a * d0 + a]);
+            const double c = sc / nv0;
             off0 += c;
             if (agg[jn] != k) outw += c;
             else {
@@ -442,14 +469,27 @@ __global__ __launch_bounds__(WAVE) void k_features(int nagg, int n, const int32_
                 cmin = fmin(cmin, c);
             }
         }
-        for (int p = A11.rp[i]; p < A11.rp[i + 1]; ++p)
-            if (A11.ci[p] != i) off1 += cvv(A11, p, nv1);
+        for (int p = A11.rp[i]; p < A11.rp[i + 1]; ++p) {
+            double blk[16];
+            load_block_n(A11.val + (int64_t)p * d1 * d1, d1 * d1, blk);
+#pragma unroll
+            for (int x = 0; x < 16; ++x)
+                if (x < d1 * d1) fro11 += blk[x] * blk[x];
+            double sd = 0.0;
+            if (A11.ci[p] == i) {
+                for (int a = 0; a < nv1; ++a) sd += blk[a * d1 + a];
+                dv1 = sd / nv1;
+            } else {
+                for (int a = 0; a < nv1; ++a) sd += fabs(blk[a * d1 + a]);
+                off1 += sd / nv1;
+            }
+        }
         tot += off0;
         f9 += off0 / dv0;
         f10 += off1 / dv1;
         if (d0 > nv0) f11 += g2 / fmax(dv0 * cpp, 1e-300);
-        a00 += row_fro2(A00, i);
-        a11 += row_fro2(A11, i);
+        a00 += fro00;
+        a11 += fro11;
         if (A01.rp) a01 += row_fro2(A01, i);
         if (A10.rp) a10 += row_fro2(A10, i);
     }

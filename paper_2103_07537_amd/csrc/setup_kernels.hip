@@ -1116,18 +1116,39 @@ __global__ __launch_bounds__(WAVE) void k_transpose_rank(int br, int bc, const i
                                                          const int32_t* __restrict__ tsrc,
                                                          const double* __restrict__ val, int32_t* __restrict__ tci,
                                                          double* __restrict__ tval) {
+    constexpr int TR_LDS = 1024;
+    __shared__ int32_t rows[TR_LDS], dst[TR_LDS];
     const int k = blockIdx.x, lane = threadIdx.x;
-    const int b = trp[k], e = trp[k + 1];
-    for (int a = b + lane; a < e; a += WAVE) {
-        const int r = trow[a];
+    const int b = trp[k], e = trp[k + 1], len = e - b, bs = br * bc;
+    if (len > TR_LDS) {   // long rows: ranks from global memory, one lane per entry
+        for (int a = b + lane; a < e; a += WAVE) {
+            const int r = trow[a];
+            int rank = 0;
+            for (int u = b; u < e; ++u) rank += trow[u] < r;
+            const int dp = b + rank;
+            tci[dp] = r;
+            const double* src = val + (int64_t)tsrc[a] * bs;
+            double* out = tval + (int64_t)dp * bs;
+            for (int r2 = 0; r2 < br; ++r2)
+                for (int c = 0; c < bc; ++c) out[c * br + r2] = src[r2 * bc + c];
+        }
+        return;
+    }
+    // the row's source rows in LDS, ranked there; then the blocks are copied
+    // 16 lanes per block (bs <= 16), each a contiguous read and write
+    for (int u = lane; u < len; u += WAVE) rows[u] = trow[b + u];
+    for (int a = lane; a < len; a += WAVE) {
+        const int r = rows[a];
         int rank = 0;
-        for (int u = b; u < e; ++u) rank += trow[u] < r;
-        const int dp = b + rank;
-        tci[dp] = r;
-        const double* src = val + (int64_t)tsrc[a] * br * bc;
-        double* dst = tval + (int64_t)dp * br * bc;
-        for (int r2 = 0; r2 < br; ++r2)
-            for (int c = 0; c < bc; ++c) dst[c * br + r2] = src[r2 * bc + c];
+        for (int u = 0; u < len; ++u) rank += rows[u] < r;
+        dst[a] = rank;
+        tci[b + rank] = r;
+    }
+    for (int t = lane; t < len * 16; t += WAVE) {
+        const int a = t >> 4, ent = t & 15;
+        if (ent >= bs) continue;
+        const int r2 = ent / bc, c = ent % bc;
+        tval[(int64_t)(b + dst[a]) * bs + c * br + r2] = val[(int64_t)tsrc[b + a] * bs + ent];
     }
 }
 
@@ -1681,6 +1702,7 @@ SetupBsr sa_prolongator(const SetupBsr& A, int nv, const Aggregates& G, const do
 }
 
 SetupBsr block_transpose(const SetupBsr& P, hipStream_t s) {
+    MB_CHECK(P.br * P.bc <= 16, MBAMG_E_INVALID, "block transpose: blocks of at most 16 entries");
     const int n = P.n_rows, nc = P.n_cols;
     SetupBsr T;
     T.n_rows = nc;
