@@ -798,6 +798,10 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
             B.d_perm.upload(B.perm, s);
             B.d_iperm.upload(B.iperm, s);
         }
+        // long rows (dense coarse stencils) in both block rows: one wavefront per row, and
+        // the sliced parts of the level are not built
+        bool rows_level = l > 0 && Lv.A[0][0].nnzb >= (int64_t)32 * Lv.n && Lv.A[1][1].nnzb >= (int64_t)32 * Lv.n;
+        if (const char* fo = form_override("MBAMG_ROWS_FORM")) rows_level = l > 0 && std::strcmp(fo, "rows") == 0;
         for (int f = 0; f < 2 && !shared; ++f) {
             const int g = 1 - f;
             BlockLevel& B = Lv.blk[f];
@@ -806,6 +810,38 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
             if (f == 0) clk.mark("colouring", l);
             build_dinv(Lv.A[f][f], dinv.p, s);
             clk.mark("dinv", l);
+            B.rows = rows_level;
+            if (B.rows) {
+                // the per-colour counts the sliced parts would have recorded (byte model)
+                const std::vector<int64_t> cs7 =
+                    row_colour_stats(Lv.n, B.d_perm.p, Lv.A[f][f], Lv.A[f][g], dinv.p, B.colour_row, s);
+                B.cstats.assign(B.n_colours, ColourStats{});
+                for (int c = 0; c < B.n_colours; ++c) {
+                    ColourStats& cs = B.cstats[c];
+                    const int64_t* v = &cs7[(size_t)c * 7];
+                    cs.off_nz = v[0];
+                    cs.off_bl = v[1];
+                    cs.cpl_nz = v[2];
+                    cs.cpl_bl = v[3];
+                    cs.dinv_nz = v[4];
+                    B.all_nz += v[0] + v[2] + v[5];
+                    B.all_bl += v[1] + v[3] + v[6];
+                }
+                B.split = 1;
+                build_rows(B.raff, Lv.n, B.d_perm.p, Lv.A[f][f], B.d_iperm.p, want32, s);
+                build_rows(B.rafg, Lv.n, B.d_perm.p, Lv.A[f][g], Lv.blk[g].d_iperm.p, want32, s);
+                B.rdinv64.alloc((size_t)Lv.n * df * df);
+                gather_blocks(Lv.n, df * df, B.d_perm.p, dinv.p, B.rdinv64.p, s);
+                if (want32) {
+                    B.rdinv32.alloc((size_t)Lv.n * df * df);
+                    cast_to_f32(B.rdinv64.p, B.rdinv32.p, (int64_t)Lv.n * df * df, s);
+                }
+                MB_HIP(hipStreamSynchronize(s));   // dinv is released at the end of this iteration
+                if (clk.on)
+                    std::fprintf(stderr, "[mbamg setup] level %d block %d: %d nodes, %d colours, row form\n", l, f,
+                                 Lv.n, B.n_colours);
+                continue;
+            }
             build_part(B.off, PartKind::Off, B, &Lv.A[f][f], B.d_iperm.p, Lv.A[f][f].val.p, df, df, want32, s);
             build_part(B.diag, PartKind::Diag, B, &Lv.A[f][f], B.d_iperm.p, Lv.A[f][f].val.p, df, df, want32, s);
             build_part(B.cpl, PartKind::Cpl, B, &Lv.A[f][g], Lv.blk[g].d_iperm.p, Lv.A[f][g].val.p, df, dg, want32,
@@ -829,24 +865,9 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
             const double avg_width = B.n_slices ? (double)slots / B.n_slices : 0.0;
             const double per_colour = (double)B.n_slices / std::max(1, B.n_colours);
             B.split = slot_split(per_colour, avg_width);
-            // long rows (dense coarse stencils): one wavefront per row instead
-            B.rows = l > 0 && Lv.A[f][f].nnzb >= (int64_t)32 * Lv.n;
-            if (const char* fo = form_override("MBAMG_ROWS_FORM")) B.rows = l > 0 && std::strcmp(fo, "rows") == 0;
-            if (B.rows) {
-                build_rows(B.raff, Lv.n, B.d_perm.p, Lv.A[f][f], B.d_iperm.p, want32, s);
-                build_rows(B.rafg, Lv.n, B.d_perm.p, Lv.A[f][g], Lv.blk[g].d_iperm.p, want32, s);
-                B.rdinv64.alloc((size_t)Lv.n * df * df);
-                gather_blocks(Lv.n, df * df, B.d_perm.p, dinv.p, B.rdinv64.p, s);
-                if (want32) {
-                    B.rdinv32.alloc((size_t)Lv.n * df * df);
-                    cast_to_f32(B.rdinv64.p, B.rdinv32.p, (int64_t)Lv.n * df * df, s);
-                }
-                MB_HIP(hipStreamSynchronize(s));   // dinv is released at the end of this iteration
-            }
             if (clk.on)
                 std::fprintf(stderr, "[mbamg setup] level %d block %d: %d nodes, %d colours, %d slices, %.1f slots/slice, "
-                             "split %d%s\n", l, f, Lv.n, B.n_colours, B.n_slices, avg_width, B.split,
-                             B.rows ? ", row form" : "");
+                             "split %d\n", l, f, Lv.n, B.n_colours, B.n_slices, avg_width, B.split);
         }
         clk.mark("sliced parts", l);
         // transfers between this level's and the next level's colour orders

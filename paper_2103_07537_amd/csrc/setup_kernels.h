@@ -68,6 +68,12 @@ void build_rows(RowPart& R, int n, const int32_t* perm, const SetupBsr& A, const
                 hipStream_t s);
 // dst[p] = src[perm[p]] for blocks of bs values
 void gather_blocks(int n, int bs, const int32_t* perm, const double* src, double* dst, hipStream_t s);
+// For each colour c (rows colour_row[c] .. colour_row[c+1] in colour order,
+// node perm[p]): 7 sums -- nonzero entries and blocks of A_ff's off-diagonal
+// blocks, of A_fg, nonzero entries of D^-1 (natural order), nonzero entries
+// and blocks of A_ff's diagonal block.
+std::vector<int64_t> row_colour_stats(int n, const int32_t* perm, const SetupBsr& Aff, const SetupBsr& Afg,
+                                      const double* dinv, const std::vector<int>& colour_row, hipStream_t s);
 
 // true when X and Y have identical block patterns (synchronous)
 bool same_pattern(const SetupBsr& X, const SetupBsr& Y, hipStream_t s);

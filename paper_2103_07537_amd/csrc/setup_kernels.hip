@@ -1796,6 +1796,61 @@ void build_rows(RowPart& R, int n, const int32_t* perm, const SetupBsr& A, const
     MB_HIP(hipStreamSynchronize(s));   // cnt is released on return
 }
 
+// Per row (colour order p, node perm[p]) of a block row: nonzero entries and
+// blocks of A_ff's off-diagonal blocks, of A_fg, of D^-1 and of A_ff's
+// diagonal block -- the counts the sliced parts would record.
+__global__ void k_row_stats(int n, const int32_t* __restrict__ perm, const int32_t* __restrict__ frp,
+                            const int32_t* __restrict__ fci, const double* __restrict__ fval, int fbs,
+                            const int32_t* __restrict__ grp, const double* __restrict__ gval, int gbs,
+                            const double* __restrict__ dinv, int32_t* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int node = perm[p];
+    int off_nz = 0, off_bl = 0, cpl_nz = 0, cpl_bl = 0, dinv_nz = 0, diag_nz = 0, diag_bl = 0;
+    for (int q = frp[node]; q < frp[node + 1]; ++q) {
+        int nz = 0;
+        for (int e = 0; e < fbs; ++e) nz += fval[(int64_t)q * fbs + e] != 0.0;
+        if (fci[q] == node) {
+            diag_nz += nz;
+            ++diag_bl;
+        } else {
+            off_nz += nz;
+            ++off_bl;
+        }
+    }
+    if (grp)
+        for (int q = grp[node]; q < grp[node + 1]; ++q) {
+            for (int e = 0; e < gbs; ++e) cpl_nz += gval[(int64_t)q * gbs + e] != 0.0;
+            ++cpl_bl;
+        }
+    for (int e = 0; e < fbs; ++e) dinv_nz += dinv[(int64_t)node * fbs + e] != 0.0;
+    int32_t* o = out + (int64_t)p * 7;
+    o[0] = off_nz;
+    o[1] = off_bl;
+    o[2] = cpl_nz;
+    o[3] = cpl_bl;
+    o[4] = dinv_nz;
+    o[5] = diag_nz;
+    o[6] = diag_bl;
+}
+
+std::vector<int64_t> row_colour_stats(int n, const int32_t* perm, const SetupBsr& Aff, const SetupBsr& Afg,
+                                      const double* dinv, const std::vector<int>& colour_row, hipStream_t s) {
+    const int nc = (int)colour_row.size() - 1;
+    std::vector<int64_t> sums((size_t)std::max(nc, 0) * 7, 0);
+    if (n == 0) return sums;
+    DevBuf<int32_t> per((size_t)n * 7);
+    k_row_stats<<<grid_for(n), 256, 0, s>>>(n, perm, Aff.rp.p, Aff.ci.p, Aff.val.p, Aff.br * Aff.bc,
+                                             Afg.nnzb ? Afg.rp.p : nullptr, Afg.val.p, Afg.br * Afg.bc, dinv,
+                                             per.p);
+    MB_LAUNCH_CHECK();
+    const std::vector<int32_t> h = per.download(s, (size_t)n * 7);
+    for (int c = 0; c < nc; ++c)
+        for (int p = colour_row[c]; p < colour_row[c + 1]; ++p)
+            for (int k = 0; k < 7; ++k) sums[(size_t)c * 7 + k] += h[(size_t)p * 7 + k];
+    return sums;
+}
+
 void gather_blocks(int n, int bs, const int32_t* perm, const double* src, double* dst, hipStream_t s) {
     if (n == 0) return;
     k_gather_blocks<<<grid_for((int64_t)n * bs), 256, 0, s>>>(n, bs, perm, src, dst);
