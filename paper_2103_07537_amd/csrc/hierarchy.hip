@@ -143,6 +143,42 @@ struct PendingCoarse {
     std::future<void> job;
 };
 
+// Hand-over from the fixed-weight build to a learned build running at the
+// same time on another host thread and stream: the fixed build publishes its
+// level-0 aggregates, then its level-0 smoother data (true), or that it has
+// none (false); each publication comes with an event on the fixed build's
+// stream after which the data is complete.
+struct DonorLink {
+    std::promise<bool> agg_p, smooth_p;
+    std::shared_future<bool> agg, smooth;
+    bool agg_set = false, smooth_set = false;
+    hipEvent_t agg_ev = nullptr, smooth_ev = nullptr;
+    const Level* level0 = nullptr;   // the fixed build's level 0 (stable: heap-allocated)
+    DonorLink() : agg(agg_p.get_future().share()), smooth(smooth_p.get_future().share()) {
+        MB_HIP(hipEventCreateWithFlags(&agg_ev, hipEventDisableTiming));
+        MB_HIP(hipEventCreateWithFlags(&smooth_ev, hipEventDisableTiming));
+    }
+    ~DonorLink() {
+        close();
+        (void)hipEventDestroy(agg_ev);
+        (void)hipEventDestroy(smooth_ev);
+    }
+    void publish_agg(bool ok) {
+        if (agg_set) return;
+        agg_set = true;
+        agg_p.set_value(ok);
+    }
+    void publish_smooth(bool ok) {
+        if (smooth_set) return;
+        smooth_set = true;
+        smooth_p.set_value(ok);
+    }
+    void close() {   // whatever was not published is not coming
+        publish_agg(false);
+        publish_smooth(false);
+    }
+};
+
 thread_local std::string g_last_error;
 
 // Krylov scalar buffer layout (device and pinned host copies)
@@ -554,9 +590,6 @@ static void clone_smoother(BlockLevel& d, const BlockLevel& b, hipStream_t s) {
     clone_part(d.dinv, b.dinv, s);
 }
 
-// donor: a hierarchy built from the same blocks with the same level-0
-// parameters (aggregation, precision); its level-0 aggregates and smoother
-// data are copied instead of recomputed.
 // Join a build's coarsest inverse: the launches are issued, the inverse is
 // checked, and stream s waits for it.
 static void finish_coarse(mbamg_hierarchy* h, hipStream_t s) {
@@ -570,8 +603,17 @@ static void finish_coarse(mbamg_hierarchy* h, hipStream_t s) {
     h->coarse_pending.reset();
 }
 
-static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, const mbamg_hierarchy* donor,
+// from: a build of the same blocks with the same level-0 parameters
+// (aggregation, precision) running at the same time; its level-0 aggregates
+// and smoother data are copied instead of recomputed.  to: this build
+// publishes its own level-0 aggregates and smoother data there.
+static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, DonorLink* from, DonorLink* to,
                        bool defer_coarse) {
+    struct Publish {   // on every exit, whatever this build has not published is not coming
+        DonorLink* to;
+        ~Publish() { if (to) to->close(); }
+    } publish_guard{to};
+    const Level* donor0 = nullptr;   // the donor's level 0, once its aggregates are published
     auto t0 = std::chrono::steady_clock::now();
     const mbamg_params& p = h->p;
     const int d0 = h->d[0], d1 = h->d[1];
@@ -616,7 +658,11 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
         const int64_t ndof = (int64_t)cur.n * (d0 + d1);
         if (ndof <= p.max_coarse || (int)h->L.size() >= p.max_levels) break;
         clk.mark("start", lvl);
-        const bool donor_level = lvl == 0 && donor && donor->L.size() > 1 && donor->L[0]->n == cur.n;
+        if (lvl == 0 && from && from->agg.get()) {
+            MB_HIP(hipStreamWaitEvent(s, from->agg_ev, 0));
+            if (from->level0->n == cur.n) donor0 = from->level0;
+        }
+        const bool donor_level = lvl == 0 && donor0 != nullptr;
         // level 0's pattern is final now: its colouring starts before aggregation (the job
         // is simply not used if level 0 turns out to be the coarsest)
         if (lvl == 0 && !donor_level) {
@@ -627,9 +673,9 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
             Level* lp = &cur;
             colour_jobs[lvl] = std::async(std::launch::async, [lp, ev, device] { colour_level(*lp, ev, device); });
         }
-        Aggregates G;
+        Aggregates& G = cur.G;
         if (donor_level) {
-            const Aggregates& D = donor->L[0]->G;
+            const Aggregates& D = donor0->G;
             G.n = D.n;
             G.n_agg = D.n_agg;
             G.mis_rounds = D.mis_rounds;
@@ -642,7 +688,15 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
             G = build_aggregates(S, p.seed, lvl, s);
         }
         clk.mark("aggregates", lvl);
-        if ((double)G.n_agg > 0.9 * cur.n) break;
+        if ((double)G.n_agg > 0.9 * cur.n) {   // this level is the coarsest
+            G = Aggregates();
+            break;
+        }
+        if (to && lvl == 0) {
+            to->level0 = &cur;
+            MB_HIP(hipEventRecord(to->agg_ev, s));
+            to->publish_agg(true);
+        }
         // this level is not the coarsest: colour it on a host thread while the GPU
         // builds the next level (the level-0 colouring comes with the donor's copy)
         if (!donor_level && !colour_jobs.count(lvl)) {
@@ -729,7 +783,6 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
         // keep q on the fine level (natural order) for the transfer maps
         cur.blk[0].q64 = std::move(q[0]);
         cur.blk[1].q64 = std::move(q[1]);
-        cur.G = std::move(G);
         Bn[0] = std::move(Bc[0]);
         Bn[1] = std::move(Bc[1]);
         h->L.push_back(std::move(nxt));
@@ -771,9 +824,10 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
     for (int l = (int)h->L.size() - 2; l >= 0; --l) {
         Level& Lv = *h->L[l];
         Level& Nx = *h->L[l + 1];
-        const bool shared = l == 0 && donor && donor->L.size() > 1 && donor->L[0]->n == Lv.n;
+        bool shared = l == 0 && donor0 != nullptr && from->smooth.get();
         if (shared) {
-            for (int f = 0; f < 2; ++f) clone_smoother(Lv.blk[f], donor->L[0]->blk[f], s);
+            MB_HIP(hipStreamWaitEvent(s, from->smooth_ev, 0));
+            for (int f = 0; f < 2; ++f) clone_smoother(Lv.blk[f], donor0->blk[f], s);
             clk.mark("smoother data copied", l);
         }
         // colouring is sequential by definition (first fit in node order): done on the host from
@@ -907,6 +961,10 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, c
     }
 
     clk.mark("smoother data done", 0);
+    if (to && to->agg_set && h->L.size() > 1) {   // level 0's smoother data is complete on s
+        MB_HIP(hipEventRecord(to->smooth_ev, s));
+        to->publish_smooth(true);
+    }
     if (!defer_coarse) {
         finish_coarse(h, s);
         clk.mark("coarse inverse joined", 0);
@@ -1454,49 +1512,54 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
             MB_CHECK(fm->n_vec[f] >= 0 && fm->n_vec[f] <= fm->dofs[f], MBAMG_E_INVALID, "n_vec out of range");
         hipStream_t s = (hipStream_t)hip_stream;
         auto t0 = std::chrono::steady_clock::now();
-        auto build = [&](const mbamg_params& pp, const mbamg_hierarchy* donor, bool defer_coarse) {
+        auto make = [&](const mbamg_params& pp, hipStream_t st) {
             auto h = std::make_unique<mbamg_hierarchy>();
             h->p = pp;
             h->fm = *fm;
             h->d[0] = fm->dofs[0];
             h->d[1] = fm->dofs[1];
-            if (pp.learned == 1) h->mlp.upload(pp.mlp, N_MLP_PARAMS + 2 * N_FEATURES, s);
-            setup_impl(h.get(), A_blocks, s, donor, defer_coarse);
-            if (!defer_coarse) {
-                // the build's temporaries are idle now and can serve the next allocations
-                MB_HIP(hipDeviceSynchronize());
-                pool_device_idle();
-            }
+            if (pp.learned == 1) h->mlp.upload(pp.mlp, N_MLP_PARAMS + 2 * N_FEATURES, st);
             return h;
+        };
+        auto settle = [] {   // the build's temporaries are idle now and can serve the next allocations
+            MB_HIP(hipDeviceSynchronize());
+            pool_device_idle();
         };
         std::unique_ptr<mbamg_hierarchy> h;
         if (p->learned != 0 && p->judge) {
-            // the fixed-weight method is the fallback and the judge.  It is built first: its
-            // coarsest inverse and then its probe run on their own stream during the learned
-            // build, which copies the fixed build's level-0 aggregates and smoother data
+            // the fixed-weight method is the fallback and the judge.  It is built, and then
+            // probed, on a host thread and stream of its own while the learned hierarchy is
+            // built here; the learned build copies the fixed build's level-0 aggregates and
+            // smoother data as soon as they are published (the hierarchies share no buffers)
             mbamg_params pf = *p;
             pf.learned = 0;
             pf.omega_p = 0.0;
             PhaseClock jclk(s);
-            auto hf = build(pf, nullptr, true);
-            jclk.mark("fixed hierarchy built", 0);
-            // the fixed hierarchy is probed on a stream and host thread of its own while the
-            // learned one is built (the learned build only reads the fixed one's level-0 data;
-            // the hierarchies share no buffers).  Declared after hf: on an exception the probe
-            // is waited for before hf goes away.
             int device = 0;
             MB_HIP(hipGetDevice(&device));
-            SideStream s2;
-            mbamg_hierarchy* fixed = hf.get();
-            auto fixed_probe = std::async(std::launch::async, [fixed, device, &s2] {
+            SideStream sf;
+            MB_HIP(hipEventRecord(sf.ready, s));   // the caller's inputs are ready on s
+            MB_HIP(hipStreamWaitEvent(sf.stream, sf.ready, 0));
+            auto hf = make(pf, sf.stream);
+            DonorLink link;
+            // declared after hf, sf and link: on an exception here the job is waited for first
+            auto fixed_job = std::async(std::launch::async, [&hf, &link, &sf, A_blocks, device] {
                 MB_HIP(hipSetDevice(device));
-                finish_coarse(fixed, s2.stream);
-                return probe_impl(fixed, 10, 12345, s2.stream);
+                try {
+                    setup_impl(hf.get(), A_blocks, sf.stream, nullptr, &link, true);
+                } catch (...) {
+                    link.close();
+                    throw;
+                }
+                finish_coarse(hf.get(), sf.stream);
+                return probe_impl(hf.get(), 10, 12345, sf.stream);
             });
-            h = build(*p, hf.get(), false);
+            h = make(*p, s);
+            setup_impl(h.get(), A_blocks, s, &link, nullptr, false);
+            settle();
             jclk.mark("learned hierarchy built", 0);
             const double rl = probe_impl(h.get(), 10, 12345, s);
-            const double rf = fixed_probe.get();
+            const double rf = fixed_job.get();
             jclk.mark("judge probes", 0);
             h->judge_rho[0] = hf->judge_rho[0] = rl;
             h->judge_rho[1] = hf->judge_rho[1] = rf;
@@ -1507,7 +1570,9 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
                 h->info.used_learned = 1;
             }
         } else {
-            h = build(*p, nullptr, false);
+            h = make(*p, s);
+            setup_impl(h.get(), A_blocks, s, nullptr, nullptr, false);
+            settle();
             h->info.used_learned = p->learned != 0;
         }
         MB_HIP(hipDeviceSynchronize());
