@@ -76,3 +76,24 @@ def test_block_shape_mismatch_is_rejected():
     log(f"  {e.value}")
     assert e.value.code == E_INVALID
     _still_works()
+
+
+def test_singular_nodal_block_with_judge_is_reported():
+    """The same error while the fixed and learned hierarchies are built at the
+    same time on two host threads: reported once, and nothing is left running."""
+    from paper_2103_07537_amd import mbamg
+    s = _small()
+    A00 = s.blocks[0][0]
+    vals = A00.vals.copy()
+    rows = np.repeat(np.arange(A00.n_brows), np.diff(A00.row_ptr))
+    vals[(rows == 3) & (A00.col_idx == 3)] = 0.0
+    blocks = [[dataclasses.replace(A00, vals=vals), s.blocks[0][1]], s.blocks[1]]
+
+    def weights(level, n_agg, F):
+        return np.full(n_agg, 0.5), np.full(n_agg, 0.8)
+
+    with pytest.raises(mbamg.MbamgError) as e:
+        mbamg.Hierarchy(blocks, s.dofs, s.n_vec, max_coarse=60, weights=weights, judge=1)
+    log(f"  {e.value}")
+    assert e.value.code == E_SINGULAR
+    _still_works()
