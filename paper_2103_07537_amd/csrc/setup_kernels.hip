@@ -321,12 +321,14 @@ __global__ __launch_bounds__(WAVE) void k_sort_members_w(int nagg, const int32_t
 // ----------------------------------------------------------------------------
 // tentative prolongator: q = B / ||B over the aggregate||, per component
 // ----------------------------------------------------------------------------
+// one thread per (aggregate, component); each sum over the members in order
 __global__ void k_tentative(int nagg, int d, const int32_t* mptr, const int32_t* midx, const double* B,
                             double* q, double* Bc) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nagg) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nagg * d) return;
+    const int k = (int)(t / d), c = (int)(t % d);
     int b = mptr[k], e = mptr[k + 1];
-    for (int c = 0; c < d; ++c) {
+    {
         double acc = 0.0;
         for (int m = b; m < e; ++m) {
             double v = B[(int64_t)midx[m] * d + c];
@@ -944,6 +946,44 @@ __global__ __launch_bounds__(128) void k_spgemm_num_k(int64_t nnz, const int32_t
 #pragma unroll
         for (int e = 0; e < BR * BC; ++e) dst[e] = acc[k][e];
     }
+}
+
+// K products as in k_spgemm_num_k, one lane per output entry and 16 lanes
+// per output block (tiny outputs): each column lookup serves all K products.
+template <int BR, int BM, int BC, int K>
+__global__ __launch_bounds__(256) void k_spgemm_num_ek(int64_t nnz, const int32_t* __restrict__ arp,
+                                                       const int32_t* __restrict__ aci,
+                                                       const int32_t* __restrict__ brp,
+                                                       const int32_t* __restrict__ bci,
+                                                       const int32_t* __restrict__ crow,
+                                                       const int32_t* __restrict__ cci, SpgemmVals<K> v) {
+    static_assert(BR * BC <= 16, "at most 16 entries per output block");
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = tid / 16;
+    const int ent = (int)(tid % 16);
+    if (k >= nnz) return;
+    const int r = ent / BC, cc = ent % BC;
+    const bool live = ent < BR * BC;
+    const int i = crow[k], l = cci[k];
+    double acc[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) acc[u] = 0.0;
+    for (int p = arp[i]; p < arp[i + 1]; ++p) {
+        const int j = aci[p];
+        const int q = find_col_short(bci, brp[j], brp[j + 1], l);
+        if (q < 0 || !live) continue;
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+#pragma unroll
+            for (int m = 0; m < BM; ++m) {
+                const double term = v.a[u][(int64_t)p * BR * BM + r * BM + m] *
+                                    v.b[u][(int64_t)q * BM * BC + m * BC + cc];
+                acc[u] = acc[u] + term;
+            }
+    }
+    if (live)
+#pragma unroll
+        for (int u = 0; u < K; ++u) v.c[u][k * BR * BC + ent] = acc[u];
 }
 
 // the same with one lane per output entry and 16 lanes per output block, for
@@ -1585,7 +1625,7 @@ Aggregates build_aggregates(const Strength& S, uint64_t seed, int level, hipStre
 }
 
 void build_tentative(const Aggregates& G, int d, const double* B, double* q, double* Bc, hipStream_t s) {
-    k_tentative<<<grid_for(G.n_agg), 256, 0, s>>>(G.n_agg, d, G.mptr.p, G.midx.p, B, q, Bc);
+    k_tentative<<<grid_for((int64_t)G.n_agg * d), 256, 0, s>>>(G.n_agg, d, G.mptr.p, G.midx.p, B, q, Bc);
     MB_LAUNCH_CHECK();
 }
 
@@ -1799,36 +1839,49 @@ void build_rows(RowPart& R, int n, const int32_t* perm, const SetupBsr& A, const
 // Per row (colour order p, node perm[p]) of a block row: nonzero entries and
 // blocks of A_ff's off-diagonal blocks, of A_fg, of D^-1 and of A_ff's
 // diagonal block -- the counts the sliced parts would record.
-__global__ void k_row_stats(int n, const int32_t* __restrict__ perm, const int32_t* __restrict__ frp,
-                            const int32_t* __restrict__ fci, const double* __restrict__ fval, int fbs,
-                            const int32_t* __restrict__ grp, const double* __restrict__ gval, int gbs,
-                            const double* __restrict__ dinv, int32_t* __restrict__ out) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+__global__ __launch_bounds__(256) void k_row_stats(int n, const int32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ frp, const int32_t* __restrict__ fci,
+                                                   const double* __restrict__ fval, int fbs,
+                                                   const int32_t* __restrict__ grp, const double* __restrict__ gval,
+                                                   int gbs, const double* __restrict__ dinv,
+                                                   int32_t* __restrict__ out) {
+    // one wavefront per row: lanes over the row's values (contiguous), counts by ballot
+    const int p = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
+    if (p >= n) return;   // whole wavefronts
+    const int lane = threadIdx.x & (WAVE - 1);
     const int node = perm[p];
-    int off_nz = 0, off_bl = 0, cpl_nz = 0, cpl_bl = 0, dinv_nz = 0, diag_nz = 0, diag_bl = 0;
-    for (int q = frp[node]; q < frp[node + 1]; ++q) {
-        int nz = 0;
-        for (int e = 0; e < fbs; ++e) nz += fval[(int64_t)q * fbs + e] != 0.0;
-        if (fci[q] == node) {
-            diag_nz += nz;
-            ++diag_bl;
-        } else {
-            off_nz += nz;
-            ++off_bl;
+    int off_nz = 0, diag_nz = 0, diag_bl = 0, cpl_nz = 0, dinv_nz = 0;
+    const int f0 = frp[node], flen = frp[node + 1] - f0;
+    for (int u0 = 0; u0 < flen * fbs; u0 += WAVE) {
+        const int u = u0 + lane;
+        bool nz = false, diag = false;
+        if (u < flen * fbs) {
+            nz = fval[(int64_t)f0 * fbs + u] != 0.0;
+            diag = fci[f0 + u / fbs] == node;
+        }
+        diag_nz += (int)__popcll(__ballot(nz && diag));
+        off_nz += (int)__popcll(__ballot(nz && !diag));
+    }
+    for (int q = lane; q < flen; q += WAVE) diag_bl += fci[f0 + q] == node;
+    for (int off = WAVE / 2; off > 0; off >>= 1) diag_bl += __shfl_xor(diag_bl, off);
+    int glen = 0;
+    if (grp) {
+        const int g0 = grp[node];
+        glen = grp[node + 1] - g0;
+        for (int u0 = 0; u0 < glen * gbs; u0 += WAVE) {
+            const int u = u0 + lane;
+            const bool nz = u < glen * gbs && gval[(int64_t)g0 * gbs + u] != 0.0;
+            cpl_nz += (int)__popcll(__ballot(nz));
         }
     }
-    if (grp)
-        for (int q = grp[node]; q < grp[node + 1]; ++q) {
-            for (int e = 0; e < gbs; ++e) cpl_nz += gval[(int64_t)q * gbs + e] != 0.0;
-            ++cpl_bl;
-        }
-    for (int e = 0; e < fbs; ++e) dinv_nz += dinv[(int64_t)node * fbs + e] != 0.0;
+    for (int u0 = 0; u0 < fbs; u0 += WAVE)
+        dinv_nz += (int)__popcll(__ballot(u0 + lane < fbs && dinv[(int64_t)node * fbs + u0 + lane] != 0.0));
+    if (lane != 0) return;
     int32_t* o = out + (int64_t)p * 7;
     o[0] = off_nz;
-    o[1] = off_bl;
+    o[1] = flen - diag_bl;
     o[2] = cpl_nz;
-    o[3] = cpl_bl;
+    o[3] = glen;
     o[4] = dinv_nz;
     o[5] = diag_nz;
     o[6] = diag_bl;
@@ -1840,9 +1893,9 @@ std::vector<int64_t> row_colour_stats(int n, const int32_t* perm, const SetupBsr
     std::vector<int64_t> sums((size_t)std::max(nc, 0) * 7, 0);
     if (n == 0) return sums;
     DevBuf<int32_t> per((size_t)n * 7);
-    k_row_stats<<<grid_for(n), 256, 0, s>>>(n, perm, Aff.rp.p, Aff.ci.p, Aff.val.p, Aff.br * Aff.bc,
-                                             Afg.nnzb ? Afg.rp.p : nullptr, Afg.val.p, Afg.br * Afg.bc, dinv,
-                                             per.p);
+    k_row_stats<<<grid_for((int64_t)n * WAVE), 256, 0, s>>>(n, perm, Aff.rp.p, Aff.ci.p, Aff.val.p,
+                                                            Aff.br * Aff.bc, Afg.nnzb ? Afg.rp.p : nullptr,
+                                                            Afg.val.p, Afg.br * Afg.bc, dinv, per.p);
     MB_LAUNCH_CHECK();
     const std::vector<int32_t> h = per.download(s, (size_t)n * 7);
     for (int c = 0; c < nc; ++c)
@@ -1994,8 +2047,13 @@ static void launch_num_k(const SetupBsr* const* A, const SetupBsr* const* B, Set
     }
     const SetupBsr& A0 = *A[0];
     const SetupBsr& B0 = *B[0];
-    k_spgemm_num_k<BR, BM, BC, K><<<grid_for(C[0]->nnzb, 128), 128, 0, s>>>(C[0]->nnzb, A0.rp.p, A0.ci.p, B0.rp.p,
-                                                                           B0.ci.p, crow, C[0]->ci.p, v);
+    const int64_t z = C[0]->nnzb;
+    if (z < SPGEMM_ENTRY_MAX)
+        k_spgemm_num_ek<BR, BM, BC, K><<<grid_for(z * 16, 256), 256, 0, s>>>(z, A0.rp.p, A0.ci.p, B0.rp.p, B0.ci.p,
+                                                                            crow, C[0]->ci.p, v);
+    else
+        k_spgemm_num_k<BR, BM, BC, K><<<grid_for(z, 128), 128, 0, s>>>(z, A0.rp.p, A0.ci.p, B0.rp.p, B0.ci.p, crow,
+                                                                      C[0]->ci.p, v);
     MB_LAUNCH_CHECK();
 }
 
@@ -2034,11 +2092,11 @@ void spgemm_multi(const SetupBsr* const* A, const SetupBsr* const* B, int K, Set
     const SetupBsr& B0 = *B[0];
     const bool shape4 = A0.br == 4 && A0.bc == 4 && B0.bc == 4, shape3 = A0.br == 3 && A0.bc == 3 && B0.bc == 3;
     // one launch for the group, one lookup per output block and row entry (measured: pays
-    // for groups of three or four, where the lookups dominate; pairs are faster apart); the
-    // forced single-product forms and tiny outputs take one launch per product
+    // for groups of three or four, where the lookups dominate, and for tiny outputs; larger
+    // pairs are faster apart); the forced single-product forms take one launch per product
     const char* fo = form_override("MBAMG_SPGEMM_FORM");
     const bool fuse = (shape4 || shape3) && (fo ? std::strcmp(fo, "fused") == 0 && K >= 2
-                                                : K >= 3 && z >= SPGEMM_ENTRY_MAX);
+                                                : K >= 3 || (K >= 2 && z < SPGEMM_ENTRY_MAX));
     if (!fuse) {
         for (int k = 0; k < K; ++k) spgemm_values(*A[k], *B[k], *C[k], crow.p, s);
     } else if (shape4) {
