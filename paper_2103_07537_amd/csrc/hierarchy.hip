@@ -463,7 +463,8 @@ static void choose_weights(mbamg_hierarchy* h, Level& cur, const Aggregates& G, 
     }
     BsrView A[2][2];
     for (int f = 0; f < 2; ++f)
-        for (int g = 0; g < 2; ++g) A[f][g] = {cur.A[f][g].rp.p, cur.A[f][g].ci.p, cur.A[f][g].val.p, cur.A[f][g].br};
+        for (int g = 0; g < 2; ++g) A[f][g] = {cur.A[f][g].rp.p, cur.A[f][g].ci.p, cur.A[f][g].val.p, cur.A[f][g].br,
+                                                       cur.A[f][g].nnzb};
     cur.feat.alloc((size_t)std::max(nc, 1) * N_FEATURES);
     aggregate_features(nc, cur.n, G.agg.p, G.mptr.p, G.midx.p, A, h->fm.n_vec[0], h->fm.n_vec[1], lvl, nullptr,
                        nullptr, cur.feat.p, s);

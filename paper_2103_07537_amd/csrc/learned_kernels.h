@@ -14,6 +14,7 @@ struct BsrView {
     const int32_t* ci;
     const double* val;
     int d;
+    int64_t nnzb;   // blocks (host-side launch choices)
 };
 
 // out[n][2] = (omega_P, omega_S) for normalised features x[n][12]

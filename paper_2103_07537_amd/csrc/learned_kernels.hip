@@ -405,22 +405,61 @@ __device__ inline double wave_min(double v) {
     return v;
 }
 
-// One 64-lane wavefront per aggregate, one lane per member (strided), sums
-// and extrema combined across the wave.
-__global__ __launch_bounds__(WAVE) void k_features(int nagg, int n, const int32_t* __restrict__ agg,
-                                                   const int32_t* __restrict__ mptr, const int32_t* __restrict__ midx,
-                                                   BsrView A00, BsrView A01, BsrView A10, BsrView A11, int nv0,
-                                                   int nv1, const double* __restrict__ ld,
-                                                   const double* __restrict__ ld_sum, float level_feature,
-                                                   const float* __restrict__ mean, const float* __restrict__ stdv,
-                                                   float* __restrict__ out) {
-    const int k = blockIdx.x, lane = threadIdx.x;
+// v from the lane selected by the DPP control CTRL within the rows of
+// ROWMASK, 0 where that lane is outside the row
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_in(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// sum over a group of G lanes (16: one DPP row; 64: the wavefront), valid in
+// the group's last lane
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    v += dpp_in<0x111, 0xF>(v);   // row_shr:1
+    v += dpp_in<0x112, 0xF>(v);   // row_shr:2
+    v += dpp_in<0x114, 0xF>(v);   // row_shr:4
+    v += dpp_in<0x118, 0xF>(v);   // row_shr:8
+    if constexpr (G == 64) {
+        v += dpp_in<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+        v += dpp_in<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    }
+    return v;
+}
+
+// One workgroup of W wavefronts per aggregate.  Members go to groups of G
+// lanes (G = 16: four members per wavefront at once, for short rows; G = 64:
+// one, for long coarse rows); within a group, 16 lanes take the entries of
+// one block (lane x holds entry x), G / 16 blocks per pass.  The lane holding
+// a block's entry 0 also reads that block's diagonal (just fetched, so cached).
+template <int G, int W>
+__global__ __launch_bounds__(W * WAVE) void k_features(int nagg, int n, const int32_t* __restrict__ agg,
+                                                       const int32_t* __restrict__ mptr,
+                                                       const int32_t* __restrict__ midx, BsrView A00, BsrView A01,
+                                                       BsrView A10, BsrView A11, int nv0, int nv1,
+                                                       const double* __restrict__ ld,
+                                                       const double* __restrict__ ld_sum, float level_feature,
+                                                       const float* __restrict__ mean,
+                                                       const float* __restrict__ stdv, float* __restrict__ out) {
+    static_assert(G == 16 || G == 64, "a group is one DPP row or the wavefront");
+    constexpr int NT = W * WAVE;       // threads per aggregate
+    constexpr int NG = NT / G;         // member groups per aggregate
+    constexpr int BPP = G / 16;        // blocks per pass
+    constexpr int U = 4;               // passes in flight
+    __shared__ double red[W][12];
+    const int k = blockIdx.x, tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    const int grp = tid / G, glane = tid % G;
+    const int sub = glane / 16, x = glane % 16;
     const int b = mptr[k], e = mptr[k + 1];
     const double m = (double)(e - b);
     const double mu = *ld_sum / n;
+
+    // pass 1: the members' log-diagonal statistics
     double sld = 0, mx = -1e300, mn = 1e300;
-    for (int q = b + lane; q < e; q += WAVE) {
-        double v = ld[midx[q]];
+    for (int q = b + tid; q < e; q += NT) {
+        const double v = ld[midx[q]];
         sld += v;
         mx = fmax(mx, v);
         mn = fmin(mn, v);
@@ -428,102 +467,181 @@ __global__ __launch_bounds__(WAVE) void k_features(int nagg, int n, const int32_
     sld = wave_sum(sld);
     mx = wave_max(mx);
     mn = wave_min(mn);
-    const double mld = sld / m;
-    double var = 0;
-    double cmax = -1.0, cmin = 1e300;
-    double tot = 0, outw = 0, f9 = 0, f10 = 0, f11 = 0;
-    double a00 = 0, a01 = 0, a10 = 0, a11 = 0;
-    const int d0 = A00.d;
-    const int d1 = A11.d;
-    for (int q = b + lane; q < e; q += WAVE) {
-        const int i = midx[q];
-        var += (ld[i] - mld) * (ld[i] - mld);
-        // every block of the member's A00 and A11 rows is read once, into registers;
-        // the sums run in the order of vdiag, cvv and row_fro2
-        double dv0 = 0.0, dv1 = 0.0, fro00 = 0.0, fro11 = 0.0;
-        double off0 = 0, off1 = 0, g2 = 0, cpp = 0;
-        for (int p = A00.rp[i]; p < A00.rp[i + 1]; ++p) {
-            const int jn = A00.ci[p];
-            double blk[16];
-            load_block_n(A00.val + (int64_t)p * d0 * d0, d0 * d0, blk);
-#pragma unroll
-            for (int x = 0; x < 16; ++x)
-                if (x < d0 * d0) fro00 += blk[x] * blk[x];
-            if (d0 > nv0)
-                for (int a = 0; a < nv0; ++a)
-                    for (int c = nv0; c < d0; ++c) g2 += blk[a * d0 + c] * blk[a * d0 + c];
-            if (jn == i) {
-                if (d0 > nv0) cpp = fabs(blk[nv0 * d0 + nv0]);
-                double sd = 0.0;
-                for (int a = 0; a < nv0; ++a) sd += blk[a * d0 + a];
-                dv0 = sd / nv0;
-                continue;
-            }
-            double sc = 0.0;
-            for (int a = 0; a < nv0; ++a) sc += fabs(blk[a * d0 + a]);
-            const double c = sc / nv0;
-            off0 += c;
-            if (agg[jn] != k) outw += c;
-            else {
-                cmax = fmax(cmax, c);
-                cmin = fmin(cmin, c);
-            }
+    if (W > 1) {
+        if (lane == 0) {
+            red[wv][0] = sld;
+            red[wv][1] = mx;
+            red[wv][2] = mn;
         }
-        for (int p = A11.rp[i]; p < A11.rp[i + 1]; ++p) {
-            double blk[16];
-            load_block_n(A11.val + (int64_t)p * d1 * d1, d1 * d1, blk);
-#pragma unroll
-            for (int x = 0; x < 16; ++x)
-                if (x < d1 * d1) fro11 += blk[x] * blk[x];
-            double sd = 0.0;
-            if (A11.ci[p] == i) {
-                for (int a = 0; a < nv1; ++a) sd += blk[a * d1 + a];
-                dv1 = sd / nv1;
-            } else {
-                for (int a = 0; a < nv1; ++a) sd += fabs(blk[a * d1 + a]);
-                off1 += sd / nv1;
-            }
+        __syncthreads();
+        sld = 0;
+        mx = -1e300;
+        mn = 1e300;
+        for (int w = 0; w < W; ++w) {
+            sld += red[w][0];
+            mx = fmax(mx, red[w][1]);
+            mn = fmin(mn, red[w][2]);
         }
-        tot += off0;
-        f9 += off0 / dv0;
-        f10 += off1 / dv1;
-        if (d0 > nv0) f11 += g2 / fmax(dv0 * cpp, 1e-300);
-        a00 += fro00;
-        a11 += fro11;
-        if (A01.rp) a01 += row_fro2(A01, i);
-        if (A10.rp) a10 += row_fro2(A10, i);
+        __syncthreads();
     }
-    var = wave_sum(var);
-    cmax = wave_max(cmax);
-    cmin = wave_min(cmin);
-    tot = wave_sum(tot);
-    outw = wave_sum(outw);
-    f9 = wave_sum(f9);
-    f10 = wave_sum(f10);
-    f11 = wave_sum(f11);
-    a00 = wave_sum(a00);
-    a01 = wave_sum(a01);
-    a10 = wave_sum(a10);
-    a11 = wave_sum(a11);
-    if (lane >= 12) return;
+    const double mld = sld / m;
+
+    // pass 2: members by groups, block entries by lanes
+    const int d0 = A00.d, d1 = A11.d, dd0 = d0 * d0, dd1 = d1 * d1;
+    const int a0 = x / d0, c0 = x % d0;
+    const bool g2_entry = x < dd0 && a0 < nv0 && c0 >= nv0;
+    double fro00 = 0, fro11 = 0, a01 = 0, a10 = 0, outw = 0, cmax = -1.0, cmin = 1e300;
+    double var = 0, tot = 0, f9 = 0, f10 = 0, f11 = 0;   // last lane of each group
+    for (int q = b + grp; q < e; q += NG) {
+        const int i = midx[q];
+        double off0 = 0, dv0 = 0, cpp = 0, g2 = 0, off1 = 0, dv1 = 0;
+        // chunks of G blocks: the group first fetches their columns (and the
+        // columns' aggregates), one block per lane, so no pass waits on a
+        // dependent load; then U passes of BPP blocks at a time, lanes over
+        // entries, with the U passes' loads issued before any is used
+        for (int base = A00.rp[i], r1 = A00.rp[i + 1]; base < r1; base += G) {
+            const int nb = min(G, r1 - base);
+            int jn_l = -1, ag_l = -1;
+            if (glane < nb) {
+                jn_l = A00.ci[base + glane];
+                ag_l = agg[jn_l];
+            }
+            for (int t0 = 0; t0 < nb; t0 += U * BPP) {
+                double vv[U];
+#pragma unroll
+                for (int h = 0; h < U; ++h) {
+                    const int t = t0 + h * BPP + sub;
+                    vv[h] = t < nb && x < dd0 ? A00.val[(int64_t)(base + t) * dd0 + x] : 0.0;
+                }
+#pragma unroll
+                for (int h = 0; h < U; ++h) {
+                    const int t = t0 + h * BPP + sub;
+                    const int src = t < nb ? t : 0;
+                    const int jn = __shfl(jn_l, src, G), ag = __shfl(ag_l, src, G);
+                    if (t >= nb || x >= dd0) continue;
+                    const double v = vv[h];
+                    fro00 += v * v;
+                    if (g2_entry) g2 += v * v;
+                    if (x != 0) continue;
+                    const double* blk = A00.val + (int64_t)(base + t) * dd0;   // just fetched: cached
+                    if (jn == i) {
+                        if (d0 > nv0) cpp = fabs(blk[nv0 * d0 + nv0]);
+                        double sd = 0.0;
+                        for (int a = 0; a < nv0; ++a) sd += blk[a * d0 + a];
+                        dv0 = sd / nv0;
+                    } else {
+                        double sc = 0.0;
+                        for (int a = 0; a < nv0; ++a) sc += fabs(blk[a * d0 + a]);
+                        const double c = sc / nv0;
+                        off0 += c;
+                        if (ag != k) outw += c;
+                        else {
+                            cmax = fmax(cmax, c);
+                            cmin = fmin(cmin, c);
+                        }
+                    }
+                }
+            }
+        }
+        for (int base = A11.rp[i], r1 = A11.rp[i + 1]; base < r1; base += G) {
+            const int nb = min(G, r1 - base);
+            const int jn_l = glane < nb ? A11.ci[base + glane] : -1;
+            for (int t0 = 0; t0 < nb; t0 += U * BPP) {
+                double vv[U];
+#pragma unroll
+                for (int h = 0; h < U; ++h) {
+                    const int t = t0 + h * BPP + sub;
+                    vv[h] = t < nb && x < dd1 ? A11.val[(int64_t)(base + t) * dd1 + x] : 0.0;
+                }
+#pragma unroll
+                for (int h = 0; h < U; ++h) {
+                    const int t = t0 + h * BPP + sub;
+                    const int jn = __shfl(jn_l, t < nb ? t : 0, G);
+                    if (t >= nb || x >= dd1) continue;
+                    const double v = vv[h];
+                    fro11 += v * v;
+                    if (x != 0) continue;
+                    const double* blk = A11.val + (int64_t)(base + t) * dd1;
+                    double sd = 0.0;
+                    if (jn == i) {
+                        for (int a = 0; a < nv1; ++a) sd += blk[a * d1 + a];
+                        dv1 = sd / nv1;
+                    } else {
+                        for (int a = 0; a < nv1; ++a) sd += fabs(blk[a * d1 + a]);
+                        off1 += sd / nv1;
+                    }
+                }
+            }
+        }
+        if (A01.rp && x < A01.d * A01.d)
+#pragma unroll 4
+            for (int p = A01.rp[i] + sub; p < A01.rp[i + 1]; p += BPP) {
+                const double v = A01.val[(int64_t)p * A01.d * A01.d + x];
+                a01 += v * v;
+            }
+        if (A10.rp && x < A10.d * A10.d)
+#pragma unroll 4
+            for (int p = A10.rp[i] + sub; p < A10.rp[i + 1]; p += BPP) {
+                const double v = A10.val[(int64_t)p * A10.d * A10.d + x];
+                a10 += v * v;
+            }
+        off0 = group_sum<G>(off0);
+        dv0 = group_sum<G>(dv0);
+        cpp = group_sum<G>(cpp);
+        g2 = group_sum<G>(g2);
+        off1 = group_sum<G>(off1);
+        dv1 = group_sum<G>(dv1);
+        if (glane == G - 1) {
+            const double li = ld[i];
+            var += (li - mld) * (li - mld);
+            tot += off0;
+            f9 += off0 / dv0;
+            f10 += off1 / dv1;
+            if (d0 > nv0) f11 += g2 / fmax(dv0 * cpp, 1e-300);
+        }
+    }
+    double S[12] = {var, tot, outw, f9, f10, f11, fro00, a01, a10, fro11, cmax, cmin};
+#pragma unroll
+    for (int t = 0; t < 10; ++t) S[t] = wave_sum(S[t]);
+    S[10] = wave_max(S[10]);
+    S[11] = wave_min(S[11]);
+    if (W > 1) {
+        if (lane < 12) {
+            double v = S[0];
+#pragma unroll
+            for (int t = 1; t < 12; ++t)
+                if (lane == t) v = S[t];
+            red[wv][lane] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 12; ++t) {
+            double v = red[0][t];
+            for (int w = 1; w < W; ++w) v = t == 10 ? fmax(v, red[w][t]) : t == 11 ? fmin(v, red[w][t]) : v + red[w][t];
+            S[t] = v;
+        }
+    }
+    if (tid >= 12) return;
+    var = S[0]; tot = S[1]; outw = S[2]; f9 = S[3]; f10 = S[4]; f11 = S[5];
+    fro00 = S[6]; a01 = S[7]; a10 = S[8]; fro11 = S[9]; cmax = S[10]; cmin = S[11];
     double F;
-    switch (lane) {
+    switch (tid) {
         case 0: F = mld - mu; break;
         case 1: F = sqrt(fmax(var / m, 0.0)); break;
         case 2: F = mx - mn; break;
         case 3: F = (cmax >= 0.0 && cmin > 0.0) ? log(cmax) - log(cmin) : 0.0; break;
         case 4: F = m / ((double)n / nagg); break;
         case 5: F = tot > 0 ? outw / tot : 0.0; break;
-        case 6: F = sqrt(a01) / sqrt(a00); break;
-        case 7: F = sqrt(a10) / sqrt(a11); break;
+        case 6: F = sqrt(a01) / sqrt(fro00); break;
+        case 7: F = sqrt(a10) / sqrt(fro11); break;
         case 8: F = f9 / m; break;
         case 9: F = f10 / m; break;
         case 10: F = f11 / m; break;
         default: F = level_feature; break;
     }
     float v = (float)F;
-    if (mean) v = (v - mean[lane]) / stdv[lane];
-    out[(int64_t)k * 12 + lane] = v;
+    if (mean) v = (v - mean[tid]) / stdv[tid];
+    out[(int64_t)k * 12 + tid] = v;
 }
 
 // per-aggregate weights -> per-row smoother damping in colour order
@@ -578,9 +696,23 @@ void aggregate_features(int nagg, int n, const int32_t* agg, const int32_t* mptr
     k_logdiag<<<gridn(n), 256, 0, s>>>(n, A[0][0], nv0, ld.p);
     k_sum_partial<<<256, 256, 0, s>>>(ld.p, n, part.p);
     k_sum_final<<<1, 64, 0, s>>>(part.p, 256, tot.p);
-    if (nagg > 0)
-        k_features<<<nagg, WAVE, 0, s>>>(nagg, n, agg, mptr, midx, A[0][0], A[0][1], A[1][0], A[1][1], nv0, nv1, ld.p,
-                                         tot.p, (float)level / 4.0f, mean, stdv, out);
+    MB_CHECK(A[0][0].d <= 4 && A[1][1].d <= 4 && A[0][1].d <= 4 && A[1][0].d <= 4, MBAMG_E_INVALID,
+             "features: blocks of at most 4 x 4");
+    if (nagg > 0) {
+        // long coarse rows: one wavefront per member, and more of them per aggregate when
+        // the aggregates are few; short rows: four members per wavefront
+        const bool long_rows = n > 0 && A[0][0].nnzb >= (int64_t)16 * n;
+        const float lf = (float)level / 4.0f;
+        if (!long_rows)
+            k_features<16, 1><<<nagg, WAVE, 0, s>>>(nagg, n, agg, mptr, midx, A[0][0], A[0][1], A[1][0], A[1][1],
+                                                     nv0, nv1, ld.p, tot.p, lf, mean, stdv, out);
+        else if (nagg >= 1024)
+            k_features<64, 4><<<nagg, 4 * WAVE, 0, s>>>(nagg, n, agg, mptr, midx, A[0][0], A[0][1], A[1][0],
+                                                         A[1][1], nv0, nv1, ld.p, tot.p, lf, mean, stdv, out);
+        else
+            k_features<64, 8><<<nagg, 8 * WAVE, 0, s>>>(nagg, n, agg, mptr, midx, A[0][0], A[0][1], A[1][0],
+                                                           A[1][1], nv0, nv1, ld.p, tot.p, lf, mean, stdv, out);
+    }
     MB_LAUNCH_CHECK();
     MB_HIP(hipStreamSynchronize(s));
 }

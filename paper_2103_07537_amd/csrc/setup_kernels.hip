@@ -948,8 +948,47 @@ __global__ __launch_bounds__(128) void k_spgemm_num_k(int64_t nnz, const int32_t
     }
 }
 
-// K products as in k_spgemm_num_k, one lane per output entry and 16 lanes
-// per output block (tiny outputs): each column lookup serves all K products.
+// one output block by a group of 16 lanes, lane `ent` holding entry `ent`:
+// the group looks up 16 consecutive row entries at once (one per lane), then
+// every lane adds their terms in row order, so each entry's sum runs in the
+// same order as in the one-thread-per-block kernels
+template <int BR, int BM, int BC, int K>
+__device__ __forceinline__ void entry_sums(const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                                           const int32_t* __restrict__ brp, const int32_t* __restrict__ bci,
+                                           int i, int l, int ent, const double* const (&a)[K],
+                                           const double* const (&b)[K], double (&acc)[K]) {
+    static_assert(BR * BC <= 16, "at most 16 entries per output block");
+    const bool live = ent < BR * BC;
+    const int r = live ? ent / BC : 0, cc = live ? ent % BC : 0;
+    const int p0 = arp[i], p1 = arp[i + 1];
+    for (int pb = p0; pb < p1; pb += 16) {
+        int q = -1;
+        if (pb + ent < p1) {
+            const int j = aci[pb + ent];
+            q = find_col_short(bci, brp[j], brp[j + 1], l);
+        }
+        const int cnt = min(16, p1 - pb);
+#pragma unroll 4
+        for (int t = 0; t < cnt; ++t) {
+            const int qt = __shfl(q, t, 16);
+            const bool hit = qt >= 0 && live;
+            const int64_t p = pb + t, qs = hit ? qt : 0;
+#pragma unroll
+            for (int u = 0; u < K; ++u) {
+                double s = acc[u];
+#pragma unroll
+                for (int m = 0; m < BM; ++m) {
+                    const double term = a[u][p * BR * BM + r * BM + m] * b[u][qs * BM * BC + m * BC + cc];
+                    s = s + term;
+                }
+                acc[u] = hit ? s : acc[u];
+            }
+        }
+    }
+}
+
+// K products as in k_spgemm_num_k, 16 lanes per output block (small outputs):
+// each column lookup serves all K products
 template <int BR, int BM, int BC, int K>
 __global__ __launch_bounds__(256) void k_spgemm_num_ek(int64_t nnz, const int32_t* __restrict__ arp,
                                                        const int32_t* __restrict__ aci,
@@ -957,38 +996,21 @@ __global__ __launch_bounds__(256) void k_spgemm_num_ek(int64_t nnz, const int32_
                                                        const int32_t* __restrict__ bci,
                                                        const int32_t* __restrict__ crow,
                                                        const int32_t* __restrict__ cci, SpgemmVals<K> v) {
-    static_assert(BR * BC <= 16, "at most 16 entries per output block");
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t k = tid / 16;
     const int ent = (int)(tid % 16);
-    if (k >= nnz) return;
-    const int r = ent / BC, cc = ent % BC;
-    const bool live = ent < BR * BC;
-    const int i = crow[k], l = cci[k];
+    if (k >= nnz) return;   // whole groups of 16
     double acc[K];
 #pragma unroll
     for (int u = 0; u < K; ++u) acc[u] = 0.0;
-    for (int p = arp[i]; p < arp[i + 1]; ++p) {
-        const int j = aci[p];
-        const int q = find_col_short(bci, brp[j], brp[j + 1], l);
-        if (q < 0 || !live) continue;
-#pragma unroll
-        for (int u = 0; u < K; ++u)
-#pragma unroll
-            for (int m = 0; m < BM; ++m) {
-                const double term = v.a[u][(int64_t)p * BR * BM + r * BM + m] *
-                                    v.b[u][(int64_t)q * BM * BC + m * BC + cc];
-                acc[u] = acc[u] + term;
-            }
-    }
-    if (live)
+    entry_sums<BR, BM, BC, K>(arp, aci, brp, bci, crow[k], cci[k], ent, v.a, v.b, acc);
+    if (ent < BR * BC)
 #pragma unroll
         for (int u = 0; u < K; ++u) v.c[u][k * BR * BC + ent] = acc[u];
 }
 
-// the same with one lane per output entry and 16 lanes per output block, for
-// outputs too small to fill the GPU one block per thread; each entry's sum
-// runs in the same order
+// one product with 16 lanes per output block, for outputs too small to fill
+// the GPU one block per thread
 template <int BR, int BM, int BC>
 __global__ __launch_bounds__(256) void k_spgemm_num_e(int64_t nnz, const int32_t* __restrict__ arp,
                                                       const int32_t* __restrict__ aci,
@@ -998,26 +1020,15 @@ __global__ __launch_bounds__(256) void k_spgemm_num_e(int64_t nnz, const int32_t
                                                       const double* __restrict__ bval,
                                                       const int32_t* __restrict__ crow,
                                                       const int32_t* __restrict__ cci, double* __restrict__ cval) {
-    static_assert(BR * BC <= 16, "at most 16 entries per output block");
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t k = tid / 16;
     const int ent = (int)(tid % 16);
-    if (k >= nnz) return;
-    const int r = ent / BC, cc = ent % BC;
-    const bool live = ent < BR * BC;
-    const int i = crow[k], l = cci[k];
-    double acc = 0.0;
-    for (int p = arp[i]; p < arp[i + 1]; ++p) {
-        const int j = aci[p];
-        const int q = find_col_short(bci, brp[j], brp[j + 1], l);
-        if (q < 0 || !live) continue;
-#pragma unroll
-        for (int m = 0; m < BM; ++m) {
-            const double term = aval[(int64_t)p * BR * BM + r * BM + m] * bval[(int64_t)q * BM * BC + m * BC + cc];
-            acc = acc + term;
-        }
-    }
-    if (live) cval[k * BR * BC + ent] = acc;
+    if (k >= nnz) return;   // whole groups of 16
+    const double* const a[1] = {aval};
+    const double* const b[1] = {bval};
+    double acc[1] = {0.0};
+    entry_sums<BR, BM, BC, 1>(arp, aci, brp, bci, crow[k], cci[k], ent, a, b, acc);
+    if (ent < BR * BC) cval[k * BR * BC + ent] = acc[0];
 }
 
 // the same for any block shape with at most 16 entries per output block

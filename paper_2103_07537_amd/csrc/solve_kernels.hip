@@ -68,6 +68,12 @@ __device__ __forceinline__ void load_vec<float, 4>(const float* __restrict__ p, 
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
 
+template <>
+__device__ __forceinline__ void load_vec<double, 2>(const double* __restrict__ p, double (&v)[2]) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    v[0] = a.x; v[1] = a.y;
+}
+
 template <class T, int D>
 __device__ __forceinline__ void store_vec(T* __restrict__ p, const T (&v)[D]) {
 #pragma unroll
@@ -289,6 +295,52 @@ __device__ __forceinline__ void row_sub(const RowView<T>& A, int row, int lane, 
     }
 }
 
+// The same sums with the row's values read back to back: in a pass over the
+// row, lane u reads the u-th 16-byte piece (one block row of a float block,
+// half of a double one), so one load instruction covers 1 KiB with no gaps.
+// Every lane keeps one block-row position (the row's first block starts a
+// piece group), so its partial sum belongs to one component r.
+template <class T, int D, int MODE, bool SKIP_DIAG>
+__device__ __forceinline__ void row_sub_c(const RowView<T>& A, int row, int lane, const T* __restrict__ xa,
+                                          const T* __restrict__ xb, int cstart, T (&acc)[D]) {
+    constexpr int V = 16 / (int)sizeof(T);   // values per piece
+    static_assert(D % V == 0, "block rows split into 16-byte pieces");
+    constexpr int LR = D / V;                // pieces per block row
+    constexpr int LB = D * LR;               // pieces per block
+    static_assert(WAVE % LB == 0, "a pass keeps every lane on one block-row position");
+    constexpr int UNROLL = 4;
+    const int part = lane % LB;
+    const int r = part / LR, c0 = (part % LR) * V;
+    const int64_t u0 = (int64_t)A.rp[row] * LB, u1 = (int64_t)A.rp[row + 1] * LB;
+    T sum = T(0);
+    for (int64_t ub = u0; ub < u1; ub += UNROLL * WAVE) {
+        T av[UNROLL][V], xv[UNROLL][V];
+        bool ok[UNROLL];
+#pragma unroll
+        for (int h = 0; h < UNROLL; ++h) {
+            const int64_t u = ub + h * WAVE + lane;
+            ok[h] = u < u1;
+            const int64_t uc = ok[h] ? u : u0 + part;   // in range: the row's first block
+            const int j = A.col[uc / LB];
+            if (SKIP_DIAG && j == row) ok[h] = false;
+            const T* src = xa;
+            if (MODE == 1 && j >= cstart) src = xb;
+            if (MODE == 2 && j >= cstart) ok[h] = false;
+            load_vec<T, V>(A.val + uc * V, av[h]);
+            load_vec<T, V>(src + (int64_t)j * D + c0, xv[h]);
+        }
+#pragma unroll
+        for (int h = 0; h < UNROLL; ++h) {
+            T s = T(0);
+#pragma unroll
+            for (int c = 0; c < V; ++c) s += av[h][c] * xv[h][c];
+            sum += ok[h] ? s : T(0);
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < D; ++rr) acc[rr] -= rr == r ? sum : T(0);
+}
+
 // v from lane src (by the DPP control CTRL, in the rows of ROWMASK; 0 where
 // the source lane is out of range or the row is masked)
 template <int CTRL, int ROWMASK>
@@ -336,11 +388,19 @@ __global__ __launch_bounds__(256) void k_gs_rows(GsRowArgs<T> a) {
     T acc[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) acc[r] = T(0);
-    if (!a.skip_off) {
-        if (ZX) row_sub<T, D, D, 2, true>(a.aff, row, lane, a.t, nullptr, a.cstart, acc);
-        else row_sub<T, D, D, 1, true>(a.aff, row, lane, a.t, a.x, a.cstart, acc);
+    if constexpr (D == 4) {
+        if (!a.skip_off) {
+            if (ZX) row_sub_c<T, D, 2, true>(a.aff, row, lane, a.t, nullptr, a.cstart, acc);
+            else row_sub_c<T, D, 1, true>(a.aff, row, lane, a.t, a.x, a.cstart, acc);
+        }
+        if (CPL) row_sub_c<T, D, 0, false>(a.afg, row, lane, a.xg, nullptr, 0, acc);
+    } else {
+        if (!a.skip_off) {
+            if (ZX) row_sub<T, D, D, 2, true>(a.aff, row, lane, a.t, nullptr, a.cstart, acc);
+            else row_sub<T, D, D, 1, true>(a.aff, row, lane, a.t, a.x, a.cstart, acc);
+        }
+        if (CPL) row_sub<T, D, D, 0, false>(a.afg, row, lane, a.xg, nullptr, 0, acc);
     }
-    if (CPL) row_sub<T, D, D, 0, false>(a.afg, row, lane, a.xg, nullptr, 0, acc);
     wave_sum_vec<T, D>(acc);
     if (lane != WAVE - 1) return;
 #pragma unroll
@@ -382,8 +442,13 @@ __global__ __launch_bounds__(256) void k_resid_rows(ResidRowArgs<T> a) {
     T acc[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) acc[r] = T(0);
-    row_sub<T, D, D, 0, false>(a.aff[f], row, lane, a.x[f], nullptr, 0, acc);
-    row_sub<T, D, D, 0, false>(a.afg[f], row, lane, a.x[g], nullptr, 0, acc);
+    if constexpr (D == 4) {
+        row_sub_c<T, D, 0, false>(a.aff[f], row, lane, a.x[f], nullptr, 0, acc);
+        row_sub_c<T, D, 0, false>(a.afg[f], row, lane, a.x[g], nullptr, 0, acc);
+    } else {
+        row_sub<T, D, D, 0, false>(a.aff[f], row, lane, a.x[f], nullptr, 0, acc);
+        row_sub<T, D, D, 0, false>(a.afg[f], row, lane, a.x[g], nullptr, 0, acc);
+    }
     wave_sum_vec<T, D>(acc);
     if (lane != WAVE - 1) return;
     T out[D];
