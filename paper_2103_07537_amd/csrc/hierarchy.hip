@@ -1191,7 +1191,7 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
         T* X = cur < 0 ? nullptr : buf[cur];
         // block 0 (uses the current x1 for the coupling term)
         smooth_block<T>(h, l, 0, zero, b, X, buf[nx], zero ? nullptr : X + n0, s);
-        // block 1 (uses the updated x0, Algorithm 1 line 7)
+        // block 1 (Algorithm 1 relaxes it with the already updated x0)
         smooth_block<T>(h, l, 1, zero, b + n0, X ? X + n0 : nullptr, buf[nx] + n0, buf[nx], s);
         cur = nx;
     };
@@ -1221,7 +1221,7 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
             a.in[f] = V.r.p + (f ? n0 : 0);
             a.out[f] = C.b.p + (f ? nc0 : 0);
         }
-        launch_restrict<T>(Lv.d[0], a, s);
+        launch_restrict<T>(Lv.d[0], a, Nx.n > 0 ? (int)ceil_div((int64_t)Lv.n, Nx.n) : 1, s);
     }
     vcycle_level<T>(h, l + 1, C.b.p, C.x.p, s);
     if (Lv.smoothed) {

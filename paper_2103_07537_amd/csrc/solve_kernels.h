@@ -123,7 +123,7 @@ template <class T>
 void launch_resid_rows(int d, const ResidRowArgs<T>& a, hipStream_t s);
 
 template <class T>
-void launch_restrict(int d, const TransferArgs<T>& a, hipStream_t s);
+void launch_restrict(int d, const TransferArgs<T>& a, int members_per_row, hipStream_t s);
 template <class T>
 void launch_prolong(int d, const TransferArgs<T>& a, hipStream_t s);
 template <class T>

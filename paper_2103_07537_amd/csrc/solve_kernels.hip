@@ -550,22 +550,47 @@ __global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_xfer(XferArgs<T
     store_vec<T, D>(a.y[f] + (int64_t)row * D, out);
 }
 
-// coarse b_k = sum over members i of aggregate k of q_i .* r_i (per component)
-template <class T, int D>
-__global__ void k_restrict(TransferArgs<T> a) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum over groups of G lanes (G = 4, 8, 16 or 64, groups aligned in the
+// wavefront), valid in each group's last lane: the row shifts by 1, 2, 4 and 8
+// only ever add lanes of the same group into that lane.
+template <class T, int D, int G>
+__device__ __forceinline__ void group_sum_vec(T (&acc)[D]) {
+    static_assert(G == 4 || G == 8 || G == 16 || G == 64, "group of 4, 8, 16 or 64 lanes");
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        T v = acc[r];
+        v += dpp_in<0x111, 0xF>(v);   // row_shr:1
+        v += dpp_in<0x112, 0xF>(v);   // row_shr:2
+        if constexpr (G >= 8) v += dpp_in<0x114, 0xF>(v);   // row_shr:4
+        if constexpr (G >= 16) v += dpp_in<0x118, 0xF>(v);  // row_shr:8
+        if constexpr (G == 64) {
+            v += dpp_in<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+            v += dpp_in<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+        }
+        acc[r] = v;
+    }
+}
+
+// coarse b_k = sum over members i of aggregate k of q_i .* r_i (per component):
+// G lanes per coarse row, the members strided over them (their rows are
+// scattered over the fine vector, so many are fetched at once)
+template <class T, int D, int G>
+__global__ __launch_bounds__(256) void k_restrict(TransferArgs<T> a) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int k = (int)(t / G);
+    const int gl = (int)(t % G);
     int f = 0;
     if (k >= a.n_rows[0]) {
         k -= a.n_rows[0];
         f = 1;
-        if (k >= a.n_rows[1]) return;
+        if (k >= a.n_rows[1]) return;   // whole groups
     }
     const int32_t* mp = a.map[f];
     const int32_t* mi = a.idx[f];
     T acc[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[c] = T(0);
-    for (int m = mp[k]; m < mp[k + 1]; ++m) {
+    for (int m = mp[k] + gl; m < mp[k + 1]; m += G) {
         const int64_t i = mi[m];
         T q[D], r[D];
         load_vec<T, D>(a.q[f] + i * D, q);
@@ -573,7 +598,8 @@ __global__ void k_restrict(TransferArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < D; ++c) acc[c] += q[c] * r[c];
     }
-    store_vec<T, D>(a.out[f] + (int64_t)k * D, acc);
+    group_sum_vec<T, D, G>(acc);
+    if (gl == G - 1) store_vec<T, D>(a.out[f] + (int64_t)k * D, acc);
 }
 
 // x_i += q_i .* x_c[agg(i)] (per component)
@@ -755,16 +781,28 @@ void launch_xfer(int d, int P, const XferArgs<T>& a, hipStream_t s) {
 template void launch_xfer<double>(int, int, const XferArgs<double>&, hipStream_t);
 template void launch_xfer<float>(int, int, const XferArgs<float>&, hipStream_t);
 
+template <class T, int D>
+static void restrict_dispatch(int64_t total, int G, const TransferArgs<T>& a, hipStream_t s) {
+    const unsigned grid = (unsigned)ceil_div(total * G, 256);
+    switch (G) {
+        case 4: k_restrict<T, D, 4><<<grid, 256, 0, s>>>(a); break;
+        case 8: k_restrict<T, D, 8><<<grid, 256, 0, s>>>(a); break;
+        case 16: k_restrict<T, D, 16><<<grid, 256, 0, s>>>(a); break;
+        default: k_restrict<T, D, 64><<<grid, 256, 0, s>>>(a); break;
+    }
+}
+
 template <class T>
-void launch_restrict(int d, const TransferArgs<T>& a, hipStream_t s) {
-    const int total = a.n_rows[0] + a.n_rows[1];
+void launch_restrict(int d, const TransferArgs<T>& a, int members_per_row, hipStream_t s) {
+    const int64_t total = (int64_t)a.n_rows[0] + a.n_rows[1];
     if (total <= 0) return;
-    unsigned grid = (unsigned)ceil_div(total, 256);
+    // about two members per lane
+    const int G = members_per_row <= 8 ? 4 : members_per_row <= 16 ? 8 : members_per_row <= 32 ? 16 : 64;
     switch (d) {
-        case 1: k_restrict<T, 1><<<grid, 256, 0, s>>>(a); break;
-        case 2: k_restrict<T, 2><<<grid, 256, 0, s>>>(a); break;
-        case 3: k_restrict<T, 3><<<grid, 256, 0, s>>>(a); break;
-        case 4: k_restrict<T, 4><<<grid, 256, 0, s>>>(a); break;
+        case 1: restrict_dispatch<T, 1>(total, G, a, s); break;
+        case 2: restrict_dispatch<T, 2>(total, G, a, s); break;
+        case 3: restrict_dispatch<T, 3>(total, G, a, s); break;
+        case 4: restrict_dispatch<T, 4>(total, G, a, s); break;
         default: throw Error(MBAMG_E_INVALID, "dofs per node must be 1..4");
     }
     MB_LAUNCH_CHECK();
@@ -796,8 +834,8 @@ template void launch_gs<double>(int, int, bool, bool, const GsArgs<double>&, hip
 template void launch_gs<float>(int, int, bool, bool, const GsArgs<float>&, hipStream_t);
 template void launch_resid<double>(int, int, const ResidArgs<double>&, hipStream_t);
 template void launch_resid<float>(int, int, const ResidArgs<float>&, hipStream_t);
-template void launch_restrict<double>(int, const TransferArgs<double>&, hipStream_t);
-template void launch_restrict<float>(int, const TransferArgs<float>&, hipStream_t);
+template void launch_restrict<double>(int, const TransferArgs<double>&, int, hipStream_t);
+template void launch_restrict<float>(int, const TransferArgs<float>&, int, hipStream_t);
 template void launch_prolong<double>(int, const TransferArgs<double>&, hipStream_t);
 template void launch_prolong<float>(int, const TransferArgs<float>&, hipStream_t);
 template void launch_coarse<double>(int, const double*, const double*, double*, hipStream_t);

@@ -270,7 +270,7 @@ def test_bgs_closed_form(si):
     r0 = w * M[0] @ b0
     assert np.allclose(z0, r0, rtol=1e-12, atol=1e-12)
     assert np.allclose(z1, w * M[1] @ (b1 - A[1][0] @ r0), rtol=1e-12, atol=1e-12)
-    # from a nonzero iterate: line 7 uses the updated x0
+    # from a nonzero iterate: the second block is relaxed with the updated x0
     y0, y1 = amg.bgs(lev, x0, x1, b0, b1, p)
     n0 = x0 + w * M[0] @ (b0 - A[0][0] @ x0 - A[0][1] @ x1)
     n1 = x1 + w * M[1] @ (b1 - A[1][0] @ n0 - A[1][1] @ x1)
