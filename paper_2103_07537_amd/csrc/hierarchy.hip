@@ -379,17 +379,18 @@ enum class PartKind { Off = 0, Cpl = 1, Diag = 2, Dinv = 3 };
 // Waves per slice (1..16) for a launch over `slices` slices of `width` slots
 // on average: wide slices are shared by more waves until the launch has
 // about 2048 waves, keeping at least 4 slots per wave.
-static int slot_split(double slices, double width) {
+static int slot_split(double slices, double width, double target = 2048) {
     int P = 1;
-    while (P < 16 && slices * P < 2048 && width >= 8.0 * P) P *= 2;
+    while (P < 16 && slices * P < target && width >= 8.0 * P) P *= 2;
     return P;
 }
 
+// a transfer is one launch over the whole level (both block rows), not one colour
 static int transfer_split(const SellPart& P, int n_slices) {
     int64_t slots = 0;
     for (int w : P.h_width) slots += w;
     const double avg = n_slices ? (double)slots / n_slices : 0.0;
-    return slot_split(n_slices, avg);
+    return slot_split(n_slices, avg, 32768);
 }
 
 // Pack one part of block row f into masked slices on the device.  A: the
