@@ -858,36 +858,57 @@ __device__ __forceinline__ int find_col_short(const int32_t* __restrict__ ci, in
     return pos;
 }
 
-template <int BR, int BM, int BC>
-__global__ void k_spgemm_num(int64_t nnz, const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
-                             const double* __restrict__ aval, const int32_t* __restrict__ brp,
-                             const int32_t* __restrict__ bci, const double* __restrict__ bval,
-                             const int32_t* __restrict__ crow, const int32_t* __restrict__ cci,
-                             double* __restrict__ cval) {
+// Numeric product, one thread per output block (i, l): the sum over the row
+// entries p of A_i whose B row holds column l, in row order, each block
+// product's terms in m order.  The lookups of CH consecutive row entries are
+// issued together (their column, row-range and column loads do not wait on
+// each other).
+template <int BR, int BM, int BC, int CH>
+__global__ __launch_bounds__(128) void k_spgemm_num_c(int64_t nnz, const int32_t* __restrict__ arp,
+                                                      const int32_t* __restrict__ aci,
+                                                      const double* __restrict__ aval,
+                                                      const int32_t* __restrict__ brp,
+                                                      const int32_t* __restrict__ bci,
+                                                      const double* __restrict__ bval,
+                                                      const int32_t* __restrict__ crow,
+                                                      const int32_t* __restrict__ cci, double* __restrict__ cval) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nnz) return;
     const int i = crow[k], l = cci[k];
     double acc[BR * BC];
 #pragma unroll
     for (int e = 0; e < BR * BC; ++e) acc[e] = 0.0;
-    for (int p = arp[i]; p < arp[i + 1]; ++p) {
-        const int j = aci[p];
-        const int q = find_col_short(bci, brp[j], brp[j + 1], l);
-        if (q < 0) continue;
-        double a[BR * BM], bb[BM * BC];
+    const int p0 = arp[i], p1 = arp[i + 1];
+    for (int pb = p0; pb < p1; pb += CH) {
+        int j[CH], lo[CH], hi[CH], q[CH];
 #pragma unroll
-        for (int e = 0; e < BR * BM; ++e) a[e] = aval[(int64_t)p * BR * BM + e];
+        for (int u = 0; u < CH; ++u) j[u] = pb + u < p1 ? aci[pb + u] : -1;
 #pragma unroll
-        for (int e = 0; e < BM * BC; ++e) bb[e] = bval[(int64_t)q * BM * BC + e];
+        for (int u = 0; u < CH; ++u) {
+            lo[u] = j[u] >= 0 ? brp[j[u]] : 0;
+            hi[u] = j[u] >= 0 ? brp[j[u] + 1] : 0;
+        }
 #pragma unroll
-        for (int r = 0; r < BR; ++r)
+        for (int u = 0; u < CH; ++u) q[u] = find_col_short(bci, lo[u], hi[u], l);
 #pragma unroll
-            for (int cc = 0; cc < BC; ++cc)
+        for (int u = 0; u < CH; ++u) {
+            if (q[u] < 0) continue;
+            const int64_t p = pb + u;
+            double a[BR * BM], bb[BM * BC];
 #pragma unroll
-                for (int m = 0; m < BM; ++m) {
-                    double term = a[r * BM + m] * bb[m * BC + cc];
-                    acc[r * BC + cc] = acc[r * BC + cc] + term;
-                }
+            for (int e = 0; e < BR * BM; ++e) a[e] = aval[p * BR * BM + e];
+#pragma unroll
+            for (int e = 0; e < BM * BC; ++e) bb[e] = bval[(int64_t)q[u] * BM * BC + e];
+#pragma unroll
+            for (int r = 0; r < BR; ++r)
+#pragma unroll
+                for (int cc = 0; cc < BC; ++cc)
+#pragma unroll
+                    for (int m = 0; m < BM; ++m) {
+                        double term = a[r * BM + m] * bb[m * BC + cc];
+                        acc[r * BC + cc] = acc[r * BC + cc] + term;
+                    }
+        }
     }
     double* dst = cval + k * BR * BC;
 #pragma unroll
@@ -903,7 +924,7 @@ struct SpgemmVals {
     const double* b[K];
     double* c[K];
 };
-template <int BR, int BM, int BC, int K>
+template <int BR, int BM, int BC, int K, int CH>
 __global__ __launch_bounds__(128) void k_spgemm_num_k(int64_t nnz, const int32_t* __restrict__ arp,
                                                       const int32_t* __restrict__ aci,
                                                       const int32_t* __restrict__ brp,
@@ -918,26 +939,40 @@ __global__ __launch_bounds__(128) void k_spgemm_num_k(int64_t nnz, const int32_t
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int e = 0; e < BR * BC; ++e) acc[k][e] = 0.0;
-    for (int p = arp[i]; p < arp[i + 1]; ++p) {
-        const int j = aci[p];
-        const int q = find_col_short(bci, brp[j], brp[j + 1], l);
-        if (q < 0) continue;
+    const int p0 = arp[i], p1 = arp[i + 1];
+    for (int pb = p0; pb < p1; pb += CH) {
+        // the lookups of CH row entries are issued together, as in k_spgemm_num_c
+        int j[CH], lo[CH], hi[CH], q[CH];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double a[BR * BM], bb[BM * BC];
+        for (int u = 0; u < CH; ++u) j[u] = pb + u < p1 ? aci[pb + u] : -1;
 #pragma unroll
-            for (int e = 0; e < BR * BM; ++e) a[e] = v.a[k][(int64_t)p * BR * BM + e];
+        for (int u = 0; u < CH; ++u) {
+            lo[u] = j[u] >= 0 ? brp[j[u]] : 0;
+            hi[u] = j[u] >= 0 ? brp[j[u] + 1] : 0;
+        }
 #pragma unroll
-            for (int e = 0; e < BM * BC; ++e) bb[e] = v.b[k][(int64_t)q * BM * BC + e];
+        for (int u = 0; u < CH; ++u) q[u] = find_col_short(bci, lo[u], hi[u], l);
 #pragma unroll
-            for (int r = 0; r < BR; ++r)
+        for (int u = 0; u < CH; ++u) {
+            if (q[u] < 0) continue;
+            const int64_t p = pb + u;
 #pragma unroll
-                for (int cc = 0; cc < BC; ++cc)
+            for (int k = 0; k < K; ++k) {
+                double a[BR * BM], bb[BM * BC];
 #pragma unroll
-                    for (int m = 0; m < BM; ++m) {
-                        const double term = a[r * BM + m] * bb[m * BC + cc];
-                        acc[k][r * BC + cc] = acc[k][r * BC + cc] + term;
-                    }
+                for (int e = 0; e < BR * BM; ++e) a[e] = v.a[k][p * BR * BM + e];
+#pragma unroll
+                for (int e = 0; e < BM * BC; ++e) bb[e] = v.b[k][(int64_t)q[u] * BM * BC + e];
+#pragma unroll
+                for (int r = 0; r < BR; ++r)
+#pragma unroll
+                    for (int cc = 0; cc < BC; ++cc)
+#pragma unroll
+                        for (int m = 0; m < BM; ++m) {
+                            const double term = a[r * BM + m] * bb[m * BC + cc];
+                            acc[k][r * BC + cc] = acc[k][r * BC + cc] + term;
+                        }
+            }
         }
     }
 #pragma unroll
@@ -1937,12 +1972,30 @@ bool same_pattern(const SetupBsr& X, const SetupBsr& Y, hipStream_t s) {
 // column searches)
 constexpr int64_t SPGEMM_ENTRY_MAX = (int64_t)1 << 15;
 
+template <int BR, int BM, int BC>
+static void num_chunked(int chunk, unsigned g, int64_t z, const SetupBsr& A, const SetupBsr& B, SetupBsr& C,
+                        const int32_t* crow, hipStream_t s) {
+    if (chunk == 1)
+        k_spgemm_num_c<BR, BM, BC, 1><<<g, 128, 0, s>>>(z, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, crow,
+                                                        C.ci.p, C.val.p);
+    else if (chunk == 2)
+        k_spgemm_num_c<BR, BM, BC, 2><<<g, 128, 0, s>>>(z, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, crow,
+                                                        C.ci.p, C.val.p);
+    else
+        k_spgemm_num_c<BR, BM, BC, 4><<<g, 128, 0, s>>>(z, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, crow,
+                                                        C.ci.p, C.val.p);
+}
+
 static void spgemm_values(const SetupBsr& A, const SetupBsr& B, SetupBsr& C, const int32_t* crow, hipStream_t s) {
     if (C.nnzb == 0) return;
     const unsigned g = grid_for(C.nnzb, 128);
     const int64_t z = C.nnzb;
     bool entry = z < SPGEMM_ENTRY_MAX;
-    if (const char* f = form_override("MBAMG_SPGEMM_FORM")) entry = std::strcmp(f, "entry") == 0;
+    int chunk = 4;   // measured: lookups of 4 row entries at once beat 1 and 2
+    if (const char* f = form_override("MBAMG_SPGEMM_FORM")) {
+        entry = std::strcmp(f, "entry") == 0;
+        chunk = std::strcmp(f, "chunk2") == 0 ? 2 : std::strcmp(f, "block") == 0 ? 1 : 4;
+    }
     const unsigned ge = grid_for(z * 16, 256);
     if (entry && A.br == 4 && A.bc == 4 && B.bc == 4)
         k_spgemm_num_e<4, 4, 4><<<ge, 256, 0, s>>>(z, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, crow, C.ci.p,
@@ -1951,11 +2004,9 @@ static void spgemm_values(const SetupBsr& A, const SetupBsr& B, SetupBsr& C, con
         k_spgemm_num_e<3, 3, 3><<<ge, 256, 0, s>>>(z, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, crow, C.ci.p,
                                                   C.val.p);
     else if (A.br == 4 && A.bc == 4 && B.bc == 4)
-        k_spgemm_num<4, 4, 4><<<g, 128, 0, s>>>(z, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, crow, C.ci.p,
-                                                C.val.p);
+        num_chunked<4, 4, 4>(chunk, g, z, A, B, C, crow, s);
     else if (A.br == 3 && A.bc == 3 && B.bc == 3)
-        k_spgemm_num<3, 3, 3><<<g, 128, 0, s>>>(z, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p, crow, C.ci.p,
-                                                C.val.p);
+        num_chunked<3, 3, 3>(chunk, g, z, A, B, C, crow, s);
     else
         k_spgemm_num_any<<<g, 128, 0, s>>>(z, A.br, A.bc, B.bc, A.rp.p, A.ci.p, A.val.p, B.rp.p, B.ci.p, B.val.p,
                                            crow, C.ci.p, C.val.p);
@@ -2063,8 +2114,10 @@ static void launch_num_k(const SetupBsr* const* A, const SetupBsr* const* B, Set
         k_spgemm_num_ek<BR, BM, BC, K><<<grid_for(z * 16, 256), 256, 0, s>>>(z, A0.rp.p, A0.ci.p, B0.rp.p, B0.ci.p,
                                                                             crow, C[0]->ci.p, v);
     else
-        k_spgemm_num_k<BR, BM, BC, K><<<grid_for(z, 128), 128, 0, s>>>(z, A0.rp.p, A0.ci.p, B0.rp.p, B0.ci.p, crow,
-                                                                      C[0]->ci.p, v);
+        // one lookup at a time here: the K accumulators leave no room for more (measured
+        // slower with two)
+        k_spgemm_num_k<BR, BM, BC, K, 1><<<grid_for(z, 128), 128, 0, s>>>(z, A0.rp.p, A0.ci.p, B0.rp.p, B0.ci.p,
+                                                                         crow, C[0]->ci.p, v);
     MB_LAUNCH_CHECK();
 }
 

@@ -31,6 +31,7 @@ CASES = {
 
 FORMS = [("MBAMG_SA_FORM", "thread"), ("MBAMG_SA_FORM", "wave"), ("MBAMG_SA_FORM", "generic"),
          ("MBAMG_SPGEMM_FORM", "block"), ("MBAMG_SPGEMM_FORM", "entry"), ("MBAMG_SPGEMM_FORM", "fused"),
+         ("MBAMG_SPGEMM_FORM", "chunk2"), ("MBAMG_SPGEMM_FORM", "chunk4"),
          ("MBAMG_SORT_FORM", "thread"), ("MBAMG_SORT_FORM", "wave"),
          ("MBAMG_SYM_FORM", "thread"), ("MBAMG_SYM_FORM", "wave")]
 
