@@ -797,25 +797,60 @@ __global__ __launch_bounds__(128) void k_spgemm_sym_t(int n, const int32_t* __re
 }
 
 // Pattern of C = A B: pass 0 counts each row's distinct columns, pass 1
-// writes them in increasing order.
+// writes them in increasing order.  The candidates (the columns of the B rows
+// named by the row of A) are enumerated flat: for up to 64 entries of the A
+// row at a time, every lane fetches one entry's B row range, a wavefront scan
+// of the range lengths places them end to end, and each lane then takes every
+// 64th candidate, so the loads of all the B rows are in flight together.
 __global__ __launch_bounds__(WAVE) void k_spgemm_sym(const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
                                                      const int32_t* __restrict__ brp, const int32_t* __restrict__ bci,
                                                      int pass, int32_t* cnt, const int32_t* crp, int32_t* cci,
                                                      int32_t* overflow) {
     __shared__ KeySet S;
+    __shared__ int32_t s_start[WAVE], s_base[WAVE];
     const int i = blockIdx.x, lane = threadIdx.x;
     const int ab = arp[i], ae = arp[i + 1];
     int64_t cand = 0;
-    for (int p = ab; p < ae; ++p) {
-        const int j = aci[p];
-        cand += brp[j + 1] - brp[j];
+    for (int c0 = ab; c0 < ae; c0 += WAVE) {
+        const int p = c0 + lane;
+        int len = 0;
+        if (p < ae) {
+            const int j = aci[p];
+            len = brp[j + 1] - brp[j];
+        }
+        for (int off = WAVE / 2; off > 0; off >>= 1) len += __shfl_xor(len, off);
+        cand += len;
     }
     ks_clear(S, lane, cand);
-    for (int p = ab; p < ae; ++p) {
-        const int j = aci[p];
-        for (int q = brp[j] + lane; q < brp[j + 1]; q += WAVE) ks_insert(S, bci[q]);
+    for (int c0 = ab; c0 < ae; c0 += WAVE) {
+        const int p = c0 + lane;
+        int b0 = 0, len = 0;
+        if (p < ae) {
+            const int j = aci[p];
+            b0 = brp[j];
+            len = brp[j + 1] - b0;
+        }
+        int incl = len;   // inclusive scan of the lengths over the lanes
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const int v = __shfl_up(incl, off);
+            if (lane >= off) incl += v;
+        }
+        const int total = __shfl(incl, WAVE - 1);
+        s_start[lane] = incl - len;
+        s_base[lane] = b0;
+        __syncthreads();
+        for (int t = lane; t < total; t += WAVE) {
+            // the entry whose range holds candidate t: the last one starting at or before t
+            int lo = 0, hi = WAVE - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_start[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            ks_insert(S, bci[s_base[lo] + (t - s_start[lo])]);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const int K = ks_count(S);
     if (K < 0) {
         if (lane == 0) {
