@@ -822,10 +822,14 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
         if (want32) alloc_vecs(c.v32, (int64_t)c.n * (d0 + d1));
     }
 
-    // smoother format on every other level, coarsest first (transfer maps need the next level's order)
-    for (int l = (int)h->L.size() - 2; l >= 0; --l) {
+    // smoother format on every other level, in two rounds: first each level's own smoother
+    // blocks (its colouring, order and parts), then the transfers, which need the next
+    // level's order.  A build that lends its level 0 does that level first and publishes
+    // it at once; a build that borrows it does it last.
+    const int n_fine_levels = (int)h->L.size() - 1;
+    for (int k = 0; k < n_fine_levels; ++k) {
+        const int l = to ? k : n_fine_levels - 1 - k;
         Level& Lv = *h->L[l];
-        Level& Nx = *h->L[l + 1];
         bool shared = l == 0 && donor0 != nullptr && from->smooth.get();
         if (shared) {
             MB_HIP(hipStreamWaitEvent(s, from->smooth_ev, 0));
@@ -926,6 +930,15 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
                              "split %d\n", l, f, Lv.n, B.n_colours, B.n_slices, avg_width, B.split);
         }
         clk.mark("sliced parts", l);
+        if (l == 0 && to && to->agg_set) {   // level 0's smoother blocks are complete on s
+            MB_HIP(hipEventRecord(to->smooth_ev, s));
+            to->publish_smooth(true);
+        }
+        MB_HIP(hipStreamSynchronize(s));
+    }
+    for (int l = n_fine_levels - 1; l >= 0; --l) {
+        Level& Lv = *h->L[l];
+        Level& Nx = *h->L[l + 1];
         // transfers between this level's and the next level's colour orders
         for (int f = 0; f < 2 && Lv.smoothed; ++f) {
             BlockLevel& B = Lv.blk[f];
@@ -963,10 +976,6 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
     }
 
     clk.mark("smoother data done", 0);
-    if (to && to->agg_set && h->L.size() > 1) {   // level 0's smoother data is complete on s
-        MB_HIP(hipEventRecord(to->smooth_ev, s));
-        to->publish_smooth(true);
-    }
     if (!defer_coarse) {
         finish_coarse(h, s);
         clk.mark("coarse inverse joined", 0);
