@@ -103,8 +103,11 @@ int scan_exclusive(const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
 // Kernel-form overrides for tests: every form computes the same sums in the
 // same order, so a hierarchy must come out bit-identical under each.
 //   MBAMG_SA_FORM     = thread | wave | generic   (smoothed prolongator)
-//   MBAMG_SPGEMM_FORM = block | entry | fused      (numeric Galerkin product; fused:
-//                                                   one launch for every group of pairs)
+//   MBAMG_SPGEMM_FORM = block | chunk2 | chunk4 | entry | fused
+//                                                  (numeric Galerkin product: thread per
+//                                                   output block with 1, 2 or 4 lookups
+//                                                   in flight, lane per entry, or one
+//                                                   launch for every group of pairs)
 //   MBAMG_SORT_FORM   = thread | wave              (aggregate member lists)
 //   MBAMG_SYM_FORM    = thread | wave              (product pattern)
 //   MBAMG_ROWS_FORM   = rows | sliced              (coarse-level smoother layout;
