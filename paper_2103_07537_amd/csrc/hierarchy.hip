@@ -78,6 +78,7 @@ struct BlockLevel {
     // smoothed transfers: P rows of this level, P^T rows of the next level (sliced by the next level)
     SellPart pro, res;
     int pro_split = 1, res_split = 1;          // waves per slice in the transfer kernels
+    int res_group = 4;                         // lanes per coarse row in the tentative restriction
     // coarse levels with long rows: the smoother and residual run on the row form
     bool rows = false;
     RowPart raff, rafg;
@@ -386,6 +387,19 @@ static int slot_split(double slices, double width, double target = 2048) {
 }
 
 // a transfer is one launch over the whole level (both block rows), not one colour
+// lanes per coarse row in the tentative restriction: about two members per lane
+// (MBAMG_RESTRICT_GROUP = 4 | 8 | 16 | 64 forces one, for tests: the group
+// size changes the summation order)
+static int restrict_group(int n_fine, int n_coarse) {
+    if (const char* f = form_override("MBAMG_RESTRICT_GROUP")) {
+        const int g = std::atoi(f);
+        MB_CHECK(g == 4 || g == 8 || g == 16 || g == 64, MBAMG_E_INVALID, "MBAMG_RESTRICT_GROUP must be 4, 8, 16 or 64");
+        return g;
+    }
+    const int64_t m = n_coarse > 0 ? ceil_div(n_fine, n_coarse) : 1;
+    return m <= 8 ? 4 : m <= 16 ? 8 : m <= 32 ? 16 : 64;
+}
+
 static int transfer_split(const SellPart& P, int n_slices) {
     int64_t slots = 0;
     for (int w : P.h_width) slots += w;
@@ -962,6 +976,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
             const BlockLevel& C = Nx.blk[f];
             transfer_maps(Lv.n, Nx.n, B.d_perm.p, B.d_iperm.p, Lv.G.agg.p, C.d_perm.p, C.d_iperm.p, Lv.G.mptr.p,
                           Lv.G.midx.p, B.agg_p, B.mem_ptr, B.mem_idx, s);
+            B.res_group = restrict_group(Lv.n, Nx.n);
             DevBuf<double> qp((size_t)Lv.n * B.d);
             launch_gather(Lv.n, B.d, B.d_perm.p, B.q64.p, qp.p, s);
             B.q64 = std::move(qp);
@@ -1231,7 +1246,7 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
             a.in[f] = V.r.p + (f ? n0 : 0);
             a.out[f] = C.b.p + (f ? nc0 : 0);
         }
-        launch_restrict<T>(Lv.d[0], a, Nx.n > 0 ? (int)ceil_div((int64_t)Lv.n, Nx.n) : 1, s);
+        launch_restrict<T>(Lv.d[0], a, Lv.blk[0].res_group, s);
     }
     vcycle_level<T>(h, l + 1, C.b.p, C.x.p, s);
     if (Lv.smoothed) {

@@ -123,7 +123,8 @@ template <class T>
 void launch_resid_rows(int d, const ResidRowArgs<T>& a, hipStream_t s);
 
 template <class T>
-void launch_restrict(int d, const TransferArgs<T>& a, int members_per_row, hipStream_t s);
+// G: lanes per coarse row (4, 8, 16 or 64)
+void launch_restrict(int d, const TransferArgs<T>& a, int G, hipStream_t s);
 template <class T>
 void launch_prolong(int d, const TransferArgs<T>& a, hipStream_t s);
 template <class T>

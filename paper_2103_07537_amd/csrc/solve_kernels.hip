@@ -793,11 +793,10 @@ static void restrict_dispatch(int64_t total, int G, const TransferArgs<T>& a, hi
 }
 
 template <class T>
-void launch_restrict(int d, const TransferArgs<T>& a, int members_per_row, hipStream_t s) {
+void launch_restrict(int d, const TransferArgs<T>& a, int G, hipStream_t s) {
     const int64_t total = (int64_t)a.n_rows[0] + a.n_rows[1];
     if (total <= 0) return;
-    // about two members per lane
-    const int G = members_per_row <= 8 ? 4 : members_per_row <= 16 ? 8 : members_per_row <= 32 ? 16 : 64;
+    MB_CHECK(G == 4 || G == 8 || G == 16 || G == 64, MBAMG_E_INVALID, "restriction group of 4, 8, 16 or 64 lanes");
     switch (d) {
         case 1: restrict_dispatch<T, 1>(total, G, a, s); break;
         case 2: restrict_dispatch<T, 2>(total, G, a, s); break;

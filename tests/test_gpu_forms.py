@@ -4,11 +4,16 @@ choice (which the oracle tests pin):
 
 - smoothed prolongator: one thread per row with the row in registers, the
   generic one-thread form, one wavefront per row;
-- numeric Galerkin product: one thread per output block, one lane per entry,
-  one launch for the block pairs that share their patterns;
+- numeric Galerkin product: one thread per output block (with 1, 2 or 4 row
+  entries' lookups in flight), one lane per entry, one launch for the block
+  pairs that share their patterns;
 - aggregate member lists: one lane per aggregate, one wavefront per aggregate;
 - product pattern: one thread per row (registers), one wavefront per row (LDS
   hash set); a forced thread form falls back where a row overflows.
+
+The solve-phase forms that change the summation order (the row form of the
+coarse-level smoother, the restriction's lane-group size) are pinned to the
+oracle's V-cycle instead.
 """
 import numpy as np
 import pytest
@@ -107,4 +112,27 @@ def test_row_form_matches_oracle(case, precision, monkeypatch):
     A = s.to_scipy()
     assert info["converged"]
     assert np.linalg.norm(s.b - A @ x.cpu().numpy()) <= 1e-8 * np.linalg.norm(s.b) * (1 + 1e-6)
+    hg.close()
+
+
+# The tentative restriction gives each coarse row a group of 4, 8, 16 or 64
+# lanes and adds the group's partial sums in a tree, so each group size sums
+# in its own order: every one is pinned to the oracle's V-cycle (FP64, 1e-12),
+# including the sizes the test systems' aggregates would not select.
+@pytest.mark.parametrize("group", [4, 8, 16, 64])
+def test_restriction_groups_match_oracle(group, monkeypatch):
+    from oracle import amg
+    from gpu_util import rel, torch_dev
+    s = make_system(11, 3, 2.0, seed=5, kappa="lognormal")
+    ho = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=60), n_vec=s.n_vec)
+    monkeypatch.setenv("MBAMG_RESTRICT_GROUP", str(group))
+    hg = gpu_hierarchy(s, max_coarse=60)
+    log(f"group={group} levels={hg.num_levels()}")
+    assert hg.num_levels() == len(ho.levels) >= 3
+    r = np.random.default_rng(8).standard_normal(s.n_dofs)
+    z = torch_dev(np.zeros(s.n_dofs))
+    hg.vcycle(torch_dev(r), z)
+    e = rel(z.cpu().numpy(), amg.vcycle(ho, r))
+    log(f"  vcycle rel {e:.2e}")
+    assert e <= 1e-12
     hg.close()
