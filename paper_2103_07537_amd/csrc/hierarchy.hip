@@ -508,14 +508,19 @@ static void choose_weights(mbamg_hierarchy* h, Level& cur, const Aggregates& G, 
 // are copied on a stream of the calling thread.
 static void colour_level(Level& Lv, hipEvent_t ready, int device) {
     MB_HIP(hipSetDevice(device));   // the calling thread may be a fresh one
+    const bool verbose = std::getenv("MBAMG_VERBOSE") != nullptr;
+    using clock = std::chrono::steady_clock;
+    const auto t0 = clock::now();
     hipStream_t cs = nullptr;
     MB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     std::vector<int32_t> rp[2], ci[2];
     bool same = false;
+    auto t1 = t0, t2 = t0;
     try {
         MB_HIP(hipStreamWaitEvent(cs, ready, 0));
         // block 1's pattern is compared on the device and copied only when it differs
         same = same_pattern(Lv.A[0][0], Lv.A[1][1], cs);
+        t1 = clock::now();
         for (int f = 0; f < (same ? 1 : 2); ++f) {
             rp[f].resize((size_t)Lv.n + 1);
             ci[f].resize((size_t)Lv.A[f][f].nnzb);
@@ -526,11 +531,26 @@ static void colour_level(Level& Lv, hipEvent_t ready, int device) {
                                       hipMemcpyDeviceToHost, cs));
         }
         MB_HIP(hipStreamSynchronize(cs));
+        t2 = clock::now();
     } catch (...) {
         (void)hipStreamDestroy(cs);
         throw;
     }
     (void)hipStreamDestroy(cs);
+    struct Report {   // host time of the job's steps, printed when it ends
+        bool on;
+        int n;
+        clock::time_point t0, t1, t2;
+        ~Report() {
+            if (!on) return;
+            const auto t3 = clock::now();
+            auto ms = [](clock::time_point a, clock::time_point b) {
+                return std::chrono::duration<double, std::milli>(b - a).count();
+            };
+            std::fprintf(stderr, "[mbamg setup] colouring job, %d nodes: wait+compare %.2f ms, copy %.2f ms, "
+                         "colour %.2f ms\n", n, ms(t0, t1), ms(t1, t2), ms(t2, t3));
+        }
+    } report{verbose, Lv.n, t0, t1, t2};
     for (int f = 0; f < 2; ++f) {
         BlockLevel& B = Lv.blk[f];
         B.d = Lv.d[f];
