@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <numeric>
 
 #include "learned_kernels.h"
@@ -325,8 +326,7 @@ static void copy_block(const mbamg_bsr& src, SetupBsr& dst, int n_rows, int n_co
 }
 
 // First-fit greedy colouring in increasing node order over the (symmetric) pattern.
-static int greedy_colour(int n, const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
-                         std::vector<int32_t>& colour) {
+static int greedy_colour(int n, const int32_t* rp, const int32_t* ci, std::vector<int32_t>& colour) {
     colour.assign(n, -1);
     std::vector<int32_t> mark(64, -1);
     int ncol = 0;
@@ -502,6 +502,54 @@ static void choose_weights(mbamg_hierarchy* h, Level& cur, const Aggregates& G, 
     cur.damped = true;
 }
 
+// Page-locked host buffers for the colouring jobs' pattern copies: a copy into
+// pageable memory is staged by the runtime and ran at 1.6-2.6 GB/s here.  The
+// buffers are kept for the life of the process and handed out one per job.
+class PinnedPool {
+  public:
+    void* take(size_t bytes) {
+        {
+            std::lock_guard<std::mutex> g(m_);
+            size_t best = free_.size();
+            for (size_t k = 0; k < free_.size(); ++k)
+                if (free_[k].second >= bytes && (best == free_.size() || free_[k].second < free_[best].second))
+                    best = k;
+            if (best < free_.size()) {
+                void* p = free_[best].first;
+                size_[p] = free_[best].second;
+                free_.erase(free_.begin() + (std::ptrdiff_t)best);
+                return p;
+            }
+        }
+        void* p = nullptr;
+        MB_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+        std::lock_guard<std::mutex> g(m_);
+        size_[p] = bytes;
+        return p;
+    }
+    void give(void* p) {
+        std::lock_guard<std::mutex> g(m_);
+        free_.emplace_back(p, size_[p]);
+        size_.erase(p);
+    }
+
+  private:
+    std::mutex m_;
+    std::vector<std::pair<void*, size_t>> free_;
+    std::map<void*, size_t> size_;
+};
+static PinnedPool& pinned_pool() {
+    static PinnedPool* pool = new PinnedPool();   // never destroyed: its buffers outlive every job
+    return *pool;
+}
+struct PinnedBuf {
+    int32_t* p = nullptr;
+    explicit PinnedBuf(size_t n_int) : p((int32_t*)pinned_pool().take(std::max<size_t>(n_int, 1) * sizeof(int32_t))) {}
+    ~PinnedBuf() { pinned_pool().give(p); }
+    PinnedBuf(const PinnedBuf&) = delete;
+    PinnedBuf& operator=(const PinnedBuf&) = delete;
+};
+
 // First-fit colouring, colour order and slices of both block rows of one level
 // (host work on the diagonal blocks' patterns).  `ready` marks the point on
 // the setup stream after which the level's blocks are complete; the patterns
@@ -513,7 +561,9 @@ static void colour_level(Level& Lv, hipEvent_t ready, int device) {
     const auto t0 = clock::now();
     hipStream_t cs = nullptr;
     MB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    std::vector<int32_t> rp[2], ci[2];
+    std::unique_ptr<PinnedBuf> buf[2];
+    const int32_t* rp[2] = {nullptr, nullptr};
+    const int32_t* ci[2] = {nullptr, nullptr};
     bool same = false;
     auto t1 = t0, t2 = t0;
     try {
@@ -522,17 +572,18 @@ static void colour_level(Level& Lv, hipEvent_t ready, int device) {
         same = same_pattern(Lv.A[0][0], Lv.A[1][1], cs);
         t1 = clock::now();
         for (int f = 0; f < (same ? 1 : 2); ++f) {
-            rp[f].resize((size_t)Lv.n + 1);
-            ci[f].resize((size_t)Lv.A[f][f].nnzb);
-            MB_HIP(hipMemcpyAsync(rp[f].data(), Lv.A[f][f].rp.p, sizeof(int32_t) * rp[f].size(),
-                                  hipMemcpyDeviceToHost, cs));
-            if (!ci[f].empty())
-                MB_HIP(hipMemcpyAsync(ci[f].data(), Lv.A[f][f].ci.p, sizeof(int32_t) * ci[f].size(),
-                                      hipMemcpyDeviceToHost, cs));
+            const size_t nrp = (size_t)Lv.n + 1, nci = (size_t)Lv.A[f][f].nnzb;
+            buf[f] = std::make_unique<PinnedBuf>(nrp + nci);
+            int32_t* h = buf[f]->p;
+            rp[f] = h;
+            ci[f] = h + nrp;
+            MB_HIP(hipMemcpyAsync(h, Lv.A[f][f].rp.p, sizeof(int32_t) * nrp, hipMemcpyDeviceToHost, cs));
+            if (nci) MB_HIP(hipMemcpyAsync(h + nrp, Lv.A[f][f].ci.p, sizeof(int32_t) * nci, hipMemcpyDeviceToHost, cs));
         }
         MB_HIP(hipStreamSynchronize(cs));
         t2 = clock::now();
     } catch (...) {
+        (void)hipStreamSynchronize(cs);   // no copy may still write into a buffer going back to the pool
         (void)hipStreamDestroy(cs);
         throw;
     }

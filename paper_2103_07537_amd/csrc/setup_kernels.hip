@@ -1132,15 +1132,17 @@ __global__ void k_spgemm_num_any(int64_t nnz, int br, int bm, int bc, const int3
     for (int e = 0; e < br * bc; ++e) dst[e] = acc[e];
 }
 
-// flag (initially 1) is cleared when the two patterns differ in any row
-__global__ void k_same_pattern(int n, const int32_t* __restrict__ rpa, const int32_t* __restrict__ cia,
-                               const int32_t* __restrict__ rpb, const int32_t* __restrict__ cib, int32_t* flag) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int a0 = rpa[i], a1 = rpa[i + 1];
-    bool same = a0 == rpb[i] && a1 == rpb[i + 1];
-    for (int p = a0; same && p < a1; ++p) same = cia[p] == cib[p];
-    if (!same) atomicAnd(flag, 0);
+// flag (initially 1) is cleared when two index arrays of equal length differ
+// anywhere: row pointers and then columns, one element per thread (grid-stride,
+// coalesced), one atomic per wavefront that found a difference
+__global__ void k_same_pattern(int64_t n_rp, int64_t n_ci, const int32_t* __restrict__ rpa,
+                               const int32_t* __restrict__ cia, const int32_t* __restrict__ rpb,
+                               const int32_t* __restrict__ cib, int32_t* flag) {
+    bool diff = false;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_rp + n_ci; t += stride)
+        diff |= t < n_rp ? rpa[t] != rpb[t] : cia[t - n_rp] != cib[t - n_rp];
+    if (__ballot(diff) != 0 && (threadIdx.x & (WAVE - 1)) == 0) atomicAnd(flag, 0);
 }
 
 // One wavefront per row (long rows, at most SA_WROW entries and KS_MAX
@@ -2000,7 +2002,9 @@ bool same_pattern(const SetupBsr& X, const SetupBsr& Y, hipStream_t s) {
     DevBuf<int32_t> flag(1);
     const std::vector<int32_t> one(1, 1);
     flag.upload(one, s);
-    k_same_pattern<<<grid_for(X.n_rows), 256, 0, s>>>(X.n_rows, X.rp.p, X.ci.p, Y.rp.p, Y.ci.p, flag.p);
+    const int64_t total = (int64_t)X.n_rows + 1 + X.nnzb;
+    k_same_pattern<<<(unsigned)std::min<int64_t>(4096, ceil_div(total, 256)), 256, 0, s>>>(
+        (int64_t)X.n_rows + 1, X.nnzb, X.rp.p, X.ci.p, Y.rp.p, Y.ci.p, flag.p);
     MB_LAUNCH_CHECK();
     return flag.download(s, 1)[0] != 0;
 }
