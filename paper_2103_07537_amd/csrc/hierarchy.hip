@@ -12,7 +12,6 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
-#include <mutex>
 #include <numeric>
 
 #include "learned_kernels.h"
@@ -502,53 +501,6 @@ static void choose_weights(mbamg_hierarchy* h, Level& cur, const Aggregates& G, 
     cur.damped = true;
 }
 
-// Page-locked host buffers for the colouring jobs' pattern copies: a copy into
-// pageable memory is staged by the runtime and ran at 1.6-2.6 GB/s here.  The
-// buffers are kept for the life of the process and handed out one per job.
-class PinnedPool {
-  public:
-    void* take(size_t bytes) {
-        {
-            std::lock_guard<std::mutex> g(m_);
-            size_t best = free_.size();
-            for (size_t k = 0; k < free_.size(); ++k)
-                if (free_[k].second >= bytes && (best == free_.size() || free_[k].second < free_[best].second))
-                    best = k;
-            if (best < free_.size()) {
-                void* p = free_[best].first;
-                size_[p] = free_[best].second;
-                free_.erase(free_.begin() + (std::ptrdiff_t)best);
-                return p;
-            }
-        }
-        void* p = nullptr;
-        MB_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
-        std::lock_guard<std::mutex> g(m_);
-        size_[p] = bytes;
-        return p;
-    }
-    void give(void* p) {
-        std::lock_guard<std::mutex> g(m_);
-        free_.emplace_back(p, size_[p]);
-        size_.erase(p);
-    }
-
-  private:
-    std::mutex m_;
-    std::vector<std::pair<void*, size_t>> free_;
-    std::map<void*, size_t> size_;
-};
-static PinnedPool& pinned_pool() {
-    static PinnedPool* pool = new PinnedPool();   // never destroyed: its buffers outlive every job
-    return *pool;
-}
-struct PinnedBuf {
-    int32_t* p = nullptr;
-    explicit PinnedBuf(size_t n_int) : p((int32_t*)pinned_pool().take(std::max<size_t>(n_int, 1) * sizeof(int32_t))) {}
-    ~PinnedBuf() { pinned_pool().give(p); }
-    PinnedBuf(const PinnedBuf&) = delete;
-    PinnedBuf& operator=(const PinnedBuf&) = delete;
-};
 
 // First-fit colouring, colour order and slices of both block rows of one level
 // (host work on the diagonal blocks' patterns).  `ready` marks the point on
@@ -561,7 +513,7 @@ static void colour_level(Level& Lv, hipEvent_t ready, int device) {
     const auto t0 = clock::now();
     hipStream_t cs = nullptr;
     MB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    std::unique_ptr<PinnedBuf> buf[2];
+    std::unique_ptr<PinnedBuf<int32_t>> buf[2];
     const int32_t* rp[2] = {nullptr, nullptr};
     const int32_t* ci[2] = {nullptr, nullptr};
     bool same = false;
@@ -573,7 +525,7 @@ static void colour_level(Level& Lv, hipEvent_t ready, int device) {
         t1 = clock::now();
         for (int f = 0; f < (same ? 1 : 2); ++f) {
             const size_t nrp = (size_t)Lv.n + 1, nci = (size_t)Lv.A[f][f].nnzb;
-            buf[f] = std::make_unique<PinnedBuf>(nrp + nci);
+            buf[f] = std::make_unique<PinnedBuf<int32_t>>(nrp + nci);
             int32_t* h = buf[f]->p;
             rp[f] = h;
             ci[f] = h + nrp;

@@ -111,6 +111,51 @@ void dev_free(void* p, size_t bytes) {
 }
 
 // the current device has been synchronised: its pending blocks are idle
+namespace {
+struct PinnedPool {
+    std::mutex m;
+    std::vector<std::pair<void*, size_t>> free_list;   // buffers not handed out
+    std::unordered_map<void*, size_t> taken;
+};
+PinnedPool& pinned_pool() {
+    static PinnedPool* pool = new PinnedPool();   // never destroyed: its buffers live as long as the process
+    return *pool;
+}
+}  // namespace
+
+void* pinned_take(size_t bytes) {
+    PinnedPool& P = pinned_pool();
+    {
+        std::lock_guard<std::mutex> g(P.m);
+        size_t best = P.free_list.size();
+        for (size_t k = 0; k < P.free_list.size(); ++k)
+            if (P.free_list[k].second >= bytes &&
+                (best == P.free_list.size() || P.free_list[k].second < P.free_list[best].second))
+                best = k;
+        if (best < P.free_list.size()) {
+            const auto e = P.free_list[best];
+            P.free_list.erase(P.free_list.begin() + (std::ptrdiff_t)best);
+            P.taken[e.first] = e.second;
+            return e.first;
+        }
+    }
+    void* p = nullptr;
+    MB_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+    std::lock_guard<std::mutex> g(P.m);
+    P.taken[p] = bytes;
+    return p;
+}
+
+void pinned_give(void* p) {
+    if (!p) return;
+    PinnedPool& P = pinned_pool();
+    std::lock_guard<std::mutex> g(P.m);
+    const auto it = P.taken.find(p);
+    if (it == P.taken.end()) return;
+    P.free_list.emplace_back(p, it->second);
+    P.taken.erase(it);
+}
+
 void pool_device_idle() {
     const int dev = current_device();
     std::lock_guard<std::mutex> g(pool().m);
