@@ -116,7 +116,10 @@ struct PinnedPool {
     std::mutex m;
     std::vector<std::pair<void*, size_t>> free_list;   // buffers not handed out
     std::unordered_map<void*, size_t> taken;
+    size_t total = 0;                                    // bytes held, free or taken
 };
+// above this many pinned bytes, idle buffers are released before a new one is made
+constexpr size_t PINNED_POOL_CAP = (size_t)1 << 30;
 PinnedPool& pinned_pool() {
     static PinnedPool* pool = new PinnedPool();   // never destroyed: its buffers live as long as the process
     return *pool;
@@ -139,10 +142,20 @@ void* pinned_take(size_t bytes) {
             return e.first;
         }
     }
+    std::vector<std::pair<void*, size_t>> drop;
+    {
+        std::lock_guard<std::mutex> g(P.m);
+        if (P.total + bytes > PINNED_POOL_CAP) {
+            drop.swap(P.free_list);
+            for (const auto& e : drop) P.total -= e.second;
+        }
+    }
+    for (const auto& e : drop) (void)hipHostFree(e.first);
     void* p = nullptr;
     MB_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
     std::lock_guard<std::mutex> g(P.m);
     P.taken[p] = bytes;
+    P.total += bytes;
     return p;
 }
 
