@@ -93,6 +93,8 @@ class Params:
     seed: int = 0               # aggregation priority seed
     omega_p: float = 0.0        # uniform prolongator-smoothing weight (0: piecewise constant P)
     weights: object = None      # callable(level, n_agg, features) -> (omega_p[n_agg], omega_s[n_agg])
+    smoother: int = 0           # 0: block Gauss-Seidel over the two blocks (Algorithm 1);
+                                # 1: nodal-block Gauss-Seidel over the full node blocks (FC-AMG analogue)
 
 
 @dataclasses.dataclass
@@ -126,6 +128,8 @@ class Level:
     n_colours: list = None
     dinv: list = None           # per block (n, d, d)
     gs: list = None             # per block: list over colours of (rows, off-diag rows, Dinv)
+    fc: list = None             # full node blocks: list over colours of (rows, off-node-block rows, Dinv)
+    fc_colour: np.ndarray = None
     omega_s: np.ndarray = None  # per-node smoother damping (None: Params.omega)
     omega_p: np.ndarray = None  # per-aggregate prolongator-smoothing weights used for P
     features: np.ndarray = None
@@ -308,6 +312,73 @@ def _prepare_gs(lev: Level, f: int):
     return out
 
 
+def _node_dofs(lev: Level, nodes: np.ndarray) -> np.ndarray:
+    """Indices of the nodes' dofs in the full vector [field 0 | field 1], node
+    by node (field 0's dofs, then field 1's)."""
+    d0, d1 = lev.dofs
+    nodes = np.asarray(nodes)
+    i0 = nodes[:, None] * d0 + np.arange(d0)[None, :]
+    i1 = lev.n * d0 + nodes[:, None] * d1 + np.arange(d1)[None, :]
+    return np.concatenate([i0, i1], axis=1).reshape(-1)
+
+
+def fc_colouring(lev: Level):
+    """First-fit greedy colours in increasing node order over the union of the
+    four blocks' node graphs (symmetrised): nodes of one colour share no block
+    of any A_fg."""
+    n = lev.n
+    rows, cols = [], []
+    for f in range(2):
+        for g in range(2):
+            A = lev.A[f][g]
+            rows.append(np.repeat(np.arange(n), np.diff(A.rp)))
+            cols.append(np.asarray(A.ci))
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    M = sp.csr_matrix((np.ones(r.shape[0]), (r, c)), shape=(n, n))
+    M = (M + M.T).tocsr()
+    M.sum_duplicates()
+    M.sort_indices()
+    col = np.zeros(n, dtype=np.int32)
+    nc = _load().or_colour(n, M.indptr.astype(np.int32), M.indices.astype(np.int32), col)
+    return col, nc
+
+
+def node_blocks(lev: Level) -> np.ndarray:
+    """Full node-diagonal blocks D_i = [[A00_ii, A01_ii], [A10_ii, A11_ii]]."""
+    d0, d1 = lev.dofs
+    D = np.zeros((lev.n, d0 + d1, d0 + d1))
+    for f, (a, b) in enumerate(((0, d0), (d0, d0 + d1))):
+        for g, (c, e) in enumerate(((0, d0), (d0, d0 + d1))):
+            A = lev.A[f][g]
+            rows = np.repeat(np.arange(lev.n), np.diff(A.rp))
+            m = rows == A.ci
+            D[rows[m], a:b, c:e] = A.val[m]
+    return D
+
+
+def _prepare_fc(lev: Level):
+    """Per colour of the full node graph: the dofs of its nodes, the rows of
+    the full operator without the node-diagonal blocks, and the inverses of
+    the full node blocks (block diagonal over the colour's nodes)."""
+    Afull = sp.bmat([[lev.csr[0][0], lev.csr[0][1]], [lev.csr[1][0], lev.csr[1][1]]]).tocsr()
+    D = node_blocks(lev)
+    m = D.shape[1]
+    idx = _node_dofs(lev, np.arange(lev.n)).reshape(lev.n, m)
+    r = np.repeat(idx[:, :, None], m, axis=2).reshape(-1)
+    c = np.repeat(idx[:, None, :], m, axis=1).reshape(-1)
+    Dsp = sp.csr_matrix((D.reshape(-1), (r, c)), shape=Afull.shape)
+    Aoff = (Afull - Dsp).tocsr()
+    Dinv = np.linalg.inv(D)
+    col, nc = fc_colouring(lev)
+    out = []
+    for k in range(nc):
+        nodes = np.nonzero(col == k)[0]
+        rows = _node_dofs(lev, nodes)
+        out.append((rows, Aoff[rows, :].tocsr(), sp.block_diag(list(Dinv[nodes]), format="csr")))
+    return col, out
+
+
 def spgemm(A: BsrM, B: BsrM) -> BsrM:
     """A B with the ordered sums of seq.c (columns of each row increasing)."""
     lib = _load()
@@ -418,6 +489,8 @@ def setup(blocks, dofs, params: Params | None = None, n_vec=None) -> Hierarchy:
             lev.dinv.append(np.linalg.inv(D))
         for f in range(2):
             lev.gs.append(_prepare_gs(lev, f))
+        if p.smoother == 1:
+            lev.fc_colour, lev.fc = _prepare_fc(lev)
     last = levels[-1]
     Ad = sp.bmat([[last.csr[0][0], last.csr[0][1]], [last.csr[1][0], last.csr[1][1]]]).toarray()
     h = Hierarchy(levels=levels, params=p)
@@ -466,6 +539,35 @@ def bgs(lev: Level, x0: np.ndarray, x1: np.ndarray, b0, b1, p: Params, omega=Non
     return x0, x1
 
 
+def fc(lev: Level, x0: np.ndarray, x1: np.ndarray, b0, b1, p: Params, omega=None):
+    """Damped nodal-block Gauss-Seidel over the full node blocks, the FC-AMG
+    analogue the paper compares the blocked smoother with: per sweep
+    r = b - A x, then the correction e from zero by multicolour sweeps over the
+    full node graph, node i of colour c taking
+    e_i = D_i^-1 (r_i - sum_{j != i} A[i, j] e_j) with the (d0+d1)-square node
+    blocks of the whole operator, then x += omega e (both fields at once)."""
+    w = p.omega if omega is None else omega
+    if omega is None and lev.omega_s is not None:
+        w = lev.omega_s
+    d0, d1 = lev.dofs
+    x = np.concatenate([x0, x1])
+    b = np.concatenate([b0, b1])
+    wv = np.concatenate([np.repeat(w, d0), np.repeat(w, d1)]) if np.ndim(w) else w
+    for _ in range(p.bgs_sweeps):
+        r = b - apply_A(lev, x)
+        e = np.zeros_like(r)
+        for _ in range(p.inner_sweeps):
+            for rows, Aoff_c, Dc in lev.fc:
+                e[rows] = Dc @ (r[rows] - Aoff_c @ e)
+        x = x + wv * e
+    return _split(lev, x)
+
+
+def smooth(lev: Level, x0, x1, b0, b1, p: Params):
+    """The level's smoother: Algorithm 1 (p.smoother = 0) or the full-node form (1)."""
+    return fc(lev, x0, x1, b0, b1, p) if p.smoother == 1 else bgs(lev, x0, x1, b0, b1, p)
+
+
 def apply_A(lev: Level, x: np.ndarray) -> np.ndarray:
     x0, x1 = _split(lev, x)
     return np.concatenate([lev.csr[0][0] @ x0 + lev.csr[0][1] @ x1,
@@ -503,7 +605,7 @@ def mgv(h: Hierarchy, lvl: int, b: np.ndarray) -> np.ndarray:
         return sla.lu_solve(h.coarse_lu, b)
     b0, b1 = _split(lev, b)
     z = np.zeros(lev.n * lev.dofs[0])
-    x0, x1 = bgs(lev, z, np.zeros(lev.n * lev.dofs[1]), b0, b1, h.params)
+    x0, x1 = smooth(lev, z, np.zeros(lev.n * lev.dofs[1]), b0, b1, h.params)
     u = np.concatenate([x0, x1])
     r = b - apply_A(lev, u)
     r0, r1 = _split(lev, r)
@@ -513,7 +615,7 @@ def mgv(h: Hierarchy, lvl: int, b: np.ndarray) -> np.ndarray:
     nc0 = nxt.n * nxt.dofs[0]
     x0 = x0 + lev.P[0] @ uc[:nc0]
     x1 = x1 + lev.P[1] @ uc[nc0:]
-    x0, x1 = bgs(lev, x0, x1, b0, b1, h.params)
+    x0, x1 = smooth(lev, x0, x1, b0, b1, h.params)
     return np.concatenate([x0, x1])
 
 

@@ -382,3 +382,86 @@ def test_apply_rows_equals_dense_product():
     for k, i in enumerate(nodes):
         want = np.concatenate([ref[i * 3:(i + 1) * 3], ref[N * 3 + i * 3:N * 3 + (i + 1) * 3]])
         assert np.allclose(got[k], want, rtol=1e-13, atol=1e-13)
+
+
+# ----------------------------------------------------------------------------- full-node smoother
+
+def _node_order_gs(Afull, dofs, n, order, b, x, sweeps_from_zero=False):
+    """One sweep of nodal-block Gauss-Seidel written out node by node in the
+    given order over the dense full operator: node i takes
+    x_i = D_i^-1 (b_i - sum_{j != i} A[i, j] x_j), x_j already updated when j
+    comes earlier in the order."""
+    d0, d1 = dofs
+    idx = [np.r_[i * d0:(i + 1) * d0, n * d0 + i * d1:n * d0 + (i + 1) * d1] for i in range(n)]
+    x = x.copy()
+    for i in order:
+        I = idx[i]
+        s = b[I] - Afull[I, :] @ x + Afull[np.ix_(I, I)] @ x[I]
+        x[I] = np.linalg.solve(Afull[np.ix_(I, I)], s)
+    return x
+
+
+@pytest.mark.parametrize("si", [0, 1])
+def test_full_node_sweep_is_nodal_block_gauss_seidel(si):
+    s = _systems()[si]
+    p = amg.Params(max_coarse=1, omega=1.0, smoother=1)
+    h = amg.setup(s.blocks, s.dofs, p)
+    for lev in h.levels[:-1]:
+        Afull = np.block([[lev.csr[f][g].toarray() for g in range(2)] for f in range(2)])
+        n, dofs = lev.n, lev.dofs
+        # the colours are a valid first-fit colouring of the full node graph: the
+        # nodes in colour order, any order inside a colour, give the same sweep
+        order = np.lexsort((np.arange(n), lev.fc_colour))
+        rng = np.random.default_rng(11)
+        b = rng.standard_normal(Afull.shape[0])
+        x = rng.standard_normal(Afull.shape[0])
+        n0 = n * dofs[0]
+        y0, y1 = amg.fc(lev, x[:n0], x[n0:], b[:n0], b[n0:], p)
+        ref = _node_order_gs(Afull, dofs, n, order, b, x)
+        assert np.allclose(np.concatenate([y0, y1]), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+        rev = np.lexsort((-np.arange(n), lev.fc_colour))
+        assert np.allclose(_node_order_gs(Afull, dofs, n, rev, b, x), ref, rtol=1e-12,
+                           atol=1e-12 * np.abs(ref).max())
+
+
+def test_full_node_damping_and_zero_start():
+    s = _systems()[1]
+    p = amg.Params(max_coarse=1, omega=0.6, smoother=1, bgs_sweeps=2)
+    h = amg.setup(s.blocks, s.dofs, p)
+    lev = h.levels[0]
+    Afull = np.block([[lev.csr[f][g].toarray() for g in range(2)] for f in range(2)])
+    n, dofs = lev.n, lev.dofs
+    order = np.lexsort((np.arange(n), lev.fc_colour))
+    b = np.random.default_rng(2).standard_normal(Afull.shape[0])
+    n0 = n * dofs[0]
+    # x_{k+1} = x_k + w (GS(b; x_k) - x_k), two sweeps from zero
+    x = np.zeros_like(b)
+    for _ in range(2):
+        x = x + 0.6 * (_node_order_gs(Afull, dofs, n, order, b, x) - x)
+    y0, y1 = amg.fc(lev, np.zeros(n0), np.zeros(Afull.shape[0] - n0), b[:n0], b[n0:], p)
+    assert np.allclose(np.concatenate([y0, y1]), x, rtol=1e-12, atol=1e-12 * np.abs(x).max())
+
+
+def test_full_node_colouring_covers_the_coupling():
+    s = make_system(7, 2, 0.8, seed=4)
+    h = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=1, smoother=1))
+    for lev in h.levels[:-1]:
+        col = lev.fc_colour
+        for f in range(2):
+            for g in range(2):
+                A = lev.A[f][g]
+                rows = np.repeat(np.arange(lev.n), np.diff(A.rp))
+                off = rows != A.ci
+                assert np.all(col[rows[off]] != col[A.ci[off]])
+
+
+def test_full_node_equals_blocked_without_coupling():
+    # with gamma = 0 the fields do not couple: the node blocks are block diagonal and a
+    # full-node sweep relaxes each field exactly as Algorithm 1 does
+    s = make_system(10, 2, 0.0, seed=2, blk1_scale=3.0)
+    r = np.random.default_rng(4).standard_normal(s.n_dofs)
+    hb = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=50))
+    hf = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=50, smoother=1))
+    assert len(hb.levels) == len(hf.levels) >= 3
+    zb, zf = amg.vcycle(hb, r), amg.vcycle(hf, r)
+    assert np.linalg.norm(zb - zf) <= 1e-13 * np.linalg.norm(zb)
