@@ -104,6 +104,13 @@ typedef struct {
                                  convergence factors with mbamg_probe and keep the better one (1) */
     mbamg_weight_fn weight_fn;
     void* weight_ctx;
+    int32_t smoother;         /* 0: damped block Gauss-Seidel over the two blocks (Sec. 4.3.2, Algorithm 1);
+                                 1: damped nodal-block Gauss-Seidel over the full (d0+d1)-square node blocks,
+                                 the fully coupled (FC-AMG) reference of Sec. 5.1, here with nodal-block
+                                 Gauss-Seidel in place of its Schwarz relaxation.  1 needs
+                                 every block's pattern inside A00's and equal patterns of A00 and A11 on
+                                 every level (MBAMG_E_INVALID otherwise); it uses the sliced smoother
+                                 layout on every level (0) */
 } mbamg_params;
 
 typedef struct {

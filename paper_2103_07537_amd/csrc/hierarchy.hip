@@ -108,6 +108,10 @@ struct Level {
     SetupBsr P[2], PT[2];
     DevBuf<double> wp_agg, ws_agg;
     DevBuf<float> feat;
+    // full-node smoother: inverses of the (d0+d1)-square node blocks, slice-major in block 0's order
+    bool fc = false;
+    DevBuf<double> fc_inv64;
+    DevBuf<float> fc_inv32;
     Vecs<double> v64;
     Vecs<float> v32;
     int64_t nnzb_total() const { return A[0][0].nnzb + A[0][1].nnzb + A[1][0].nnzb + A[1][1].nnzb; }
@@ -899,6 +903,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
         // the sliced parts of the level are not built
         bool rows_level = l > 0 && Lv.A[0][0].nnzb >= (int64_t)32 * Lv.n && Lv.A[1][1].nnzb >= (int64_t)32 * Lv.n;
         if (const char* fo = form_override("MBAMG_ROWS_FORM")) rows_level = l > 0 && std::strcmp(fo, "rows") == 0;
+        if (p.smoother == 1) rows_level = false;   // the full-node kernel reads the sliced parts
         for (int f = 0; f < 2 && !shared; ++f) {
             const int g = 1 - f;
             BlockLevel& B = Lv.blk[f];
@@ -967,6 +972,21 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
                              "split %d\n", l, f, Lv.n, B.n_colours, B.n_slices, avg_width, B.split);
         }
         clk.mark("sliced parts", l);
+        if (p.smoother == 1) {
+            // nodal-block Gauss-Seidel over the full node blocks: both blocks in one colour
+            // order, valid for the whole node graph (the coupling blocks inside A00's pattern)
+            const BlockLevel& B0 = Lv.blk[0];
+            const BlockLevel& B1 = Lv.blk[1];
+            MB_CHECK(B0.colour == B1.colour && B0.perm == B1.perm && B0.h_row0 == B1.h_row0, MBAMG_E_INVALID,
+                     "the full-node smoother needs the two diagonal blocks' patterns equal");
+            MB_CHECK(within_pattern(Lv.A[0][0], Lv.A[0][1], s) && within_pattern(Lv.A[0][0], Lv.A[1][0], s) &&
+                         within_pattern(Lv.A[0][0], Lv.A[1][1], s),
+                     MBAMG_E_INVALID, "the full-node smoother needs every block's pattern inside A00's");
+            build_node_inverses(Lv.A, B0.n_slices, B0.row0.p, B0.nrow.p, B0.d_perm.p, Lv.fc_inv64,
+                                want32 ? &Lv.fc_inv32 : nullptr, s);
+            Lv.fc = true;
+            clk.mark("full node inverses", l);
+        }
         if (l == 0 && to && to->agg_set) {   // level 0's smoother blocks are complete on s
             MB_HIP(hipEventRecord(to->smooth_ev, s));
             to->publish_smooth(true);
@@ -1125,6 +1145,47 @@ template <>
 const float* wrow<float>(const BlockLevel& B) { return B.w_row32.p; }
 
 template <class T>
+static const T* fc_inv(const Level& Lv);
+template <>
+const double* fc_inv<double>(const Level& Lv) { return Lv.fc_inv64.p; }
+template <>
+const float* fc_inv<float>(const Level& Lv) { return Lv.fc_inv32.p; }
+
+// One sweep of the nodal-block Gauss-Seidel over the full node blocks (both
+// blocks of a node relaxed together, colour by colour) from x (NULL: zero)
+// into xn; b, x and xn hold both blocks.
+template <class T>
+static void smooth_fc(mbamg_hierarchy* h, int l, bool zero, const T* b, const T* x, T* xn, hipStream_t s) {
+    Level& Lv = *h->L[l];
+    const BlockLevel& B0 = Lv.blk[0];
+    const int64_t n0 = (int64_t)Lv.n * Lv.d[0];
+    T* t = vecs<T>(Lv).t.p;
+    const int P = std::max(Lv.blk[0].split, Lv.blk[1].split);
+    for (int k = 0; k < h->p.inner_sweeps; ++k)
+        for (int c = 0; c < B0.n_colours; ++c) {
+            GsFcArgs<T> a{};
+            a.s_begin = B0.colour_slice[c];
+            a.s_count = B0.colour_slice[c + 1] - B0.colour_slice[c];
+            a.sl = B0.slices();
+            for (int f = 0; f < 2; ++f) {
+                const int64_t off = f ? n0 : 0;
+                a.off[f] = Lv.blk[f].off.view<T>();
+                a.cpl[f] = Lv.blk[f].cpl.view<T>();
+                a.b[f] = b + off;
+                a.x[f] = x ? x + off : nullptr;
+                a.t[f] = t + off;
+                a.xn[f] = xn + off;
+            }
+            a.dinv = fc_inv<T>(Lv);
+            a.cstart = k == 0 ? B0.colour_row[c] : INT_MAX;
+            a.omega = (T)h->p.omega;
+            a.w_row = Lv.damped ? wrow<T>(Lv.blk[0]) : nullptr;
+            a.skip_off = (zero && k == 0 && c == 0) ? 1 : 0;
+            launch_gs_fc<T>(B0.d, P, zero, a, s);
+        }
+}
+
+template <class T>
 static void smooth_block(mbamg_hierarchy* h, int l, int f, bool zero, const T* b, const T* x, T* xn, const T* xg,
                          hipStream_t s) {
     Level& Lv = *h->L[l];
@@ -1237,6 +1298,11 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
     auto sweep = [&](bool zero) {
         int nx = cur < 0 ? 0 : 1 - cur;
         T* X = cur < 0 ? nullptr : buf[cur];
+        if (Lv.fc) {
+            smooth_fc<T>(h, l, zero, b, X, buf[nx], s);
+            cur = nx;
+            return;
+        }
         // block 0 (uses the current x1 for the coupling term)
         smooth_block<T>(h, l, 0, zero, b, X, buf[nx], zero ? nullptr : X + n0, s);
         // block 1 (Algorithm 1 relaxes it with the already updated x0)
@@ -1557,6 +1623,7 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
         MB_CHECK(p->learned != 1 || p->mlp != nullptr, MBAMG_E_INVALID, "learned == 1 needs the network parameters");
         MB_CHECK(p->learned != 2 || p->weight_fn != nullptr, MBAMG_E_INVALID, "learned == 2 needs a weight callback");
         MB_CHECK(p->omega_p >= 0.0 && std::isfinite(p->omega_p), MBAMG_E_INVALID, "omega_p must be >= 0");
+        MB_CHECK(p->smoother == 0 || p->smoother == 1, MBAMG_E_INVALID, "smoother must be 0 or 1");
         for (int f = 0; f < 2; ++f)
             MB_CHECK(fm->n_vec[f] >= 0 && fm->n_vec[f] <= fm->dofs[f], MBAMG_E_INVALID, "n_vec out of range");
         hipStream_t s = (hipStream_t)hip_stream;

@@ -368,23 +368,18 @@ __global__ void k_fill_f64(double* a, int64_t n, double v) {
 // ----------------------------------------------------------------------------
 // nodal block inverses: LU with partial pivoting of the diagonal block, d <= 8
 // ----------------------------------------------------------------------------
-__global__ void k_dinv(int n, int d, const int32_t* rp, const int32_t* ci, const double* val, double* dinv,
-                       int32_t* singular) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double a[64], x[64];
+// x = a^-1 for a d x d block (d <= 8, row-major) by LU with partial pivoting,
+// the identity's columns solved one by one; false (a overwritten) when a
+// pivot is zero
+__device__ bool lu_inverse(double (&a)[64], int d, double (&x)[64]) {
     int piv[8];
-    const int bs = d * d;
-    int pd = find_col(ci, rp[i], rp[i + 1], i);
-    for (int k = 0; k < bs; ++k) a[k] = pd >= 0 ? val[(int64_t)pd * bs + k] : 0.0;
-    bool sing = false;
     for (int k = 0; k < d; ++k) {
         int p = k;
         double m = fabs(a[k * d + k]);
         for (int r = k + 1; r < d; ++r)
             if (fabs(a[r * d + k]) > m) { m = fabs(a[r * d + k]); p = r; }
         piv[k] = p;
-        if (m == 0.0) { sing = true; break; }
+        if (m == 0.0) return false;
         if (p != k)
             for (int c = 0; c < d; ++c) { double t = a[k * d + c]; a[k * d + c] = a[p * d + c]; a[p * d + c] = t; }
         for (int r = k + 1; r < d; ++r) {
@@ -393,12 +388,6 @@ __global__ void k_dinv(int n, int d, const int32_t* rp, const int32_t* ci, const
             for (int c = k + 1; c < d; ++c) a[r * d + c] = a[r * d + c] - l * a[k * d + c];
         }
     }
-    if (sing) {
-        atomicAdd(singular, 1);
-        for (int k = 0; k < bs; ++k) dinv[(int64_t)i * bs + k] = 0.0;
-        return;
-    }
-    // solve A X = I column by column
     for (int col = 0; col < d; ++col) {
         double y[8];
         for (int r = 0; r < d; ++r) y[r] = r == col ? 1.0 : 0.0;
@@ -411,7 +400,79 @@ __global__ void k_dinv(int n, int d, const int32_t* rp, const int32_t* ci, const
         }
         for (int r = 0; r < d; ++r) x[r * d + col] = y[r];
     }
+    return true;
+}
+
+__global__ void k_dinv(int n, int d, const int32_t* rp, const int32_t* ci, const double* val, double* dinv,
+                       int32_t* singular) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a[64], x[64];
+    const int bs = d * d;
+    int pd = find_col(ci, rp[i], rp[i + 1], i);
+    for (int k = 0; k < bs; ++k) a[k] = pd >= 0 ? val[(int64_t)pd * bs + k] : 0.0;
+    if (!lu_inverse(a, d, x)) {
+        atomicAdd(singular, 1);
+        for (int k = 0; k < bs; ++k) dinv[(int64_t)i * bs + k] = 0.0;
+        return;
+    }
     for (int k = 0; k < bs; ++k) dinv[(int64_t)i * bs + k] = x[k];
+}
+
+// Inverse of the full node block D_i = [[A00_ii, A01_ii], [A10_ii, A11_ii]]
+// (m = d0 + d1 <= 8, row-major) of every node
+struct NodeBlocks {
+    const int32_t* rp[4];
+    const int32_t* ci[4];
+    const double* val[4];
+};
+__global__ void k_node_inv(int n, int d0, int d1, NodeBlocks B, double* inv, int32_t* singular) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int m = d0 + d1;
+    double a[64], x[64];
+    for (int k = 0; k < m * m; ++k) a[k] = 0.0;
+    for (int f = 0; f < 2; ++f)
+        for (int g = 0; g < 2; ++g) {
+            const int q = f * 2 + g;
+            if (!B.rp[q]) continue;
+            const int br = f ? d1 : d0, bc = g ? d1 : d0;
+            const int pd = find_col(B.ci[q], B.rp[q][i], B.rp[q][i + 1], i);
+            if (pd < 0) continue;
+            for (int r = 0; r < br; ++r)
+                for (int c = 0; c < bc; ++c)
+                    a[(f * d0 + r) * m + g * d0 + c] = B.val[q][(int64_t)pd * br * bc + r * bc + c];
+        }
+    if (!lu_inverse(a, m, x)) {
+        atomicAdd(singular, 1);
+        for (int k = 0; k < m * m; ++k) inv[(int64_t)i * m * m + k] = 0.0;
+        return;
+    }
+    for (int k = 0; k < m * m; ++k) inv[(int64_t)i * m * m + k] = x[k];
+}
+
+// slice-major copy for the smoother: out[(s * mm + k) * 64 + lane] = in[perm[row0[s] + lane] * mm + k]
+template <class T>
+__global__ void k_node_inv_pack(int n_slices, int mm, const int32_t* row0, const int32_t* nrow, const int32_t* perm,
+                                const double* in, T* out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_slices * mm * WAVE) return;
+    const int lane = (int)(t % WAVE);
+    const int64_t sk = t / WAVE;
+    const int s = (int)(sk / mm), k = (int)(sk % mm);
+    out[t] = lane < nrow[s] ? (T)in[(int64_t)perm[row0[s] + lane] * mm + k] : T(0);
+}
+
+// flag (initially 1) is cleared when a block of B lies outside A's pattern
+__global__ void k_subpattern(int n, const int32_t* __restrict__ rpa, const int32_t* __restrict__ cia,
+                             const int32_t* __restrict__ rpb, const int32_t* __restrict__ cib, int32_t* flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int p = rpb[i]; p < rpb[i + 1]; ++p)
+        if (find_col(cia, rpa[i], rpa[i + 1], cib[p]) < 0) {
+            atomicAnd(flag, 0);
+            return;
+        }
 }
 
 // ----------------------------------------------------------------------------
@@ -1745,6 +1806,50 @@ void build_dinv(const SetupBsr& A, double* dinv, hipStream_t s) {
     MB_HIP(hipMemcpyAsync(&h, sing.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     MB_HIP(hipStreamSynchronize(s));
     MB_CHECK(h == 0, MBAMG_E_SINGULAR, "a nodal diagonal block is singular");
+}
+
+void build_node_inverses(const SetupBsr (&A)[2][2], int n_slices, const int32_t* row0, const int32_t* nrow,
+                         const int32_t* perm, DevBuf<double>& inv64, DevBuf<float>* inv32, hipStream_t s) {
+    const int n = A[0][0].n_rows, d0 = A[0][0].br, d1 = A[1][1].br, m = d0 + d1;
+    MB_CHECK(m <= 8, MBAMG_E_INVALID, "full node blocks of at most 8 dofs");
+    NodeBlocks B{};
+    for (int f = 0; f < 2; ++f)
+        for (int g = 0; g < 2; ++g) {
+            const SetupBsr& X = A[f][g];
+            const int q = f * 2 + g;
+            B.rp[q] = X.nnzb ? X.rp.p : nullptr;
+            B.ci[q] = X.ci.p;
+            B.val[q] = X.val.p;
+        }
+    DevBuf<double> nat((size_t)std::max(n, 1) * m * m);
+    DevBuf<int32_t> sing(1);
+    MB_HIP(hipMemsetAsync(sing.p, 0, sizeof(int32_t), s));
+    k_node_inv<<<grid_for(n, 64), 64, 0, s>>>(n, d0, d1, B, nat.p, sing.p);
+    MB_LAUNCH_CHECK();
+    const int64_t total = (int64_t)n_slices * m * m * WAVE;
+    inv64.alloc((size_t)std::max<int64_t>(total, 1));
+    if (total) k_node_inv_pack<double><<<grid_for(total), 256, 0, s>>>(n_slices, m * m, row0, nrow, perm, nat.p,
+                                                                       inv64.p);
+    if (inv32) {
+        inv32->alloc((size_t)std::max<int64_t>(total, 1));
+        if (total) k_node_inv_pack<float><<<grid_for(total), 256, 0, s>>>(n_slices, m * m, row0, nrow, perm, nat.p,
+                                                                          inv32->p);
+    }
+    MB_LAUNCH_CHECK();
+    int32_t h = 0;
+    MB_HIP(hipMemcpyAsync(&h, sing.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MB_HIP(hipStreamSynchronize(s));
+    MB_CHECK(h == 0, MBAMG_E_SINGULAR, "a full node block is singular");
+}
+
+bool within_pattern(const SetupBsr& A, const SetupBsr& B, hipStream_t s) {
+    if (B.nnzb == 0) return true;
+    DevBuf<int32_t> flag(1);
+    const std::vector<int32_t> one(1, 1);
+    flag.upload(one, s);
+    k_subpattern<<<grid_for(B.n_rows), 256, 0, s>>>(B.n_rows, A.rp.p, A.ci.p, B.rp.p, B.ci.p, flag.p);
+    MB_LAUNCH_CHECK();
+    return flag.download(s, 1)[0] != 0;
 }
 
 void sell_masks(int64_t n_slots, int bs, const int64_t* src, const double* val, uint32_t* mask, uint32_t* slot_nz,

@@ -43,6 +43,26 @@ struct GsArgs {
     int skip_off;              // nothing processed yet and zero start: the A_ff term vanishes
 };
 
+// One colour of the nodal-block Gauss-Seidel over the full node blocks (both
+// blocks' rows of a node relaxed together): the two blocks share one colour
+// order and slicing; the node inverses are ((d0+d1) x (d0+d1)), stored
+// slice-major as dinv[(s * KK + k) * 64 + lane], KK = (d0+d1)^2.
+template <class T>
+struct GsFcArgs {
+    int s_begin, s_count;
+    SliceView sl;
+    SellView<T> off[2], cpl[2];    // A_ff without its diagonal block; A_fg with it (skipped)
+    const T* dinv;
+    const T* b[2];
+    const T* x[2];                 // current iterates (unused when starting from zero)
+    T* t[2];                       // undamped iterates x + e
+    T* xn[2];                      // damped results x + omega e
+    int cstart;                    // rows below this index already carry this sweep's update
+    T omega;
+    const T* w_row;                // per-row damping (NULL: use omega)
+    int skip_off;                  // nothing processed yet and zero start: the sums vanish
+};
+
 // A block row of a coarse level in row form: rows in colour order, each row's
 // blocks contiguous (row-major br x bc) with columns in the column block's
 // colour order.  Used where rows are long (dense coarse stencils): one
@@ -117,6 +137,8 @@ template <class T>
 void launch_gs(int d, int P, bool zero_x, bool has_cpl, const GsArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_resid(int d, int P, const ResidArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_gs_fc(int d, int P, bool zero_x, const GsFcArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_gs_rows(int d, bool zero_x, bool has_cpl, const GsRowArgs<T>& a, hipStream_t s);
 template <class T>

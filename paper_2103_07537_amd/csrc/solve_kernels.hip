@@ -103,9 +103,10 @@ __device__ __forceinline__ void store_vec<float, 4>(float* __restrict__ p, const
 template <class T, int P>
 constexpr int sell_chunk() { return P >= 4 && sizeof(T) == 4 ? 4 : CHUNK; }
 
-template <class T, int BR, int BC, int MODE, int P>
+// SKIPD: the slot holding column `self` (the row's own node) is left out.
+template <class T, int BR, int BC, int MODE, int P, bool SKIPD = false>
 __device__ __forceinline__ void sell_sub(const SellView<T>& A, int s, int lane, int part, const T* __restrict__ xa,
-                                         const T* __restrict__ xb, int cstart, T (&acc)[BR]) {
+                                         const T* __restrict__ xb, int cstart, T (&acc)[BR], int self = -1) {
     constexpr int CH = sell_chunk<T, P>();
     constexpr bool PF = P >= 4;
     const int w = A.width[s];
@@ -147,7 +148,7 @@ __device__ __forceinline__ void sell_sub(const SellView<T>& A, int s, int lane, 
             if (MODE == 0) src = xa;
             else if (MODE == 1) src = jj < cstart ? xa : xb;
             else src = jj < cstart ? xa : nullptr;
-            if (jj >= 0 && src) load_vec<T, BC>(src + (int64_t)jj * BC, xj[u]);
+            if (jj >= 0 && src && !(SKIPD && jj == self)) load_vec<T, BC>(src + (int64_t)jj * BC, xj[u]);
             else {
 #pragma unroll
                 for (int c = 0; c < BC; ++c) xj[u][c] = T(0);
@@ -244,6 +245,78 @@ __global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_gs(GsArgs<T> a,
     }
     store_vec<T, D>(a.t + (int64_t)row * D, tn);
     store_vec<T, D>(a.xn + (int64_t)row * D, xn);
+}
+
+// One colour of the nodal-block Gauss-Seidel over the full node blocks (the
+// FC-AMG comparison smoother): for each node i of the colour, both blocks' rows
+//   t_i  = D_i^-1 (b_i - sum_{j != i} A[i,j] t_j / x_j)   (D_i: the full node block)
+//   xn_i = x_i + omega (t_i - x_i)
+// with the sums over A_ff's off-diagonal blocks and A_fg's blocks other than
+// the node's own, t_j for rows of earlier colours and x_j otherwise.
+template <class T, int D, bool ZX, int P>
+__global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_gs_fc(GsFcArgs<T> a, int padded_blocks) {
+    constexpr int M = 2 * D;
+    const int wave = wave_id();
+    const int part = wave % P;
+    const int sidx = xcd_block(padded_blocks) * (waves_per_block<P>() / P) + wave / P;
+    const bool valid = sidx < a.s_count;
+    if (P == 1 && !valid) return;
+    const int s = a.s_begin + (valid ? sidx : 0);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int row0 = a.sl.row0[s], nrow = a.sl.nrow[s];
+    const bool act = valid && lane < nrow;
+    const int row = row0 + (lane < nrow ? lane : 0);
+    T acc0[D], acc1[D];
+    if (part == 0) {
+        load_vec<T, D>(a.b[0] + (int64_t)row * D, acc0);
+        load_vec<T, D>(a.b[1] + (int64_t)row * D, acc1);
+    } else {
+#pragma unroll
+        for (int r = 0; r < D; ++r) acc0[r] = acc1[r] = T(0);
+    }
+    if (valid && !a.skip_off) {
+        constexpr int MODE = ZX ? 2 : 1;
+        sell_sub<T, D, D, MODE, P>(a.off[0], s, lane, part, a.t[0], a.x[0], a.cstart, acc0);
+        sell_sub<T, D, D, MODE, P, true>(a.cpl[0], s, lane, part, a.t[1], a.x[1], a.cstart, acc0, row);
+        sell_sub<T, D, D, MODE, P>(a.off[1], s, lane, part, a.t[1], a.x[1], a.cstart, acc1);
+        sell_sub<T, D, D, MODE, P, true>(a.cpl[1], s, lane, part, a.t[0], a.x[0], a.cstart, acc1, row);
+    }
+    T acc[M];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        acc[r] = acc0[r];
+        acc[D + r] = acc1[r];
+    }
+    combine_parts<T, M, P>(acc, wave, part, lane);
+    if (part != 0 || !valid) return;
+    T tn[M];
+    const T* dv = a.dinv + (int64_t)s * M * M * WAVE + lane;
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        T sum = T(0);
+#pragma unroll
+        for (int c = 0; c < M; ++c) sum += dv[(int64_t)(r * M + c) * WAVE] * acc[c];
+        tn[r] = sum;
+    }
+    if (!act) return;
+    const T w = a.w_row ? a.w_row[row] : a.omega;
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+        T tf[D], xn[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) tf[r] = tn[f * D + r];
+        if (ZX) {
+#pragma unroll
+            for (int r = 0; r < D; ++r) xn[r] = w * tf[r];
+        } else {
+            T xo[D];
+            load_vec<T, D>(a.x[f] + (int64_t)row * D, xo);
+#pragma unroll
+            for (int r = 0; r < D; ++r) xn[r] = xo[r] + w * (tf[r] - xo[r]);
+        }
+        store_vec<T, D>(a.t[f] + (int64_t)row * D, tf);
+        store_vec<T, D>(a.xn[f] + (int64_t)row * D, xn);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -679,6 +752,39 @@ void launch_gs(int d, int P, bool zero_x, bool has_cpl, const GsArgs<T>& a, hipS
     MB_LAUNCH_CHECK();
 }
 
+template <class T, int D, int P>
+static void gs_fc_dispatch(bool zx, const GsFcArgs<T>& a, hipStream_t s) {
+    const unsigned grid = xcd_grid(a.s_count, P);
+    constexpr int TPB = waves_per_block<P>() * WAVE;
+    if (zx) k_gs_fc<T, D, true, P><<<grid, TPB, 0, s>>>(a, (int)grid);
+    else k_gs_fc<T, D, false, P><<<grid, TPB, 0, s>>>(a, (int)grid);
+}
+
+template <class T, int D>
+static void gs_fc_dispatch_p(int P, bool zx, const GsFcArgs<T>& a, hipStream_t s) {
+    switch (P) {
+        case 1: gs_fc_dispatch<T, D, 1>(zx, a, s); break;
+        case 2: gs_fc_dispatch<T, D, 2>(zx, a, s); break;
+        case 4: gs_fc_dispatch<T, D, 4>(zx, a, s); break;
+        case 8: gs_fc_dispatch<T, D, 8>(zx, a, s); break;
+        case 16: gs_fc_dispatch<T, D, 16>(zx, a, s); break;
+        default: throw Error(MBAMG_E_INVALID, "slot split must be 1, 2, 4, 8 or 16");
+    }
+}
+
+template <class T>
+void launch_gs_fc(int d, int P, bool zero_x, const GsFcArgs<T>& a, hipStream_t s) {
+    if (a.s_count <= 0) return;
+    switch (d) {
+        case 1: gs_fc_dispatch_p<T, 1>(P, zero_x, a, s); break;
+        case 2: gs_fc_dispatch_p<T, 2>(P, zero_x, a, s); break;
+        case 3: gs_fc_dispatch_p<T, 3>(P, zero_x, a, s); break;
+        case 4: gs_fc_dispatch_p<T, 4>(P, zero_x, a, s); break;
+        default: throw Error(MBAMG_E_INVALID, "dofs per node must be 1..4");
+    }
+    MB_LAUNCH_CHECK();
+}
+
 template <class T, int D>
 static void gs_rows_dispatch(bool zx, bool cpl, const GsRowArgs<T>& a, hipStream_t s) {
     const unsigned grid = (unsigned)ceil_div(a.r_count, WPB);
@@ -830,6 +936,8 @@ void launch_coarse(int n, const double* inv, const T* x, T* y, hipStream_t s) {
 }
 
 template void launch_gs<double>(int, int, bool, bool, const GsArgs<double>&, hipStream_t);
+template void launch_gs_fc<double>(int, int, bool, const GsFcArgs<double>&, hipStream_t);
+template void launch_gs_fc<float>(int, int, bool, const GsFcArgs<float>&, hipStream_t);
 template void launch_gs<float>(int, int, bool, bool, const GsArgs<float>&, hipStream_t);
 template void launch_resid<double>(int, int, const ResidArgs<double>&, hipStream_t);
 template void launch_resid<float>(int, int, const ResidArgs<float>&, hipStream_t);

@@ -44,7 +44,8 @@ class Params(ctypes.Structure):
                 ("clone_aggregates", ctypes.c_int32), ("reuse_P", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("learned", ctypes.c_int32),
                 ("mlp", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("omega_p", ctypes.c_double),
-                ("judge", ctypes.c_int32), ("weight_fn", WEIGHT_FN), ("weight_ctx", ctypes.c_void_p)]
+                ("judge", ctypes.c_int32), ("weight_fn", WEIGHT_FN), ("weight_ctx", ctypes.c_void_p),
+                ("smoother", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
