@@ -1,14 +1,18 @@
-"""Smoother parameter studies on the synthetic workloads.
+"""Smoother studies on the synthetic workloads.
 
 The paper studies two knobs of the block Gauss-Seidel smoother on its MHD
 generator problem: the damping omega of Algorithm 1, and one against two
-smoothing sweeps (more sweeps cut the iterations but not the time).  This
-module repeats both on the synthetic systems with the library's own
-hierarchy: every point is a fresh setup plus GMRES(30) to rtol 1e-8 on one
-GPU, timed with the device synchronised on both sides.
+smoothing sweeps (more sweeps cut the iterations but not the time); and it
+compares the blocked method with a fully coupled AMG whose relaxation acts on
+the whole coupled system (Sec. 5.1).  This module repeats these on the
+synthetic systems with the library's own hierarchy (the fully coupled
+reference as nodal-block Gauss-Seidel over the full node blocks,
+`smoother = 1`): every point is a fresh setup plus GMRES(30) to rtol 1e-8 on
+one GPU, timed with the device synchronised on both sides.
 
-    python -m paper_2103_07537_amd.studies omega  --workload 2d-256
-    python -m paper_2103_07537_amd.studies sweeps --workload 2d-512-lognormal --precision 1
+    python -m paper_2103_07537_amd.studies omega    --workload 2d-256
+    python -m paper_2103_07537_amd.studies sweeps   --workload 2d-512-lognormal --precision 1
+    python -m paper_2103_07537_amd.studies smoother --workload 3d-64
 
 Each point prints one JSON line; a markdown table follows on stderr.
 """
@@ -23,6 +27,8 @@ import time
 OMEGAS = (0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1)
 # (BGS sweeps for pre- and post-smoothing, inner multicolour sweeps per block)
 SWEEPS = ((1, 1), (2, 1), (1, 2), (2, 2))
+# 0: block Gauss-Seidel over the two blocks (Algorithm 1); 1: nodal-block Gauss-Seidel over the full node blocks
+SMOOTHERS = (0, 1)
 
 
 def run_point(blocks, system, b, *, repeats: int = 3, rtol: float = 1e-8, **params) -> dict:
@@ -67,6 +73,9 @@ def study(kind: str, name: str, *, seed: int = 1, precision: int = 0, repeats: i
         for bgs, inner in (points or SWEEPS):
             out.append(run_point(blocks, s, b, repeats=repeats, precision=precision, bgs_sweeps=bgs,
                                  inner_sweeps=inner))
+    elif kind == "smoother":
+        for sm in (points or SMOOTHERS):
+            out.append(run_point(blocks, s, b, repeats=repeats, precision=precision, smoother=sm))
     else:
         raise ValueError(kind)
     for r in out:
@@ -88,7 +97,7 @@ def table(rows: list) -> str:
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("kind", choices=["omega", "sweeps"])
+    ap.add_argument("kind", choices=["omega", "sweeps", "smoother"])
     ap.add_argument("--workload", default="2d-256")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--precision", type=int, default=0, choices=[0, 1])

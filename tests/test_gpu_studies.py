@@ -25,3 +25,12 @@ def test_more_sweeps_need_no_more_iterations():
     assert all(r["converged"] for r in rows)
     assert its[1] <= its[0] and its[2] <= its[1]
     assert "| parameters |" in studies.table(rows)
+
+
+def test_smoother_study_compares_both_smoothers():
+    from paper_2103_07537_amd import studies
+    rows = studies.study("smoother", "2d-32", repeats=1)
+    assert [r["params"]["smoother"] for r in rows] == [0, 1]
+    for r in rows:
+        log(f"  smoother={r['params']['smoother']}: {r['iterations']} its, {r['total_ms']:.1f} ms")
+        assert r["converged"] and r["rel_residual"] <= 1e-8 * (1 + 1e-6)
