@@ -109,3 +109,26 @@ def test_full_node_smoother_rejects_patterns_outside_a00():
     # the blocked smoother takes the same system
     h = mbamg.Hierarchy(blocks, s.dofs, s.n_vec, max_coarse=40)
     h.close()
+
+
+def test_full_node_smoother_with_the_judge():
+    # both builds of the judged learned form take the full-node smoother; the
+    # learned one borrows level 0's aggregates and smoother blocks and builds
+    # its own node inverses
+    from oracle import amg
+    s = CASES["3d-lognormal-distinct"]()
+    hg = gpu_hierarchy(s, max_coarse=40, smoother=1, weights=weights_fn, judge=1)
+    used = hg.info()["used_learned"]
+    ho = amg.setup(s.blocks, s.dofs, oracle_params(max_coarse=40, smoother=1,
+                                                   **(dict(weights=weights_fn) if used else {})),
+                   n_vec=s.n_vec)
+    r = np.random.default_rng(12).standard_normal(s.n_dofs)
+    z = torch_dev(np.zeros(s.n_dofs))
+    hg.vcycle(torch_dev(r), z)
+    e = rel(z.cpu().numpy(), amg.vcycle(ho, r))
+    log(f"  used_learned={used} vcycle rel {e:.2e}")
+    assert e <= 1e-12
+    x = torch_dev(np.zeros(s.n_dofs))
+    info = hg.solve(torch_dev(s.b), x, rtol=1e-8)
+    assert info["converged"]
+    hg.close()
