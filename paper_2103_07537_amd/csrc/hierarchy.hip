@@ -79,6 +79,7 @@ struct BlockLevel {
     SellPart pro, res;
     int pro_split = 1, res_split = 1;          // waves per slice in the transfer kernels
     int res_group = 4;                         // lanes per coarse row in the tentative restriction
+    int row_split = 1;                         // row form smoother: wavefronts per row (1, or 4 with 4 x 4 blocks)
     // coarse levels with long rows: the smoother and residual run on the row form
     bool rows = false;
     RowPart raff, rafg;
@@ -930,6 +931,11 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
                     B.all_bl += v[1] + v[3] + v[6];
                 }
                 B.split = 1;
+                // few rows per colour (small, latency-bound launches): a workgroup's four
+                // wavefronts share each row, for shorter chains of dependent passes (measured
+                // 12 % faster on a 98-rows-per-colour level, 60 % slower on 10K rows per colour)
+                B.row_split = (df == 4 && Lv.n <= 1024 * std::max(1, B.n_colours)) ? 4 : 1;
+                if (const char* fo = form_override("MBAMG_ROW_SPLIT")) B.row_split = df == 4 ? std::atoi(fo) : 1;
                 build_rows(B.raff, Lv.n, B.d_perm.p, Lv.A[f][f], B.d_iperm.p, want32, s);
                 build_rows(B.rafg, Lv.n, B.d_perm.p, Lv.A[f][g], Lv.blk[g].d_iperm.p, want32, s);
                 B.rdinv64.alloc((size_t)Lv.n * df * df);
@@ -1213,7 +1219,7 @@ static void smooth_block(mbamg_hierarchy* h, int l, int f, bool zero, const T* b
                 a.omega = (T)h->p.omega;
                 a.w_row = Lv.damped ? wrow<T>(B) : nullptr;
                 a.skip_off = (zero && k == 0 && c == 0) ? 1 : 0;
-                launch_gs_rows<T>(B.d, zero, has_cpl, a, s);
+                launch_gs_rows<T>(B.d, B.row_split, zero, has_cpl, a, s);
             }
         return;
     }

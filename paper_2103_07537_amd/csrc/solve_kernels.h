@@ -140,7 +140,8 @@ void launch_resid(int d, int P, const ResidArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_gs_fc(int d, int P, bool zero_x, const GsFcArgs<T>& a, hipStream_t s);
 template <class T>
-void launch_gs_rows(int d, bool zero_x, bool has_cpl, const GsRowArgs<T>& a, hipStream_t s);
+// rp: wavefronts per row (1, or 4 with 4 x 4 blocks for long rows)
+void launch_gs_rows(int d, int rp, bool zero_x, bool has_cpl, const GsRowArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_resid_rows(int d, const ResidRowArgs<T>& a, hipStream_t s);
 

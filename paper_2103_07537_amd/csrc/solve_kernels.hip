@@ -373,9 +373,10 @@ __device__ __forceinline__ void row_sub(const RowView<T>& A, int row, int lane, 
 // half of a double one), so one load instruction covers 1 KiB with no gaps.
 // Every lane keeps one block-row position (the row's first block starts a
 // piece group), so its partial sum belongs to one component r.
-template <class T, int D, int MODE, bool SKIP_DIAG>
+// With RP wavefronts on one row, wavefront `part` takes every RP-th pass.
+template <class T, int D, int MODE, bool SKIP_DIAG, int RP = 1>
 __device__ __forceinline__ void row_sub_c(const RowView<T>& A, int row, int lane, const T* __restrict__ xa,
-                                          const T* __restrict__ xb, int cstart, T (&acc)[D]) {
+                                          const T* __restrict__ xb, int cstart, T (&acc)[D], int wpart = 0) {
     constexpr int V = 16 / (int)sizeof(T);   // values per piece
     static_assert(D % V == 0, "block rows split into 16-byte pieces");
     constexpr int LR = D / V;                // pieces per block row
@@ -386,12 +387,12 @@ __device__ __forceinline__ void row_sub_c(const RowView<T>& A, int row, int lane
     const int r = part / LR, c0 = (part % LR) * V;
     const int64_t u0 = (int64_t)A.rp[row] * LB, u1 = (int64_t)A.rp[row + 1] * LB;
     T sum = T(0);
-    for (int64_t ub = u0; ub < u1; ub += UNROLL * WAVE) {
+    for (int64_t ub = u0 + (int64_t)wpart * WAVE; ub < u1; ub += UNROLL * RP * WAVE) {
         T av[UNROLL][V], xv[UNROLL][V];
         bool ok[UNROLL];
 #pragma unroll
         for (int h = 0; h < UNROLL; ++h) {
-            const int64_t u = ub + h * WAVE + lane;
+            const int64_t u = ub + (int64_t)h * RP * WAVE + lane;
             ok[h] = u < u1;
             const int64_t uc = ok[h] ? u : u0 + part;   // in range: the row's first block
             const int j = A.col[uc / LB];
@@ -445,28 +446,56 @@ __device__ __forceinline__ void wave_sum_vec(T (&acc)[D]) {
     }
 }
 
+// Sum of the RP wavefronts' partial sums of one row (each valid in its lane
+// WAVE - 1), in wavefront order, left in wavefront 0's lane WAVE - 1.
+template <class T, int D, int RP>
+__device__ __forceinline__ void combine_row_parts(T (&acc)[D], int wpart, int lane) {
+    if constexpr (RP > 1) {
+        __shared__ T red[RP][D];
+        if (lane == WAVE - 1)
+#pragma unroll
+            for (int r = 0; r < D; ++r) red[wpart][r] = acc[r];
+        __syncthreads();
+        if (wpart == 0 && lane == WAVE - 1) {
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                T v = red[0][r];
+#pragma unroll
+                for (int q = 1; q < RP; ++q) v += red[q][r];
+                acc[r] = v;
+            }
+        }
+    }
+}
+
 // One colour of the block row's Gauss-Seidel sub-solve (the arithmetic of k_gs).
-template <class T, int D, bool ZX, bool CPL>
+// RP = 1: one wavefront per row; RP = 4: the four wavefronts of a workgroup
+// share one long row (4 x 4 blocks only).
+template <class T, int D, bool ZX, bool CPL, int RP>
 __global__ __launch_bounds__(256) void k_gs_rows(GsRowArgs<T> a) {
+    static_assert(RP == 1 || (RP == WPB && D == 4), "rows shared by the workgroup's wavefronts: 4 x 4 blocks");
     const int lane = threadIdx.x & (WAVE - 1);
-    const int w = blockIdx.x * WPB + wave_id();
-    if (w >= a.r_count) return;   // whole wavefront
+    const int wpart = RP > 1 ? wave_id() : 0;
+    const int w = RP > 1 ? (int)blockIdx.x : (int)blockIdx.x * WPB + wave_id();
+    if (w >= a.r_count) return;   // whole wavefronts (the whole workgroup when RP > 1)
     const int row = a.r_begin + w;
     // the row's own data first: its latency overlaps the row sums'
     T bb[D], dv[D * D], xo[D];
-    load_vec<T, D>(a.b + (int64_t)row * D, bb);
-    load_block<T, D * D>(a.dinv + (int64_t)row * D * D, dv);
-    if (!ZX) load_vec<T, D>(a.x + (int64_t)row * D, xo);
+    if (wpart == 0) {
+        load_vec<T, D>(a.b + (int64_t)row * D, bb);
+        load_block<T, D * D>(a.dinv + (int64_t)row * D * D, dv);
+        if (!ZX) load_vec<T, D>(a.x + (int64_t)row * D, xo);
+    }
     const T wgt = a.w_row ? a.w_row[row] : a.omega;
     T acc[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) acc[r] = T(0);
     if constexpr (D == 4) {
         if (!a.skip_off) {
-            if (ZX) row_sub_c<T, D, 2, true>(a.aff, row, lane, a.t, nullptr, a.cstart, acc);
-            else row_sub_c<T, D, 1, true>(a.aff, row, lane, a.t, a.x, a.cstart, acc);
+            if (ZX) row_sub_c<T, D, 2, true, RP>(a.aff, row, lane, a.t, nullptr, a.cstart, acc, wpart);
+            else row_sub_c<T, D, 1, true, RP>(a.aff, row, lane, a.t, a.x, a.cstart, acc, wpart);
         }
-        if (CPL) row_sub_c<T, D, 0, false>(a.afg, row, lane, a.xg, nullptr, 0, acc);
+        if (CPL) row_sub_c<T, D, 0, false, RP>(a.afg, row, lane, a.xg, nullptr, 0, acc, wpart);
     } else {
         if (!a.skip_off) {
             if (ZX) row_sub<T, D, D, 2, true>(a.aff, row, lane, a.t, nullptr, a.cstart, acc);
@@ -475,7 +504,8 @@ __global__ __launch_bounds__(256) void k_gs_rows(GsRowArgs<T> a) {
         if (CPL) row_sub<T, D, D, 0, false>(a.afg, row, lane, a.xg, nullptr, 0, acc);
     }
     wave_sum_vec<T, D>(acc);
-    if (lane != WAVE - 1) return;
+    combine_row_parts<T, D, RP>(acc, wpart, lane);
+    if (wpart != 0 || lane != WAVE - 1) return;
 #pragma unroll
     for (int r = 0; r < D; ++r) acc[r] += bb[r];
     T tn[D];
@@ -785,32 +815,36 @@ void launch_gs_fc(int d, int P, bool zero_x, const GsFcArgs<T>& a, hipStream_t s
     MB_LAUNCH_CHECK();
 }
 
-template <class T, int D>
+template <class T, int D, int RP>
 static void gs_rows_dispatch(bool zx, bool cpl, const GsRowArgs<T>& a, hipStream_t s) {
-    const unsigned grid = (unsigned)ceil_div(a.r_count, WPB);
+    const unsigned grid = (unsigned)ceil_div(a.r_count, WPB / RP);
     if (zx) {
-        if (cpl) k_gs_rows<T, D, true, true><<<grid, 256, 0, s>>>(a);
-        else k_gs_rows<T, D, true, false><<<grid, 256, 0, s>>>(a);
+        if (cpl) k_gs_rows<T, D, true, true, RP><<<grid, 256, 0, s>>>(a);
+        else k_gs_rows<T, D, true, false, RP><<<grid, 256, 0, s>>>(a);
     } else {
-        if (cpl) k_gs_rows<T, D, false, true><<<grid, 256, 0, s>>>(a);
-        else k_gs_rows<T, D, false, false><<<grid, 256, 0, s>>>(a);
+        if (cpl) k_gs_rows<T, D, false, true, RP><<<grid, 256, 0, s>>>(a);
+        else k_gs_rows<T, D, false, false, RP><<<grid, 256, 0, s>>>(a);
     }
 }
 
 template <class T>
-void launch_gs_rows(int d, bool zero_x, bool has_cpl, const GsRowArgs<T>& a, hipStream_t s) {
+void launch_gs_rows(int d, int rp, bool zero_x, bool has_cpl, const GsRowArgs<T>& a, hipStream_t s) {
     if (a.r_count <= 0) return;
+    MB_CHECK(rp == 1 || (rp == WPB && d == 4), MBAMG_E_INVALID, "row split must be 1, or 4 with 4 x 4 blocks");
     switch (d) {
-        case 1: gs_rows_dispatch<T, 1>(zero_x, has_cpl, a, s); break;
-        case 2: gs_rows_dispatch<T, 2>(zero_x, has_cpl, a, s); break;
-        case 3: gs_rows_dispatch<T, 3>(zero_x, has_cpl, a, s); break;
-        case 4: gs_rows_dispatch<T, 4>(zero_x, has_cpl, a, s); break;
+        case 1: gs_rows_dispatch<T, 1, 1>(zero_x, has_cpl, a, s); break;
+        case 2: gs_rows_dispatch<T, 2, 1>(zero_x, has_cpl, a, s); break;
+        case 3: gs_rows_dispatch<T, 3, 1>(zero_x, has_cpl, a, s); break;
+        case 4:
+            if (rp == WPB) gs_rows_dispatch<T, 4, WPB>(zero_x, has_cpl, a, s);
+            else gs_rows_dispatch<T, 4, 1>(zero_x, has_cpl, a, s);
+            break;
         default: throw Error(MBAMG_E_INVALID, "dofs per node must be 1..4");
     }
     MB_LAUNCH_CHECK();
 }
-template void launch_gs_rows<double>(int, bool, bool, const GsRowArgs<double>&, hipStream_t);
-template void launch_gs_rows<float>(int, bool, bool, const GsRowArgs<float>&, hipStream_t);
+template void launch_gs_rows<double>(int, int, bool, bool, const GsRowArgs<double>&, hipStream_t);
+template void launch_gs_rows<float>(int, int, bool, bool, const GsRowArgs<float>&, hipStream_t);
 
 template <class T>
 void launch_resid_rows(int d, const ResidRowArgs<T>& a, hipStream_t s) {

@@ -78,9 +78,10 @@ def test_kernel_form_is_bit_identical(ref, var, form, monkeypatch):
         assert a.tobytes() == b.tobytes()
 
 
-# The row form (one wavefront per row on coarse levels) sums each row in a
-# different order from the sliced form, so it is pinned to the oracle instead:
-# forced onto every coarse level, FP64 cycles within 1e-12, FP32 within 1e-5.
+# The row form (one wavefront per row on coarse levels, or four for long rows)
+# sums each row in a different order from the sliced form, so it is pinned to
+# the oracle instead: forced onto every coarse level with either split, FP64
+# cycles within 1e-12, FP32 within 1e-5.
 ROW_CASES = {
     "3d-lognormal-weighted": (lambda: make_system(11, 3, 2.0, seed=5, kappa="lognormal"), True),
     "2d-fixed": (lambda: make_system(40, 2, 0.7, seed=3), False),
@@ -89,7 +90,8 @@ ROW_CASES = {
 
 @pytest.mark.parametrize("case", list(ROW_CASES))
 @pytest.mark.parametrize("precision", [0, 1])
-def test_row_form_matches_oracle(case, precision, monkeypatch):
+@pytest.mark.parametrize("split", ["1", "4"])
+def test_row_form_matches_oracle(case, precision, split, monkeypatch):
     from oracle import amg
     from gpu_util import rel, torch_dev
     make, weighted = ROW_CASES[case]
@@ -98,8 +100,9 @@ def test_row_form_matches_oracle(case, precision, monkeypatch):
     okw = dict(weights=weights_fn) if weighted else {}
     ho = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=60, **okw), n_vec=s.n_vec)
     monkeypatch.setenv("MBAMG_ROWS_FORM", "rows")
+    monkeypatch.setenv("MBAMG_ROW_SPLIT", split)   # wavefronts per row (4: 4 x 4 blocks only)
     hg = gpu_hierarchy(s, max_coarse=60, precision=precision, **kw)
-    log(f"case={case} precision={precision} levels={hg.num_levels()}")
+    log(f"case={case} precision={precision} split={split} levels={hg.num_levels()}")
     assert hg.num_levels() == len(ho.levels) >= 3
     r = np.random.default_rng(7).standard_normal(s.n_dofs)
     z = torch_dev(np.zeros(s.n_dofs))
