@@ -864,7 +864,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
         if (want32) alloc_vecs(c.v32, (int64_t)c.n * (d0 + d1));
     }
 
-    // smoother format on every other level, in two rounds: first each level's own smoother
+    // smoother format on every other level, in two passes: first each level's own smoother
     // blocks (its colouring, order and parts), then the transfers, which need the next
     // level's order.  A build that lends its level 0 does that level first and publishes
     // it at once; a build that borrows it does it last.
