@@ -111,6 +111,8 @@ struct Level {
     DevBuf<float> feat;
     // full-node smoother: inverses of the (d0+d1)-square node blocks, slice-major in block 0's order
     bool fc = false;
+    DevBuf<uint64_t> fc_mask;                  // per slice: entries stored
+    DevBuf<int32_t> fc_off;                    // per slice: first value group
     DevBuf<double> fc_inv64;
     DevBuf<float> fc_inv32;
     Vecs<double> v64;
@@ -988,8 +990,8 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
             MB_CHECK(within_pattern(Lv.A[0][0], Lv.A[0][1], s) && within_pattern(Lv.A[0][0], Lv.A[1][0], s) &&
                          within_pattern(Lv.A[0][0], Lv.A[1][1], s),
                      MBAMG_E_INVALID, "the full-node smoother needs every block's pattern inside A00's");
-            build_node_inverses(Lv.A, B0.n_slices, B0.row0.p, B0.nrow.p, B0.d_perm.p, Lv.fc_inv64,
-                                want32 ? &Lv.fc_inv32 : nullptr, s);
+            build_node_inverses(Lv.A, B0.n_slices, B0.row0.p, B0.nrow.p, B0.d_perm.p, Lv.fc_mask, Lv.fc_off,
+                                Lv.fc_inv64, want32 ? &Lv.fc_inv32 : nullptr, s);
             Lv.fc = true;
             clk.mark("full node inverses", l);
         }
@@ -1183,6 +1185,8 @@ static void smooth_fc(mbamg_hierarchy* h, int l, bool zero, const T* b, const T*
                 a.xn[f] = xn + off;
             }
             a.dinv = fc_inv<T>(Lv);
+            a.dmask = Lv.fc_mask.p;
+            a.doff = Lv.fc_off.p;
             a.cstart = k == 0 ? B0.colour_row[c] : INT_MAX;
             a.omega = (T)h->p.omega;
             a.w_row = Lv.damped ? wrow<T>(Lv.blk[0]) : nullptr;

@@ -37,11 +37,14 @@ void build_tentative(const Aggregates& G, int d, const double* B, double* q, dou
 // the tentative prolongator as a block matrix: row i holds diag(q_i) in column agg(i)
 SetupBsr tentative_bsr(const Aggregates& G, int d, const double* q, hipStream_t s);
 void build_dinv(const SetupBsr& A, double* dinv, hipStream_t s);
-// Inverses of the full node blocks [[A00_ii, A01_ii], [A10_ii, A11_ii]], packed
-// slice-major for the full-node smoother (inv[(s * mm + k) * 64 + lane], the
-// rows in the slices' order perm); MBAMG_E_SINGULAR when one is singular.
+// Inverses of the full node blocks [[A00_ii, A01_ii], [A10_ii, A11_ii]] for the
+// full-node smoother, the rows in the slices' order perm, masked per slice:
+// bit k of mask[s] set when entry k is nonzero in some row of slice s, the set
+// entries stored as groups of 64 (one per lane) from group off[s];
+// MBAMG_E_SINGULAR when one is singular.
 void build_node_inverses(const SetupBsr (&A)[2][2], int n_slices, const int32_t* row0, const int32_t* nrow,
-                         const int32_t* perm, DevBuf<double>& inv64, DevBuf<float>* inv32, hipStream_t s);
+                         const int32_t* perm, DevBuf<uint64_t>& mask, DevBuf<int32_t>& off, DevBuf<double>& inv64,
+                         DevBuf<float>* inv32, hipStream_t s);
 // true when every block of B lies in A's pattern (same rows)
 bool within_pattern(const SetupBsr& A, const SetupBsr& B, hipStream_t s);
 void sell_masks(int64_t n_slots, int bs, const int64_t* src, const double* val, uint32_t* mask, uint32_t* slot_nz,

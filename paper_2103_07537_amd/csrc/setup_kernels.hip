@@ -451,16 +451,39 @@ __global__ void k_node_inv(int n, int d0, int d1, NodeBlocks B, double* inv, int
     for (int k = 0; k < m * m; ++k) inv[(int64_t)i * m * m + k] = x[k];
 }
 
-// slice-major copy for the smoother: out[(s * mm + k) * 64 + lane] = in[perm[row0[s] + lane] * mm + k]
+// Masked slice-major layout of the node inverses for the smoother: per slice,
+// bit k of mask[s] is set when entry k is nonzero for some row of the slice;
+// the set entries follow each other as groups of 64 values (one per lane) from
+// group off[s].  One wavefront per slice: the mask and its group count.
+__global__ void k_node_inv_mask(int n_slices, int mm, const int32_t* row0, const int32_t* nrow, const int32_t* perm,
+                                const double* in, uint64_t* mask, int32_t* cnt) {
+    const int s = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
+    if (s >= n_slices) return;   // whole wavefronts
+    const int lane = threadIdx.x & (WAVE - 1);
+    const bool live = lane < nrow[s];
+    const int64_t base = live ? (int64_t)perm[row0[s] + lane] * mm : 0;
+    uint64_t m = 0;
+    for (int k = 0; k < mm; ++k)
+        if (__ballot(live && in[base + k] != 0.0) != 0) m |= (uint64_t)1 << k;
+    if (lane == 0) {
+        mask[s] = m;
+        cnt[s] = __popcll(m);
+    }
+}
+
 template <class T>
 __global__ void k_node_inv_pack(int n_slices, int mm, const int32_t* row0, const int32_t* nrow, const int32_t* perm,
-                                const double* in, T* out) {
+                                const double* in, const uint64_t* mask, const int32_t* off, T* out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n_slices * mm * WAVE) return;
     const int lane = (int)(t % WAVE);
     const int64_t sk = t / WAVE;
     const int s = (int)(sk / mm), k = (int)(sk % mm);
-    out[t] = lane < nrow[s] ? (T)in[(int64_t)perm[row0[s] + lane] * mm + k] : T(0);
+    const uint64_t m = mask[s];
+    if (!((m >> k) & 1)) return;
+    const int g = __popcll(m & (((uint64_t)1 << k) - 1));
+    out[((int64_t)off[s] + g) * WAVE + lane] =
+        lane < nrow[s] ? (T)in[(int64_t)perm[row0[s] + lane] * mm + k] : T(0);
 }
 
 // flag (initially 1) is cleared when a block of B lies outside A's pattern
@@ -1809,7 +1832,8 @@ void build_dinv(const SetupBsr& A, double* dinv, hipStream_t s) {
 }
 
 void build_node_inverses(const SetupBsr (&A)[2][2], int n_slices, const int32_t* row0, const int32_t* nrow,
-                         const int32_t* perm, DevBuf<double>& inv64, DevBuf<float>* inv32, hipStream_t s) {
+                         const int32_t* perm, DevBuf<uint64_t>& mask, DevBuf<int32_t>& off, DevBuf<double>& inv64,
+                         DevBuf<float>* inv32, hipStream_t s) {
     const int n = A[0][0].n_rows, d0 = A[0][0].br, d1 = A[1][1].br, m = d0 + d1;
     MB_CHECK(m <= 8, MBAMG_E_INVALID, "full node blocks of at most 8 dofs");
     NodeBlocks B{};
@@ -1826,14 +1850,21 @@ void build_node_inverses(const SetupBsr (&A)[2][2], int n_slices, const int32_t*
     MB_HIP(hipMemsetAsync(sing.p, 0, sizeof(int32_t), s));
     k_node_inv<<<grid_for(n, 64), 64, 0, s>>>(n, d0, d1, B, nat.p, sing.p);
     MB_LAUNCH_CHECK();
+    mask.alloc((size_t)std::max(n_slices, 1));
+    off.alloc((size_t)n_slices + 1);
+    DevBuf<int32_t> cnt((size_t)std::max(n_slices, 1));
+    if (n_slices) k_node_inv_mask<<<grid_for((int64_t)n_slices * WAVE), 256, 0, s>>>(n_slices, m * m, row0, nrow, perm,
+                                                                                      nat.p, mask.p, cnt.p);
+    MB_LAUNCH_CHECK();
+    const int64_t groups = scan_exclusive(cnt.p, n_slices, off.p, s);
     const int64_t total = (int64_t)n_slices * m * m * WAVE;
-    inv64.alloc((size_t)std::max<int64_t>(total, 1));
+    inv64.alloc((size_t)std::max<int64_t>(groups * WAVE, 1));
     if (total) k_node_inv_pack<double><<<grid_for(total), 256, 0, s>>>(n_slices, m * m, row0, nrow, perm, nat.p,
-                                                                       inv64.p);
+                                                                       mask.p, off.p, inv64.p);
     if (inv32) {
-        inv32->alloc((size_t)std::max<int64_t>(total, 1));
+        inv32->alloc((size_t)std::max<int64_t>(groups * WAVE, 1));
         if (total) k_node_inv_pack<float><<<grid_for(total), 256, 0, s>>>(n_slices, m * m, row0, nrow, perm, nat.p,
-                                                                          inv32->p);
+                                                                          mask.p, off.p, inv32->p);
     }
     MB_LAUNCH_CHECK();
     int32_t h = 0;

@@ -45,14 +45,17 @@ struct GsArgs {
 
 // One colour of the nodal-block Gauss-Seidel over the full node blocks (both
 // blocks' rows of a node relaxed together): the two blocks share one colour
-// order and slicing; the node inverses are ((d0+d1) x (d0+d1)), stored
-// slice-major as dinv[(s * KK + k) * 64 + lane], KK = (d0+d1)^2.
+// order and slicing; the node inverses are ((d0+d1) x (d0+d1)), masked per
+// slice: the entries k set in dmask[s] stored as groups of 64 values (one per
+// lane) from group doff[s].
 template <class T>
 struct GsFcArgs {
     int s_begin, s_count;
     SliceView sl;
     SellView<T> off[2], cpl[2];    // A_ff without its diagonal block; A_fg with it (skipped)
     const T* dinv;
+    const uint64_t* dmask;
+    const int32_t* doff;
     const T* b[2];
     const T* x[2];                 // current iterates (unused when starting from zero)
     T* t[2];                       // undamped iterates x + e

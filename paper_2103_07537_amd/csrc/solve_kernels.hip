@@ -289,13 +289,26 @@ __global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_gs_fc(GsFcArgs<
     }
     combine_parts<T, M, P>(acc, wave, part, lane);
     if (part != 0 || !valid) return;
+    // the node inverse: only the slice's nonzero entries are stored
+    const uint64_t dm = a.dmask[s];
+    const T* dv = a.dinv + (int64_t)a.doff[s] * WAVE + lane;
+    T inv[M * M];
+    int g = 0;
+#pragma unroll
+    for (int k = 0; k < M * M; ++k) {
+        if ((dm >> k) & 1) {
+            inv[k] = dv[(int64_t)g * WAVE];
+            ++g;
+        } else {
+            inv[k] = T(0);
+        }
+    }
     T tn[M];
-    const T* dv = a.dinv + (int64_t)s * M * M * WAVE + lane;
 #pragma unroll
     for (int r = 0; r < M; ++r) {
         T sum = T(0);
 #pragma unroll
-        for (int c = 0; c < M; ++c) sum += dv[(int64_t)(r * M + c) * WAVE] * acc[c];
+        for (int c = 0; c < M; ++c) sum += inv[r * M + c] * acc[c];
         tn[r] = sum;
     }
     if (!act) return;
