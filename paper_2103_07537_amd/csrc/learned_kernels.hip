@@ -8,6 +8,7 @@
 // Parameter packing (5122 FP32): W1[64][12], b1[64], W2[64][64], b2[64],
 // W3[2][64], b3[2].
 #include "learned_kernels.h"
+#include "dpp.h"
 
 #include <algorithm>
 #include <cmath>
@@ -402,30 +403,6 @@ __device__ inline double wave_max(double v) {
 }
 __device__ inline double wave_min(double v) {
     for (int off = WAVE / 2; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
-    return v;
-}
-
-// v from the lane selected by the DPP control CTRL within the rows of
-// ROWMASK, 0 where that lane is outside the row
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_in(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, true);
-    return __hiloint2double(hi, lo);
-}
-
-// sum over a group of G lanes (16: one DPP row; 64: the wavefront), valid in
-// the group's last lane
-template <int G>
-__device__ __forceinline__ double group_sum(double v) {
-    v += dpp_in<0x111, 0xF>(v);   // row_shr:1
-    v += dpp_in<0x112, 0xF>(v);   // row_shr:2
-    v += dpp_in<0x114, 0xF>(v);   // row_shr:4
-    v += dpp_in<0x118, 0xF>(v);   // row_shr:8
-    if constexpr (G == 64) {
-        v += dpp_in<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-        v += dpp_in<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
-    }
     return v;
 }
 

@@ -6,6 +6,7 @@
 // the structural nonzeros.  All loops over slots and mask bits are
 // wave-uniform (scalar branches).
 #include "solve_kernels.h"
+#include "dpp.h"
 
 #include <algorithm>
 #include <climits>
@@ -428,35 +429,11 @@ __device__ __forceinline__ void row_sub_c(const RowView<T>& A, int row, int lane
     for (int rr = 0; rr < D; ++rr) acc[rr] -= rr == r ? sum : T(0);
 }
 
-// v from lane src (by the DPP control CTRL, in the rows of ROWMASK; 0 where
-// the source lane is out of range or the row is masked)
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ float dpp_in(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, true));
-}
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_in(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, true);
-    return __hiloint2double(hi, lo);
-}
-
-// Sum over the wavefront, valid in lane WAVE - 1: shifts by 1, 2, 4 and 8
-// inside each row of 16 lanes leave every row's sum in its last lane, then
-// the row broadcasts 15 and 31 add the rows up.
+// Sum over the wavefront, valid in lane WAVE - 1, per component.
 template <class T, int D>
 __device__ __forceinline__ void wave_sum_vec(T (&acc)[D]) {
 #pragma unroll
-    for (int r = 0; r < D; ++r) {
-        T v = acc[r];
-        v += dpp_in<0x111, 0xF>(v);   // row_shr:1
-        v += dpp_in<0x112, 0xF>(v);   // row_shr:2
-        v += dpp_in<0x114, 0xF>(v);   // row_shr:4
-        v += dpp_in<0x118, 0xF>(v);   // row_shr:8
-        v += dpp_in<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-        v += dpp_in<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
-        acc[r] = v;
-    }
+    for (int r = 0; r < D; ++r) acc[r] = group_sum<64>(acc[r]);
 }
 
 // Sum of the RP wavefronts' partial sums of one row (each valid in its lane
@@ -666,25 +643,11 @@ __global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_xfer(XferArgs<T
     store_vec<T, D>(a.y[f] + (int64_t)row * D, out);
 }
 
-// Sum over groups of G lanes (G = 4, 8, 16 or 64, groups aligned in the
-// wavefront), valid in each group's last lane: the row shifts by 1, 2, 4 and 8
-// only ever add lanes of the same group into that lane.
+// Sum over aligned groups of G lanes, valid in each group's last lane, per component.
 template <class T, int D, int G>
 __device__ __forceinline__ void group_sum_vec(T (&acc)[D]) {
-    static_assert(G == 4 || G == 8 || G == 16 || G == 64, "group of 4, 8, 16 or 64 lanes");
 #pragma unroll
-    for (int r = 0; r < D; ++r) {
-        T v = acc[r];
-        v += dpp_in<0x111, 0xF>(v);   // row_shr:1
-        v += dpp_in<0x112, 0xF>(v);   // row_shr:2
-        if constexpr (G >= 8) v += dpp_in<0x114, 0xF>(v);   // row_shr:4
-        if constexpr (G >= 16) v += dpp_in<0x118, 0xF>(v);  // row_shr:8
-        if constexpr (G == 64) {
-            v += dpp_in<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-            v += dpp_in<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
-        }
-        acc[r] = v;
-    }
+    for (int r = 0; r < D; ++r) acc[r] = group_sum<G>(acc[r]);
 }
 
 // coarse b_k = sum over members i of aggregate k of q_i .* r_i (per component):
