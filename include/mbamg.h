@@ -144,7 +144,9 @@ mbamg_status mbamg_apply(mbamg_hierarchy* h, const double* x, double* w, void* h
 /* Solve A x = b by restarted GMRES (FGMRES when precision == 1), right
  * preconditioned by one V-cycle, to ||b - A x|| <= rtol ||b||.  x is read as
  * the initial guess and overwritten.  Returns MBAMG_NOT_CONVERGED after
- * max_iters.  info may be NULL.  Synchronous. */
+ * max_iters.  info may be NULL.  Synchronous.  On a one-level hierarchy (a
+ * system no larger than max_coarse) the preconditioner is the dense inverse,
+ * so the solve stops after one iteration (a few in the FP32 form). */
 mbamg_status mbamg_solve(mbamg_hierarchy* h, const double* b, double* x, double rtol,
                          mbamg_info* info, void* hip_stream);
 

@@ -101,6 +101,7 @@ struct Level {
     int n = 0;
     int d[2] = {0, 0};
     bool coarsest = false;
+    bool apply_parts = false;                  // coarsest level with its sliced operator (single-level hierarchy)
     SetupBsr A[2][2];
     Aggregates G;
     BlockLevel blk[2];
@@ -862,6 +863,21 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
             B.d_perm.upload(B.perm, s);   // used at the interface when this is the only level
             B.d_iperm.upload(B.iperm, s);
         }
+        if (h->L.size() == 1) {
+            // the only level: the operator apply of the Krylov solver reads its blocks in the
+            // sliced form (FP64, identity order, one colour); the V-cycle is the dense solve
+            for (int f = 0; f < 2; ++f) {
+                BlockLevel& B = c.blk[f];
+                const int g = 1 - f;
+                build_part(B.off, PartKind::Off, B, &c.A[f][f], B.d_iperm.p, c.A[f][f].val.p, c.d[f], c.d[f], false,
+                           s);
+                build_part(B.diag, PartKind::Diag, B, &c.A[f][f], B.d_iperm.p, c.A[f][f].val.p, c.d[f], c.d[f],
+                           false, s);
+                build_part(B.cpl, PartKind::Cpl, B, &c.A[f][g], c.blk[g].d_iperm.p, c.A[f][g].val.p, c.d[f], c.d[g],
+                           false, s);
+            }
+            c.apply_parts = true;
+        }
         alloc_vecs(c.v64, (int64_t)c.n * (d0 + d1));
         if (want32) alloc_vecs(c.v32, (int64_t)c.n * (d0 + d1));
     }
@@ -1410,7 +1426,7 @@ static void from_colour(mbamg_hierarchy* h, const double* src, double* dst, hipS
 // A x on the finest level (colour order), FP64
 static void apply_A(mbamg_hierarchy* h, const double* x, double* w, hipStream_t s, int kind = 2) {
     Level& L0 = *h->L[0];
-    if (L0.coarsest) throw Error(MBAMG_E_STATE, "single-level hierarchy: operator apply needs at least two levels");
+    if (L0.coarsest && !L0.apply_parts) throw Error(MBAMG_E_STATE, "internal: finest-level operator missing");
     resid<double>(h, 0, nullptr, x, w, s, kind);
 }
 
@@ -1440,7 +1456,6 @@ static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, d
     const int64_t n = h->n_fine;
     const int m = h->p.restart;
     const bool fp32 = h->p.precision == 1;
-    MB_CHECK(!h->L[0]->coarsest, MBAMG_E_STATE, "solve needs at least two levels");
     to_colour(h, b, h->bw.p, s);
     to_colour(h, x, h->xw.p, s);
     const double bnorm = std::sqrt(norm2_dev(h, h->bw.p, s));

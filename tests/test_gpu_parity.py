@@ -140,6 +140,31 @@ def test_single_level_is_direct_solve():
     assert rel(z.cpu().numpy(), ref) <= 1e-12
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_single_level_solve(precision):
+    """A system no larger than max_coarse is one level: the V-cycle is the dense
+    solve, so right-preconditioned GMRES with M = A^-1 (up to rounding; FP32 in the
+    flexible form) stops after one iteration (a few in FP32), the operator apply is the
+    assembled matrix's product, and the solution is dense LU's."""
+    s = make_system(7, 2, 0.5, seed=4)
+    hg = gpu_hierarchy(s, max_coarse=10 ** 6, precision=precision)
+    assert hg.num_levels() == 1
+    A = s.to_scipy()
+    xr = np.random.default_rng(3).standard_normal(s.n_dofs)
+    w = torch_dev(np.zeros(s.n_dofs))
+    hg.apply(torch_dev(xr), w)
+    assert rel(w.cpu().numpy(), A @ xr) <= 1e-14
+    x = torch_dev(np.zeros(s.n_dofs))
+    info = hg.solve(torch_dev(s.b), x, rtol=1e-10)
+    xg = x.cpu().numpy()
+    log(f"  precision={precision} its={info['iterations']} rel={info['rel_residual']:.2e}")
+    assert info["converged"] and info["levels"] == 1
+    assert info["iterations"] <= (1 if precision == 0 else 3)
+    assert np.linalg.norm(s.b - A @ xg) <= 1e-10 * np.linalg.norm(s.b) * (1 + 1e-6)
+    assert rel(xg, np.linalg.solve(A.toarray(), s.b)) <= 1e-9
+    hg.close()
+
+
 def test_invalid_arguments_are_rejected():
     from paper_2103_07537_amd import mbamg
     s = make_system(8, 2, 0.5, seed=2)
