@@ -1563,7 +1563,6 @@ static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, d
 // Asymptotic factor of e <- e - M A e from a seeded start (colour order).
 static double probe_impl(mbamg_hierarchy* h, int iters, uint64_t seed, hipStream_t s) {
     MB_CHECK(iters >= 5, MBAMG_E_INVALID, "probe needs at least 5 iterations");
-    MB_CHECK(!h->L[0]->coarsest, MBAMG_E_STATE, "probe needs at least two levels");
     const int64_t n = h->n_fine;
     double* e = h->vio.p;
     launch_seeded(n, seed, h->vio2.p, s);   // generated in the interface order, then reordered

@@ -165,6 +165,29 @@ def test_single_level_solve(precision):
     hg.close()
 
 
+def test_single_level_judged_learned_setup():
+    """The learned form with its judge on a one-level system: there are no
+    aggregates to weight, both hierarchies are the dense solve, both probes
+    measure rounding, and either one solves in one iteration."""
+    s = make_system(6, 2, 0.5, seed=3)
+    calls = []
+
+    def wfn(level, n_agg, F):
+        calls.append(level)
+        return np.full(n_agg, 0.5), np.full(n_agg, 0.8)
+
+    hg = gpu_hierarchy(s, max_coarse=10 ** 6, weights=wfn, judge=1)
+    assert hg.num_levels() == 1 and calls == []
+    rho = hg.probe()
+    log(f"  probe {rho:.2e}")
+    assert 0.0 <= rho <= 1e-6
+    x = torch_dev(np.zeros(s.n_dofs))
+    info = hg.solve(torch_dev(s.b), x, rtol=1e-10)
+    assert info["converged"] and info["iterations"] == 1
+    assert rel(x.cpu().numpy(), np.linalg.solve(s.to_scipy().toarray(), s.b)) <= 1e-9
+    hg.close()
+
+
 def test_invalid_arguments_are_rejected():
     from paper_2103_07537_amd import mbamg
     s = make_system(8, 2, 0.5, seed=2)
