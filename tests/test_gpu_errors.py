@@ -97,3 +97,37 @@ def test_singular_nodal_block_with_judge_is_reported():
     log(f"  {e.value}")
     assert e.value.code == E_SINGULAR
     _still_works()
+
+
+def test_empty_system_is_rejected():
+    """No nodes: setup returns the invalid-input code before any device work."""
+    from paper_2103_07537_amd import mbamg
+    from paper_2103_07537_amd.inputs import Bsr
+    s = _small()
+    empty = [[Bsr(0, 0, np.zeros(1, np.int32), np.zeros(0, np.int32),
+                  np.zeros((0, s.dofs[f], s.dofs[g]))) for g in range(2)] for f in range(2)]
+    with pytest.raises(mbamg.MbamgError) as e:
+        mbamg.Hierarchy(empty, s.dofs, s.n_vec)
+    log(f"  {e.value}")
+    assert e.value.code == E_INVALID
+    _still_works()
+
+
+def test_zero_rhs_and_converged_initial_guess():
+    """b = 0 gives x = 0 without an iteration whatever x held; an initial guess
+    that already meets the tolerance (dense LU's solution) is returned after no
+    iteration, unchanged up to the colour-order round trip (exact)."""
+    s = _small()
+    hg = gpu_hierarchy(s, max_coarse=60)
+    assert hg.num_levels() >= 2
+    x = torch_dev(np.random.default_rng(1).standard_normal(s.n_dofs))
+    info = hg.solve(torch_dev(np.zeros(s.n_dofs)), x, rtol=1e-8)
+    assert info["converged"] and info["iterations"] == 0
+    assert not np.any(x.cpu().numpy())
+    xs = np.linalg.solve(s.to_scipy().toarray(), s.b)
+    x = torch_dev(xs)
+    info = hg.solve(torch_dev(s.b), x, rtol=1e-8)
+    log(f"  exact guess: its={info['iterations']} rel={info['rel_residual']:.2e}")
+    assert info["converged"] and info["iterations"] == 0
+    assert np.array_equal(x.cpu().numpy(), xs)
+    hg.close()
