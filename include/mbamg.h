@@ -205,6 +205,23 @@ mbamg_status mbamg_mlp_forward(const float* params, const float* x, int64_t n, f
 mbamg_status mbamg_mlp_loss_grad(const float* params, const float* x, const float* target, int64_t n,
                                  float* grad, float* loss, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, training loops that must not call hipMalloc): the same loss and
+ * gradient as mbamg_mlp_loss_grad, bit for bit (same grid, same summation
+ * order), with the per-wavefront partial sums kept in a static device buffer
+ * of 20.0 MiB (256 workgroups x 4 wavefronts x 5123 floats) instead of
+ * library-allocated memory.  It calls no allocator: each GPU holds its own
+ * copy of the buffer, reserved when the library's code is loaded on it and
+ * held until the process ends; its device address is looked up on the first
+ * call on each device.  The need does not grow with n (at most 256 workgroups
+ * for any batch), so every n > 0 fits; a grid that would need more than the
+ * buffer holds is rejected with MBAMG_E_INVALID.  The buffer keeps the last
+ * call's contents; every call overwrites all the entries it reads, so nothing
+ * needs clearing.  Calls that overlap on one GPU (two streams, two threads)
+ * share the buffer and race: serialise them.  Device pointers, asynchronous. */
+mbamg_status mbamg_mlp_loss_grad_noalloc(const float* params, const float* x, const float* target, int64_t n,
+                                         float* grad, float* loss, void* hip_stream);
+
 /* One Adam step (Kingma & Ba 2015) on the 5122 parameters with moment buffers
  * m, v (device); step counts from 1.  Asynchronous. */
 mbamg_status mbamg_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr,

@@ -1952,6 +1952,15 @@ mbamg_status mbamg_mlp_loss_grad(const float* params, const float* x, const floa
     });
 }
 
+mbamg_status mbamg_mlp_loss_grad_noalloc(const float* params, const float* x, const float* target, int64_t n,
+                                         float* grad, float* loss, void* hip_stream) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(params && x && target && grad && n > 0, MBAMG_E_INVALID, "bad argument");
+        mlp_loss_grad_noalloc(params, x, target, n, grad, loss, (hipStream_t)hip_stream);
+        return MBAMG_OK;
+    });
+}
+
 mbamg_status mbamg_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr, float beta1,
                             float beta2, float eps, void* hip_stream) {
     return guarded([&]() -> mbamg_status {

@@ -22,6 +22,9 @@ void mlp_forward(const float* th, const float* x, int64_t n, float* out, hipStre
 // grad[5122] and loss[1] of the mean squared error against t[n][2]
 void mlp_loss_grad(const float* th, const float* x, const float* t, int64_t n, float* grad, float* loss,
                    DevBuf<float>& partial, hipStream_t s);
+// the same, with the partial sums in a static per-device buffer (no allocation)
+void mlp_loss_grad_noalloc(const float* th, const float* x, const float* t, int64_t n, float* grad, float* loss,
+                           hipStream_t s);
 void mlp_adam(float* th, const float* g, float* m, float* v, int64_t step, float lr, float b1, float b2, float eps,
               hipStream_t s);
 // 12 features per aggregate; normalised with (mean, stdv) when mean != NULL (synchronous)

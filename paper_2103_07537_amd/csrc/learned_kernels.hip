@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 namespace mbamg {
 
@@ -656,6 +657,53 @@ void mlp_loss_grad(const float* th, const float* x, const float* t, int64_t n, f
     k_mlp_grad<<<blocks, 256, 0, s>>>(th, x, t, n, partial.p);
     MB_LAUNCH_CHECK();
     k_mlp_grad_reduce<<<gridn(N_MLP_PARAMS + 1), 256, 0, s>>>(partial.p, blocks * MLP_WAVES, grad, loss);
+    MB_LAUNCH_CHECK();
+}
+
+// Scratch of the allocation-free gradient: the per-wavefront partial sums of
+// k_mlp_grad for the largest grid mlp_loss_grad launches (MLP_MAX_BLOCKS
+// workgroups of MLP_WAVES wavefronts, N_MLP_PARAMS + 1 floats each:
+// 5,245,952 floats = 20.0 MiB).  Each GPU the library runs on holds its own
+// copy until the process ends.  In host code `scratch` names a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, once per
+// device, and only that address is ever passed to a kernel.
+constexpr int64_t NOALLOC_SCRATCH_FLOATS = (int64_t)MLP_MAX_BLOCKS * MLP_WAVES * (N_MLP_PARAMS + 1);
+static __device__ __align__(256) float scratch[NOALLOC_SCRATCH_FLOATS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+// Device address of this device's scratch array (looked up on the first call
+// on each device, with that device current).
+static float* scratch_address() {
+    static std::mutex mu;
+    static float* addr[NOALLOC_MAX_DEVICES] = {};
+    int dev = 0;
+    MB_HIP(hipGetDevice(&dev));
+    MB_CHECK(dev >= 0 && dev < NOALLOC_MAX_DEVICES, MBAMG_E_INVALID, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        MB_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        MB_CHECK(p != nullptr, MBAMG_E_HIP, "scratch symbol has no device address");
+        addr[dev] = static_cast<float*>(p);
+    }
+    return addr[dev];
+}
+
+void mlp_loss_grad_noalloc(const float* th, const float* x, const float* t, int64_t n, float* grad, float* loss,
+                           hipStream_t s) {
+    MB_CHECK(n > 0, MBAMG_E_INVALID, "empty batch");
+    // the same grid as mlp_loss_grad, so the partial sums and their reduction order are the same
+    const int blocks = (int)std::min<int64_t>(MLP_MAX_BLOCKS, ceil_div(n, 64));
+    const int64_t need = (int64_t)blocks * MLP_WAVES * (N_MLP_PARAMS + 1);
+    MB_CHECK(need <= NOALLOC_SCRATCH_FLOATS, MBAMG_E_INVALID,
+             "gradient scratch: the grid needs more than the 20 MiB static buffer holds");
+    float* partial = scratch_address();
+    // every wavefront of the grid writes all N_MLP_PARAMS + 1 of its entries and the
+    // reduction reads only those: nothing needs clearing, stale entries are never read
+    k_mlp_grad<<<blocks, 256, 0, s>>>(th, x, t, n, partial);
+    MB_LAUNCH_CHECK();
+    k_mlp_grad_reduce<<<gridn(N_MLP_PARAMS + 1), 256, 0, s>>>(partial, blocks * MLP_WAVES, grad, loss);
     MB_LAUNCH_CHECK();
 }
 

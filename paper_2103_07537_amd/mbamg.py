@@ -85,6 +85,7 @@ SIGNATURES = [
     ("mbamg_level_weights", ctypes.c_int, [_P, _I32, _P, _P]),
     ("mbamg_mlp_forward", ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
     ("mbamg_mlp_loss_grad", ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P, _P]),
+    ("mbamg_mlp_loss_grad_noalloc", ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P, _P]),
     ("mbamg_mlp_adam", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_float, _P]),
     ("mbamg_probe", ctypes.c_int, [_P, _I32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), _P]),
@@ -338,6 +339,11 @@ def mlp_loss_grad(params, x, target, grad, loss, stream=None):
     _check(lib().mbamg_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(target), x.shape[0], _ptr(grad), _ptr(loss),
                                      _stream_ptr(stream)))
     return grad, loss
+
+
+def mlp_loss_grad_noalloc(params, x, target, grad, loss, stream=None):
+    _check(lib().mbamg_mlp_loss_grad_noalloc(_ptr(params), _ptr(x), _ptr(target), x.shape[0], _ptr(grad),
+                                             _ptr(loss), _stream_ptr(stream)))
 
 
 def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
