@@ -153,3 +153,107 @@ def test_features_properties_and_brute_force():
         assert F[k, 6] == pytest.approx(np.sqrt(num / den), rel=1e-12)
         off = [sum(np.mean(np.abs(np.diag(blk(A00, i, j))[:2])) for j in range(n) if j != i) for i in mem]
         assert F[k, 8] == pytest.approx(np.mean(np.array(off) / dv[mem]), rel=1e-12)
+
+
+def _brute_features(lev, n_vec, level):
+    """All twelve features node by node from dense blocks and the stored-block
+    pattern, following the definitions in the oracle's docstring."""
+    n, nagg, agg = lev.n, lev.n_agg, lev.agg
+    dense = [[lev.A[f][g].csr().toarray() for g in range(2)] for f in range(2)]
+    d0, d1 = lev.dofs
+    nv0, nv1 = n_vec
+
+    def blk(f, g, i, j):
+        df, dg = lev.dofs[f], lev.dofs[g]
+        return dense[f][g][i * df:(i + 1) * df, j * dg:(j + 1) * dg]
+
+    def stored(f, g, i):
+        A = lev.A[f][g]
+        return [int(j) for j in A.ci[A.rp[i]:A.rp[i + 1]]]
+
+    def dv(f, i):
+        nv = n_vec[f]
+        return np.mean([blk(f, f, i, i)[c, c] for c in range(nv)])
+
+    def c(f, i, j):
+        nv = n_vec[f]
+        return np.mean([abs(blk(f, f, i, j)[a, a]) for a in range(nv)])
+
+    ld = np.array([np.log(dv(0, i)) for i in range(n)])
+    F = np.zeros((nagg, 12))
+    for k in range(nagg):
+        mem = [i for i in range(n) if agg[i] == k]
+        m = len(mem)
+        lk = ld[mem]
+        F[k, 0] = lk.mean() - ld.mean()
+        F[k, 1] = np.sqrt(np.mean((lk - lk.mean()) ** 2))
+        F[k, 2] = lk.max() - lk.min()
+        inner = [c(0, i, j) for i in mem for j in stored(0, 0, i) if j != i and agg[j] == k]
+        F[k, 3] = np.log(max(inner)) - np.log(min(inner)) if inner and min(inner) > 0 else 0.0
+        F[k, 4] = m / (n / nagg)
+        tot = sum(c(0, i, j) for i in mem for j in stored(0, 0, i) if j != i)
+        out = sum(c(0, i, j) for i in mem for j in stored(0, 0, i) if j != i and agg[j] != k)
+        F[k, 5] = out / tot if tot > 0 else 0.0
+        fro = lambda f, g: sum(np.sum(blk(f, g, i, j) ** 2) for i in mem for j in range(n))
+        F[k, 6] = np.sqrt(fro(0, 1)) / np.sqrt(fro(0, 0))
+        F[k, 7] = np.sqrt(fro(1, 0)) / np.sqrt(fro(1, 1))
+        F[k, 8] = np.mean([sum(c(0, i, j) for j in stored(0, 0, i) if j != i) / dv(0, i) for i in mem])
+        F[k, 9] = np.mean([sum(c(1, i, j) for j in stored(1, 1, i) if j != i) / dv(1, i) for i in mem])
+        if d0 > nv0:
+            F[k, 10] = np.mean([sum(np.sum(blk(0, 0, i, j)[:nv0, nv0:] ** 2) for j in range(n))
+                                / (dv(0, i) * abs(blk(0, 0, i, i)[nv0, nv0])) for i in mem])
+        F[k, 11] = level / 4.0
+    return F
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_every_feature_column_matches_brute_force(case):
+    if case == "2d":
+        s = make_system(12, 2, 0.8, seed=4, kappa="lognormal", blk1_scale=1.7, a10_scale=0.6)
+        nv = (2, 2)
+    else:
+        s = make_system(5, 3, 1.3, seed=6, kappa="lognormal", blk1_scale=0.6, a10_scale=1.4)
+        nv = (3, 3)
+    h = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=1, max_levels=3,
+                                               weights=lambda l, n, F: (np.full(n, 0.3), np.ones(n))))
+    assert len(h.levels) >= 3
+    for l in range(2):      # the finest level and a Galerkin level (denser blocks, level feature 1/4)
+        lev = h.levels[l]
+        ref = _brute_features(lev, nv, l)
+        got = lev.features
+        assert got.shape == ref.shape
+        for col in range(12):
+            assert np.allclose(got[:, col], ref[:, col], rtol=1e-11, atol=1e-12), (l, col)
+        # the spread features are not all trivial in these cases
+        if lev.n_agg >= 3:
+            assert np.ptp(got[:, 3]) > 0 and np.ptp(got[:, 5]) > 0 and np.ptp(got[:, 10]) > 0
+
+
+def test_emulated_gradient_stays_within_the_bfloat16_bound():
+    # With emulation the products take bfloat16 operands (inputs, weights, hidden activations
+    # and the backward signals dO, dZ2, dZ1) and keep every sum in FP64.  Each emulated
+    # gradient entry is then the exact one up to a few relative roundings of 2^-8 in every
+    # term: bounded by a small multiple of 2^-8 times the same products taken over absolute
+    # values.  A dropped term, a wrong sign or a transposed operand moves an entry by an
+    # amount of the order of that absolute scale and fails the bound.
+    th = learned.init_params(11)
+    th[4992:5122] = np.random.default_rng(12).standard_normal(130) * 0.5
+    X = np.random.default_rng(13).standard_normal((300, 12))
+    T = np.stack([np.random.default_rng(14).uniform(0, 0.8, 300), np.random.default_rng(15).uniform(0.3, 1.3, 300)], 1)
+    L, g = learned.loss_grad(th, X, T)
+    Le, ge = learned.loss_grad(th, X, T, emulate=True)
+    # absolute-value scale of each gradient entry, from the exact forward pass
+    W1, b1, W2, b2, W3, b3 = learned.unpack(th)
+    out, (Xr, z1, h1, z2, h2, o, s) = learned.forward(th, X)
+    n = X.shape[0]
+    scale = np.array([learned.OMEGA_P_MAX, learned.OMEGA_S_SPAN])
+    dO = np.abs(2.0 / n * (np.abs(out - T) + 0.05) * scale * s * (1 - s))
+    a2 = dO @ np.abs(W3)
+    a1 = a2 @ np.abs(W2)
+    absg = np.concatenate([(a1.T @ np.abs(X)).ravel(), a1.sum(0), (a2.T @ h1).ravel(), a2.sum(0),
+                           (dO.T @ h2).ravel(), dO.sum(0)])
+    err = np.abs(ge - g)
+    assert np.all(err <= 16 * 2.0 ** -8 * absg + 1e-12)
+    assert abs(Le - L) <= 16 * 2.0 ** -8 * abs(L)
+    # and the emulation does round: the two differ
+    assert np.max(err) > 0
