@@ -257,3 +257,30 @@ def test_emulated_gradient_stays_within_the_bfloat16_bound():
     assert abs(Le - L) <= 16 * 2.0 ** -8 * abs(L)
     # and the emulation does round: the two differ
     assert np.max(err) > 0
+
+
+def test_forward_special_cases_in_closed_form():
+    # all weights zero: the outputs are the output biases through the two range maps
+    th = np.zeros(learned.N_PARAMS)
+    th[5120:5122] = [0.7, -1.2]
+    out, _ = learned.forward(th, np.random.default_rng(0).standard_normal((5, 12)))
+    sig = lambda z: 1.0 / (1.0 + np.exp(-z))
+    assert np.allclose(out[:, 0], 5.0 / 6.0 * sig(0.7), rtol=1e-15)
+    assert np.allclose(out[:, 1], 0.3 + sig(-1.2), rtol=1e-15)
+    # selection weights on non-negative inputs: layer 1 copies the features into hidden units
+    # 0..11 (ReLU is the identity there), layer 2 copies them on, layer 3 reads feature 2 into
+    # output 0 and minus feature 5 into output 1, plus the biases
+    th = np.zeros(learned.N_PARAMS)
+    W1 = np.zeros((64, 12)); W1[np.arange(12), np.arange(12)] = 1.0
+    W2 = np.eye(64)
+    W3 = np.zeros((2, 64)); W3[0, 2] = 1.0; W3[1, 5] = -1.0
+    th[0:768] = W1.ravel(); th[832:4928] = W2.ravel(); th[4992:5120] = W3.ravel()
+    th[768:832] = 0.0; th[4928:4992] = 0.0; th[5120:5122] = [0.25, 0.5]
+    X = np.abs(np.random.default_rng(1).standard_normal((7, 12)))
+    out, _ = learned.forward(th, X)
+    assert np.allclose(out[:, 0], 5.0 / 6.0 * sig(X[:, 2] + 0.25), rtol=1e-14)
+    assert np.allclose(out[:, 1], 0.3 + sig(-X[:, 5] + 0.5), rtol=1e-14)
+    # a negative hidden pre-activation is cut by the ReLU: feature 2 negated never reaches output 0
+    X2 = X.copy(); X2[:, 2] = -X[:, 2]
+    out2, _ = learned.forward(th, X2)
+    assert np.allclose(out2[:, 0], 5.0 / 6.0 * sig(0.25), rtol=1e-14)
