@@ -95,6 +95,9 @@ FORMS = {
 
 
 def run_step(blocks, system, b, form, rtol, timing, mlp=None):
+    """One step: setup + solve.  timing: the library's event mode (0 off; 1
+    every kind; 2 whole V-cycles; 3 V-cycles and levels), for the untimed
+    profiling steps only."""
     from paper_2103_07537_amd import mbamg
     import torch
     precision, use_mlp = FORMS[form]
@@ -102,15 +105,45 @@ def run_step(blocks, system, b, form, rtol, timing, mlp=None):
     h = mbamg.Hierarchy(blocks, system.dofs, system.n_vec, precision=precision, mlp=mlp if use_mlp else None)
     t1 = time.perf_counter()
     if timing:
-        h.timing_enable(True)
+        h.timing_enable(timing)
     x = torch.zeros_like(b)
     info = h.solve(b, x, rtol=rtol)
     t2 = time.perf_counter()
-    log(f"[bench]   {form}: hierarchy {1e3 * (t1 - t0):.1f} ms, solve {1e3 * (t2 - t1):.1f} ms (wall)")
-    stats = None
-    if timing:
-        stats = {k: h.timing_get(k) for k in (0, 1, 2, 3)}
-    return h, x, info, stats
+    log(f"[bench]   {form}: hierarchy {1e3 * (t1 - t0):.1f} ms, solve {1e3 * (t2 - t1):.1f} ms (wall)"
+        + (f" [profiling step, event mode {timing}]" if timing else ""))
+    return h, x, info
+
+
+def profile_steps(blocks, system, b, form, rtol, mlp):
+    """Untimed steps with HIP events: the V-cycle as the solver applies it
+    (mode 2, nothing else timed), each level's share (mode 3), and for the FP64
+    form the finest level's kernels (mode 1)."""
+    out = {}
+    h, _, info = run_step(blocks, system, b, form, rtol, 2, mlp)
+    v = h.timing_get(4)
+    out["vcycle_in_solve_ms"] = v["total_ms"] / max(v["launches"], 1)
+    out["vcycle_in_solve_count"] = v["launches"]
+    bytes_total = h.vcycle_bytes()
+    h.close()
+    h, _, info = run_step(blocks, system, b, form, rtol, 3, mlp)
+    levels = []
+    for l in range(h.num_levels()):
+        down_b, up_b = h.level_vcycle_bytes(l)
+        dn, up = h.timing_get(16 + 2 * l), h.timing_get(17 + 2 * l)
+        cyc = max(dn["launches"], 1)
+        ms = (dn["total_ms"] + up["total_ms"]) / cyc
+        levels.append({"level": l, "nodes": h.level_nodes(l), "ms_per_cycle": ms,
+                       "down_ms": dn["total_ms"] / cyc, "up_ms": up["total_ms"] / cyc,
+                       "alg_bytes": down_b + up_b,
+                       "alg_GBps": (down_b + up_b) / (ms * 1e-3) / 1e9 if ms > 0 else None})
+    out["levels"] = levels
+    h.close()
+    out["vcycle_bytes"] = bytes_total
+    if form == "fp64":
+        h, _, info = run_step(blocks, system, b, form, rtol, 1, mlp)
+        out["kernel_stats"] = {k: h.timing_get(k) for k in (0, 1, 2, 3)}
+        h.close()
+    return out
 
 
 def vcycle_rate(h, b, reps):
@@ -155,20 +188,42 @@ def stream_copy_rate():
     return 2.0 * (1 << 30) / (float(np.median(times)) * 1e-3) / 1e9
 
 
+def host_cpu():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model or platform.processor() or platform.machine(), "nproc": os.cpu_count(),
+            "usable_cpus": usable}
+
+
 def cpu_baseline(args, form, gpu_iters, mlp):
     """The oracle, single-threaded, on a bounded sample of the same workload
-    family (a smaller grid of the same generator) doing the same work as the
+    family (the same generator on a smaller grid) doing the same work as the
     reported form: for the learned form the oracle runs the same network
     (bfloat16-emulated) on its own features, builds the fixed hierarchy too and
-    lets the two probes judge.  The measured time is scaled linearly by the
-    unknown ratio and, for the solve, to the GPU's iteration count."""
+    lets the two probes judge.  The sample is timed as it stands; `value` is
+    that time extrapolated linearly to the full workload (by the unknown ratio,
+    and for the solve to the GPU's iteration count) and is labelled so.  The
+    GPU solves the same sample system in the same form, and its solution's
+    difference from the oracle's is reported."""
+    import torch
     from threadpoolctl import threadpool_limits
     from oracle import amg
+    from paper_2103_07537_amd import mbamg
     from paper_2103_07537_amd.inputs import WORKLOADS, make_system
     kw = dict(WORKLOADS[args.workload])
     full_n = kw["n"]
     dim = kw["dim"]
-    n_s = min(args.cpu_sample_n or (40 if dim == 3 else 256), full_n)
+    n_s = min(args.cpu_sample_n or (48 if dim == 3 else 256), full_n)
     kw["n"] = n_s
     s = make_system(seed=args.seed, **kw)
     learned_form = FORMS[form][1] and mlp is not None
@@ -184,23 +239,45 @@ def cpu_baseline(args, form, gpu_iters, mlp):
     with threadpool_limits(1):
         t0 = time.perf_counter()
         h = amg.setup(s.blocks, s.dofs, amg.Params(weights=weights), n_vec=s.n_vec)
+        used_learned = learned_form
         if learned_form:
             hf = amg.setup(s.blocks, s.dofs, amg.Params(), n_vec=s.n_vec)
             if not amg.probe(h, 10, 12345) < amg.probe(hf, 10, 12345):
                 h = hf
+                used_learned = False
         t1 = time.perf_counter()
-        x, info = amg.gmres(h, s.b, rtol=args.rtol)
+        xo, info = amg.gmres(h, s.b, rtol=args.rtol)
         t2 = time.perf_counter()
+    # the GPU on the same sample system, same form
+    precision, _ = FORMS[form]
+    hg = mbamg.Hierarchy(mbamg.to_device(s), s.dofs, s.n_vec, precision=precision,
+                         mlp=mlp if learned_form else None)
+    bg = torch.from_numpy(s.b).cuda()
+    xg = torch.zeros_like(bg)
+    ginfo = hg.solve(bg, xg, rtol=args.rtol)
+    xg = xg.cpu().numpy()
+    hg.close()
+    err = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
     ratio = (full_n / n_s) ** dim
     per_it = (t2 - t1) / max(info.iterations, 1)
     est_ms = 1e3 * ((t1 - t0) * ratio + per_it * ratio * gpu_iters)
     what = ("learned and fixed setups, both probes, " if learned_form else "setup, ") + "GMRES(30)"
     return {
         "value": est_ms, "unit": "ms", "cores": 1, "kind": "oracle",
+        "extrapolated": n_s < full_n,
         "sample": (f"oracle ({what}, FP64, one thread) on the same generator at {n_s}^{dim} nodes "
-                   f"({s.n_dofs} unknowns, {info.iterations} iterations, {t2 - t0:.1f} s measured), "
-                   f"scaled linearly by the unknown ratio {ratio:.0f} and to the GPU's {gpu_iters} iterations"),
-        "host": platform.processor() or platform.machine(),
+                   f"({s.n_dofs} unknowns): {1e3 * (t1 - t0):.0f} ms setup + {1e3 * (t2 - t1):.0f} ms for "
+                   f"{info.iterations} iterations, measured; value = that time extrapolated linearly by the "
+                   f"unknown ratio {ratio:.1f} and to the GPU's {gpu_iters} iterations"
+                   + ("" if n_s < full_n else " (the sample is the full workload: no extrapolation)")),
+        "sample_measured": {"n": n_s, "unknowns": s.n_dofs, "setup_ms": 1e3 * (t1 - t0),
+                            "solve_ms": 1e3 * (t2 - t1), "iterations": info.iterations,
+                            "used_learned": bool(used_learned)},
+        "gpu_on_sample": {"iterations": ginfo["iterations"], "used_learned": ginfo["used_learned"],
+                          "t_setup_ms": ginfo["t_setup_ms"], "t_solve_ms": ginfo["t_solve_ms"],
+                          "rel_diff_vs_oracle_solution": err},
+        "host": host_cpu(),
+        "threads": 1,
     }
 
 
@@ -261,17 +338,16 @@ def main():
     xs = {}
     for form in forms:
         for w in range(args.warmup):
-            h, x, info, _ = run_step(blocks, system, b, form, args.rtol, False, mlp)
+            h, x, info = run_step(blocks, system, b, form, args.rtol, 0, mlp)
             log(f"[bench] warmup {form} {w}: its {info['iterations']} setup {info['t_setup_ms']:.1f} ms "
                 f"solve {info['t_solve_ms']:.1f} ms")
             h.close()
         torch.cuda.synchronize()
         t_start = time.perf_counter()
-        infos, stats_all = [], []
+        infos = []
         for k in range(args.steps):
-            h, x, info, stats = run_step(blocks, system, b, form, args.rtol, form == "fp64", mlp)
+            h, x, info = run_step(blocks, system, b, form, args.rtol, 0, mlp)
             infos.append(info)
-            stats_all.append(stats)
             if k < args.steps - 1:
                 tc = time.perf_counter()
                 h.close()
@@ -283,6 +359,9 @@ def main():
         log(f"[bench] {form}: {ms_step:.1f} ms/step, its {last['iterations']}, rel {last['rel_residual']:.2e}")
         vc_ms, vc_bytes = vcycle_rate(h, b, args.vcycles)
         xs[form] = x.cpu().numpy()
+        h.close()
+        prof = profile_steps(blocks, system, b, form, args.rtol, mlp)
+        vin = prof["vcycle_in_solve_ms"]
         results[form] = {
             "ms_per_step": ms_step,
             "t_setup_ms": float(np.median([i["t_setup_ms"] for i in infos])),
@@ -293,18 +372,25 @@ def main():
             "used_learned": last["used_learned"],
             "conv_factor": last["conv_factor"],
             "op_complexity": last["op_complexity"],
-            "vcycle_ms": vc_ms,
-            "vcycle_alg_GBps": vc_bytes / (vc_ms * 1e-3) / 1e9,
-            "vcycle_hbm_frac": vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "kernel_stats": stats_all[-1],
+            "vcycle_bytes": vc_bytes,
+            # the V-cycle as GMRES applies it (colour-order vectors; HIP events around each one
+            # in an untimed profiling step)
+            "vcycle_ms": vin,
+            "vcycle_alg_GBps": vc_bytes / (vin * 1e-3) / 1e9,
+            "vcycle_hbm_frac": vc_bytes / (vin * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            # the same through mbamg_vcycle: adds the natural <-> colour reordering of r and z
+            "vcycle_abi_ms": vc_ms,
+            "vcycle_abi_hbm_frac": vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "per_level": prof["levels"],
+            "kernel_stats": prof.get("kernel_stats"),
         }
-        h.close()
     ref = "fp64" if "fp64" in xs else forms[0]
     for form in forms:
         results[form]["rel_diff_vs_fp64"] = float(np.linalg.norm(xs[form] - xs[ref]) / np.linalg.norm(xs[ref]))
 
     chosen = next((f for f in ("learned", "fp32") if f in results), forms[0])
-    # roofline of the dominant finest-level kernel in the FP64 form (events over the timed steps)
+    # roofline of the dominant finest-level kernel in the FP64 form (HIP events around every launch of
+    # the finest level's kernels during an untimed profiling step: the timed steps carry no events)
     roof = None
     st = results.get("fp64", {}).get("kernel_stats")
     if st:

@@ -57,8 +57,13 @@ typedef enum {
     MBAMG_E_STATE = -5         /* the hierarchy cannot do this (e.g. wrong precision form) */
 } mbamg_status;
 
-/* One matrix block in BSR form.  nnzb == 0 (pointers may then be NULL) is a
- * zero block.  on_device != 0 means the three arrays are device pointers. */
+/* One matrix block A_fg of eq. block-prec-form in BSR form.  nnzb == 0
+ * (pointers may then be NULL) is a zero block.  on_device != 0 means the three
+ * arrays are device pointers.  mbamg_setup checks every block's structure --
+ * row_ptr[0] == 0, row_ptr[n_brows] == nnzb, non-decreasing row pointers,
+ * columns in range and strictly increasing within a row -- on the host for
+ * host input and with a check kernel on its own copy for device input, before
+ * any other kernel reads the block; a malformed block gives MBAMG_E_INVALID. */
 typedef struct {
     int32_t n_brows, n_bcols, br, bc;
     int64_t nnzb;
@@ -126,23 +131,36 @@ typedef struct mbamg_hierarchy mbamg_hierarchy;
 /* Fill *p with the defaults listed above. */
 void mbamg_default_params(mbamg_params* p);
 
-/* Build the hierarchy: strength graph of A_00, distance-2 aggregation cloned
- * to block 1, piecewise-constant P per block, Galerkin products for all four
- * blocks on every level, colouring and nodal D^-1 for the smoother, and the
- * inverse of the coarsest matrix.  A_blocks points to n_blocks*n_blocks
- * blocks in row-major order (A_00, A_01, A_10, A_11).  Synchronous. */
+/* Build the hierarchy (Sec. 3 and Sec. 4.3.1): strength graph of A_00 (the
+ * amalgamated node graph), distance-2 aggregation cloned to block 1 (the
+ * aggregate-cloning figure), piecewise-constant P per block assembled as the
+ * block-diagonal transfer of eq. blocktransfers, Galerkin products P^T A P for
+ * all four blocks on every level, colouring and nodal D^-1 for the smoother of
+ * Algorithm 1 (Sec. 4.3.2), and the inverse of the coarsest matrix.  A_blocks
+ * points to n_blocks*n_blocks blocks in row-major order (A_00, A_01, A_10,
+ * A_11), deep-copied.  The colouring of a diagonal block is taken over its
+ * symmetrised pattern, so A_11 need not be structurally symmetric.  *out
+ * receives the hierarchy (the caller releases it with mbamg_destroy), or NULL
+ * on an error, when whatever the build had allocated has been released.
+ * Synchronous. */
 mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm,
                          const mbamg_params* p, void* hip_stream, mbamg_hierarchy** out);
 
-/* z = M^-1 r: one V-cycle from a zero guess on the finest level.  r and z are
- * device vectors in the blocked layout and must not alias.  Asynchronous. */
+/* z = M^-1 r: one V-cycle (Sec. 3, MGV figure) from a zero guess on the
+ * finest level, pre- and post-smoothed by Algorithm 1 (Sec. 4.3.2), coarsest
+ * level solved directly.  r and z are caller-owned device vectors of
+ * sum_f n_nodes*dofs[f] doubles in the blocked layout; they must not alias
+ * (MBAMG_E_INVALID).  Asynchronous on the stream. */
 mbamg_status mbamg_vcycle(mbamg_hierarchy* h, const double* r, double* z, void* hip_stream);
 
-/* w = A x on the finest level (device vectors, must not alias).  Asynchronous. */
+/* w = A x with the four blocks of eq. 2x2system on the finest level (device
+ * vectors in the blocked layout, must not alias).  Asynchronous. */
 mbamg_status mbamg_apply(mbamg_hierarchy* h, const double* x, double* w, void* hip_stream);
 
-/* Solve A x = b by restarted GMRES (FGMRES when precision == 1), right
- * preconditioned by one V-cycle, to ||b - A x|| <= rtol ||b||.  x is read as
+/* Solve A x = b (eq. 2x2system) by restarted GMRES (FGMRES when
+ * precision == 1), right preconditioned by one V-cycle as in Sec. 5 (a
+ * multigrid V-cycle used as the Krylov preconditioner), to
+ * ||b - A x|| <= rtol ||b||.  b and x are caller-owned device vectors.  x is read as
  * the initial guess and overwritten.  Returns MBAMG_NOT_CONVERGED after
  * max_iters.  info may be NULL.  Synchronous.  On a one-level hierarchy (a
  * system no larger than max_coarse) the preconditioner is the dense inverse,
@@ -237,19 +255,32 @@ mbamg_status mbamg_set_omega(mbamg_hierarchy* h, double omega);
 
 /* ---- measurement -------------------------------------------------------- */
 
-/* Kernel timing with HIP events on the stream the kernels run on.  While
- * enabled, every launch of the finest level's smoother and residual kernels is
+/* Kernel timing with HIP events on the stream the kernels run on.  enable:
+ * 0 off; 1 every kind below; 2 only whole V-cycles (kind 4); 3 whole V-cycles
+ * and levels (kinds 4 and 16 + ...).  While mode 1 is on, every launch of the finest level's smoother and residual kernels is
  * bracketed by events.  kind 0: smoother colour passes from a nonzero iterate
  * with the coupling term (the post-smoother), 1: residual, 2: operator apply,
  * 3: the other smoother colour passes.  Reports launches, summed event time in
  * ms and the algorithmic bytes those launches move (structural values, block
- * indices, row pointers and vectors, each counted once per launch). */
-mbamg_status mbamg_timing_enable(mbamg_hierarchy* h, int32_t enable);
+ * indices, row pointers and vectors, each counted once per launch).
+ * kind 4: whole V-cycles as the solver and the probe apply them (colour order,
+ * without the interface's reordering or the FP32 form's casts; bytes 0).
+ * kind 16 + 2 l: level l's share of each V-cycle on the way down
+ * (pre-smoothing, residual, restriction; the coarsest level's direct solve);
+ * kind 17 + 2 l: on the way up (prolongation, post-smoothing); with the
+ * bytes of mbamg_level_vcycle_bytes.  Events add a little time: time with
+ * timing disabled, collect these in a separate run. */
+mbamg_status mbamg_timing_enable(mbamg_hierarchy* h, int32_t enable);   /* resets the collected events */
 mbamg_status mbamg_timing_get(mbamg_hierarchy* h, int32_t kind, int64_t* launches,
                               double* total_ms, double* bytes);
 
 /* Algorithmic bytes of one V-cycle of the current hierarchy and form. */
 mbamg_status mbamg_vcycle_bytes(const mbamg_hierarchy* h, double* bytes);
+
+/* The same for level l's share: *down on the way down (pre-smoothing,
+ * residual, restriction; on the coarsest level its direct solve), *up on the
+ * way up (prolongation, post-smoothing). */
+mbamg_status mbamg_level_vcycle_bytes(const mbamg_hierarchy* h, int32_t level, double* down, double* up);
 
 #ifdef __cplusplus
 }

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <memory>
 #include <numeric>
+#include <optional>
 
 #include "learned_kernels.h"
 #include "setup_kernels.h"
@@ -219,7 +220,10 @@ struct mbamg_hierarchy {
     DevBuf<double> vio2;
     mbamg_info info{};
     // timing
-    bool timing = false;
+    int timing = 0;                // mbamg_timing_enable's mode
+    bool time_launches() const { return timing == 1; }
+    bool time_levels() const { return timing == 1 || timing == 3; }
+    bool time_vcycles() const { return timing != 0; }
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
     double t_setup_ms = 0.0;
@@ -330,20 +334,46 @@ static void copy_block(const mbamg_bsr& src, SetupBsr& dst, int n_rows, int n_co
     MB_HIP(hipMemcpyAsync(dst.rp.p, src.row_ptr, sizeof(int32_t) * (n_rows + 1), k, s));
     MB_HIP(hipMemcpyAsync(dst.ci.p, src.col_idx, sizeof(int32_t) * src.nnzb, k, s));
     MB_HIP(hipMemcpyAsync(dst.val.p, src.vals, sizeof(double) * src.nnzb * bs, k, s));
+    // device input: the same structure checks on the library's copy, before any other kernel reads it
+    if (src.on_device) check_bsr_device(n_rows, n_cols, src.nnzb, dst.rp.p, dst.ci.p, s);
 }
 
-// First-fit greedy colouring in increasing node order over the (symmetric) pattern.
-static int greedy_colour(int n, const int32_t* rp, const int32_t* ci, std::vector<int32_t>& colour) {
+// The transposed pattern (column -> rows), or nothing when the pattern is
+// structurally symmetric already.
+static bool transpose_pattern(int n, const int32_t* rp, const int32_t* ci, std::vector<int32_t>& trp,
+                              std::vector<int32_t>& tci) {
+    trp.assign(n + 1, 0);
+    for (int p = 0; p < rp[n]; ++p) trp[ci[p] + 1]++;
+    for (int i = 0; i < n; ++i) trp[i + 1] += trp[i];
+    tci.assign(rp[n], 0);
+    std::vector<int32_t> cur(trp.begin(), trp.end() - 1);
+    for (int i = 0; i < n; ++i)
+        for (int p = rp[i]; p < rp[i + 1]; ++p) tci[cur[ci[p]]++] = i;   // rows ascending per column
+    for (int i = 0; i <= n; ++i)
+        if (trp[i] != rp[i]) return true;
+    for (int p = 0; p < rp[n]; ++p)
+        if (tci[p] != ci[p]) return true;
+    return false;
+}
+
+// First-fit greedy colouring in increasing node order over the symmetrised
+// pattern: a node avoids the colours of every node in its row and (when the
+// pattern is not symmetric) in its column, so no two nodes coupled in either
+// direction share a colour and every colour pass is a Gauss-Seidel step.
+static int greedy_colour(int n, const int32_t* rp, const int32_t* ci, std::vector<int32_t>& colour,
+                         const int32_t* trp = nullptr, const int32_t* tci = nullptr) {
     colour.assign(n, -1);
     std::vector<int32_t> mark(64, -1);
     int ncol = 0;
+    auto visit = [&](int i, int j) {
+        if (j == i || colour[j] < 0) return;
+        if (colour[j] >= (int)mark.size()) mark.resize(colour[j] + 64, -1);
+        mark[colour[j]] = i;
+    };
     for (int i = 0; i < n; ++i) {
-        for (int p = rp[i]; p < rp[i + 1]; ++p) {
-            int j = ci[p];
-            if (j == i || colour[j] < 0) continue;
-            if (colour[j] >= (int)mark.size()) mark.resize(colour[j] + 64, -1);
-            mark[colour[j]] = i;
-        }
+        for (int p = rp[i]; p < rp[i + 1]; ++p) visit(i, ci[p]);
+        if (trp)
+            for (int p = trp[i]; p < trp[i + 1]; ++p) visit(i, tci[p]);
         int c = 0;
         while (c < (int)mark.size() && mark[c] == i) ++c;
         if (c >= (int)mark.size()) mark.resize(c + 64, -1);
@@ -579,7 +609,12 @@ static void colour_level(Level& Lv, hipEvent_t ready, int device) {
             B.colour_slice = B0.colour_slice;
             B.n_slices = B0.n_slices;
         } else {
-            int ncol = greedy_colour(Lv.n, rp[f], ci[f], B.colour);
+            // A00 is structurally symmetric (checked with its strength graph); block 1's
+            // pattern, when it differs, is symmetrised here
+            std::vector<int32_t> trp, tci;
+            const bool asym = f == 1 && transpose_pattern(Lv.n, rp[f], ci[f], trp, tci);
+            int ncol = asym ? greedy_colour(Lv.n, rp[f], ci[f], B.colour, trp.data(), tci.data())
+                            : greedy_colour(Lv.n, rp[f], ci[f], B.colour);
             order_and_slice(B, Lv.n, ncol);
         }
     }
@@ -836,6 +871,16 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
         ++lvl;
     }
     h->L.back()->coarsest = true;
+    // the finest level starts its colouring job before aggregation; when that level turns
+    // out to be the coarsest (aggregation kept more than 90 % of its nodes) the job writes
+    // the same order fields the coarsest level's identity order goes into below: join it first
+    {
+        auto job = colour_jobs.find((int)h->L.size() - 1);
+        if (job != colour_jobs.end()) {
+            job->second.get();
+            colour_jobs.erase(job);
+        }
+    }
 
     // coarsest: dense inverse
     {
@@ -991,6 +1036,14 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
             const double avg_width = B.n_slices ? (double)slots / B.n_slices : 0.0;
             const double per_colour = (double)B.n_slices / std::max(1, B.n_colours);
             B.split = slot_split(per_colour, avg_width);
+            // MBAMG_SLICE_SPLIT = 1 | 2 | 4 | 8 | 16 forces the waves per slice on every sliced
+            // level, for tests: the split changes the order of each row's partial sums
+            if (const char* fo = form_override("MBAMG_SLICE_SPLIT")) {
+                const int P = std::atoi(fo);
+                MB_CHECK(P == 1 || P == 2 || P == 4 || P == 8 || P == 16, MBAMG_E_INVALID,
+                         "MBAMG_SLICE_SPLIT must be 1, 2, 4, 8 or 16");
+                B.split = P;
+            }
             if (clk.on)
                 std::fprintf(stderr, "[mbamg setup] level %d block %d: %d nodes, %d colours, %d slices, %.1f slots/slice, "
                              "split %d\n", l, f, Lv.n, B.n_colours, B.n_slices, avg_width, B.split);
@@ -1131,6 +1184,49 @@ static double xfer_bytes(const SellPart& P, int64_t rows_out, int64_t rows_in, i
            (double)rows_out * d * s * (accumulate ? 2 : 1);
 }
 
+// Algorithmic bytes of level l's share of one V-cycle in the hierarchy's form:
+// down = pre-smoothing, residual and restriction; up = prolongation and
+// post-smoothing.  The coarsest level's direct solve (the inverse read once,
+// the vectors in and out) counts as down.
+static void level_vcycle_bytes(const mbamg_hierarchy* h, int l, double& down, double& up) {
+    const int s = h->p.precision == 1 ? 4 : 8;
+    down = up = 0.0;
+    const Level& Lv = *h->L[l];
+    if (Lv.coarsest) {
+        down = 8.0 * (double)h->coarse_n * h->coarse_n + 2.0 * s * h->coarse_n;
+        return;
+    }
+    const Level& Nx = *h->L[l + 1];
+    for (int sweep = 0; sweep < 2 * h->p.bgs_sweeps; ++sweep) {
+        const bool zero = sweep == 0;
+        double& acc = sweep < h->p.bgs_sweeps ? down : up;
+        for (int f = 0; f < 2; ++f) {
+            const BlockLevel& B = Lv.blk[f];
+            for (int k = 0; k < h->p.inner_sweeps; ++k)
+                for (int c = 0; c < B.n_colours; ++c) {
+                    const bool skip = zero && k == 0 && c == 0;
+                    const bool cpl = !(zero && f == 0);
+                    acc += gs_bytes(B, c, zero, skip, cpl, s, Lv.d[1 - f]);
+                }
+        }
+    }
+    down += resid_bytes(Lv, s, true);
+    if (Lv.smoothed) {
+        for (int f = 0; f < 2; ++f) {
+            down += xfer_bytes(Lv.blk[f].res, Nx.n, Lv.n, Lv.d[f], s, false);
+            up += xfer_bytes(Lv.blk[f].pro, Lv.n, Nx.n, Lv.d[f], s, true);
+        }
+    } else {
+        const int64_t nf = (int64_t)Lv.n * (Lv.d[0] + Lv.d[1]), nc = (int64_t)Nx.n * (Nx.d[0] + Nx.d[1]);
+        down += (double)s * (2.0 * nf + nc) + 4.0 * (Lv.n + Nx.n) * 2;   // restrict: r, q, b_c, members
+        up += (double)s * (3.0 * nf + nc) + 4.0 * Lv.n * 2;              // prolong: q, x rw, x_c, map
+    }
+}
+
+// timing kinds beyond the finest level's launches: the whole V-cycle as the
+// Krylov solver and the probe apply it, and each level's share
+constexpr int TK_VCYCLE = 4, TK_LEVEL = 16;   // level l: TK_LEVEL + 2 l (down), + 1 (up)
+
 // ----------------------------------------------------------------------------
 // V-cycle
 // ----------------------------------------------------------------------------
@@ -1220,7 +1316,7 @@ static void smooth_block(mbamg_hierarchy* h, int l, int f, bool zero, const T* b
     const int64_t off = f == 0 ? 0 : (int64_t)Lv.n * Lv.d[0];
     T* tbuf = vecs<T>(Lv).t.p + off;
     const bool has_cpl = xg != nullptr;
-    const bool timed = h->timing && l == 0;
+    const bool timed = h->time_launches() && l == 0;
     if (B.rows) {
         for (int k = 0; k < h->p.inner_sweeps; ++k)
             for (int c = 0; c < B.n_colours; ++c) {
@@ -1286,7 +1382,7 @@ static void resid(mbamg_hierarchy* h, int l, const T* b, const T* x, T* r, hipSt
         a.x[f] = x + off;
         a.r[f] = r + off;
     }
-    const bool timed = h->timing && l == 0 && kind >= 0;
+    const bool timed = h->time_launches() && l == 0 && kind >= 0;
     double bytes = timed ? resid_bytes(Lv, (int)sizeof(T), b != nullptr) : 0.0;
     TimerScope ts(h, s, timed, kind, bytes);
     if (Lv.blk[0].rows && Lv.blk[1].rows) {
@@ -1309,10 +1405,16 @@ static void resid(mbamg_hierarchy* h, int l, const T* b, const T* x, T* r, hipSt
 template <class T>
 static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStream_t s) {
     Level& Lv = *h->L[l];
+    double seg_down = 0.0, seg_up = 0.0;
+    const bool tl = h->time_levels();
+    if (tl) level_vcycle_bytes(h, l, seg_down, seg_up);
     if (Lv.coarsest) {
+        TimerScope ts(h, s, tl, TK_LEVEL + 2 * l, seg_down);
         launch_coarse<T>(h->coarse_n, h->coarse_inv.p, b, out, s);
         return;
     }
+    std::optional<TimerScope> seg;
+    seg.emplace(h, s, tl, TK_LEVEL + 2 * l, seg_down);
     Vecs<T>& V = vecs<T>(Lv);
     const int64_t n0 = (int64_t)Lv.n * Lv.d[0];
     const int writes = 2 * h->p.bgs_sweeps;
@@ -1363,7 +1465,9 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
         }
         launch_restrict<T>(Lv.d[0], a, Lv.blk[0].res_group, s);
     }
+    seg.reset();
     vcycle_level<T>(h, l + 1, C.b.p, C.x.p, s);
+    seg.emplace(h, s, tl, TK_LEVEL + 2 * l + 1, seg_up);
     if (Lv.smoothed) {
         XferArgs<T> a{};
         for (int f = 0; f < 2; ++f) {
@@ -1396,13 +1500,17 @@ static void apply_precond(mbamg_hierarchy* h, const double* v, double* z64, floa
     if (h->p.precision == 1) {
         Level& L0 = *h->L[0];
         launch_cast64to32(h->n_fine, v, h->vin32.p, s);
-        if (L0.coarsest) {
-            launch_coarse<float>(h->coarse_n, h->coarse_inv.p, h->vin32.p, z32, s);
-        } else {
-            vcycle_level<float>(h, 0, h->vin32.p, z32, s);
+        {
+            TimerScope ts(h, s, h->time_vcycles(), TK_VCYCLE, 0.0);
+            if (L0.coarsest) {
+                launch_coarse<float>(h->coarse_n, h->coarse_inv.p, h->vin32.p, z32, s);
+            } else {
+                vcycle_level<float>(h, 0, h->vin32.p, z32, s);
+            }
         }
         if (z64) launch_cast32to64(h->n_fine, z32, z64, s);
     } else {
+        TimerScope ts(h, s, h->time_vcycles(), TK_VCYCLE, 0.0);
         vcycle_level<double>(h, 0, v, z64, s);
     }
 }
@@ -1842,7 +1950,8 @@ mbamg_status mbamg_timing_enable(mbamg_hierarchy* h, int32_t enable) {
             h->event_pool.push_back(t.b);
         }
         h->timed.clear();
-        h->timing = enable != 0;
+        MB_CHECK(enable >= 0 && enable <= 3, MBAMG_E_INVALID, "timing mode must be 0..3");
+        h->timing = enable;
         return MBAMG_OK;
     });
 }
@@ -1871,37 +1980,21 @@ mbamg_status mbamg_timing_get(mbamg_hierarchy* h, int32_t kind, int64_t* launche
 mbamg_status mbamg_vcycle_bytes(const mbamg_hierarchy* h, double* bytes) {
     return guarded([&]() -> mbamg_status {
         MB_CHECK(h && bytes, MBAMG_E_INVALID, "NULL argument");
-        const int s = h->p.precision == 1 ? 4 : 8;
         double tot = 0.0;
-        for (size_t l = 0; l + 1 < h->L.size(); ++l) {
-            const Level& Lv = *h->L[l];
-            const Level& Nx = *h->L[l + 1];
-            for (int sweep = 0; sweep < 2 * h->p.bgs_sweeps; ++sweep) {
-                const bool zero = sweep == 0;
-                for (int f = 0; f < 2; ++f) {
-                    const BlockLevel& B = Lv.blk[f];
-                    for (int k = 0; k < h->p.inner_sweeps; ++k)
-                        for (int c = 0; c < B.n_colours; ++c) {
-                            bool skip = zero && k == 0 && c == 0;
-                            bool cpl = !(zero && f == 0);
-                            tot += gs_bytes(B, c, zero, skip, cpl, s, Lv.d[1 - f]);
-                        }
-                }
-            }
-            tot += resid_bytes(Lv, s, true);
-            if (Lv.smoothed) {
-                for (int f = 0; f < 2; ++f) {
-                    tot += xfer_bytes(Lv.blk[f].res, Nx.n, Lv.n, Lv.d[f], s, false);
-                    tot += xfer_bytes(Lv.blk[f].pro, Lv.n, Nx.n, Lv.d[f], s, true);
-                }
-            } else {
-                const int64_t nf = (int64_t)Lv.n * (Lv.d[0] + Lv.d[1]), nc = (int64_t)Nx.n * (Nx.d[0] + Nx.d[1]);
-                tot += (double)s * (2.0 * nf + nc) + 4.0 * (Lv.n + Nx.n) * 2;   // restrict: r, q, b_c, members
-                tot += (double)s * (3.0 * nf + nc) + 4.0 * Lv.n * 2;            // prolong: q, x rw, x_c, map
-            }
+        for (int l = 0; l < (int)h->L.size(); ++l) {
+            double down = 0.0, up = 0.0;
+            level_vcycle_bytes(h, l, down, up);
+            tot += down + up;
         }
-        tot += 8.0 * (double)h->coarse_n * h->coarse_n + 2.0 * s * h->coarse_n;
         *bytes = tot;
+        return MBAMG_OK;
+    });
+}
+
+mbamg_status mbamg_level_vcycle_bytes(const mbamg_hierarchy* h, int32_t level, double* down, double* up) {
+    return guarded([&]() -> mbamg_status {
+        MB_CHECK(h && down && up && level >= 0 && level < (int)h->L.size(), MBAMG_E_INVALID, "bad argument");
+        level_vcycle_bytes(h, level, *down, *up);
         return MBAMG_OK;
     });
 }

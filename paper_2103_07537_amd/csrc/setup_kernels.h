@@ -87,6 +87,9 @@ std::vector<int64_t> row_colour_stats(int n, const int32_t* perm, const SetupBsr
 
 // true when X and Y have identical block patterns (synchronous)
 bool same_pattern(const SetupBsr& X, const SetupBsr& Y, hipStream_t s);
+// Structure check of device-resident BSR index arrays (row pointers n_rows + 1,
+// columns nnzb); throws MBAMG_E_INVALID on a malformed block (synchronous)
+void check_bsr_device(int n_rows, int n_cols, int64_t nnzb, const int32_t* rp, const int32_t* ci, hipStream_t s);
 
 // Test-only choice between equivalent kernel forms: the value of environment
 // variable `var`, or null when it is unset or empty.

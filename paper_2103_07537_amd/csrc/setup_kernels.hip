@@ -1216,6 +1216,49 @@ __global__ void k_spgemm_num_any(int64_t nnz, int br, int bm, int bc, const int3
     for (int e = 0; e < br * bc; ++e) dst[e] = acc[e];
 }
 
+// Structure check of a BSR block that arrived in device memory (host input is
+// checked on the host): bad[0] row_ptr[0] != 0 or row_ptr[n_rows] != nnzb,
+// bad[1] a row whose range is negative, decreasing or beyond nnzb, bad[2] a
+// column outside [0, n_cols), bad[3] columns not strictly increasing within a
+// row.  One thread per row; a row's columns are read only once its range is
+// known to lie inside [0, nnzb), so no read leaves the arrays.
+__global__ void k_check_bsr(int n_rows, int n_cols, int64_t nnzb, const int32_t* __restrict__ rp,
+                            const int32_t* __restrict__ ci, int32_t* bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_rows) return;
+    if (i == 0 && rp[0] != 0) bad[0] = 1;
+    if (i == n_rows - 1 && (int64_t)rp[n_rows] != nnzb) bad[0] = 1;
+    const int a = rp[i], b = rp[i + 1];
+    if (a < 0 || b < a || (int64_t)b > nnzb) {
+        bad[1] = 1;
+        return;
+    }
+    for (int p = a; p < b; ++p) {
+        const int j = ci[p];
+        if (j < 0 || j >= n_cols) {
+            bad[2] = 1;
+            return;
+        }
+        if (p > a && j <= ci[p - 1]) {
+            bad[3] = 1;
+            return;
+        }
+    }
+}
+
+void check_bsr_device(int n_rows, int n_cols, int64_t nnzb, const int32_t* rp, const int32_t* ci, hipStream_t s) {
+    if (n_rows <= 0) return;
+    DevBuf<int32_t> bad(4);
+    MB_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t) * 4, s));
+    k_check_bsr<<<(unsigned)ceil_div(n_rows, 256), 256, 0, s>>>(n_rows, n_cols, nnzb, rp, ci, bad.p);
+    MB_LAUNCH_CHECK();
+    const std::vector<int32_t> f = bad.download(s, 4);
+    MB_CHECK(!f[0], MBAMG_E_INVALID, "row_ptr inconsistent with nnzb");
+    MB_CHECK(!f[1], MBAMG_E_INVALID, "row_ptr not monotone");
+    MB_CHECK(!f[2], MBAMG_E_INVALID, "column index out of range");
+    MB_CHECK(!f[3], MBAMG_E_INVALID, "column indices must be strictly increasing within a row");
+}
+
 // flag (initially 1) is cleared when two index arrays of equal length differ
 // anywhere: row pointers and then columns, one element per thread (grid-stride,
 // coalesced), one atomic per wavefront that found a difference

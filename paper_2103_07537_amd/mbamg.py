@@ -81,6 +81,8 @@ SIGNATURES = [
     ("mbamg_timing_get", ctypes.c_int, [_P, _I32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]),
     ("mbamg_vcycle_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    ("mbamg_level_vcycle_bytes", ctypes.c_int, [_P, _I32, ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(ctypes.c_double)]),
     ("mbamg_features", ctypes.c_int, [_P, _I32, _P]),
     ("mbamg_level_weights", ctypes.c_int, [_P, _I32, _P, _P]),
     ("mbamg_mlp_forward", ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
@@ -310,8 +312,10 @@ class Hierarchy:
         _check(lib().mbamg_set_omega(self._h, float(omega)))
 
     # -- measurement ---------------------------------------------------------
-    def timing_enable(self, on: bool = True):
-        _check(lib().mbamg_timing_enable(self._h, 1 if on else 0))
+    def timing_enable(self, on=True):
+        """on: False/0 off, True/1 every kind, 2 whole V-cycles only, 3 V-cycles and levels."""
+        mode = int(on) if not isinstance(on, bool) else (1 if on else 0)
+        _check(lib().mbamg_timing_enable(self._h, mode))
 
     def timing_get(self, kind: int) -> dict:
         n = ctypes.c_int64()
@@ -324,6 +328,11 @@ class Hierarchy:
         b = ctypes.c_double()
         _check(lib().mbamg_vcycle_bytes(self._h, ctypes.byref(b)))
         return b.value
+
+    def level_vcycle_bytes(self, level: int):
+        d, u = ctypes.c_double(), ctypes.c_double()
+        _check(lib().mbamg_level_vcycle_bytes(self._h, level, ctypes.byref(d), ctypes.byref(u)))
+        return d.value, u.value
 
 
 N_MLP_PARAMS = 5122

@@ -28,3 +28,14 @@ def oracle_params(**kw):
 def rel(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def assert_close(got, ref, tol, what="vcycle"):
+    """Element by element and as a norm: max|got - ref| <= tol max|ref| and
+    ||got - ref|| <= tol ||ref||."""
+    m = np.max(np.abs(ref))
+    ew = np.max(np.abs(got - ref)) / (m if m > 0 else 1.0)
+    nw = rel(got, ref)
+    log(f"  {what}: element-wise {ew:.2e}, norm-wise {nw:.2e}")
+    assert ew <= tol, f"{what}: element-wise {ew:.3e} > {tol:.1e}"
+    assert nw <= tol, f"{what}: norm-wise {nw:.3e} > {tol:.1e}"

@@ -93,7 +93,7 @@ ROW_CASES = {
 @pytest.mark.parametrize("split", ["1", "4"])
 def test_row_form_matches_oracle(case, precision, split, monkeypatch):
     from oracle import amg
-    from gpu_util import rel, torch_dev
+    from gpu_util import assert_close, torch_dev
     make, weighted = ROW_CASES[case]
     s = make()
     kw = dict(weights=weights_fn, judge=0) if weighted else {}
@@ -107,9 +107,7 @@ def test_row_form_matches_oracle(case, precision, split, monkeypatch):
     r = np.random.default_rng(7).standard_normal(s.n_dofs)
     z = torch_dev(np.zeros(s.n_dofs))
     hg.vcycle(torch_dev(r), z)
-    e = rel(z.cpu().numpy(), amg.vcycle(ho, r))
-    log(f"  vcycle rel {e:.2e}")
-    assert e <= (1e-12 if precision == 0 else 1e-5)
+    assert_close(z.cpu().numpy(), amg.vcycle(ho, r), 1e-12 if precision == 0 else 1e-5)
     x = torch_dev(np.zeros(s.n_dofs))
     info = hg.solve(torch_dev(s.b), x, rtol=1e-8)
     A = s.to_scipy()
@@ -125,7 +123,7 @@ def test_row_form_matches_oracle(case, precision, split, monkeypatch):
 @pytest.mark.parametrize("group", [4, 8, 16, 64])
 def test_restriction_groups_match_oracle(group, monkeypatch):
     from oracle import amg
-    from gpu_util import rel, torch_dev
+    from gpu_util import assert_close, torch_dev
     s = make_system(11, 3, 2.0, seed=5, kappa="lognormal")
     ho = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=60), n_vec=s.n_vec)
     monkeypatch.setenv("MBAMG_RESTRICT_GROUP", str(group))
@@ -135,7 +133,5 @@ def test_restriction_groups_match_oracle(group, monkeypatch):
     r = np.random.default_rng(8).standard_normal(s.n_dofs)
     z = torch_dev(np.zeros(s.n_dofs))
     hg.vcycle(torch_dev(r), z)
-    e = rel(z.cpu().numpy(), amg.vcycle(ho, r))
-    log(f"  vcycle rel {e:.2e}")
-    assert e <= 1e-12
+    assert_close(z.cpu().numpy(), amg.vcycle(ho, r), 1e-12)
     hg.close()

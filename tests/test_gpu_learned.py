@@ -5,7 +5,7 @@ and Adam step, the convergence probe and the fixed-method judge."""
 import numpy as np
 import pytest
 
-from gpu_util import gpu_hierarchy, log, rel, torch_dev
+from gpu_util import assert_close, gpu_hierarchy, log, rel, torch_dev
 from paper_2103_07537_amd.inputs import make_system, workload
 
 pytestmark = pytest.mark.gpu
@@ -69,9 +69,7 @@ def test_weighted_vcycle_and_solve_match_oracle(case, precision):
     r = np.random.default_rng(2).standard_normal(s.n_dofs)
     z = torch_dev(np.zeros(s.n_dofs))
     hg.vcycle(torch_dev(r), z)
-    e = rel(z.cpu().numpy(), amg.vcycle(ho, r))
-    log(f"  vcycle rel {e:.2e}")
-    assert e <= (1e-12 if precision == 0 else 1e-5)
+    assert_close(z.cpu().numpy(), amg.vcycle(ho, r), 1e-12 if precision == 0 else 1e-5)
     x = torch_dev(np.zeros(s.n_dofs))
     info = hg.solve(torch_dev(s.b), x, rtol=1e-8)
     xo, io = amg.gmres(ho, s.b, rtol=1e-8)
@@ -91,7 +89,7 @@ def test_uniform_omega_p_matches_oracle():
     r = np.random.default_rng(4).standard_normal(s.n_dofs)
     z = torch_dev(np.zeros(s.n_dofs))
     hg.vcycle(torch_dev(r), z)
-    assert rel(z.cpu().numpy(), amg.vcycle(ho, r)) <= 1e-12
+    assert_close(z.cpu().numpy(), amg.vcycle(ho, r), 1e-12)
 
 
 @pytest.mark.parametrize("case", list(CASES))
