@@ -265,6 +265,8 @@ mbamg_status mbamg_set_omega(mbamg_hierarchy* h, double omega);
  * indices, row pointers and vectors, each counted once per launch).
  * kind 4: whole V-cycles as the solver and the probe apply them (colour order,
  * without the interface's reordering or the FP32 form's casts; bytes 0).
+ * kind 5: restrictions from the finest level, 6: prolongations to it; on a
+ * coarser level l, kind 64 + 8 l + k for the same launches (k = 0, 1, 3, 5, 6).
  * kind 16 + 2 l: level l's share of each V-cycle on the way down
  * (pre-smoothing, residual, restriction; the coarsest level's direct solve);
  * kind 17 + 2 l: on the way up (prolongation, post-smoothing); with the

@@ -83,6 +83,8 @@ struct BlockLevel {
     int row_split = 1;                         // row form smoother: wavefronts per row (1, or 4 with 4 x 4 blocks)
     // coarse levels with long rows: the smoother and residual run on the row form
     bool rows = false;
+    // within-colour row order sorted by length in windows (coarse levels with mixed row lengths)
+    bool sell_sorted = false;
     RowPart raff, rafg;
     DevBuf<double> rdinv64;
     DevBuf<float> rdinv32;
@@ -90,6 +92,8 @@ struct BlockLevel {
     DevBuf<int32_t> agg_p, mem_ptr, mem_idx;
     DevBuf<double> q64;
     DevBuf<float> q32;
+    DevBuf<double> qm64;                       // q in member-list order (the restriction's reads)
+    DevBuf<float> qm32;
     SliceView slices() const { return {row0.p, nrow.p}; }
 };
 
@@ -383,7 +387,34 @@ static int greedy_colour(int n, const int32_t* rp, const int32_t* ci, std::vecto
     return ncol;
 }
 
-static void order_and_slice(BlockLevel& B, int n, int ncol) {
+// Rows of one colour are independent in a Gauss-Seidel colour pass, so their
+// order within the colour changes no result (each row's own sum runs over its
+// columns in the same order).  A slice of 64 rows is as wide as its longest
+// row; where rows of different lengths mix (coarse levels) the colour's rows
+// are sorted by decreasing length within windows of SELL_SIGMA rows, which
+// keeps the padding small while rows stay near their neighbours.
+constexpr int SELL_SIGMA = 1024;
+
+// Fraction of a sliced layout's slots that hold a stored block, for rows in
+// the given order cut into slices of 64 (per colour).
+static double slice_fill(const std::vector<int32_t>& order, const std::vector<int>& colour_row, const int32_t* rp) {
+    int64_t blocks = 0, slots = 0;
+    for (size_t c = 0; c + 1 < colour_row.size(); ++c)
+        for (int r = colour_row[c]; r < colour_row[c + 1]; r += WAVE) {
+            int w = 0;
+            for (int q = r; q < std::min(r + WAVE, colour_row[c + 1]); ++q) {
+                const int len = rp[order[q] + 1] - rp[order[q]];
+                blocks += len;
+                w = std::max(w, len);
+            }
+            slots += (int64_t)w * WAVE;
+        }
+    return slots ? (double)blocks / (double)slots : 1.0;
+}
+
+// rp: row pointers of the block row's diagonal block (row lengths), or NULL
+// for the natural order within each colour.
+static void order_and_slice(BlockLevel& B, int n, int ncol, const int32_t* rp = nullptr) {
     B.n = n;
     B.n_colours = ncol;
     std::vector<int> cnt(ncol + 1, 0);
@@ -393,11 +424,19 @@ static void order_and_slice(BlockLevel& B, int n, int ncol) {
     B.perm.assign(n, 0);
     B.iperm.assign(n, 0);
     std::vector<int> cur(B.colour_row.begin(), B.colour_row.end() - 1);
-    for (int i = 0; i < n; ++i) {
-        int p = cur[B.colour[i]]++;
-        B.perm[p] = i;
-        B.iperm[i] = p;
+    for (int i = 0; i < n; ++i) B.perm[cur[B.colour[i]]++] = i;
+    B.sell_sorted = false;
+    if (rp && slice_fill(B.perm, B.colour_row, rp) < 0.9) {
+        B.sell_sorted = true;
+        auto len = [rp](int32_t i) { return rp[i + 1] - rp[i]; };
+        for (int c = 0; c < ncol; ++c)
+            for (int w0 = B.colour_row[c]; w0 < B.colour_row[c + 1]; w0 += SELL_SIGMA) {
+                const int w1 = std::min(w0 + SELL_SIGMA, B.colour_row[c + 1]);
+                std::stable_sort(B.perm.begin() + w0, B.perm.begin() + w1,
+                                 [&len](int32_t a, int32_t b) { return len(a) > len(b); });
+            }
     }
+    for (int p = 0; p < n; ++p) B.iperm[B.perm[p]] = p;
     B.h_row0.clear();
     B.h_nrow.clear();
     B.colour_slice.assign(ncol + 1, 0);
@@ -413,6 +452,9 @@ static void order_and_slice(BlockLevel& B, int n, int ncol) {
 }
 
 enum class PartKind { Off = 0, Cpl = 1, Diag = 2, Dinv = 3 };
+
+// coarse levels with at most this many rows per colour (on average) take the row form
+constexpr int ROWS_PER_COLOUR_MAX = 2048;
 
 // Waves per slice (1..16) for a launch over `slices` slices of `width` slots
 // on average: wide slices are shared by more waves until the launch has
@@ -604,6 +646,7 @@ static void colour_level(Level& Lv, hipEvent_t ready, int device) {
             B.colour_row = B0.colour_row;
             B.perm = B0.perm;
             B.iperm = B0.iperm;
+            B.sell_sorted = B0.sell_sorted;
             B.h_row0 = B0.h_row0;
             B.h_nrow = B0.h_nrow;
             B.colour_slice = B0.colour_slice;
@@ -615,7 +658,7 @@ static void colour_level(Level& Lv, hipEvent_t ready, int device) {
             const bool asym = f == 1 && transpose_pattern(Lv.n, rp[f], ci[f], trp, tci);
             int ncol = asym ? greedy_colour(Lv.n, rp[f], ci[f], B.colour, trp.data(), tci.data())
                             : greedy_colour(Lv.n, rp[f], ci[f], B.colour);
-            order_and_slice(B, Lv.n, ncol);
+            order_and_slice(B, Lv.n, ncol, rp[f]);
         }
     }
 }
@@ -657,6 +700,7 @@ static void clone_smoother(BlockLevel& d, const BlockLevel& b, hipStream_t s) {
     d.all_bl = b.all_bl;
     d.perm = b.perm;
     d.iperm = b.iperm;
+    d.sell_sorted = b.sell_sorted;
     d.colour = b.colour;
     d.h_row0 = b.h_row0;
     d.h_nrow = b.h_nrow;
@@ -963,9 +1007,17 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
             B.d_perm.upload(B.perm, s);
             B.d_iperm.upload(B.iperm, s);
         }
-        // long rows (dense coarse stencils) in both block rows: one wavefront per row, and
-        // the sliced parts of the level are not built
-        bool rows_level = l > 0 && Lv.A[0][0].nnzb >= (int64_t)32 * Lv.n && Lv.A[1][1].nnzb >= (int64_t)32 * Lv.n;
+        // coarse levels with few rows per colour take the row form: every colour pass is a short,
+        // latency-bound launch, and one wavefront per row (four on rows of 4 x 4 blocks) shortens
+        // its chain of dependent loads (the 128^3 workload's third level, 7461 nodes in 11
+        // colours: 10.8 -> 7.3 us per pass; 2735 nodes in 28 colours with smoothed transfers:
+        // 15 -> 6.7 us).  Larger levels keep the sliced layout, whose rows are sorted by length
+        // within each colour when their lengths differ (the smoothed-transfer form's second
+        // level, 188,588 nodes in 18 colours: 1.56 -> 1.36 ms per V-cycle against one wavefront
+        // per row).  The row form's sliced parts are not built.
+        const int max_colours = std::max(Lv.blk[0].n_colours, Lv.blk[1].n_colours);
+        bool rows_level = l > 0 && (int64_t)Lv.n <= (int64_t)ROWS_PER_COLOUR_MAX * max_colours;
+        // MBAMG_ROWS_FORM (tests): "rows" forces the row form on every coarse level, anything else the sliced one
         if (const char* fo = form_override("MBAMG_ROWS_FORM")) rows_level = l > 0 && std::strcmp(fo, "rows") == 0;
         if (p.smoother == 1) rows_level = false;   // the full-node kernel reads the sliced parts
         for (int f = 0; f < 2 && !shared; ++f) {
@@ -1100,9 +1152,13 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
             DevBuf<double> qp((size_t)Lv.n * B.d);
             launch_gather(Lv.n, B.d, B.d_perm.p, B.q64.p, qp.p, s);
             B.q64 = std::move(qp);
+            B.qm64.alloc((size_t)Lv.n * B.d);
+            launch_gather(Lv.n, B.d, B.mem_idx.p, B.q64.p, B.qm64.p, s);   // member m: fine row mem_idx[m]
             if (want32) {
                 B.q32.alloc((size_t)Lv.n * B.d);
                 cast_to_f32(B.q64.p, B.q32.p, (int64_t)Lv.n * B.d, s);
+                B.qm32.alloc((size_t)Lv.n * B.d);
+                cast_to_f32(B.qm64.p, B.qm32.p, (int64_t)Lv.n * B.d, s);
             }
         }
         alloc_vecs(Lv.v64, (int64_t)Lv.n * (d0 + d1));
@@ -1184,6 +1240,18 @@ static double xfer_bytes(const SellPart& P, int64_t rows_out, int64_t rows_in, i
            (double)rows_out * d * s * (accumulate ? 2 : 1);
 }
 
+// tentative transfers: the restriction reads r and q once and writes b_c, with
+// the member lists; the prolongation reads q, x_c and x and writes x, with the
+// aggregate map
+static double tentative_restrict_bytes(const Level& Lv, const Level& Nx, int s) {
+    const int64_t nf = (int64_t)Lv.n * (Lv.d[0] + Lv.d[1]), nc = (int64_t)Nx.n * (Nx.d[0] + Nx.d[1]);
+    return (double)s * (2.0 * nf + nc) + 4.0 * (Lv.n + Nx.n) * 2;
+}
+static double tentative_prolong_bytes(const Level& Lv, const Level& Nx, int s) {
+    const int64_t nf = (int64_t)Lv.n * (Lv.d[0] + Lv.d[1]), nc = (int64_t)Nx.n * (Nx.d[0] + Nx.d[1]);
+    return (double)s * (3.0 * nf + nc) + 4.0 * Lv.n * 2;
+}
+
 // Algorithmic bytes of level l's share of one V-cycle in the hierarchy's form:
 // down = pre-smoothing, residual and restriction; up = prolongation and
 // post-smoothing.  The coarsest level's direct solve (the inverse read once,
@@ -1217,15 +1285,18 @@ static void level_vcycle_bytes(const mbamg_hierarchy* h, int l, double& down, do
             up += xfer_bytes(Lv.blk[f].pro, Lv.n, Nx.n, Lv.d[f], s, true);
         }
     } else {
-        const int64_t nf = (int64_t)Lv.n * (Lv.d[0] + Lv.d[1]), nc = (int64_t)Nx.n * (Nx.d[0] + Nx.d[1]);
-        down += (double)s * (2.0 * nf + nc) + 4.0 * (Lv.n + Nx.n) * 2;   // restrict: r, q, b_c, members
-        up += (double)s * (3.0 * nf + nc) + 4.0 * Lv.n * 2;              // prolong: q, x rw, x_c, map
+        down += tentative_restrict_bytes(Lv, Nx, s);
+        up += tentative_prolong_bytes(Lv, Nx, s);
     }
 }
 
 // timing kinds beyond the finest level's launches: the whole V-cycle as the
 // Krylov solver and the probe apply it, and each level's share
 constexpr int TK_VCYCLE = 4, TK_LEVEL = 16;   // level l: TK_LEVEL + 2 l (down), + 1 (up)
+// launch kinds: 0 post-smoother colour passes, 1 residual, 3 other colour passes,
+// 5 restriction, 6 prolongation; kinds 0..3 keep their meaning on the finest
+// level, other levels add 64 + 8 l
+static int launch_kind(int l, int k) { return l == 0 ? k : 64 + 8 * l + k; }
 
 // ----------------------------------------------------------------------------
 // V-cycle
@@ -1256,6 +1327,13 @@ template <>
 const double* qptr<double>(const BlockLevel& B) { return B.q64.p; }
 template <>
 const float* qptr<float>(const BlockLevel& B) { return B.q32.p; }
+
+template <class T>
+static const T* qmptr(const BlockLevel& B);
+template <>
+const double* qmptr<double>(const BlockLevel& B) { return B.qm64.p; }
+template <>
+const float* qmptr<float>(const BlockLevel& B) { return B.qm32.p; }
 
 template <class T>
 static const T* wrow(const BlockLevel& B);
@@ -1316,10 +1394,13 @@ static void smooth_block(mbamg_hierarchy* h, int l, int f, bool zero, const T* b
     const int64_t off = f == 0 ? 0 : (int64_t)Lv.n * Lv.d[0];
     T* tbuf = vecs<T>(Lv).t.p + off;
     const bool has_cpl = xg != nullptr;
-    const bool timed = h->time_launches() && l == 0;
+    const bool timed = h->time_launches();
     if (B.rows) {
         for (int k = 0; k < h->p.inner_sweeps; ++k)
             for (int c = 0; c < B.n_colours; ++c) {
+                const bool skip = zero && k == 0 && c == 0;
+                double bytes = timed ? gs_bytes(B, c, zero, skip, has_cpl, (int)sizeof(T), Lv.d[g]) : 0.0;
+                TimerScope ts(h, s, timed, launch_kind(l, (!zero && has_cpl) ? 0 : 3), bytes);
                 GsRowArgs<T> a{};
                 a.r_begin = B.colour_row[c];
                 a.r_count = B.colour_row[c + 1] - B.colour_row[c];
@@ -1359,7 +1440,7 @@ static void smooth_block(mbamg_hierarchy* h, int l, int f, bool zero, const T* b
             a.skip_off = (zero && k == 0 && c == 0) ? 1 : 0;
             double bytes = timed ? gs_bytes(B, c, zero, a.skip_off, has_cpl, (int)sizeof(T), Lv.d[g]) : 0.0;
             // kind 0: passes from a nonzero iterate with the coupling term; kind 3: the others
-            TimerScope ts(h, s, timed, (!zero && has_cpl) ? 0 : 3, bytes);
+            TimerScope ts(h, s, timed, launch_kind(l, (!zero && has_cpl) ? 0 : 3), bytes);
             launch_gs<T>(B.d, B.split, zero, has_cpl, a, s);
         }
     }
@@ -1382,9 +1463,9 @@ static void resid(mbamg_hierarchy* h, int l, const T* b, const T* x, T* r, hipSt
         a.x[f] = x + off;
         a.r[f] = r + off;
     }
-    const bool timed = h->time_launches() && l == 0 && kind >= 0;
+    const bool timed = h->time_launches() && kind >= 0 && (l == 0 || kind == 1);
     double bytes = timed ? resid_bytes(Lv, (int)sizeof(T), b != nullptr) : 0.0;
-    TimerScope ts(h, s, timed, kind, bytes);
+    TimerScope ts(h, s, timed, launch_kind(l, kind), bytes);
     if (Lv.blk[0].rows && Lv.blk[1].rows) {
         ResidRowArgs<T> ra{};
         for (int f = 0; f < 2; ++f) {
@@ -1452,6 +1533,11 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
             a.y[f] = C.b.p + (f ? nc0 : 0);
         }
         a.accumulate = 0;
+        const bool tx = h->time_launches();
+        double xb = 0.0;
+        if (tx)
+            for (int f = 0; f < 2; ++f) xb += xfer_bytes(Lv.blk[f].res, Nx.n, Lv.n, Lv.d[f], (int)sizeof(T), false);
+        TimerScope ts(h, s, tx, launch_kind(l, 5), xb);
         launch_xfer<T>(Lv.d[0], Lv.blk[0].res_split, a, s);
     } else {
         TransferArgs<T> a{};
@@ -1459,10 +1545,12 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
             a.n_rows[f] = Nx.n;
             a.map[f] = Lv.blk[f].mem_ptr.p;
             a.idx[f] = Lv.blk[f].mem_idx.p;
-            a.q[f] = qptr<T>(Lv.blk[f]);
+            a.q[f] = qmptr<T>(Lv.blk[f]);
             a.in[f] = V.r.p + (f ? n0 : 0);
             a.out[f] = C.b.p + (f ? nc0 : 0);
         }
+        const bool tx = h->time_launches();
+        TimerScope ts(h, s, tx, launch_kind(l, 5), tx ? tentative_restrict_bytes(Lv, Nx, (int)sizeof(T)) : 0.0);
         launch_restrict<T>(Lv.d[0], a, Lv.blk[0].res_group, s);
     }
     seg.reset();
@@ -1478,6 +1566,11 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
             a.y[f] = buf[cur] + (f ? n0 : 0);
         }
         a.accumulate = 1;
+        const bool tx = h->time_launches();
+        double xb = 0.0;
+        if (tx)
+            for (int f = 0; f < 2; ++f) xb += xfer_bytes(Lv.blk[f].pro, Lv.n, Nx.n, Lv.d[f], (int)sizeof(T), true);
+        TimerScope ts(h, s, tx, launch_kind(l, 6), xb);
         launch_xfer<T>(Lv.d[0], Lv.blk[0].pro_split, a, s);
     } else {
         TransferArgs<T> a{};
@@ -1489,6 +1582,8 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
             a.in[f] = C.x.p + (f ? nc0 : 0);
             a.out[f] = buf[cur] + (f ? n0 : 0);
         }
+        const bool tx = h->time_launches();
+        TimerScope ts(h, s, tx, launch_kind(l, 6), tx ? tentative_prolong_bytes(Lv, Nx, (int)sizeof(T)) : 0.0);
         launch_prolong<T>(Lv.d[0], a, s);
     }
     for (int k = 0; k < h->p.bgs_sweeps; ++k) sweep(false);

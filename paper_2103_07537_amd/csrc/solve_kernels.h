@@ -117,7 +117,7 @@ struct TransferArgs {
     int n_rows[2];             // fine rows (prolongation) or coarse rows (restriction) per block
     const int32_t* map[2];     // prolongation: coarse row of each fine row; restriction: member pointer
     const int32_t* idx[2];     // restriction: member rows
-    const T* q[2];
+    const T* q[2];             // prolongation: per fine row; restriction: per member, in member-list order
     const T* in[2];
     T* out[2];
 };

@@ -652,7 +652,8 @@ __device__ __forceinline__ void group_sum_vec(T (&acc)[D]) {
 
 // coarse b_k = sum over members i of aggregate k of q_i .* r_i (per component):
 // G lanes per coarse row, the members strided over them (their rows are
-// scattered over the fine vector, so many are fetched at once)
+// scattered over the fine vector, so many are fetched at once; the weights q
+// are stored in member-list order, so only r is gathered)
 template <class T, int D, int G>
 __global__ __launch_bounds__(256) void k_restrict(TransferArgs<T> a) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -672,7 +673,7 @@ __global__ __launch_bounds__(256) void k_restrict(TransferArgs<T> a) {
     for (int m = mp[k] + gl; m < mp[k + 1]; m += G) {
         const int64_t i = mi[m];
         T q[D], r[D];
-        load_vec<T, D>(a.q[f] + i * D, q);
+        load_vec<T, D>(a.q[f] + (int64_t)m * D, q);
         load_vec<T, D>(a.in[f] + i * D, r);
 #pragma unroll
         for (int c = 0; c < D; ++c) acc[c] += q[c] * r[c];

@@ -1,9 +1,10 @@
 """GPU parity on the edges of the method and of the kernel forms, element by
 element against the oracle:
 
-- the sliced smoother and residual kernels forced to 1, 2, 4, 8 and 16
-  wavefronts per slice on every level (the 3D 4 x 4-block case at split 1 is
-  the kernel form that runs on the finest level of the 128^3 workload);
+- the sliced smoother and residual kernels forced onto every level with 1, 2,
+  4, 8 and 16 wavefronts per slice (the 3D 4 x 4-block case at split 1 is the
+  kernel form that runs on the finest level of the 128^3 workload; coarse
+  levels sort each colour's rows by length, which these cases reach);
 - a strength threshold that drops weak edges (isolated nodes become singleton
   aggregates), another priority seed, a level cap, and the ratio stop that ends
   coarsening when a level would keep more than 90 % of its nodes;
@@ -46,6 +47,7 @@ def test_forced_slice_split_matches_oracle(case, precision, split, monkeypatch):
     s = SPLIT_CASES[case]()
     ho = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=60), n_vec=s.n_vec)
     monkeypatch.setenv("MBAMG_SLICE_SPLIT", str(split))
+    monkeypatch.setenv("MBAMG_ROWS_FORM", "sliced")   # the sliced layout on every level
     log(f"case={case} precision={precision} split={split}")
     hg = gpu_hierarchy(s, max_coarse=60, precision=precision)
     assert hg.num_levels() == len(ho.levels) >= 3
