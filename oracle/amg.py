@@ -95,6 +95,9 @@ class Params:
     weights: object = None      # callable(level, n_agg, features) -> (omega_p[n_agg], omega_s[n_agg])
     smoother: int = 0           # 0: block Gauss-Seidel over the two blocks (Algorithm 1);
                                 # 1: nodal-block Gauss-Seidel over the full node blocks (FC-AMG analogue)
+    clone: bool = True          # block 1 reuses block 0's aggregates (Sec. 4.3.1, the cloning figure);
+                                # False: each block is aggregated from its own diagonal block's graph,
+                                # the separate AMG setup per block for fields on different node sets
 
 
 @dataclasses.dataclass
@@ -114,7 +117,7 @@ class BsrM:
 
 @dataclasses.dataclass
 class Level:
-    n: int                      # nodes
+    n: int                      # nodes of block 0
     dofs: tuple
     A: list                     # 2x2 BsrM
     csr: list                   # 2x2 scipy CSR
@@ -133,6 +136,19 @@ class Level:
     omega_s: np.ndarray = None  # per-node smoother damping (None: Params.omega)
     omega_p: np.ndarray = None  # per-aggregate prolongator-smoothing weights used for P
     features: np.ndarray = None
+    n1: int = -1                # nodes of block 1 (-1: n, co-located fields)
+    agg1: np.ndarray = None     # block 1's aggregates when it is aggregated separately
+    n_agg1: int = 0
+
+    def __post_init__(self):
+        if self.n1 < 0:
+            self.n1 = self.n
+
+    def nodes(self, f: int) -> int:
+        return self.n if f == 0 else self.n1
+
+    def n_dofs(self) -> int:
+        return self.n * self.dofs[0] + self.n1 * self.dofs[1]
 
 
 @dataclasses.dataclass
@@ -438,6 +454,11 @@ def setup(blocks, dofs, params: Params | None = None, n_vec=None) -> Hierarchy:
     A = [[BsrM(b.n_brows, b.n_bcols, np.asarray(b.row_ptr, np.int32), np.asarray(b.col_idx, np.int32),
                np.asarray(b.vals, np.float64)) for b in row] for row in blocks]
     n = A[0][0].n_rows
+    n1 = A[1][1].n_rows
+    if p.clone and n1 != n:
+        raise ValueError("cloned aggregation needs co-located fields (equal node counts)")
+    if not p.clone:
+        return _setup_separate(A, dofs, p, n_vec)
     levels = []
     B = [np.ones((n, dofs[0])), np.ones((n, dofs[1]))]
     lvl = 0
@@ -478,7 +499,55 @@ def setup(blocks, dofs, params: Params | None = None, n_vec=None) -> Hierarchy:
         B = Bc
         n = n_agg
         lvl += 1
-    # smoothers on every level but the last
+    return _finish(levels, p)
+
+
+def _setup_separate(A, dofs, p: Params, n_vec) -> Hierarchy:
+    """Hierarchy with each block aggregated from the graph of its own diagonal
+    block (Sec. 4.3.1: fields that do not share nodes get a separate AMG setup
+    per block): aggregates, tentative P_ff and near-null space per block, the
+    transfer P = diag(P00, P11) with P00 != P11, and the Galerkin products of
+    all four blocks as P_f^T (A_fg P_g).  Coarsening stops when the level has
+    at most max_coarse dofs, at max_levels levels, or when the two blocks'
+    aggregates together keep more than 90 % of the level's nodes."""
+    if p.weights is not None or p.omega_p != 0.0 or p.smoother != 0:
+        raise ValueError("separate aggregation is built for the fixed form with the blocked smoother")
+    n = [A[0][0].n_rows, A[1][1].n_rows]
+    B = [np.ones((n[0], dofs[0])), np.ones((n[1], dofs[1]))]
+    levels = []
+    lvl = 0
+    while True:
+        lev = Level(n=n[0], n1=n[1], dofs=tuple(dofs), A=A,
+                    csr=[[A[f][g].csr() for g in range(2)] for f in range(2)])
+        levels.append(lev)
+        if n[0] * dofs[0] + n[1] * dofs[1] <= p.max_coarse or len(levels) >= p.max_levels:
+            break
+        aggs = [aggregate(A[f][f], p.theta, p.seed, lvl) for f in range(2)]
+        if aggs[0][1] + aggs[1][1] > 0.9 * (n[0] + n[1]):
+            break
+        Pb, q, Bc = [], [], []
+        for f in range(2):
+            agg, n_agg = aggs[f]
+            m_ptr, m_idx = members(agg, n_agg)
+            qf, bc = tentative(B[f], agg, m_ptr, m_idx)
+            q.append(qf)
+            Bc.append(bc)
+            Pb.append(tentative_bsr(qf, agg, n_agg))
+        lev.agg, lev.n_agg = aggs[0]
+        lev.agg1, lev.n_agg1 = aggs[1]
+        lev.m_ptr, lev.m_idx = members(*aggs[0])
+        lev.q = q
+        lev.P = [Pb[f].csr() for f in range(2)]
+        PT = [transpose(Pb[f]) for f in range(2)]
+        A = [[spgemm(PT[f], spgemm(A[f][g], Pb[g])) for g in range(2)] for f in range(2)]
+        B = Bc
+        n = [aggs[0][1], aggs[1][1]]
+        lvl += 1
+    return _finish(levels, p)
+
+
+def _finish(levels, p: Params) -> Hierarchy:
+    """Smoother data on every level but the last, and the last level's LU."""
     for lev in levels[:-1]:
         lev.colour, lev.n_colours, lev.dinv, lev.gs = [], [], [], []
         for f in range(2):
@@ -605,7 +674,7 @@ def mgv(h: Hierarchy, lvl: int, b: np.ndarray) -> np.ndarray:
         return sla.lu_solve(h.coarse_lu, b)
     b0, b1 = _split(lev, b)
     z = np.zeros(lev.n * lev.dofs[0])
-    x0, x1 = smooth(lev, z, np.zeros(lev.n * lev.dofs[1]), b0, b1, h.params)
+    x0, x1 = smooth(lev, z, np.zeros(lev.n1 * lev.dofs[1]), b0, b1, h.params)
     u = np.concatenate([x0, x1])
     r = b - apply_A(lev, u)
     r0, r1 = _split(lev, r)
@@ -704,7 +773,7 @@ def probe(h: Hierarchy, iters: int = 10, seed: int = 12345) -> float:
     """Asymptotic factor of the stationary iteration e <- e - M A e:
     (||e_iters|| / ||e_{iters-4}||)^(1/4)."""
     lev = h.levels[0]
-    e = seeded_vector(lev.n * sum(lev.dofs), seed)
+    e = seeded_vector(lev.n_dofs(), seed)
     n4 = nk = 0.0
     for k in range(1, iters + 1):
         e = e - vcycle(h, apply_A(lev, e))

@@ -118,7 +118,8 @@ class Bsr:
 
 @dataclasses.dataclass
 class BlockSystem:
-    """A 2x2 block system A x = b on N co-located nodes."""
+    """A 2x2 block system A x = b: block 0 on N nodes, block 1 on N1 nodes
+    (N1 = N when the fields are co-located)."""
     dim: int
     n: int
     N: int
@@ -127,10 +128,23 @@ class BlockSystem:
     blocks: list         # [[A00, A01], [A10, A11]] as Bsr
     b: np.ndarray        # [b0; b1]
     params: dict
+    N1: int = -1         # nodes of block 1 (-1: N)
+
+    def __post_init__(self):
+        if self.N1 < 0:
+            self.N1 = self.N
+
+    @property
+    def nodes(self) -> tuple:
+        return (self.N, self.N1)
+
+    @property
+    def co_located(self) -> bool:
+        return self.N1 == self.N
 
     @property
     def n_dofs(self) -> int:
-        return self.N * sum(self.dofs)
+        return self.N * self.dofs[0] + self.N1 * self.dofs[1]
 
     def to_scipy(self):
         """Monolithic scalar CSR in the blocked [x0; x1] ordering."""
@@ -285,6 +299,154 @@ def make_system(n: int, dim: int, gamma: float, *, seed: int = 1, kappa: str = "
                   reaction=reaction, blk1_scale=blk1_scale, a10_scale=a10_scale)
     return BlockSystem(dim=dim, n=n, N=N, dofs=(d, d), n_vec=(dim, dim),
                        blocks=[[A00, A01], [A10, A11]], b=b, params=params)
+
+
+def make_mixed_system(n: int, dim: int, gamma: float, *, seed: int = 1, kappa: str = "const",
+                      sigma: float = 1.0, tau: float = 1.0, reaction: float = 1.0) -> BlockSystem:
+    """The same two saddle blocks with block 1 on a grid twice as coarse, the
+    synthetic counterpart of a mixed discretisation whose fields live on
+    different node sets (block 0 on the finer nodes, block 1 on the coarser).
+
+    n must be odd: block 0 has n^dim interior nodes with spacing h = 1/(n+1),
+    block 1 has m^dim with m = (n-1)/2 and spacing 2h; coarse node J sits on
+    fine node 2J+1 along each axis.  kappa is drawn on the fine nodes and read
+    at the coincident ones for block 1.  Coupling: block-0 vector component a
+    at fine node i couples to block-1 component a at the coarse nodes of the
+    (multi)linear interpolation stencil of x_i, Z[(i,a),(J,a)] =
+    gamma g(i) phi_J(x_i) / (2h) with g the smooth seeded field of the
+    co-located generator; A01 = Z and A10 = -Z^T, so the coupling part of A is
+    skew and its symmetric part is the two saddle blocks' (A is positive-real).
+    """
+    if dim not in (2, 3):
+        raise ValueError("dim must be 2 or 3")
+    if n % 2 != 1 or n < 3:
+        raise ValueError("the mixed system needs an odd n >= 3")
+    m = (n - 1) // 2
+    fine = make_system(n, dim, gamma, seed=seed, kappa=kappa, sigma=sigma, tau=tau, reaction=reaction)
+    h = 1.0 / (n + 1)
+    N, N1 = n ** dim, m ** dim
+    d = dim + 1
+    # block 1: the saddle block on the coarse grid with kappa read at the coincident fine nodes
+    cidx = np.arange(N1, dtype=np.int64)
+    ccoords, rem = [], cidx.copy()
+    for a in range(dim):
+        ccoords.append(rem % m)
+        rem //= m
+    fine_of_coarse = sum((2 * ccoords[a] + 1) * n ** a for a in range(dim))
+    if kappa == "const":
+        kap_f = np.ones(N)
+    else:
+        kap_f = np.exp(sigma * rng_normal(seed, 2, np.arange(N, dtype=np.int64)))
+    coarse = _saddle_on_grid(m, dim, kap_f[fine_of_coarse], tau, reaction)
+    # coupling: fine node i, coarse nodes of its interpolation stencil
+    idx = np.arange(N, dtype=np.int64)
+    coords, rem = [], idx.copy()
+    for a in range(dim):
+        coords.append(rem % n)
+        rem //= n
+    per_axis = []            # per axis: list of (coarse index, weight) candidates for each fine index
+    for a in range(dim):
+        ia = coords[a]
+        odd = ia % 2 == 1
+        j_lo = np.where(odd, (ia - 1) // 2, ia // 2 - 1)
+        j_hi = np.where(odd, (ia - 1) // 2, ia // 2)
+        w = np.where(odd, 1.0, 0.5)
+        per_axis.append([(j_lo, w, np.ones(N, bool)), (j_hi, w, ~odd)])
+    gfield = _coupling_field(n, dim, seed, h)[0].reshape(-1) if gamma != 0.0 else np.zeros(N)
+    rows, cols, wts = [], [], []
+    import itertools
+    for choice in itertools.product(range(2), repeat=dim):
+        J = np.zeros(N, dtype=np.int64)
+        wgt = np.ones(N)
+        ok = np.ones(N, bool)
+        for a, c in enumerate(choice):
+            j, w, use = per_axis[a][c]
+            ok &= use & (j >= 0) & (j < m)
+            J += np.clip(j, 0, m - 1) * m ** a
+            wgt *= w
+        rows.append(idx[ok])
+        cols.append(J[ok])
+        wts.append(wgt[ok])
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    wts = np.concatenate(wts)
+    order = np.lexsort((cols, rows))
+    rows, cols, wts = rows[order], cols[order], wts[order]
+    zval = gamma * gfield[rows] * wts / (2.0 * h)
+    vals = np.zeros((rows.shape[0], d, d))
+    for a in range(dim):
+        vals[:, a, a] = zval
+    rp = np.zeros(N + 1, dtype=np.int32)
+    np.add.at(rp, rows + 1, 1)
+    rp = np.cumsum(rp).astype(np.int32)
+    A01 = Bsr(n_brows=N, n_bcols=N1, row_ptr=rp, col_idx=cols.astype(np.int32), vals=vals)
+    A10 = _negative_transpose(A01)
+    b = 2.0 * rng_uniform(seed, 3, np.arange(N * d + N1 * d)) - 1.0
+    params = dict(n=n, dim=dim, gamma=gamma, seed=seed, kappa=kappa, sigma=sigma, tau=tau, reaction=reaction,
+                  mixed=True)
+    return BlockSystem(dim=dim, n=n, N=N, dofs=(d, d), n_vec=(dim, dim),
+                       blocks=[[fine.blocks[0][0], A01], [A10, coarse]], b=b, params=params, N1=N1)
+
+
+def _saddle_on_grid(n: int, dim: int, kap: np.ndarray, tau: float, reaction: float) -> Bsr:
+    """The saddle block of make_system on an n^dim grid (spacing 1/(n+1)) for
+    given nodal kappa values."""
+    h = 1.0 / (n + 1)
+    N = n ** dim
+    d = dim + 1
+    idx = np.arange(N, dtype=np.int64)
+    coords, rem = [], idx.copy()
+    for a in range(dim):
+        coords.append(rem % n)
+        rem //= n
+    strides = [n ** a for a in range(dim)]
+    slots = _offsets(n, dim)
+    ns = len(slots)
+    valid = np.zeros((N, ns), dtype=bool)
+    cols = np.zeros((N, ns), dtype=np.int64)
+    kedge = np.zeros((N, ns))
+    diag_lap = np.zeros(N)
+    for s, (axis, sign) in enumerate(slots):
+        if sign == 0:
+            valid[:, s] = True
+            cols[:, s] = idx
+            continue
+        ci = coords[axis] + sign
+        inside = (ci >= 0) & (ci < n)
+        j = idx + sign * strides[axis]
+        valid[:, s] = inside
+        cols[:, s] = np.where(inside, j, idx)
+        kj = kap[np.where(inside, j, idx)]
+        ke = np.where(inside, 2.0 * kap * kj / (kap + kj), kap)
+        kedge[:, s] = np.where(inside, ke, 0.0)
+        diag_lap += ke
+    inv_h2, inv_2h = 1.0 / (h * h), 1.0 / (2.0 * h)
+    v = np.zeros((N, ns, d, d))
+    for s, (axis, sign) in enumerate(slots):
+        if sign == 0:
+            for a in range(dim):
+                v[:, s, a, a] = diag_lap * inv_h2 + reaction
+            v[:, s, dim, dim] = tau * 2.0 * dim
+        else:
+            mk = valid[:, s]
+            for a in range(dim):
+                v[:, s, a, a] = -kedge[:, s] * inv_h2
+            v[:, s, axis, dim] = np.where(mk, sign * inv_2h, 0.0)
+            v[:, s, dim, axis] = np.where(mk, sign * inv_2h, 0.0)
+            v[:, s, dim, dim] = np.where(mk, -tau, 0.0)
+    return _compress(N, valid, cols, v)
+
+
+def _negative_transpose(A: Bsr) -> Bsr:
+    """-A^T of a BSR block (blocks transposed, columns sorted within rows)."""
+    rows = np.repeat(np.arange(A.n_brows), np.diff(A.row_ptr))
+    cols = A.col_idx.astype(np.int64)
+    order = np.lexsort((rows, cols))
+    rp = np.zeros(A.n_bcols + 1, dtype=np.int64)
+    np.add.at(rp, cols + 1, 1)
+    rp = np.cumsum(rp).astype(np.int32)
+    vals = -np.transpose(A.vals[order], (0, 2, 1)).copy()
+    return Bsr(n_brows=A.n_bcols, n_bcols=A.n_brows, row_ptr=rp, col_idx=rows[order].astype(np.int32), vals=vals)
 
 
 def _compress(N: int, valid: np.ndarray, cols: np.ndarray, v: np.ndarray) -> Bsr:
