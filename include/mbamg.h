@@ -16,8 +16,8 @@
  *   Matrix blocks: BSR, int32 row pointers and column indices (columns sorted
  *   within each row), FP64 values, each block br x bc row-major.  Block (f,g)
  *   has br = dofs[f], bc = dofs[g].  A_00 must be structurally symmetric.
- *   Vectors: FP64, blocked [x_0; x_1]; segment f holds n_nodes*dofs[f]
- *   entries, node-major (x_f[node*dofs[f] + component]).
+ *   Vectors: FP64, blocked [x_0; x_1]; segment f holds N_f*dofs[f] entries
+ *   (N_f: block f's node count), node-major (x_f[node*dofs[f] + component]).
  *
  * Ownership
  *   mbamg_setup deep-copies the blocks (host or device memory), so the caller
@@ -74,7 +74,9 @@ typedef struct {
 } mbamg_bsr;
 
 /* Field grouping (eq. 2x2system): block f has dofs[f] unknowns per node, the
- * first n_vec[f] of them vector components.  Only n_blocks == 2 is built. */
+ * first n_vec[f] of them vector components.  Only n_blocks == 2 is built, with
+ * dofs[0] == dofs[1].  Block f's node count is A_ff's n_brows; the two are
+ * equal unless clone_aggregates == 0. */
 typedef struct {
     int32_t n_blocks;
     int32_t dofs[4];
@@ -95,7 +97,14 @@ typedef struct {
     double theta;             /* strength threshold on squared block norms (0) */
     int32_t max_levels;       /* (10) */
     int32_t max_coarse;       /* stop coarsening at or below this many dofs (2500) */
-    int32_t clone_aggregates; /* block 1 reuses block 0's aggregates (1; required) */
+    int32_t clone_aggregates; /* 1: block 1 reuses block 0's aggregates (the aggregate-cloning figure of
+                                 Sec. 4.3.1; needs co-located fields, equal node counts).  0: each block is
+                                 aggregated from the strong graph of its own diagonal block, the separate
+                                 per-block AMG setup of Sec. 4.3.1 for fields on different node sets
+                                 (A_00 on N_0 nodes, A_11 on N_1, A_01 N_0 x N_1); P = diag(P_00, P_11) with
+                                 P_00 != P_11, coarsening until both blocks' aggregates together keep more
+                                 than 90 % of a level's nodes; fixed form with the blocked smoother only
+                                 (learned = 0, omega_p = 0, smoother = 0).  (1) */
     int32_t reuse_P;          /* kept for the interface; P_11 = P_00 holds when clone is on */
     int32_t precision;        /* 0: FP64 V-cycle + GMRES; 1: FP32 V-cycle inside FP64 FGMRES */
     int32_t restart;          /* GMRES restart length (30, at most 31) */
@@ -180,8 +189,13 @@ mbamg_status mbamg_level_nodes(const mbamg_hierarchy* h, int32_t level, int32_t*
 
 /* Aggregate of every node of level l (l < n_levels-1), node order of the
  * level as built by the Galerkin products (not the smoother's colour order).
- * agg is a host buffer of n_nodes int32. */
+ * agg is a host buffer of n_nodes int32.  Block 0's aggregates. */
 mbamg_status mbamg_copy_aggregates(const mbamg_hierarchy* h, int32_t level, int32_t* agg);
+
+/* The same per block f: node count of block f on level l, and block f's
+ * aggregates (block 0's when cloned). */
+mbamg_status mbamg_level_block_nodes(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t* n_nodes);
+mbamg_status mbamg_copy_block_aggregates(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t* agg);
 
 /* Number of stored blocks of block (f,g) on level l. */
 mbamg_status mbamg_level_nnzb(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t g,

@@ -103,12 +103,15 @@ struct Vecs {
 };
 
 struct Level {
-    int n = 0;
+    int n = 0;                                 // nodes of block 0
+    int n1 = 0;                                // nodes of block 1 (n when the fields are co-located)
     int d[2] = {0, 0};
     bool coarsest = false;
     bool apply_parts = false;                  // coarsest level with its sliced operator (single-level hierarchy)
     SetupBsr A[2][2];
-    Aggregates G;
+    Aggregates G;                              // block 0's aggregates (both blocks' when cloned)
+    Aggregates G1;                             // block 1's own aggregates (separate aggregation)
+    bool separate = false;
     BlockLevel blk[2];
     // smoothed prolongators (natural order) and the weights that built them
     bool smoothed = false, damped = false;
@@ -124,6 +127,9 @@ struct Level {
     Vecs<double> v64;
     Vecs<float> v32;
     int64_t nnzb_total() const { return A[0][0].nnzb + A[0][1].nnzb + A[1][0].nnzb + A[1][1].nnzb; }
+    int nodes(int f) const { return f == 0 ? n : n1; }
+    int64_t ndof() const { return (int64_t)n * d[0] + (int64_t)n1 * d[1]; }
+    const Aggregates& agg_of(int f) const { return (f == 1 && separate) ? G1 : G; }
 };
 
 struct TimedLaunch {
@@ -604,7 +610,7 @@ static void colour_level(Level& Lv, hipEvent_t ready, int device) {
         same = same_pattern(Lv.A[0][0], Lv.A[1][1], cs);
         t1 = clock::now();
         for (int f = 0; f < (same ? 1 : 2); ++f) {
-            const size_t nrp = (size_t)Lv.n + 1, nci = (size_t)Lv.A[f][f].nnzb;
+            const size_t nrp = (size_t)Lv.nodes(f) + 1, nci = (size_t)Lv.A[f][f].nnzb;
             buf[f] = std::make_unique<PinnedBuf<int32_t>>(nrp + nci);
             int32_t* h = buf[f]->p;
             rp[f] = h;
@@ -655,10 +661,11 @@ static void colour_level(Level& Lv, hipEvent_t ready, int device) {
             // A00 is structurally symmetric (checked with its strength graph); block 1's
             // pattern, when it differs, is symmetrised here
             std::vector<int32_t> trp, tci;
-            const bool asym = f == 1 && transpose_pattern(Lv.n, rp[f], ci[f], trp, tci);
-            int ncol = asym ? greedy_colour(Lv.n, rp[f], ci[f], B.colour, trp.data(), tci.data())
-                            : greedy_colour(Lv.n, rp[f], ci[f], B.colour);
-            order_and_slice(B, Lv.n, ncol, rp[f]);
+            const int nf = Lv.nodes(f);
+            const bool asym = f == 1 && transpose_pattern(nf, rp[f], ci[f], trp, tci);
+            int ncol = asym ? greedy_colour(nf, rp[f], ci[f], B.colour, trp.data(), tci.data())
+                            : greedy_colour(nf, rp[f], ci[f], B.colour);
+            order_and_slice(B, nf, ncol, rp[f]);
         }
     }
 }
@@ -744,7 +751,11 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
     const mbamg_params& p = h->p;
     const int d0 = h->d[0], d1 = h->d[1];
     const int N = Ab[0].n_brows;
-    MB_CHECK(N > 0, MBAMG_E_INVALID, "empty system");
+    const int N1 = Ab[3].n_brows;
+    MB_CHECK(N > 0 && N1 > 0, MBAMG_E_INVALID, "empty system");
+    const bool separate = p.clone_aggregates == 0;
+    MB_CHECK(separate || N1 == N, MBAMG_E_INVALID,
+             "cloned aggregation needs co-located fields (equal node counts of A_00 and A_11)");
     const bool want32 = p.precision == 1;
     PhaseClock clk(s);
     h->coarse_pending = std::make_unique<PendingCoarse>();
@@ -765,23 +776,26 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
     // level 0 from the caller's blocks
     auto first = std::make_unique<Level>();
     first->n = N;
+    first->n1 = N1;
     first->d[0] = d0;
     first->d[1] = d1;
     for (int f = 0; f < 2; ++f)
-        for (int g = 0; g < 2; ++g) copy_block(Ab[f * 2 + g], first->A[f][g], N, N, h->d[f], h->d[g], s);
+        for (int g = 0; g < 2; ++g)
+            copy_block(Ab[f * 2 + g], first->A[f][g], first->nodes(f), first->nodes(g), h->d[f], h->d[g], s);
     MB_CHECK(first->A[0][0].nnzb > 0 && first->A[1][1].nnzb > 0, MBAMG_E_INVALID, "diagonal blocks must be nonzero");
     h->L.push_back(std::move(first));
 
     // near-null space per block: constants on the finest level
     DevBuf<double> Bn[2];
     for (int f = 0; f < 2; ++f) {
-        Bn[f].alloc((size_t)N * h->d[f]);
-        fill_ones(Bn[f].p, (int64_t)N * h->d[f], s);
+        const int64_t nb = (int64_t)h->L[0]->nodes(f) * h->d[f];
+        Bn[f].alloc((size_t)nb);
+        fill_ones(Bn[f].p, nb, s);
     }
     int lvl = 0;
     while (true) {
         Level& cur = *h->L.back();
-        const int64_t ndof = (int64_t)cur.n * (d0 + d1);
+        const int64_t ndof = cur.ndof();
         if (ndof <= p.max_coarse || (int)h->L.size() >= p.max_levels) break;
         clk.mark("start", lvl);
         if (lvl == 0 && from && from->agg.get()) {
@@ -813,9 +827,18 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
             clk.mark("strength", lvl);
             G = build_aggregates(S, p.seed, lvl, s);
         }
+        if (separate) {   // block 1 from the graph of its own diagonal block (Sec. 4.3.1)
+            Strength S1 = build_strength(cur.A[1][1], p.theta, s);
+            cur.G1 = build_aggregates(S1, p.seed, lvl, s);
+            cur.separate = true;
+        }
         clk.mark("aggregates", lvl);
-        if ((double)G.n_agg > 0.9 * cur.n) {   // this level is the coarsest
+        const bool stop = separate ? (double)(G.n_agg + cur.G1.n_agg) > 0.9 * ((double)cur.n + cur.n1)
+                                   : (double)G.n_agg > 0.9 * cur.n;
+        if (stop) {   // this level is the coarsest
             G = Aggregates();
+            cur.G1 = Aggregates();
+            cur.separate = false;
             break;
         }
         if (to && lvl == 0) {
@@ -835,13 +858,15 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
         }
         const int nc = G.n_agg;
         DevBuf<double> q[2], Bc[2];
-        for (int f = 0; f < 2; ++f) {     // block 1 reuses block 0's aggregates
-            q[f].alloc((size_t)cur.n * h->d[f]);
-            Bc[f].alloc((size_t)std::max(nc, 1) * h->d[f]);
-            build_tentative(G, h->d[f], Bn[f].p, q[f].p, Bc[f].p, s);
+        for (int f = 0; f < 2; ++f) {     // block 1 reuses block 0's aggregates unless aggregated separately
+            const Aggregates& Gf = cur.agg_of(f);
+            q[f].alloc((size_t)cur.nodes(f) * h->d[f]);
+            Bc[f].alloc((size_t)std::max(Gf.n_agg, 1) * h->d[f]);
+            build_tentative(Gf, h->d[f], Bn[f].p, q[f].p, Bc[f].p, s);
         }
         auto nxt = std::make_unique<Level>();
         nxt->n = nc;
+        nxt->n1 = cur.agg_of(1).n_agg;
         nxt->d[0] = d0;
         nxt->d[1] = d1;
         // A_c[f][g] = P_f^T A_fg P_g.  The four block pairs usually share one
@@ -900,7 +925,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
         } else {
             SetupBsr P[2], PT[2];
             for (int f = 0; f < 2; ++f) {
-                P[f] = tentative_bsr(G, h->d[f], q[f].p, s);
+                P[f] = tentative_bsr(cur.agg_of(f), h->d[f], q[f].p, s);
                 PT[f] = block_transpose(P[f], s);
             }
             galerkin_all(P, PT);
@@ -934,7 +959,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
         MB_HIP(hipStreamWaitEvent(side.stream, side.ready, 0));
         // its thousands of small launches are issued from a host thread of their own, so this
         // thread goes on queueing the smoother data at once
-        h->coarse_n = c.n * (c.d[0] + c.d[1]);
+        h->coarse_n = (int)c.ndof();
         Level* cp = &c;
         coarse_job = std::async(std::launch::async, [h, cp, &cwork, &side, device] {
             MB_HIP(hipSetDevice(device));
@@ -944,9 +969,9 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
         for (int f = 0; f < 2; ++f) {      // identity order
             BlockLevel& B = c.blk[f];
             B.d = c.d[f];
-            B.n = c.n;
-            B.colour.assign(c.n, 0);
-            order_and_slice(B, c.n, 1);     // one colour: identity order, slices for the transfer kernels
+            B.n = c.nodes(f);
+            B.colour.assign(c.nodes(f), 0);
+            order_and_slice(B, c.nodes(f), 1);   // one colour: identity order, slices for the transfer kernels
             B.row0.upload(B.h_row0, s);
             B.nrow.upload(B.h_nrow, s);
             B.d_perm.upload(B.perm, s);   // used at the interface when this is the only level
@@ -967,8 +992,8 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
             }
             c.apply_parts = true;
         }
-        alloc_vecs(c.v64, (int64_t)c.n * (d0 + d1));
-        if (want32) alloc_vecs(c.v32, (int64_t)c.n * (d0 + d1));
+        alloc_vecs(c.v64, c.ndof());
+        if (want32) alloc_vecs(c.v32, c.ndof());
     }
 
     // smoother format on every other level, in two passes: first each level's own smoother
@@ -1016,7 +1041,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
         // level, 188,588 nodes in 18 colours: 1.56 -> 1.36 ms per V-cycle against one wavefront
         // per row).  The row form's sliced parts are not built.
         const int max_colours = std::max(Lv.blk[0].n_colours, Lv.blk[1].n_colours);
-        bool rows_level = l > 0 && (int64_t)Lv.n <= (int64_t)ROWS_PER_COLOUR_MAX * max_colours;
+        bool rows_level = l > 0 && (int64_t)std::max(Lv.n, Lv.n1) <= (int64_t)ROWS_PER_COLOUR_MAX * max_colours;
         // MBAMG_ROWS_FORM (tests): "rows" forces the row form on every coarse level, anything else the sliced one
         if (const char* fo = form_override("MBAMG_ROWS_FORM")) rows_level = l > 0 && std::strcmp(fo, "rows") == 0;
         if (p.smoother == 1) rows_level = false;   // the full-node kernel reads the sliced parts
@@ -1024,7 +1049,8 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
             const int g = 1 - f;
             BlockLevel& B = Lv.blk[f];
             const int df = Lv.d[f], dg = Lv.d[g];
-            DevBuf<double> dinv((size_t)Lv.n * df * df);
+            const int nf = Lv.nodes(f);
+            DevBuf<double> dinv((size_t)nf * df * df);
             if (f == 0) clk.mark("colouring", l);
             build_dinv(Lv.A[f][f], dinv.p, s);
             clk.mark("dinv", l);
@@ -1032,7 +1058,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
             if (B.rows) {
                 // the per-colour counts the sliced parts would have recorded (byte model)
                 const std::vector<int64_t> cs7 =
-                    row_colour_stats(Lv.n, B.d_perm.p, Lv.A[f][f], Lv.A[f][g], dinv.p, B.colour_row, s);
+                    row_colour_stats(nf, B.d_perm.p, Lv.A[f][f], Lv.A[f][g], dinv.p, B.colour_row, s);
                 B.cstats.assign(B.n_colours, ColourStats{});
                 for (int c = 0; c < B.n_colours; ++c) {
                     ColourStats& cs = B.cstats[c];
@@ -1049,20 +1075,20 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
                 // few rows per colour (small, latency-bound launches): a workgroup's four
                 // wavefronts share each row, for shorter chains of dependent passes (measured
                 // 12 % faster on a 98-rows-per-colour level, 60 % slower on 10K rows per colour)
-                B.row_split = (df == 4 && Lv.n <= 1024 * std::max(1, B.n_colours)) ? 4 : 1;
+                B.row_split = (df == 4 && nf <= 1024 * std::max(1, B.n_colours)) ? 4 : 1;
                 if (const char* fo = form_override("MBAMG_ROW_SPLIT")) B.row_split = df == 4 ? std::atoi(fo) : 1;
-                build_rows(B.raff, Lv.n, B.d_perm.p, Lv.A[f][f], B.d_iperm.p, want32, s);
-                build_rows(B.rafg, Lv.n, B.d_perm.p, Lv.A[f][g], Lv.blk[g].d_iperm.p, want32, s);
-                B.rdinv64.alloc((size_t)Lv.n * df * df);
-                gather_blocks(Lv.n, df * df, B.d_perm.p, dinv.p, B.rdinv64.p, s);
+                build_rows(B.raff, nf, B.d_perm.p, Lv.A[f][f], B.d_iperm.p, want32, s);
+                build_rows(B.rafg, nf, B.d_perm.p, Lv.A[f][g], Lv.blk[g].d_iperm.p, want32, s);
+                B.rdinv64.alloc((size_t)nf * df * df);
+                gather_blocks(nf, df * df, B.d_perm.p, dinv.p, B.rdinv64.p, s);
                 if (want32) {
-                    B.rdinv32.alloc((size_t)Lv.n * df * df);
-                    cast_to_f32(B.rdinv64.p, B.rdinv32.p, (int64_t)Lv.n * df * df, s);
+                    B.rdinv32.alloc((size_t)nf * df * df);
+                    cast_to_f32(B.rdinv64.p, B.rdinv32.p, (int64_t)nf * df * df, s);
                 }
                 MB_HIP(hipStreamSynchronize(s));   // dinv is released at the end of this iteration
                 if (clk.on)
                     std::fprintf(stderr, "[mbamg setup] level %d block %d: %d nodes, %d colours, row form\n", l, f,
-                                 Lv.n, B.n_colours);
+                                 nf, B.n_colours);
                 continue;
             }
             build_part(B.off, PartKind::Off, B, &Lv.A[f][f], B.d_iperm.p, Lv.A[f][f].val.p, df, df, want32, s);
@@ -1098,7 +1124,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
             }
             if (clk.on)
                 std::fprintf(stderr, "[mbamg setup] level %d block %d: %d nodes, %d colours, %d slices, %.1f slots/slice, "
-                             "split %d\n", l, f, Lv.n, B.n_colours, B.n_slices, avg_width, B.split);
+                             "split %d\n", l, f, nf, B.n_colours, B.n_slices, avg_width, B.split);
         }
         clk.mark("sliced parts", l);
         if (p.smoother == 1) {
@@ -1146,23 +1172,25 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
         for (int f = 0; f < 2 && !Lv.smoothed; ++f) {
             BlockLevel& B = Lv.blk[f];
             const BlockLevel& C = Nx.blk[f];
-            transfer_maps(Lv.n, Nx.n, B.d_perm.p, B.d_iperm.p, Lv.G.agg.p, C.d_perm.p, C.d_iperm.p, Lv.G.mptr.p,
-                          Lv.G.midx.p, B.agg_p, B.mem_ptr, B.mem_idx, s);
-            B.res_group = restrict_group(Lv.n, Nx.n);
-            DevBuf<double> qp((size_t)Lv.n * B.d);
-            launch_gather(Lv.n, B.d, B.d_perm.p, B.q64.p, qp.p, s);
+            const Aggregates& Gf = Lv.agg_of(f);
+            const int nf = Lv.nodes(f);
+            transfer_maps(nf, Nx.nodes(f), B.d_perm.p, B.d_iperm.p, Gf.agg.p, C.d_perm.p, C.d_iperm.p, Gf.mptr.p,
+                          Gf.midx.p, B.agg_p, B.mem_ptr, B.mem_idx, s);
+            B.res_group = restrict_group(Lv.n + Lv.n1, Nx.n + Nx.n1);
+            DevBuf<double> qp((size_t)nf * B.d);
+            launch_gather(nf, B.d, B.d_perm.p, B.q64.p, qp.p, s);
             B.q64 = std::move(qp);
-            B.qm64.alloc((size_t)Lv.n * B.d);
-            launch_gather(Lv.n, B.d, B.mem_idx.p, B.q64.p, B.qm64.p, s);   // member m: fine row mem_idx[m]
+            B.qm64.alloc((size_t)nf * B.d);
+            launch_gather(nf, B.d, B.mem_idx.p, B.q64.p, B.qm64.p, s);   // member m: fine row mem_idx[m]
             if (want32) {
-                B.q32.alloc((size_t)Lv.n * B.d);
-                cast_to_f32(B.q64.p, B.q32.p, (int64_t)Lv.n * B.d, s);
-                B.qm32.alloc((size_t)Lv.n * B.d);
-                cast_to_f32(B.qm64.p, B.qm32.p, (int64_t)Lv.n * B.d, s);
+                B.q32.alloc((size_t)nf * B.d);
+                cast_to_f32(B.q64.p, B.q32.p, (int64_t)nf * B.d, s);
+                B.qm32.alloc((size_t)nf * B.d);
+                cast_to_f32(B.qm64.p, B.qm32.p, (int64_t)nf * B.d, s);
             }
         }
-        alloc_vecs(Lv.v64, (int64_t)Lv.n * (d0 + d1));
-        if (want32) alloc_vecs(Lv.v32, (int64_t)Lv.n * (d0 + d1));
+        alloc_vecs(Lv.v64, Lv.ndof());
+        if (want32) alloc_vecs(Lv.v32, Lv.ndof());
         MB_HIP(hipStreamSynchronize(s));
     }
 
@@ -1172,7 +1200,7 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
         clk.mark("coarse inverse joined", 0);
     }
     // Krylov workspace
-    h->n_fine = (int64_t)N * (d0 + d1);
+    h->n_fine = h->L[0]->ndof();
     const int m = p.restart;
     const int64_t n = h->n_fine;
     h->V.alloc((size_t)(m + 1) * n);
@@ -1244,12 +1272,12 @@ static double xfer_bytes(const SellPart& P, int64_t rows_out, int64_t rows_in, i
 // the member lists; the prolongation reads q, x_c and x and writes x, with the
 // aggregate map
 static double tentative_restrict_bytes(const Level& Lv, const Level& Nx, int s) {
-    const int64_t nf = (int64_t)Lv.n * (Lv.d[0] + Lv.d[1]), nc = (int64_t)Nx.n * (Nx.d[0] + Nx.d[1]);
-    return (double)s * (2.0 * nf + nc) + 4.0 * (Lv.n + Nx.n) * 2;
+    const int64_t nf = Lv.ndof(), nc = Nx.ndof();
+    return (double)s * (2.0 * nf + nc) + 4.0 * ((double)Lv.n + Lv.n1 + Nx.n + Nx.n1);
 }
 static double tentative_prolong_bytes(const Level& Lv, const Level& Nx, int s) {
-    const int64_t nf = (int64_t)Lv.n * (Lv.d[0] + Lv.d[1]), nc = (int64_t)Nx.n * (Nx.d[0] + Nx.d[1]);
-    return (double)s * (3.0 * nf + nc) + 4.0 * Lv.n * 2;
+    const int64_t nf = Lv.ndof(), nc = Nx.ndof();
+    return (double)s * (3.0 * nf + nc) + 4.0 * ((double)Lv.n + Lv.n1);
 }
 
 // Algorithmic bytes of level l's share of one V-cycle in the hierarchy's form:
@@ -1469,7 +1497,7 @@ static void resid(mbamg_hierarchy* h, int l, const T* b, const T* x, T* r, hipSt
     if (Lv.blk[0].rows && Lv.blk[1].rows) {
         ResidRowArgs<T> ra{};
         for (int f = 0; f < 2; ++f) {
-            ra.n[f] = Lv.n;
+            ra.n[f] = Lv.nodes(f);
             ra.aff[f] = rview<T>(Lv.blk[f].raff);
             ra.afg[f] = rview<T>(Lv.blk[f].rafg);
             ra.b[f] = a.b[f];
@@ -1542,7 +1570,7 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
     } else {
         TransferArgs<T> a{};
         for (int f = 0; f < 2; ++f) {
-            a.n_rows[f] = Nx.n;
+            a.n_rows[f] = Nx.nodes(f);
             a.map[f] = Lv.blk[f].mem_ptr.p;
             a.idx[f] = Lv.blk[f].mem_idx.p;
             a.q[f] = qmptr<T>(Lv.blk[f]);
@@ -1575,7 +1603,7 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
     } else {
         TransferArgs<T> a{};
         for (int f = 0; f < 2; ++f) {
-            a.n_rows[f] = Lv.n;
+            a.n_rows[f] = Lv.nodes(f);
             a.map[f] = Lv.blk[f].agg_p.p;
             a.idx[f] = nullptr;
             a.q[f] = qptr<T>(Lv.blk[f]);
@@ -1615,7 +1643,7 @@ static void to_colour(mbamg_hierarchy* h, const double* src, double* dst, hipStr
     MB_CHECK(L0.blk[0].d_perm.p && L0.blk[1].d_perm.p, MBAMG_E_STATE, "internal: finest-level order missing");
     const int64_t n0 = (int64_t)L0.n * L0.d[0];
     for (int f = 0; f < 2; ++f)
-        launch_gather(L0.n, L0.d[f], L0.blk[f].d_perm.p, src + (f ? n0 : 0), dst + (f ? n0 : 0), s);
+        launch_gather(L0.nodes(f), L0.d[f], L0.blk[f].d_perm.p, src + (f ? n0 : 0), dst + (f ? n0 : 0), s);
 }
 
 static void from_colour(mbamg_hierarchy* h, const double* src, double* dst, hipStream_t s) {
@@ -1623,7 +1651,7 @@ static void from_colour(mbamg_hierarchy* h, const double* src, double* dst, hipS
     MB_CHECK(L0.blk[0].d_perm.p && L0.blk[1].d_perm.p, MBAMG_E_STATE, "internal: finest-level order missing");
     const int64_t n0 = (int64_t)L0.n * L0.d[0];
     for (int f = 0; f < 2; ++f)
-        launch_scatter(L0.n, L0.d[f], L0.blk[f].d_perm.p, src + (f ? n0 : 0), dst + (f ? n0 : 0), s);
+        launch_scatter(L0.nodes(f), L0.d[f], L0.blk[f].d_perm.p, src + (f ? n0 : 0), dst + (f ? n0 : 0), s);
 }
 
 // A x on the finest level (colour order), FP64
@@ -1844,7 +1872,9 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
         MB_CHECK(p->omega > 0.0 && p->bgs_sweeps >= 1 && p->inner_sweeps >= 1 && p->max_levels >= 1 &&
                      p->restart >= 1 && p->restart <= KMAXQ - 2 && p->max_iters >= 0 && p->theta >= 0.0,
                  MBAMG_E_INVALID, "invalid parameters");
-        MB_CHECK(p->clone_aggregates != 0, MBAMG_E_INVALID, "separate block-1 aggregation is not built");
+        MB_CHECK(p->clone_aggregates != 0 || (p->learned == 0 && p->omega_p == 0.0 && p->smoother == 0),
+                 MBAMG_E_INVALID,
+                 "separate block-1 aggregation is built for the fixed form with the blocked smoother");
         MB_CHECK(p->precision == 0 || p->precision == 1, MBAMG_E_INVALID, "precision must be 0 or 1");
         MB_CHECK(p->learned >= 0 && p->learned <= 2, MBAMG_E_INVALID, "learned must be 0, 1 or 2");
         MB_CHECK(p->learned != 1 || p->mlp != nullptr, MBAMG_E_INVALID, "learned == 1 needs the network parameters");
@@ -1993,10 +2023,24 @@ mbamg_status mbamg_level_nodes(const mbamg_hierarchy* h, int32_t level, int32_t*
 }
 
 mbamg_status mbamg_copy_aggregates(const mbamg_hierarchy* h, int32_t level, int32_t* agg) {
+    return mbamg_copy_block_aggregates(h, level, 0, agg);
+}
+
+mbamg_status mbamg_level_block_nodes(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t* n_nodes) {
+    if (!h || !n_nodes || level < 0 || level >= (int)h->L.size() || f < 0 || f > 1) {
+        g_last_error = "bad argument";
+        return MBAMG_E_INVALID;
+    }
+    *n_nodes = h->L[level]->nodes(f);
+    return MBAMG_OK;
+}
+
+mbamg_status mbamg_copy_block_aggregates(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t* agg) {
     return guarded([&]() -> mbamg_status {
-        MB_CHECK(h && agg && level >= 0 && level + 1 < (int)h->L.size(), MBAMG_E_INVALID, "bad argument");
+        MB_CHECK(h && agg && level >= 0 && level + 1 < (int)h->L.size() && f >= 0 && f < 2, MBAMG_E_INVALID,
+                 "bad argument");
         const Level& L = *h->L[level];
-        MB_HIP(hipMemcpy(agg, L.G.agg.p, sizeof(int32_t) * L.n, hipMemcpyDeviceToHost));
+        MB_HIP(hipMemcpy(agg, L.agg_of(f).agg.p, sizeof(int32_t) * L.nodes(f), hipMemcpyDeviceToHost));
         return MBAMG_OK;
     });
 }

@@ -2478,8 +2478,8 @@ static void gj_run(CoarseWork& w, int n, hipStream_t s, double** result, const i
 
 void coarse_inverse_launch(const SetupBsr (&A)[2][2], const int d[2], DevBuf<double>& inv, CoarseWork& w,
                            hipStream_t s) {
-    const int nn = A[0][0].n_rows;
-    const int n = nn * (d[0] + d[1]);
+    const int nn = A[0][0].n_rows, nn1 = A[1][1].n_rows;   // nodes of each block
+    const int n = nn * d[0] + nn1 * d[1];
     MB_CHECK(n <= 16384, MBAMG_E_INVALID, "coarsest level too large for the dense solve (raise max_levels)");
     w.n = n;
     w.M.alloc((size_t)2 * n * n);
@@ -2495,8 +2495,8 @@ void coarse_inverse_launch(const SetupBsr (&A)[2][2], const int d[2], DevBuf<dou
         for (int g = 0; g < 2; ++g) {
             const SetupBsr& B = A[f][g];
             if (B.nnzb == 0) continue;
-            k_dense_scatter<<<grid_for(nn, 64), 64, 0, s>>>(nn, B.br, B.bc, B.rp.p, B.ci.p, B.val.p, off[f], off[g],
-                                                           (int64_t)n, w.M.p);
+            k_dense_scatter<<<grid_for(B.n_rows, 64), 64, 0, s>>>(B.n_rows, B.br, B.bc, B.rp.p, B.ci.p, B.val.p,
+                                                                 off[f], off[g], (int64_t)n, w.M.p);
             MB_LAUNCH_CHECK();
         }
     // threads T and rows per thread R set the panel width B: R * B doubles stay in registers

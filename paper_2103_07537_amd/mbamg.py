@@ -74,6 +74,8 @@ SIGNATURES = [
     ("mbamg_num_levels", ctypes.c_int, [_P, ctypes.POINTER(_I32)]),
     ("mbamg_level_nodes", ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32)]),
     ("mbamg_copy_aggregates", ctypes.c_int, [_P, _I32, _P]),
+    ("mbamg_level_block_nodes", ctypes.c_int, [_P, _I32, _I32, ctypes.POINTER(_I32)]),
+    ("mbamg_copy_block_aggregates", ctypes.c_int, [_P, _I32, _I32, _P]),
     ("mbamg_level_nnzb", ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_int64)]),
     ("mbamg_copy_level_block", ctypes.c_int, [_P, _I32, _I32, _I32, _P, _P, _P]),
     ("mbamg_copy_colours", ctypes.c_int, [_P, _I32, _I32, _P]),
@@ -157,7 +159,8 @@ class Hierarchy:
         self._h = ctypes.c_void_p()
         self.dofs = tuple(int(d) for d in dofs)
         self.n_nodes = int(blocks[0][0].n_brows)
-        self.n_dofs = self.n_nodes * sum(self.dofs)
+        self.n_nodes1 = int(blocks[1][1].n_brows)
+        self.n_dofs = self.n_nodes * self.dofs[0] + self.n_nodes1 * self.dofs[1]
         p = params if params is not None else default_params(**param_kw)
         self.params = p
         keep_alive = []
@@ -266,18 +269,23 @@ class Hierarchy:
         _check(lib().mbamg_level_nodes(self._h, level, ctypes.byref(n)))
         return n.value
 
-    def aggregates(self, level: int) -> np.ndarray:
-        a = np.zeros(self.level_nodes(level), dtype=np.int32)
-        _check(lib().mbamg_copy_aggregates(self._h, level, a.ctypes.data_as(ctypes.c_void_p)))
+    def block_nodes(self, level: int, f: int) -> int:
+        n = ctypes.c_int32()
+        _check(lib().mbamg_level_block_nodes(self._h, level, f, ctypes.byref(n)))
+        return n.value
+
+    def aggregates(self, level: int, f: int = 0) -> np.ndarray:
+        a = np.zeros(self.block_nodes(level, f), dtype=np.int32)
+        _check(lib().mbamg_copy_block_aggregates(self._h, level, f, a.ctypes.data_as(ctypes.c_void_p)))
         return a
 
     def colours(self, level: int, f: int) -> np.ndarray:
-        a = np.zeros(self.level_nodes(level), dtype=np.int32)
+        a = np.zeros(self.block_nodes(level, f), dtype=np.int32)
         _check(lib().mbamg_copy_colours(self._h, level, f, a.ctypes.data_as(ctypes.c_void_p)))
         return a
 
     def level_block(self, level: int, f: int, g: int):
-        n = self.level_nodes(level)
+        n = self.block_nodes(level, f)
         nnzb = ctypes.c_int64()
         _check(lib().mbamg_level_nnzb(self._h, level, f, g, ctypes.byref(nnzb)))
         rp = np.zeros(n + 1, dtype=np.int32)
