@@ -701,15 +701,17 @@ class SolveInfo:
     history: list
 
 
-def gmres(h: Hierarchy, b: np.ndarray, rtol: float = 1e-8, restart: int = 30,
-          max_iters: int = 1000, precond=None) -> tuple:
+def gmres(h, b: np.ndarray, rtol: float = 1e-8, restart: int = 30,
+          max_iters: int = 1000, precond=None, operator=None) -> tuple:
     """Restarted GMRES, right preconditioned by one V-cycle, x0 = 0.
 
     Stops when the recurrence residual |g_{j+1}| <= rtol*||b||, then confirms
-    with the true residual and restarts if that test fails.
+    with the true residual and restarts if that test fails.  ``precond`` and
+    ``operator`` replace the V-cycle and the operator apply of ``h`` (which may
+    then be None).
     """
     M = precond or (lambda v: vcycle(h, v))
-    A = lambda v: apply_A(h.levels[0], v)
+    A = operator or (lambda v: apply_A(h.levels[0], v))
     b = np.asarray(b, dtype=np.float64)
     bnorm = np.linalg.norm(b)
     x = np.zeros_like(b)

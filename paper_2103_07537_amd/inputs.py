@@ -388,6 +388,65 @@ def make_mixed_system(n: int, dim: int, gamma: float, *, seed: int = 1, kappa: s
                        blocks=[[fine.blocks[0][0], A01], [A10, coarse]], b=b, params=params, N1=N1)
 
 
+@dataclasses.dataclass
+class NBlockSystem:
+    """A block system of n_b co-located fields: blocks[f][g] couples field f's
+    dofs (dofs[f] per node) to field g's; b = [b_0; ...; b_(n_b-1)], each
+    segment node-major."""
+    dim: int
+    n: int
+    N: int
+    dofs: tuple
+    n_vec: tuple
+    blocks: list
+    b: np.ndarray
+    params: dict
+
+    @property
+    def n_dofs(self) -> int:
+        return self.N * sum(self.dofs)
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.bmat([[blk.to_scipy() for blk in row] for row in self.blocks], format="csr")
+
+
+def split_fields(s: BlockSystem) -> NBlockSystem:
+    """The 4 x 4 field split of a co-located 2 x 2 system: each block's vector
+    and scalar components become fields of their own -- (u, p, b, r), with
+    dim, 1, dim and 1 dofs per node.  A block between two fields stores a node
+    pair only where its sub-block has a nonzero entry; a field pair with no
+    such entry is a zero block."""
+    if not s.co_located:
+        raise ValueError("the field split needs co-located blocks")
+    dim = s.dim
+    comps = [(0, list(range(dim))), (0, [dim]), (1, list(range(dim))), (1, [dim])]
+    blocks = []
+    for F, rsel in comps:
+        row = []
+        for G, csel in comps:
+            B = s.blocks[F][G]
+            sub = B.vals[:, rsel, :][:, :, csel]
+            keep = np.any(sub != 0.0, axis=(1, 2))
+            rows = np.repeat(np.arange(B.n_brows), np.diff(B.row_ptr))[keep]
+            rp = np.zeros(B.n_brows + 1, dtype=np.int32)
+            np.add.at(rp, rows + 1, 1)
+            rp = np.cumsum(rp).astype(np.int32)
+            vals = np.ascontiguousarray(sub[keep])
+            if vals.shape[0] == 0:
+                vals = np.zeros((0, len(rsel), len(csel)))
+            row.append(Bsr(n_brows=B.n_brows, n_bcols=B.n_bcols, row_ptr=rp,
+                           col_idx=np.ascontiguousarray(B.col_idx[keep]).astype(np.int32), vals=vals))
+        blocks.append(row)
+    N = s.N
+    d0 = s.dofs[0]
+    b0 = s.b[:N * d0].reshape(N, d0)
+    b1 = s.b[N * d0:].reshape(N, s.dofs[1])
+    b = np.concatenate([b0[:, :dim].reshape(-1), b0[:, dim], b1[:, :dim].reshape(-1), b1[:, dim]])
+    return NBlockSystem(dim=dim, n=s.n, N=N, dofs=(dim, 1, dim, 1), n_vec=(dim, 0, dim, 0), blocks=blocks, b=b,
+                        params=dict(s.params, split="u,p,b,r"))
+
+
 def _saddle_on_grid(n: int, dim: int, kap: np.ndarray, tau: float, reaction: float) -> Bsr:
     """The saddle block of make_system on an n^dim grid (spacing 1/(n+1)) for
     given nodal kappa values."""
