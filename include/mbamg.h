@@ -16,8 +16,9 @@
  *   Matrix blocks: BSR, int32 row pointers and column indices (columns sorted
  *   within each row), FP64 values, each block br x bc row-major.  Block (f,g)
  *   has br = dofs[f], bc = dofs[g].  A_00 must be structurally symmetric.
- *   Vectors: FP64, blocked [x_0; x_1]; segment f holds N_f*dofs[f] entries
- *   (N_f: block f's node count), node-major (x_f[node*dofs[f] + component]).
+ *   Vectors: FP64, blocked [x_0; x_1; ...]; segment f holds N_f*dofs[f]
+ *   entries (N_f: block f's node count), node-major
+ *   (x_f[node*dofs[f] + component]).
  *
  * Ownership
  *   mbamg_setup deep-copies the blocks (host or device memory), so the caller
@@ -73,10 +74,18 @@ typedef struct {
     int32_t on_device;
 } mbamg_bsr;
 
-/* Field grouping (eq. 2x2system): block f has dofs[f] unknowns per node, the
- * first n_vec[f] of them vector components.  Only n_blocks == 2 is built, with
- * dofs[0] == dofs[1].  Block f's node count is A_ff's n_brows; the two are
- * equal unless clone_aggregates == 0. */
+/* Field grouping (eq. block-prec-form; eq. 2x2system for two blocks): block f
+ * has dofs[f] unknowns per node, the first n_vec[f] of them vector
+ * components.  n_blocks = 2 with dofs[0] == dofs[1] is the full method (FP64
+ * and FP32 forms, learned weights, both smoothers); block f's node count is
+ * A_ff's n_brows, equal for both blocks unless clone_aggregates == 0.
+ * n_blocks = 3 or 4 (e.g. the 4 x 4 split into u, p, b, r of Sec. 2.1, dofs
+ * 1..4 per block) takes co-located fields: the aggregates of A_00 cloned to
+ * every block and Algorithm 1 (Sec. 4.3.2) over the blocks in order; FP64,
+ * fixed weights and the blocked smoother only (precision = 0, learned = 0,
+ * omega_p = 0, smoother = 0, clone_aggregates = 1; MBAMG_E_INVALID
+ * otherwise).  A block may be a zero block (nnzb = 0) except the diagonal
+ * ones. */
 typedef struct {
     int32_t n_blocks;
     int32_t dofs[4];
@@ -147,7 +156,7 @@ void mbamg_default_params(mbamg_params* p);
  * all four blocks on every level, colouring and nodal D^-1 for the smoother of
  * Algorithm 1 (Sec. 4.3.2), and the inverse of the coarsest matrix.  A_blocks
  * points to n_blocks*n_blocks blocks in row-major order (A_00, A_01, A_10,
- * A_11), deep-copied.  The colouring of a diagonal block is taken over its
+ * A_11 for two blocks), deep-copied.  The colouring of a diagonal block is taken over its
  * symmetrised pattern, so A_11 need not be structurally symmetric.  *out
  * receives the hierarchy (the caller releases it with mbamg_destroy), or NULL
  * on an error, when whatever the build had allocated has been released.
@@ -290,7 +299,8 @@ mbamg_status mbamg_timing_enable(mbamg_hierarchy* h, int32_t enable);   /* reset
 mbamg_status mbamg_timing_get(mbamg_hierarchy* h, int32_t kind, int64_t* launches,
                               double* total_ms, double* bytes);
 
-/* Algorithmic bytes of one V-cycle of the current hierarchy and form. */
+/* Algorithmic bytes of one V-cycle of the current hierarchy and form (two-block
+ * hierarchies; MBAMG_E_STATE for more blocks). */
 mbamg_status mbamg_vcycle_bytes(const mbamg_hierarchy* h, double* bytes);
 
 /* The same for level l's share: *down on the way down (pre-smoothing,

@@ -132,6 +132,42 @@ struct Level {
     const Aggregates& agg_of(int f) const { return (f == 1 && separate) ? G1 : G; }
 };
 
+// Systems of more than two blocks (eq. block-prec-form), co-located fields:
+// the aggregates of A_00 are cloned to every block, and Algorithm 1 runs over
+// the blocks in order with each block's couplings folded into its right-hand
+// side.  Every block keeps its own colour order and sliced smoother parts
+// (A_ff without its diagonal, nodal inverses); every block A_fg is also held
+// in row form (rows in block f's colour order, columns in block g's) for the
+// couplings, the residual and the operator.
+constexpr int MAXB = 4;
+struct GLevel {
+    int n = 0, nb = 0;
+    int d[MAXB] = {0, 0, 0, 0};
+    int64_t off[MAXB + 1] = {0, 0, 0, 0, 0};   // first dof of each block
+    bool coarsest = false;
+    SetupBsr A[MAXB][MAXB];
+    Aggregates G;
+    BlockLevel blk[MAXB];
+    RowPart R[MAXB][MAXB];
+    DevBuf<double> b, x, xs, t, r, rhs;
+    void set_blocks(int nodes, int nblocks, const int* dofs) {
+        n = nodes;
+        nb = nblocks;
+        off[0] = 0;
+        for (int f = 0; f < nb; ++f) {
+            d[f] = dofs[f];
+            off[f + 1] = off[f] + (int64_t)n * d[f];
+        }
+    }
+    int64_t ndof() const { return off[nb]; }
+    int64_t nnzb_total() const {
+        int64_t t = 0;
+        for (int f = 0; f < nb; ++f)
+            for (int g = 0; g < nb; ++g) t += A[f][g].nnzb;
+        return t;
+    }
+};
+
 struct TimedLaunch {
     int kind;
     hipEvent_t a, b;
@@ -213,7 +249,9 @@ struct mbamg_hierarchy {
     mbamg_params p{};
     mbamg_field_map fm{};
     int d[2] = {0, 0};
+    int nb = 2;                                // blocks; more than two use GL instead of L
     std::vector<std::unique_ptr<Level>> L;
+    std::vector<std::unique_ptr<GLevel>> GL;
     DevBuf<double> coarse_inv;
     int coarse_n = 0;
     // Krylov workspace
@@ -1618,8 +1656,297 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
     MB_CHECK(buf[cur] == out, MBAMG_E_STATE, "internal: V-cycle result not in the output buffer");
 }
 
+
+// ----------------------------------------------------------------------------
+// more than two blocks: setup and V-cycle
+// ----------------------------------------------------------------------------
+static void zero_block(SetupBsr& Z, int n_rows, int n_cols, int br, int bc, hipStream_t s) {
+    Z = SetupBsr();
+    Z.n_rows = n_rows;
+    Z.n_cols = n_cols;
+    Z.br = br;
+    Z.bc = bc;
+    Z.nnzb = 0;
+    Z.rp.alloc(n_rows + 1);
+    MB_HIP(hipMemsetAsync(Z.rp.p, 0, sizeof(int32_t) * (n_rows + 1), s));
+    Z.ci.alloc(1);
+    Z.val.alloc(1);
+}
+
+// Hierarchy of an nb-block system (nb = 3 or 4): strength graph and aggregates
+// of A_00 cloned to every block (Sec. 4.3.1), a piecewise-constant P_f per
+// block, Galerkin products P_f^T A_fg P_g of every stored block pair (a zero
+// block stays zero), the coarsest inverse, and per level every block's colour
+// order, smoother parts and row forms.  FP64, fixed weights.
+static void gen_setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    const mbamg_params& p = h->p;
+    const int nb = h->nb;
+    const int N = Ab[0].n_brows;
+    MB_CHECK(N > 0, MBAMG_E_INVALID, "empty system");
+    const int* dofs = h->fm.dofs;
+    {
+        auto first = std::make_unique<GLevel>();
+        first->set_blocks(N, nb, dofs);
+        for (int f = 0; f < nb; ++f)
+            for (int g = 0; g < nb; ++g) copy_block(Ab[f * nb + g], first->A[f][g], N, N, dofs[f], dofs[g], s);
+        for (int f = 0; f < nb; ++f)
+            MB_CHECK(first->A[f][f].nnzb > 0, MBAMG_E_INVALID, "diagonal blocks must be nonzero");
+        h->GL.push_back(std::move(first));
+    }
+    DevBuf<double> Bn[MAXB];
+    for (int f = 0; f < nb; ++f) {
+        Bn[f].alloc((size_t)N * dofs[f]);
+        fill_ones(Bn[f].p, (int64_t)N * dofs[f], s);
+    }
+    int lvl = 0;
+    while (true) {
+        GLevel& cur = *h->GL.back();
+        if (cur.ndof() <= p.max_coarse || (int)h->GL.size() >= p.max_levels) break;
+        Strength S = build_strength(cur.A[0][0], p.theta, s);
+        cur.G = build_aggregates(S, p.seed, lvl, s);
+        if ((double)cur.G.n_agg > 0.9 * cur.n) {   // this level is the coarsest
+            cur.G = Aggregates();
+            break;
+        }
+        const int nc = cur.G.n_agg;
+        auto nxt = std::make_unique<GLevel>();
+        nxt->set_blocks(nc, nb, dofs);
+        SetupBsr P[MAXB], PT[MAXB];
+        DevBuf<double> q[MAXB], Bc[MAXB];
+        for (int f = 0; f < nb; ++f) {
+            q[f].alloc((size_t)cur.n * dofs[f]);
+            Bc[f].alloc((size_t)std::max(nc, 1) * dofs[f]);
+            build_tentative(cur.G, dofs[f], Bn[f].p, q[f].p, Bc[f].p, s);
+            P[f] = tentative_bsr(cur.G, dofs[f], q[f].p, s);
+            PT[f] = block_transpose(P[f], s);
+        }
+        for (int f = 0; f < nb; ++f)
+            for (int g = 0; g < nb; ++g) {
+                if (cur.A[f][g].nnzb == 0) {
+                    zero_block(nxt->A[f][g], nc, nc, dofs[f], dofs[g], s);
+                    continue;
+                }
+                SetupBsr T = spgemm(cur.A[f][g], P[g], s);
+                nxt->A[f][g] = spgemm(PT[f], T, s);
+            }
+        for (int f = 0; f < nb; ++f) {
+            cur.blk[f].q64 = std::move(q[f]);
+            Bn[f] = std::move(Bc[f]);
+        }
+        h->GL.push_back(std::move(nxt));
+        ++lvl;
+    }
+    h->GL.back()->coarsest = true;
+    {   // coarsest: dense inverse
+        GLevel& c = *h->GL.back();
+        h->coarse_n = (int)c.ndof();
+        const SetupBsr* ab[MAXB * MAXB];
+        for (int f = 0; f < nb; ++f)
+            for (int g = 0; g < nb; ++g) ab[f * nb + g] = &c.A[f][g];
+        CoarseWork w;
+        coarse_inverse_launch_blocks(ab, nb, c.d, h->coarse_inv, w, s);
+        coarse_inverse_finish(w, s);
+    }
+    // colour orders (first fit over each diagonal block's symmetrised pattern), smoother
+    // parts and row forms
+    for (auto& lp : h->GL) {
+        GLevel& Lv = *lp;
+        for (int f = 0; f < nb; ++f) {
+            BlockLevel& B = Lv.blk[f];
+            B.d = Lv.d[f];
+            if (Lv.coarsest) {
+                B.colour.assign(Lv.n, 0);
+                order_and_slice(B, Lv.n, 1);
+            } else {
+                const std::vector<int32_t> rp = Lv.A[f][f].rp.download(s, (size_t)Lv.n + 1);
+                const std::vector<int32_t> ci = Lv.A[f][f].ci.download(s, (size_t)Lv.A[f][f].nnzb);
+                std::vector<int32_t> trp, tci;
+                const bool asym = transpose_pattern(Lv.n, rp.data(), ci.data(), trp, tci);
+                const int ncol = asym ? greedy_colour(Lv.n, rp.data(), ci.data(), B.colour, trp.data(), tci.data())
+                                      : greedy_colour(Lv.n, rp.data(), ci.data(), B.colour);
+                order_and_slice(B, Lv.n, ncol, rp.data());
+            }
+            B.row0.upload(B.h_row0, s);
+            B.nrow.upload(B.h_nrow, s);
+            B.d_perm.upload(B.perm, s);
+            B.d_iperm.upload(B.iperm, s);
+        }
+        for (int f = 0; f < nb; ++f)
+            for (int g = 0; g < nb; ++g)
+                build_rows(Lv.R[f][g], Lv.n, Lv.blk[f].d_perm.p, Lv.A[f][g], Lv.blk[g].d_iperm.p, false, s);
+        if (!Lv.coarsest) {
+            for (int f = 0; f < nb; ++f) {
+                BlockLevel& B = Lv.blk[f];
+                const int df = Lv.d[f];
+                DevBuf<double> dinv((size_t)Lv.n * df * df);
+                build_dinv(Lv.A[f][f], dinv.p, s);
+                build_part(B.off, PartKind::Off, B, &Lv.A[f][f], B.d_iperm.p, Lv.A[f][f].val.p, df, df, false, s);
+                build_part(B.dinv, PartKind::Dinv, B, nullptr, nullptr, dinv.p, df, df, false, s);
+                int64_t slots = 0;
+                for (int sl = 0; sl < B.n_slices; ++sl) slots += B.off.h_width[sl];
+                const double avg_width = B.n_slices ? (double)slots / B.n_slices : 0.0;
+                B.split = slot_split((double)B.n_slices / std::max(1, B.n_colours), avg_width);
+            }
+        }
+        const int64_t nd = std::max<int64_t>(Lv.ndof(), 1);
+        Lv.b.alloc(nd);
+        Lv.x.alloc(nd);
+        Lv.xs.alloc(nd);
+        Lv.t.alloc(nd);
+        Lv.r.alloc(nd);
+        Lv.rhs.alloc(nd);
+        MB_HIP(hipStreamSynchronize(s));
+    }
+    // transfers between each level's and the next level's colour orders
+    for (size_t l = 0; l + 1 < h->GL.size(); ++l) {
+        GLevel& Lv = *h->GL[l];
+        GLevel& Nx = *h->GL[l + 1];
+        for (int f = 0; f < nb; ++f) {
+            BlockLevel& B = Lv.blk[f];
+            const BlockLevel& C = Nx.blk[f];
+            transfer_maps(Lv.n, Nx.n, B.d_perm.p, B.d_iperm.p, Lv.G.agg.p, C.d_perm.p, C.d_iperm.p, Lv.G.mptr.p,
+                          Lv.G.midx.p, B.agg_p, B.mem_ptr, B.mem_idx, s);
+            B.res_group = restrict_group(Lv.n, Nx.n);
+            DevBuf<double> qp((size_t)Lv.n * B.d);
+            launch_gather(Lv.n, B.d, B.d_perm.p, B.q64.p, qp.p, s);
+            B.q64 = std::move(qp);
+            B.qm64.alloc((size_t)Lv.n * B.d);
+            launch_gather(Lv.n, B.d, B.mem_idx.p, B.q64.p, B.qm64.p, s);
+        }
+        MB_HIP(hipStreamSynchronize(s));
+    }
+    // Krylov workspace
+    h->n_fine = h->GL[0]->ndof();
+    const int m = p.restart;
+    const int64_t n = h->n_fine;
+    h->V.alloc((size_t)(m + 1) * n);
+    h->Z64.alloc((size_t)m * n);
+    h->w.alloc(n);
+    h->xw.alloc(n);
+    h->bw.alloc(n);
+    h->vio.alloc(n);
+    h->vio2.alloc(n);
+    h->partial.alloc((size_t)KBLOCKS * KMAXQ);
+    h->hbuf.alloc(KB_TOTAL);
+    h->ybuf.alloc(KMAXQ);
+    h->sig2.alloc(KMAXQ);
+    MB_HIP(hipHostMalloc((void**)&h->hbuf_host, sizeof(double) * KB_TOTAL, hipHostMallocDefault));
+    MB_HIP(hipHostMalloc((void**)&h->sig2_host, sizeof(double) * KMAXQ, hipHostMallocDefault));
+    MB_HIP(hipHostMalloc((void**)&h->y_host, sizeof(double) * KMAXQ, hipHostMallocDefault));
+    MB_HIP(hipStreamSynchronize(s));
+    h->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    int64_t nz0 = h->GL[0]->nnzb_total(), nzs = 0;
+    for (auto& lv : h->GL) nzs += lv->nnzb_total();
+    h->info.levels = (int)h->GL.size();
+    h->info.op_complexity = nz0 ? (double)nzs / (double)nz0 : 1.0;
+    h->info.t_setup_ms = h->t_setup_ms;
+}
+
+static RowView<double> grview(const RowPart& R) { return {R.rp.p, R.col.p, R.v64.p}; }
+
+// y_f = b_f - sum over blocks g of A_fg x_g (b NULL: y = sum A_fg x_g); xs[g] NULL skips block g
+static void gen_block_rows(const GLevel& Lv, int f, const double* b, const double* const* xs, double* y, bool skip_f,
+                           hipStream_t s) {
+    const int64_t len = (int64_t)Lv.n * Lv.d[f];
+    if (b) MB_HIP(hipMemcpyAsync(y, b, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
+    else MB_HIP(hipMemsetAsync(y, 0, sizeof(double) * len, s));
+    for (int g = 0; g < Lv.nb; ++g) {
+        if ((skip_f && g == f) || !xs[g] || Lv.R[f][g].nnzb == 0) continue;
+        launch_rows_acc<double>(Lv.n, Lv.d[f], Lv.d[g], grview(Lv.R[f][g]), xs[g], y, b ? -1.0 : 1.0, s);
+    }
+}
+
+// w = A x (b NULL) or r = b - A x on level l (colour order, all blocks)
+static void gen_resid(mbamg_hierarchy* h, int l, const double* b, const double* x, double* r, hipStream_t s) {
+    GLevel& Lv = *h->GL[l];
+    const double* xs[MAXB];
+    for (int g = 0; g < Lv.nb; ++g) xs[g] = x + Lv.off[g];
+    for (int f = 0; f < Lv.nb; ++f) gen_block_rows(Lv, f, b ? b + Lv.off[f] : nullptr, xs, r + Lv.off[f], false, s);
+}
+
+// One V-cycle on level l from a zero guess (the MGV figure of Sec. 3) with
+// Algorithm 1 over the level's blocks as pre- and post-smoother.
+static void gen_vcycle_level(mbamg_hierarchy* h, int l, const double* b, double* out, hipStream_t s) {
+    GLevel& Lv = *h->GL[l];
+    if (Lv.coarsest) {
+        launch_coarse<double>(h->coarse_n, h->coarse_inv.p, b, out, s);
+        return;
+    }
+    const int nb = Lv.nb;
+    const int writes = 2 * h->p.bgs_sweeps;
+    double* buf[2];
+    buf[0] = (writes % 2 == 0) ? Lv.xs.p : out;
+    buf[1] = (writes % 2 == 0) ? out : Lv.xs.p;
+    int cur = -1;
+    auto sweep = [&](bool zero) {
+        const int nx = cur < 0 ? 0 : 1 - cur;
+        const double* X = cur < 0 ? nullptr : buf[cur];
+        double* XN = buf[nx];
+        for (int f = 0; f < nb; ++f) {
+            // the couplings of block f with the blocks before it (already relaxed in this sweep)
+            // and after it (the incoming iterate) go into its right-hand side
+            const double* xs[MAXB];
+            for (int g = 0; g < nb; ++g) xs[g] = g < f ? XN + Lv.off[g] : (X ? X + Lv.off[g] : nullptr);
+            double* rhs = Lv.rhs.p + Lv.off[f];
+            gen_block_rows(Lv, f, b + Lv.off[f], xs, rhs, true, s);
+            BlockLevel& B = Lv.blk[f];
+            for (int k = 0; k < h->p.inner_sweeps; ++k)
+                for (int c = 0; c < B.n_colours; ++c) {
+                    GsArgs<double> a{};
+                    a.s_begin = B.colour_slice[c];
+                    a.s_count = B.colour_slice[c + 1] - B.colour_slice[c];
+                    a.sl = B.slices();
+                    a.off = B.off.view<double>();
+                    a.dinv = B.dinv.view<double>();
+                    a.b = rhs;
+                    a.x = X ? X + Lv.off[f] : nullptr;
+                    a.t = Lv.t.p + Lv.off[f];
+                    a.xn = XN + Lv.off[f];
+                    a.xg = nullptr;
+                    a.cstart = k == 0 ? B.colour_row[c] : INT_MAX;
+                    a.omega = h->p.omega;
+                    a.w_row = nullptr;
+                    a.skip_off = (zero && k == 0 && c == 0) ? 1 : 0;
+                    launch_gs<double>(B.d, B.split, zero, false, a, s);
+                }
+        }
+        cur = nx;
+    };
+    for (int k = 0; k < h->p.bgs_sweeps; ++k) sweep(k == 0);
+    gen_resid(h, l, b, buf[cur], Lv.r.p, s);
+    GLevel& Nx = *h->GL[l + 1];
+    for (int f = 0; f < nb; ++f) {   // restriction, one block at a time (its own block size)
+        TransferArgs<double> a{};
+        a.n_rows[0] = Nx.n;
+        a.map[0] = Lv.blk[f].mem_ptr.p;
+        a.idx[0] = Lv.blk[f].mem_idx.p;
+        a.q[0] = Lv.blk[f].qm64.p;
+        a.in[0] = Lv.r.p + Lv.off[f];
+        a.out[0] = Nx.b.p + Nx.off[f];
+        launch_restrict<double>(Lv.d[f], a, Lv.blk[f].res_group, s);
+    }
+    gen_vcycle_level(h, l + 1, Nx.b.p, Nx.x.p, s);
+    for (int f = 0; f < nb; ++f) {   // prolongation
+        TransferArgs<double> a{};
+        a.n_rows[0] = Lv.n;
+        a.map[0] = Lv.blk[f].agg_p.p;
+        a.q[0] = Lv.blk[f].q64.p;
+        a.in[0] = Nx.x.p + Nx.off[f];
+        a.out[0] = buf[cur] + Lv.off[f];
+        launch_prolong<double>(Lv.d[f], a, s);
+    }
+    for (int k = 0; k < h->p.bgs_sweeps; ++k) sweep(false);
+    MB_CHECK(buf[cur] == out, MBAMG_E_STATE, "internal: V-cycle result not in the output buffer");
+}
+
 // z = M^-1 v for FP64 colour-order vectors of the finest level (either form).
 static void apply_precond(mbamg_hierarchy* h, const double* v, double* z64, float* z32, hipStream_t s) {
+    if (h->nb > 2) {
+        TimerScope ts(h, s, h->time_vcycles(), TK_VCYCLE, 0.0);
+        gen_vcycle_level(h, 0, v, z64, s);
+        return;
+    }
     if (h->p.precision == 1) {
         Level& L0 = *h->L[0];
         launch_cast64to32(h->n_fine, v, h->vin32.p, s);
@@ -1639,6 +1966,12 @@ static void apply_precond(mbamg_hierarchy* h, const double* v, double* z64, floa
 }
 
 static void to_colour(mbamg_hierarchy* h, const double* src, double* dst, hipStream_t s) {
+    if (h->nb > 2) {
+        const GLevel& L0 = *h->GL[0];
+        for (int f = 0; f < L0.nb; ++f)
+            launch_gather(L0.n, L0.d[f], L0.blk[f].d_perm.p, src + L0.off[f], dst + L0.off[f], s);
+        return;
+    }
     Level& L0 = *h->L[0];
     MB_CHECK(L0.blk[0].d_perm.p && L0.blk[1].d_perm.p, MBAMG_E_STATE, "internal: finest-level order missing");
     const int64_t n0 = (int64_t)L0.n * L0.d[0];
@@ -1647,6 +1980,12 @@ static void to_colour(mbamg_hierarchy* h, const double* src, double* dst, hipStr
 }
 
 static void from_colour(mbamg_hierarchy* h, const double* src, double* dst, hipStream_t s) {
+    if (h->nb > 2) {
+        const GLevel& L0 = *h->GL[0];
+        for (int f = 0; f < L0.nb; ++f)
+            launch_scatter(L0.n, L0.d[f], L0.blk[f].d_perm.p, src + L0.off[f], dst + L0.off[f], s);
+        return;
+    }
     Level& L0 = *h->L[0];
     MB_CHECK(L0.blk[0].d_perm.p && L0.blk[1].d_perm.p, MBAMG_E_STATE, "internal: finest-level order missing");
     const int64_t n0 = (int64_t)L0.n * L0.d[0];
@@ -1656,6 +1995,10 @@ static void from_colour(mbamg_hierarchy* h, const double* src, double* dst, hipS
 
 // A x on the finest level (colour order), FP64
 static void apply_A(mbamg_hierarchy* h, const double* x, double* w, hipStream_t s, int kind = 2) {
+    if (h->nb > 2) {
+        gen_resid(h, 0, nullptr, x, w, s);
+        return;
+    }
     Level& L0 = *h->L[0];
     if (L0.coarsest && !L0.apply_parts) throw Error(MBAMG_E_STATE, "internal: finest-level operator missing");
     resid<double>(h, 0, nullptr, x, w, s, kind);
@@ -1703,7 +2046,8 @@ static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, d
     } else {
         while (true) {
             // true residual into V_0
-            resid<double>(h, 0, h->bw.p, h->xw.p, h->V.p, s, 1);
+            if (h->nb > 2) gen_resid(h, 0, h->bw.p, h->xw.p, h->V.p, s);
+            else resid<double>(h, 0, h->bw.p, h->xw.p, h->V.p, s, 1);
             const double beta = std::sqrt(norm2_dev(h, h->V.p, s));
             rel = beta / bnorm;
             if (beta <= rtol * bnorm) break;
@@ -1866,9 +2210,18 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
     return guarded([&]() -> mbamg_status {
         MB_CHECK(A_blocks && fm && p && out, MBAMG_E_INVALID, "NULL argument");
         *out = nullptr;
-        MB_CHECK(fm->n_blocks == 2, MBAMG_E_INVALID, "only two blocks are supported");
-        MB_CHECK(fm->dofs[0] >= 1 && fm->dofs[0] <= 4 && fm->dofs[1] == fm->dofs[0], MBAMG_E_INVALID,
-                 "both blocks must have the same 1..4 dofs per node (co-located fields)");
+        MB_CHECK(fm->n_blocks >= 2 && fm->n_blocks <= MAXB, MBAMG_E_INVALID, "2 to 4 blocks");
+        if (fm->n_blocks > 2) {
+            for (int f = 0; f < fm->n_blocks; ++f)
+                MB_CHECK(fm->dofs[f] >= 1 && fm->dofs[f] <= 4, MBAMG_E_INVALID, "1..4 dofs per node and block");
+            MB_CHECK(p->clone_aggregates != 0 && p->learned == 0 && p->omega_p == 0.0 && p->smoother == 0 &&
+                         p->precision == 0,
+                     MBAMG_E_INVALID,
+                     "more than two blocks: co-located fields, FP64, fixed weights and the blocked smoother");
+        } else {
+            MB_CHECK(fm->dofs[0] >= 1 && fm->dofs[0] <= 4 && fm->dofs[1] == fm->dofs[0], MBAMG_E_INVALID,
+                     "both blocks must have the same 1..4 dofs per node");
+        }
         MB_CHECK(p->omega > 0.0 && p->bgs_sweeps >= 1 && p->inner_sweeps >= 1 && p->max_levels >= 1 &&
                      p->restart >= 1 && p->restart <= KMAXQ - 2 && p->max_iters >= 0 && p->theta >= 0.0,
                  MBAMG_E_INVALID, "invalid parameters");
@@ -1899,7 +2252,13 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
             pool_device_idle();
         };
         std::unique_ptr<mbamg_hierarchy> h;
-        if (p->learned != 0 && p->judge) {
+        if (fm->n_blocks > 2) {
+            h = make(*p, s);
+            h->nb = fm->n_blocks;
+            gen_setup_impl(h.get(), A_blocks, s);
+            settle();
+            h->info.used_learned = 0;
+        } else if (p->learned != 0 && p->judge) {
             // the fixed-weight method is the fallback and the judge.  It is built, and then
             // probed, on a host thread and stream of its own while the learned hierarchy is
             // built here; the learned build copies the fixed build's level-0 aggregates and
@@ -1964,7 +2323,9 @@ mbamg_status mbamg_vcycle(mbamg_hierarchy* h, const double* r, double* z, void* 
         MB_CHECK(r != z, MBAMG_E_INVALID, "r and z must not alias");
         hipStream_t s = (hipStream_t)hip_stream;
         to_colour(h, r, h->vio.p, s);
-        if (h->p.precision == 1) {
+        if (h->nb > 2) {
+            gen_vcycle_level(h, 0, h->vio.p, h->vio2.p, s);
+        } else if (h->p.precision == 1) {
             apply_precond(h, h->vio.p, h->vio2.p, h->vin32.p == nullptr ? nullptr : h->Z32.p, s);
         } else {
             if (h->L[0]->coarsest) launch_coarse<double>(h->coarse_n, h->coarse_inv.p, h->vio.p, h->vio2.p, s);
@@ -2011,12 +2372,17 @@ void mbamg_destroy(mbamg_hierarchy* h) {
 }
 
 mbamg_status mbamg_num_levels(const mbamg_hierarchy* h, int32_t* n_levels) {
+    if (h && n_levels && h->nb > 2) {
+        *n_levels = (int32_t)h->GL.size();
+        return MBAMG_OK;
+    }
     if (!h || !n_levels) { g_last_error = "NULL argument"; return MBAMG_E_INVALID; }
     *n_levels = (int32_t)h->L.size();
     return MBAMG_OK;
 }
 
 mbamg_status mbamg_level_nodes(const mbamg_hierarchy* h, int32_t level, int32_t* n_nodes) {
+    if (h && h->nb > 2) return mbamg_level_block_nodes(h, level, 0, n_nodes);
     if (!h || !n_nodes || level < 0 || level >= (int)h->L.size()) { g_last_error = "bad argument"; return MBAMG_E_INVALID; }
     *n_nodes = h->L[level]->n;
     return MBAMG_OK;
@@ -2027,6 +2393,14 @@ mbamg_status mbamg_copy_aggregates(const mbamg_hierarchy* h, int32_t level, int3
 }
 
 mbamg_status mbamg_level_block_nodes(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t* n_nodes) {
+    if (h && n_nodes && h->nb > 2) {
+        if (level < 0 || level >= (int)h->GL.size() || f < 0 || f >= h->nb) {
+            g_last_error = "bad argument";
+            return MBAMG_E_INVALID;
+        }
+        *n_nodes = h->GL[level]->n;
+        return MBAMG_OK;
+    }
     if (!h || !n_nodes || level < 0 || level >= (int)h->L.size() || f < 0 || f > 1) {
         g_last_error = "bad argument";
         return MBAMG_E_INVALID;
@@ -2037,6 +2411,13 @@ mbamg_status mbamg_level_block_nodes(const mbamg_hierarchy* h, int32_t level, in
 
 mbamg_status mbamg_copy_block_aggregates(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t* agg) {
     return guarded([&]() -> mbamg_status {
+        if (h && h->nb > 2) {
+            MB_CHECK(agg && level >= 0 && level + 1 < (int)h->GL.size() && f >= 0 && f < h->nb, MBAMG_E_INVALID,
+                     "bad argument");
+            const GLevel& L = *h->GL[level];
+            MB_HIP(hipMemcpy(agg, L.G.agg.p, sizeof(int32_t) * L.n, hipMemcpyDeviceToHost));
+            return MBAMG_OK;
+        }
         MB_CHECK(h && agg && level >= 0 && level + 1 < (int)h->L.size() && f >= 0 && f < 2, MBAMG_E_INVALID,
                  "bad argument");
         const Level& L = *h->L[level];
@@ -2046,6 +2427,14 @@ mbamg_status mbamg_copy_block_aggregates(const mbamg_hierarchy* h, int32_t level
 }
 
 mbamg_status mbamg_level_nnzb(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t g, int64_t* nnzb) {
+    if (h && nnzb && h->nb > 2) {
+        if (level < 0 || level >= (int)h->GL.size() || f < 0 || f >= h->nb || g < 0 || g >= h->nb) {
+            g_last_error = "bad argument";
+            return MBAMG_E_INVALID;
+        }
+        *nnzb = h->GL[level]->A[f][g].nnzb;
+        return MBAMG_OK;
+    }
     if (!h || !nnzb || level < 0 || level >= (int)h->L.size() || f < 0 || f > 1 || g < 0 || g > 1) {
         g_last_error = "bad argument";
         return MBAMG_E_INVALID;
@@ -2057,9 +2446,9 @@ mbamg_status mbamg_level_nnzb(const mbamg_hierarchy* h, int32_t level, int32_t f
 mbamg_status mbamg_copy_level_block(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t g, int32_t* row_ptr,
                                     int32_t* col_idx, double* vals) {
     return guarded([&]() -> mbamg_status {
-        MB_CHECK(h && row_ptr && level >= 0 && level < (int)h->L.size() && f >= 0 && f < 2 && g >= 0 && g < 2,
-                 MBAMG_E_INVALID, "bad argument");
-        const SetupBsr& A = h->L[level]->A[f][g];
+        MB_CHECK(h && row_ptr && f >= 0 && f < h->nb && g >= 0 && g < h->nb, MBAMG_E_INVALID, "bad argument");
+        MB_CHECK(level >= 0 && level < (int)(h->nb > 2 ? h->GL.size() : h->L.size()), MBAMG_E_INVALID, "bad argument");
+        const SetupBsr& A = h->nb > 2 ? h->GL[level]->A[f][g] : h->L[level]->A[f][g];
         MB_HIP(hipMemcpy(row_ptr, A.rp.p, sizeof(int32_t) * (A.n_rows + 1), hipMemcpyDeviceToHost));
         if (A.nnzb) {
             MB_CHECK(col_idx && vals, MBAMG_E_INVALID, "NULL argument");
@@ -2072,9 +2461,10 @@ mbamg_status mbamg_copy_level_block(const mbamg_hierarchy* h, int32_t level, int
 
 mbamg_status mbamg_copy_colours(const mbamg_hierarchy* h, int32_t level, int32_t f, int32_t* colour) {
     return guarded([&]() -> mbamg_status {
-        MB_CHECK(h && colour && level >= 0 && level + 1 < (int)h->L.size() && f >= 0 && f < 2, MBAMG_E_INVALID,
+        MB_CHECK(h && colour && f >= 0 && f < h->nb, MBAMG_E_INVALID, "bad argument");
+        MB_CHECK(level >= 0 && level + 1 < (int)(h->nb > 2 ? h->GL.size() : h->L.size()), MBAMG_E_INVALID,
                  "bad argument");
-        const BlockLevel& B = h->L[level]->blk[f];
+        const BlockLevel& B = h->nb > 2 ? h->GL[level]->blk[f] : h->L[level]->blk[f];
         std::copy(B.colour.begin(), B.colour.end(), colour);
         return MBAMG_OK;
     });
@@ -2119,6 +2509,7 @@ mbamg_status mbamg_timing_get(mbamg_hierarchy* h, int32_t kind, int64_t* launche
 mbamg_status mbamg_vcycle_bytes(const mbamg_hierarchy* h, double* bytes) {
     return guarded([&]() -> mbamg_status {
         MB_CHECK(h && bytes, MBAMG_E_INVALID, "NULL argument");
+        MB_CHECK(h->nb == 2, MBAMG_E_STATE, "the byte model covers two-block hierarchies");
         double tot = 0.0;
         for (int l = 0; l < (int)h->L.size(); ++l) {
             double down = 0.0, up = 0.0;
@@ -2133,6 +2524,7 @@ mbamg_status mbamg_vcycle_bytes(const mbamg_hierarchy* h, double* bytes) {
 mbamg_status mbamg_level_vcycle_bytes(const mbamg_hierarchy* h, int32_t level, double* down, double* up) {
     return guarded([&]() -> mbamg_status {
         MB_CHECK(h && down && up && level >= 0 && level < (int)h->L.size(), MBAMG_E_INVALID, "bad argument");
+        MB_CHECK(h->nb == 2, MBAMG_E_STATE, "the byte model covers two-block hierarchies");
         level_vcycle_bytes(h, level, *down, *up);
         return MBAMG_OK;
     });

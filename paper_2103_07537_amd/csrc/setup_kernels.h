@@ -114,6 +114,9 @@ struct CoarseWork {
     DevBuf<double> M;                    // two n x n matrices (ping-pong)
     DevBuf<int32_t> sing, rowsrc, ord;   // singular flag; a panel's row sources; row order (two copies)
 };
+// the same for nb x nb blocks (A: nb * nb pointers, row-major; block f has A[f*nb+f]->n_rows nodes of d[f] dofs)
+void coarse_inverse_launch_blocks(const SetupBsr* const* A, int nb, const int* d, DevBuf<double>& inv, CoarseWork& w,
+                                  hipStream_t s);
 void coarse_inverse_launch(const SetupBsr (&A)[2][2], const int d[2], DevBuf<double>& inv, CoarseWork& w,
                            hipStream_t s);
 void coarse_inverse_finish(CoarseWork& w, hipStream_t s);

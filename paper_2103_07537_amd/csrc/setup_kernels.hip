@@ -2476,11 +2476,13 @@ static void gj_run(CoarseWork& w, int n, hipStream_t s, double** result, const i
     *order = ord_in;
 }
 
-void coarse_inverse_launch(const SetupBsr (&A)[2][2], const int d[2], DevBuf<double>& inv, CoarseWork& w,
-                           hipStream_t s) {
-    const int nn = A[0][0].n_rows, nn1 = A[1][1].n_rows;   // nodes of each block
-    const int n = nn * d[0] + nn1 * d[1];
-    MB_CHECK(n <= 16384, MBAMG_E_INVALID, "coarsest level too large for the dense solve (raise max_levels)");
+void coarse_inverse_launch_blocks(const SetupBsr* const* A, int nb, const int* d, DevBuf<double>& inv, CoarseWork& w,
+                                  hipStream_t s) {
+    // block f's dofs start after the blocks before it (node-major within each block)
+    std::vector<int64_t> off(nb + 1, 0);
+    for (int f = 0; f < nb; ++f) off[f + 1] = off[f] + (int64_t)A[f * nb + f]->n_rows * d[f];
+    const int n = (int)off[nb];
+    MB_CHECK(off[nb] <= 16384, MBAMG_E_INVALID, "coarsest level too large for the dense solve (raise max_levels)");
     w.n = n;
     w.M.alloc((size_t)2 * n * n);
     w.sing.alloc(1);
@@ -2490,10 +2492,9 @@ void coarse_inverse_launch(const SetupBsr (&A)[2][2], const int d[2], DevBuf<dou
     MB_HIP(hipMemsetAsync(w.sing.p, 0, sizeof(int32_t), s));
     if (n == 0) return;
     MB_HIP(hipMemsetAsync(w.M.p, 0, sizeof(double) * (size_t)n * n, s));
-    int64_t off[2] = {0, (int64_t)nn * d[0]};
-    for (int f = 0; f < 2; ++f)
-        for (int g = 0; g < 2; ++g) {
-            const SetupBsr& B = A[f][g];
+    for (int f = 0; f < nb; ++f)
+        for (int g = 0; g < nb; ++g) {
+            const SetupBsr& B = *A[f * nb + g];
             if (B.nnzb == 0) continue;
             k_dense_scatter<<<grid_for(B.n_rows, 64), 64, 0, s>>>(B.n_rows, B.br, B.bc, B.rp.p, B.ci.p, B.val.p,
                                                                  off[f], off[g], (int64_t)n, w.M.p);
@@ -2511,6 +2512,12 @@ void coarse_inverse_launch(const SetupBsr (&A)[2][2], const int d[2], DevBuf<dou
     else gj_run<512, 32, 2>(w, n, s, &X, &ord);
     k_gj_extract<<<grid_for((int64_t)n * n), 256, 0, s>>>(X, n, ord, inv.p);
     MB_LAUNCH_CHECK();
+}
+
+void coarse_inverse_launch(const SetupBsr (&A)[2][2], const int d[2], DevBuf<double>& inv, CoarseWork& w,
+                           hipStream_t s) {
+    const SetupBsr* blocks[4] = {&A[0][0], &A[0][1], &A[1][0], &A[1][1]};
+    coarse_inverse_launch_blocks(blocks, 2, d, inv, w, s);
 }
 
 void coarse_inverse_finish(CoarseWork& w, hipStream_t s) {

@@ -147,6 +147,9 @@ template <class T>
 void launch_gs_rows(int d, int rp, bool zero_x, bool has_cpl, const GsRowArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_resid_rows(int d, const ResidRowArgs<T>& a, hipStream_t s);
+// y += sign * A x for one block in row form, any block shape up to 4 x 4 (one thread per row)
+template <class T>
+void launch_rows_acc(int n, int br, int bc, const RowView<T>& A, const T* x, T* y, T sign, hipStream_t s);
 
 template <class T>
 // G: lanes per coarse row (4, 8, 16 or 64)

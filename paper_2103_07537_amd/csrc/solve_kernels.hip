@@ -555,6 +555,39 @@ __global__ __launch_bounds__(256) void k_resid_rows(ResidRowArgs<T> a) {
     store_vec<T, D>(a.r[f] + (int64_t)row * D, out);
 }
 
+// y += sign * A x for one block A_fg of any block shape (br, bc <= 4) in row
+// form (rows in block f's colour order, columns in block g's): one thread per
+// row, the row's blocks in their stored order.  Used where a system has more
+// than two blocks, whose couplings are folded into the right-hand sides.
+template <class T>
+__global__ __launch_bounds__(256) void k_rows_acc(int n, int br, int bc, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                  const T* __restrict__ x, T* __restrict__ y, T sign) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    const int bs = br * bc;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int64_t j = col[p];
+        const T* v = val + (int64_t)p * bs;
+        T xj[4];
+        for (int c = 0; c < bc; ++c) xj[c] = x[j * bc + c];
+        for (int r = 0; r < br; ++r)
+            for (int c = 0; c < bc; ++c) acc[r] += v[r * bc + c] * xj[c];
+    }
+    for (int r = 0; r < br; ++r) y[(int64_t)i * br + r] += sign * acc[r];
+}
+
+template <class T>
+void launch_rows_acc(int n, int br, int bc, const RowView<T>& A, const T* x, T* y, T sign, hipStream_t s) {
+    if (n <= 0) return;
+    MB_CHECK(br >= 1 && br <= 4 && bc >= 1 && bc <= 4, MBAMG_E_INVALID, "row blocks of at most 4 x 4");
+    k_rows_acc<T><<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(n, br, bc, A.rp, A.col, A.val, x, y, sign);
+    MB_LAUNCH_CHECK();
+}
+template void launch_rows_acc<double>(int, int, int, const RowView<double>&, const double*, double*, double,
+                                      hipStream_t);
+
 // r = b - A x (or w = A x when b is NULL) for both block rows in one launch.
 template <class T, int D, int P>
 __global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_resid(ResidArgs<T> a, int padded_blocks) {

@@ -411,16 +411,18 @@ class NBlockSystem:
         return sp.bmat([[blk.to_scipy() for blk in row] for row in self.blocks], format="csr")
 
 
-def split_fields(s: BlockSystem) -> NBlockSystem:
+def split_fields(s: BlockSystem, split_second: bool = True) -> NBlockSystem:
     """The 4 x 4 field split of a co-located 2 x 2 system: each block's vector
     and scalar components become fields of their own -- (u, p, b, r), with
-    dim, 1, dim and 1 dofs per node.  A block between two fields stores a node
-    pair only where its sub-block has a nonzero entry; a field pair with no
-    such entry is a zero block."""
+    dim, 1, dim and 1 dofs per node (split_second False: (u, p, [b, r]), three
+    fields).  A block between two fields stores a node pair only where its
+    sub-block has a nonzero entry; a field pair with no such entry is a zero
+    block."""
     if not s.co_located:
         raise ValueError("the field split needs co-located blocks")
     dim = s.dim
-    comps = [(0, list(range(dim))), (0, [dim]), (1, list(range(dim))), (1, [dim])]
+    comps = [(0, list(range(dim))), (0, [dim])]
+    comps += [(1, list(range(dim))), (1, [dim])] if split_second else [(1, list(range(dim + 1)))]
     blocks = []
     for F, rsel in comps:
         row = []
@@ -442,9 +444,14 @@ def split_fields(s: BlockSystem) -> NBlockSystem:
     d0 = s.dofs[0]
     b0 = s.b[:N * d0].reshape(N, d0)
     b1 = s.b[N * d0:].reshape(N, s.dofs[1])
-    b = np.concatenate([b0[:, :dim].reshape(-1), b0[:, dim], b1[:, :dim].reshape(-1), b1[:, dim]])
-    return NBlockSystem(dim=dim, n=s.n, N=N, dofs=(dim, 1, dim, 1), n_vec=(dim, 0, dim, 0), blocks=blocks, b=b,
-                        params=dict(s.params, split="u,p,b,r"))
+    if split_second:
+        b = np.concatenate([b0[:, :dim].reshape(-1), b0[:, dim], b1[:, :dim].reshape(-1), b1[:, dim]])
+        dofs, n_vec, name = (dim, 1, dim, 1), (dim, 0, dim, 0), "u,p,b,r"
+    else:
+        b = np.concatenate([b0[:, :dim].reshape(-1), b0[:, dim], b1.reshape(-1)])
+        dofs, n_vec, name = (dim, 1, dim + 1), (dim, 0, dim), "u,p,br"
+    return NBlockSystem(dim=dim, n=s.n, N=N, dofs=dofs, n_vec=n_vec, blocks=blocks, b=b,
+                        params=dict(s.params, split=name))
 
 
 def _saddle_on_grid(n: int, dim: int, kap: np.ndarray, tau: float, reaction: float) -> Bsr:

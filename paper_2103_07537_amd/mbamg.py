@@ -158,9 +158,11 @@ class Hierarchy:
         weights: callable(level, n_agg, features[n_agg,12]) -> (omega_p, omega_s) for learned=2."""
         self._h = ctypes.c_void_p()
         self.dofs = tuple(int(d) for d in dofs)
+        nb = len(self.dofs)
+        self.n_blocks = nb
         self.n_nodes = int(blocks[0][0].n_brows)
         self.n_nodes1 = int(blocks[1][1].n_brows)
-        self.n_dofs = self.n_nodes * self.dofs[0] + self.n_nodes1 * self.dofs[1]
+        self.n_dofs = sum(int(blocks[f][f].n_brows) * self.dofs[f] for f in range(nb))
         p = params if params is not None else default_params(**param_kw)
         self.params = p
         keep_alive = []
@@ -189,14 +191,14 @@ class Hierarchy:
             p.weight_fn = cb
             p.learned = 2
         fm = FieldMap()
-        fm.n_blocks = 2
-        for f in range(2):
+        fm.n_blocks = nb
+        for f in range(nb):
             fm.dofs[f] = self.dofs[f]
             fm.n_vec[f] = int(n_vec[f]) if n_vec else self.dofs[f] - 1
-        arr = (Bsr * 4)()
+        arr = (Bsr * (nb * nb))()
         self._keep = []
-        for f in range(2):
-            for g in range(2):
+        for f in range(nb):
+            for g in range(nb):
                 b = blocks[f][g]
                 rp, ci, v = b.row_ptr, b.col_idx, b.vals
                 on_dev = 0 if isinstance(rp, np.ndarray) else 1
@@ -209,7 +211,7 @@ class Hierarchy:
                     v = np.ascontiguousarray(v, dtype=np.float64)
                     self._keep += [rp, ci, v]
                     ptrs = [rp.ctypes.data, ci.ctypes.data, v.ctypes.data]
-                e = arr[f * 2 + g]
+                e = arr[f * nb + g]
                 e.n_brows, e.n_bcols = int(b.n_brows), int(b.n_bcols)
                 e.br, e.bc = self.dofs[f], self.dofs[g]
                 e.nnzb = int(ci.shape[0])
@@ -369,16 +371,17 @@ def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8
 
 
 def to_device(system, device="cuda"):
-    """Copy a generator system's blocks and rhs into torch device tensors."""
+    """Copy a generator system's blocks into torch device tensors."""
     import torch
 
     class _B:
         pass
 
+    nb = len(system.blocks)
     out = []
-    for f in range(2):
+    for f in range(nb):
         row = []
-        for g in range(2):
+        for g in range(nb):
             b = system.blocks[f][g]
             o = _B()
             o.n_brows, o.n_bcols = b.n_brows, b.n_bcols

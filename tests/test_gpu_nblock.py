@@ -1,0 +1,111 @@
+"""More than two blocks on the GPU against the oracle (eq. block-prec-form;
+the 4 x 4 split of Sec. 2.1 into u, p, b, r, and a 3 x 3 split u, p, [b r]):
+cloned aggregates and every block's colours identical as integers, every
+Galerkin block element by element, the operator apply, V-cycles element by
+element (1e-12), and GMRES solves (iterations within +-1)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from gpu_util import assert_close, log, rel, torch_dev
+from paper_2103_07537_amd.inputs import make_system, split_fields
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "2d-23-split4": lambda: split_fields(make_system(23, 2, 0.8, seed=3, kappa="lognormal", blk1_scale=1.6,
+                                                     a10_scale=0.7)),
+    "3d-11-split4": lambda: split_fields(make_system(11, 3, 0.6, seed=5, kappa="lognormal")),
+    "2d-20-split3": lambda: split_fields(make_system(20, 2, 0.5, seed=4), split_second=False),
+}
+
+
+def _pair(case, **kw):
+    from oracle import amg, nblock
+    from paper_2103_07537_amd import mbamg
+    t = CASES[case]()
+    log(f"case={case} dofs={t.dofs} N={t.N}")
+    ho = nblock.setup(t.blocks, t.dofs, amg.Params(max_coarse=60, **kw))
+    hg = mbamg.Hierarchy(t.blocks, t.dofs, t.n_vec, max_coarse=60, **kw)
+    return t, ho, hg
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_nblock_setup_matches_oracle(case):
+    t, ho, hg = _pair(case)
+    nb = len(t.dofs)
+    L = len(ho.levels)
+    assert hg.num_levels() == L >= 3
+    for l, lev in enumerate(ho.levels):
+        assert hg.level_nodes(l) == lev.n
+        if l + 1 < L:
+            for f in range(nb):
+                assert np.array_equal(hg.aggregates(l, f), lev.agg), f"aggregates differ on level {l}"
+                assert np.array_equal(hg.colours(l, f), lev.colour[f]), f"colours of block {f} on level {l}"
+        if l == 0:
+            continue
+        prev = ho.levels[l - 1]
+        for f in range(nb):
+            for g in range(nb):
+                rp, ci, v = hg.level_block(l, f, g)
+                ref = lev.csr[f][g]
+                B = lev.A[f][g]
+                assert np.array_equal(rp, B.rp) and np.array_equal(ci, B.ci), f"pattern ({f},{g}) level {l}"
+                if B.ci.shape[0] == 0:
+                    continue
+                scale = (abs(prev.P[f]).T @ abs(prev.csr[f][g]) @ abs(prev.P[g])).toarray()
+                got = sp.bsr_matrix((v, ci, rp), shape=scale.shape).toarray()
+                assert np.all(np.abs(got - ref.toarray()) <= 1e-13 * scale), f"({f},{g}) level {l}"
+    hg.close()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_nblock_vcycle_and_apply_match_oracle(case):
+    from oracle import nblock
+    t, ho, hg = _pair(case)
+    r = np.random.default_rng(51).standard_normal(t.n_dofs)
+    z = torch_dev(np.zeros(t.n_dofs))
+    hg.vcycle(torch_dev(r), z)
+    assert_close(z.cpu().numpy(), nblock.vcycle(ho, r), 1e-12)
+    w = torch_dev(np.zeros(t.n_dofs))
+    hg.apply(torch_dev(r), w)
+    ref = t.to_scipy() @ r
+    assert np.max(np.abs(w.cpu().numpy() - ref)) <= 1e-13 * np.max(np.abs(ref))
+    hg.close()
+
+
+@pytest.mark.parametrize("case", ["2d-23-split4", "3d-11-split4"])
+def test_nblock_solve_matches_oracle(case):
+    from oracle import nblock
+    t, ho, hg = _pair(case)
+    x = torch_dev(np.zeros(t.n_dofs))
+    info = hg.solve(torch_dev(t.b), x, rtol=1e-8)
+    xg = x.cpu().numpy()
+    xo, io = nblock.gmres(ho, t.b, rtol=1e-8)
+    res = np.linalg.norm(t.b - t.to_scipy() @ xg) / np.linalg.norm(t.b)
+    log(f"  iterations gpu {info['iterations']} oracle {io.iterations}, true residual {res:.2e}, "
+        f"difference {rel(xg, xo):.2e}")
+    assert info["converged"] and io.converged and res <= 1e-8 * (1 + 1e-6)
+    assert abs(info["iterations"] - io.iterations) <= 1
+    if info["iterations"] == io.iterations:
+        assert rel(xg, xo) <= 1e-8
+    hg.close()
+
+
+def test_nblock_sweeps_and_damping_match_oracle():
+    from oracle import nblock
+    t, ho, hg = _pair("2d-23-split4", bgs_sweeps=2, inner_sweeps=2, omega=0.6)
+    r = np.random.default_rng(52).standard_normal(t.n_dofs)
+    z = torch_dev(np.zeros(t.n_dofs))
+    hg.vcycle(torch_dev(r), z)
+    assert_close(z.cpu().numpy(), nblock.vcycle(ho, r), 1e-12)
+    hg.close()
+
+
+def test_nblock_rejects_forms_it_does_not_build():
+    from paper_2103_07537_amd import mbamg
+    t = CASES["2d-20-split3"]()
+    for kw in (dict(precision=1), dict(omega_p=0.5), dict(smoother=1), dict(clone_aggregates=0)):
+        with pytest.raises(mbamg.MbamgError) as e:
+            mbamg.Hierarchy(t.blocks, t.dofs, t.n_vec, **kw)
+        assert e.value.code == -1
