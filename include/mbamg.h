@@ -142,6 +142,9 @@ typedef struct {
     double conv_factor;       /* (rel_residual)^(1/iterations) */
     double op_complexity;     /* sum over levels of structural block entries / level 0 */
     double t_setup_ms, t_solve_ms;
+    int32_t reverted;         /* 1: the solve of a judged learned hierarchy found its convergence worse than
+                                 the fixed-weight method's measured factor and finished with the fixed-weight
+                                 hierarchy (used_learned is then 0) */
 } mbamg_info;
 
 typedef struct mbamg_hierarchy mbamg_hierarchy;

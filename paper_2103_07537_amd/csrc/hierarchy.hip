@@ -263,6 +263,9 @@ struct mbamg_hierarchy {
     double* y_host = nullptr;
     int64_t reorth_count = 0;
     double judge_rho[2] = {0.0, 0.0};   // probe factors of the learned and the fixed hierarchy
+    // a learned hierarchy the judge kept holds the fixed-weight one it was judged against: a
+    // solve whose observed convergence is worse than the fixed method's factor reverts to it
+    std::unique_ptr<mbamg_hierarchy> fallback;
     DevBuf<float> Z32, vin32;
     DevBuf<double> vio;   // ABI <-> colour-order staging for vcycle/apply
     DevBuf<double> vio2;
@@ -2025,8 +2028,27 @@ static double norm2_dev(mbamg_hierarchy* h, const double* v, hipStream_t s) {
 // Gram-Schmidt with one reorthogonalisation when the new vector lost more
 // than a factor 1/sqrt(2) of its norm ("twice is enough", Daniel, Gragg,
 // Kaufman & Stewart 1976; Giraud, Langou & Rozloznik 2005).
+// Solve-time fallback of a judged learned hierarchy: GMRES right-preconditioned
+// by M converges at least as fast per iteration as the stationary iteration
+// e <- (I - A M) e, whose factor the judge measured for the fixed-weight
+// method.  When, after REVERT_MIN_ITS iterations of a cycle, the learned
+// preconditioner's residual has fallen by less than that factor per
+// iteration, the solve goes on from the current iterate with the fixed-weight
+// hierarchy.  (MBAMG_REVERT_RHO overrides the threshold, for tests.)
+constexpr int REVERT_MIN_ITS = 8;
+
+static double revert_threshold(const mbamg_hierarchy* h) {
+    if (const char* f = form_override("MBAMG_REVERT_RHO")) return std::atof(f);
+    return h->judge_rho[1];
+}
+
 static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, double rtol, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
+    const bool can_revert = h->fallback != nullptr;
+    const double revert_rho = can_revert ? revert_threshold(h) : 0.0;
+    bool revert = false;
+    h->info.reverted = 0;
+    if (can_revert) h->info.used_learned = 1;
     const int64_t n = h->n_fine;
     const int m = h->p.restart;
     const bool fp32 = h->p.precision == 1;
@@ -2111,6 +2133,11 @@ static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, d
                 ++its;
                 k = j + 1;
                 if (std::fabs(g[j + 1]) <= rtol * bnorm || its >= h->p.max_iters || nu == 0.0) break;
+                if (can_revert && k >= REVERT_MIN_ITS &&
+                    std::pow(std::fabs(g[j + 1]) / beta, 1.0 / k) > revert_rho) {
+                    revert = true;
+                    break;
+                }
             }
             // back substitution H[:k,:k] y = g[:k]; x += sum_j y_j sig_j Z_j
             for (int i = k - 1; i >= 0; --i) {
@@ -2122,10 +2149,33 @@ static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, d
             MB_HIP(hipMemcpyAsync(h->ybuf.p, h->y_host, sizeof(double) * k, hipMemcpyHostToDevice, s));
             if (fp32) launch_combine32(n, k, h->Z32.p, n, h->ybuf.p, h->xw.p, s);
             else launch_combine(n, k, h->Z64.p, n, h->ybuf.p, h->xw.p, s);
+            if (revert) break;
         }
     }
     from_colour(h, h->xw.p, x, s);
     MB_HIP(hipStreamSynchronize(s));
+    if (revert) {
+        // the rest of the solve with the fixed-weight hierarchy, from the current iterate
+        mbamg_hierarchy* fb = h->fallback.get();
+        const int keep_max = fb->p.max_iters;
+        fb->p.max_iters = std::max(0, h->p.max_iters - its);
+        try {
+            st = solve_impl(fb, b, x, rtol, s);
+        } catch (...) {
+            fb->p.max_iters = keep_max;
+            throw;
+        }
+        fb->p.max_iters = keep_max;
+        h->info.iterations = its + fb->info.iterations;
+        h->info.rel_residual = fb->info.rel_residual;
+        h->info.conv_factor = h->info.iterations > 0 && fb->info.rel_residual > 0
+                                  ? std::pow(fb->info.rel_residual, 1.0 / h->info.iterations) : 0.0;
+        h->info.reverted = 1;
+        h->info.used_learned = 0;
+        h->info.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        h->info.t_setup_ms = h->t_setup_ms;
+        return st;
+    }
     auto t1 = std::chrono::steady_clock::now();
     h->info.iterations = its;
     h->info.rel_residual = rel;
@@ -2300,6 +2350,7 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
                 h->info.used_learned = 0;
             } else {
                 h->info.used_learned = 1;
+                h->fallback = std::move(hf);
             }
         } else {
             h = make(*p, s);

@@ -52,7 +52,7 @@ class Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("levels", ctypes.c_int32), ("used_learned", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("conv_factor", ctypes.c_double),
                 ("op_complexity", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
-                ("t_solve_ms", ctypes.c_double)]
+                ("t_solve_ms", ctypes.c_double), ("reverted", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -198,3 +198,39 @@ def test_judge_falls_back_to_fixed_weights_when_worse():
     h_bad.vcycle(r, z1)
     h_fixed.vcycle(r, z2)
     assert np.array_equal(z1.cpu().numpy(), z2.cpu().numpy())
+
+
+def test_solve_reverts_to_the_fixed_hierarchy(monkeypatch):
+    """A judged learned hierarchy keeps the fixed-weight one; a solve whose
+    convergence per iteration is worse than the threshold finishes with it.
+    The threshold (normally the fixed method's measured factor) is forced to 0
+    here, so the solve reverts after its first iterations and still reaches
+    rtol with the fixed hierarchy from the learned iterate."""
+    s = CASES["2d-64-lognormal"]()
+    good = lambda l, n, F: (np.full(n, 2.0 / 3.0), np.full(n, 0.8))
+    hg = gpu_hierarchy(s, weights=good, judge=1)
+    assert hg.info()["used_learned"] == 1
+    r = torch_dev(s.b)
+    x = torch_dev(np.zeros(s.n_dofs))
+    info = hg.solve(r, x, rtol=1e-8)
+    assert info["reverted"] == 0 and info["used_learned"] == 1 and info["converged"]
+    monkeypatch.setenv("MBAMG_REVERT_RHO", "0")
+    x2 = torch_dev(np.zeros(s.n_dofs))
+    info2 = hg.solve(r, x2, rtol=1e-8)
+    A = s.to_scipy()
+    true_rel = np.linalg.norm(s.b - A @ x2.cpu().numpy()) / np.linalg.norm(s.b)
+    h_fixed = gpu_hierarchy(s)
+    x3 = torch_dev(np.zeros(s.n_dofs))
+    info3 = h_fixed.solve(r, x3, rtol=1e-8)
+    log(f"  learned {info['iterations']} its; forced revert {info2['iterations']} its "
+        f"(rel {info2['rel_residual']:.2e}); fixed alone {info3['iterations']} its")
+    assert info2["reverted"] == 1 and info2["used_learned"] == 0 and info2["converged"]
+    assert info2["rel_residual"] <= 1e-8 and true_rel <= 1e-8 * (1 + 1e-3)
+    # reverted after the minimum number of learned iterations, then the fixed method
+    assert 8 <= info2["iterations"] <= 8 + info3["iterations"] + 2
+    # the revert is per solve: without the override the next solve keeps the learned form
+    monkeypatch.delenv("MBAMG_REVERT_RHO")
+    x4 = torch_dev(np.zeros(s.n_dofs))
+    info4 = hg.solve(r, x4, rtol=1e-8)
+    assert info4["reverted"] == 0 and info4["iterations"] == info["iterations"]
+    assert np.array_equal(x4.cpu().numpy(), x.cpu().numpy())
