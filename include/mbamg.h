@@ -124,7 +124,10 @@ typedef struct {
     uint64_t seed;            /* aggregation priority seed (0) */
     double omega_p;           /* learned == 0: uniform prolongator-smoothing weight (0: piecewise constant) */
     int32_t judge;            /* learned != 0: also build the fixed-weight hierarchy, estimate both
-                                 convergence factors with mbamg_probe and keep the better one (1) */
+                                 convergence factors with mbamg_probe and keep the better one; a kept
+                                 learned hierarchy holds the fixed-weight one as its fallback, and a
+                                 solve whose observed convergence is worse than the fixed method's
+                                 factor finishes with it (mbamg_info.reverted) (1) */
     mbamg_weight_fn weight_fn;
     void* weight_ctx;
     int32_t smoother;         /* 0: damped block Gauss-Seidel over the two blocks (Sec. 4.3.2, Algorithm 1);
