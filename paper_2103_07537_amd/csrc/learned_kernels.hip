@@ -2,8 +2,12 @@
 // that predicts a prolongator-smoothing weight omega_P in (0, 5/6) and a
 // smoother damping omega_S in (0.3, 1.3) per aggregate.  The three dense
 // layers, their input-gradient products and their weight-gradient products
-// run on the matrix cores (v_mfma_f32_16x16x16_bf16: bfloat16 operands, FP32
-// accumulation); biases, activations and the output map stay in FP32.
+// run on the matrix cores with bfloat16 operands and FP32 accumulation: the
+// products that contract over the 64 hidden units take gfx950's
+// v_mfma_f32_16x16x32_bf16 (two instructions per 64), the ones that contract
+// over 16 (the 12 padded inputs, the 2 padded outputs, the 16 rows of a tile
+// in the weight gradients) v_mfma_f32_16x16x16_bf16; biases, activations and
+// the output map stay in FP32.
 //
 // Parameter packing (5122 FP32): W1[64][12], b1[64], W2[64][64], b2[64],
 // W3[2][64], b3[2].
@@ -17,6 +21,8 @@
 namespace mbamg {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int OFF_W1 = 0, OFF_B1 = 768, OFF_W2 = 832, OFF_B2 = 4928, OFF_W3 = 4992, OFF_B3 = 5120;
@@ -38,6 +44,11 @@ __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+__device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0,
+                                                   0, 0);
+}
+
 // Operand fragments of the 16x16x16 instruction.  For A (16 x K-chunk) lane l
 // supplies row l%16, columns 4*(l/16)..+3 of the chunk; for B (K-chunk x 16)
 // lane l supplies column l%16, rows 4*(l/16)..+3.  Result lane l holds rows
@@ -52,6 +63,18 @@ __device__ __forceinline__ v4s frag_cols(const short* T, int ld, int r0, int k0,
     const int c = r0 + (lane & 15);
     const int k = k0 + 4 * (lane >> 4);
     return v4s{T[(k + 0) * ld + c], T[(k + 1) * ld + c], T[(k + 2) * ld + c], T[(k + 3) * ld + c]};
+}
+
+// Operand fragments of the 16x16x32 instruction: as above with 8 K entries
+// per lane, 8*(l/16)..+7 of the 32-wide chunk.
+__device__ __forceinline__ v8s frag_rows8(const short* T, int ld, int r0, int k0, int lane) {
+    const short* p = T + (r0 + (lane & 15)) * ld + k0 + 8 * (lane >> 4);
+    return v8s{p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7]};
+}
+__device__ __forceinline__ v8s frag_cols8(const short* T, int ld, int r0, int k0, int lane) {
+    const int c = r0 + (lane & 15);
+    const short* p = T + (k0 + 8 * (lane >> 4)) * ld + c;
+    return v8s{p[0], p[ld], p[2 * ld], p[3 * ld], p[4 * ld], p[5 * ld], p[6 * ld], p[7 * ld]};
 }
 
 struct MlpShared {
@@ -113,8 +136,8 @@ __device__ v4f tile_forward(MlpShared& S, int w, int lane, const float* __restri
     for (int t = 0; t < 4; ++t) {
         v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-            acc = mfma(frag_rows(S.H1[w], 64, 0, 16 * s, lane), frag_rows(S.W2, 64, 16 * t, 16 * s, lane), acc);
+        for (int s = 0; s < 2; ++s)
+            acc = mfma32(frag_rows8(S.H1[w], 64, 0, 32 * s, lane), frag_rows8(S.W2, 64, 16 * t, 32 * s, lane), acc);
         const int col = 16 * t + (lane & 15);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -125,8 +148,8 @@ __device__ v4f tile_forward(MlpShared& S, int w, int lane, const float* __restri
     __syncthreads();
     v4f o = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-        o = mfma(frag_rows(S.H2[w], 64, 0, 16 * s, lane), frag_rows(S.W3, 64, 0, 16 * s, lane), o);
+    for (int s = 0; s < 2; ++s)
+        o = mfma32(frag_rows8(S.H2[w], 64, 0, 32 * s, lane), frag_rows8(S.W3, 64, 0, 32 * s, lane), o);
     const int j = lane & 15;
     if (j < 2) {
 #pragma unroll
@@ -233,8 +256,9 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ th, 
         for (int t = 0; t < 4; ++t) {
             v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-                acc = mfma(frag_rows(S.D2[w], 64, 0, 16 * s, lane), frag_cols(S.W2, 64, 16 * t, 16 * s, lane), acc);
+            for (int s = 0; s < 2; ++s)
+                acc = mfma32(frag_rows8(S.D2[w], 64, 0, 32 * s, lane), frag_cols8(S.W2, 64, 16 * t, 32 * s, lane),
+                             acc);
             const int col = 16 * t + j;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {

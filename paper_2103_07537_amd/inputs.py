@@ -204,12 +204,20 @@ def _coupling_field(n: int, dim: int, seed: int, h: float):
 
 def make_system(n: int, dim: int, gamma: float, *, seed: int = 1, kappa: str = "const",
                 sigma: float = 1.0, tau: float = 1.0, reaction: float = 1.0,
-                blk1_scale: float = 1.0, a10_scale: float = 1.0) -> BlockSystem:
+                blk1_scale: float = 1.0, a10_scale: float = 1.0, node_coupling: float = 0.0) -> BlockSystem:
     """Build the seeded 2x2 block system on an n^dim grid of interior nodes.
 
     ``blk1_scale`` scales the vector Laplacian of block 1 and ``a10_scale``
     scales A10 relative to A01; both default to 1 (the workload reading) and
     exist so tests can tell the four blocks apart.
+
+    ``node_coupling`` = c > 0 adds a coupling inside every node between the
+    two blocks' vector components (a cross-product-like term, as the u x B
+    terms of the MHD Jacobian couple fields at one point):
+    Z[(i,a),(i,b)] = c w_i (2 dim / h^2) K[a][b] with K the skew matrix
+    [[0, 1], [-1, 0]] (2D) or [[0, 1, -1], [-1, 0, 1], [1, -1, 0]] (3D) and
+    w_i ~ U[0.5, 1) (stream 4), so c measures the term against the vector
+    Laplacian's diagonal; Z stays skew, so A stays positive-real.
     """
     if dim not in (2, 3):
         raise ValueError("dim must be 2 or 3")
@@ -281,10 +289,18 @@ def make_system(n: int, dim: int, gamma: float, *, seed: int = 1, kappa: str = "
                 v[:, s, dim, dim] = np.where(m, -tau, 0.0)
         return _compress(N, valid, cols, v)
 
+    skew = np.array([[0.0, 1.0], [-1.0, 0.0]]) if dim == 2 else \
+        np.array([[0.0, 1.0, -1.0], [-1.0, 0.0, 1.0], [1.0, -1.0, 0.0]])
+    wnode = 0.5 + 0.5 * rng_uniform(seed, 4, idx) if node_coupling != 0.0 else None
+
     def coupling_block(scale: float) -> Bsr:
-        nb = [s for s, (axis, sign) in enumerate(slots) if sign != 0]
+        nb = [s for s, (axis, sign) in enumerate(slots) if sign != 0 or node_coupling != 0.0]
         v = np.zeros((N, len(nb), d, d))
         for t, s in enumerate(nb):
+            if slots[s][1] == 0:
+                c = scale * node_coupling * (2.0 * dim) * inv_h2 * wnode
+                v[:, t, :dim, :dim] = c[:, None, None] * skew
+                continue
             z = scale * gamma * gz[:, s] * sgn[s] * inv_2h
             for a in range(dim):
                 v[:, t, a, a] = z
@@ -296,7 +312,7 @@ def make_system(n: int, dim: int, gamma: float, *, seed: int = 1, kappa: str = "
     A10 = A01 if a10_scale == 1.0 else coupling_block(a10_scale)
     b = 2.0 * rng_uniform(seed, 3, np.arange(2 * N * d)) - 1.0
     params = dict(n=n, dim=dim, gamma=gamma, seed=seed, kappa=kappa, sigma=sigma, tau=tau,
-                  reaction=reaction, blk1_scale=blk1_scale, a10_scale=a10_scale)
+                  reaction=reaction, blk1_scale=blk1_scale, a10_scale=a10_scale, node_coupling=node_coupling)
     return BlockSystem(dim=dim, n=n, N=N, dofs=(d, d), n_vec=(dim, dim),
                        blocks=[[A00, A01], [A10, A11]], b=b, params=params)
 

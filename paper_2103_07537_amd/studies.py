@@ -13,6 +13,9 @@ one GPU, timed with the device synchronised on both sides.
     python -m paper_2103_07537_amd.studies omega    --workload 2d-256
     python -m paper_2103_07537_amd.studies sweeps   --workload 2d-512-lognormal --precision 1
     python -m paper_2103_07537_amd.studies smoother --workload 3d-64
+    python -m paper_2103_07537_amd.studies coupling --workload 2d-256
+
+(`coupling`: both smoothers as the coupling inside the nodes grows.)
 
 Each point prints one JSON line; a markdown table follows on stderr.
 """
@@ -29,6 +32,8 @@ OMEGAS = (0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1)
 SWEEPS = ((1, 1), (2, 1), (1, 2), (2, 2))
 # 0: block Gauss-Seidel over the two blocks (Algorithm 1); 1: nodal-block Gauss-Seidel over the full node blocks
 SMOOTHERS = (0, 1)
+# strength of the generator's coupling inside the nodes, against the vector Laplacian's diagonal
+NODE_COUPLINGS = (0.0, 0.05, 0.1, 0.2, 0.3, 0.5)
 
 
 def run_point(blocks, system, b, *, repeats: int = 3, rtol: float = 1e-8, **params) -> dict:
@@ -76,6 +81,17 @@ def study(kind: str, name: str, *, seed: int = 1, precision: int = 0, repeats: i
     elif kind == "smoother":
         for sm in (points or SMOOTHERS):
             out.append(run_point(blocks, s, b, repeats=repeats, precision=precision, smoother=sm))
+    elif kind == "coupling":
+        # both smoothers on the workload with a coupling inside the nodes of growing strength
+        del blocks, b
+        for c in (points or NODE_COUPLINGS):
+            sc = workload(name, seed=seed, node_coupling=c)
+            bc = mbamg.to_device(sc)
+            rhs = torch.from_numpy(sc.b).cuda()
+            for sm in SMOOTHERS:
+                r = run_point(bc, sc, rhs, repeats=repeats, precision=precision, smoother=sm)
+                r["params"] = dict(node_coupling=c, **r["params"])
+                out.append(r)
     else:
         raise ValueError(kind)
     for r in out:
@@ -97,7 +113,7 @@ def table(rows: list) -> str:
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("kind", choices=["omega", "sweeps", "smoother"])
+    ap.add_argument("kind", choices=["omega", "sweeps", "smoother", "coupling"])
     ap.add_argument("--workload", default="2d-256")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--precision", type=int, default=0, choices=[0, 1])

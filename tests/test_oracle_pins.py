@@ -465,3 +465,30 @@ def test_full_node_equals_blocked_without_coupling():
     assert len(hb.levels) == len(hf.levels) >= 3
     zb, zf = amg.vcycle(hb, r), amg.vcycle(hf, r)
     assert np.linalg.norm(zb - zf) <= 1e-13 * np.linalg.norm(zb)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_node_coupling_is_skew_and_full_node_sweep_inverts_it(dim):
+    # the generator's coupling inside a node keeps the coupling part skew (A stays
+    # positive-real), and the full-node sweep, now with node blocks that are not block
+    # diagonal, is still nodal-block Gauss-Seidel over them
+    s = make_system(7 if dim == 2 else 4, dim, 0.8, seed=4, node_coupling=1.0)
+    Z01 = s.blocks[0][1].to_scipy().toarray()
+    Z10 = s.blocks[1][0].to_scipy().toarray()
+    assert np.array_equal(Z01, Z10) and np.allclose(Z01, -Z01.T, rtol=0, atol=0)
+    d = dim + 1
+    own = np.array([Z01[i * d:i * d + dim, i * d:i * d + dim] for i in range(s.N)])
+    assert np.all(np.abs(own).max(axis=(1, 2)) > 0)
+    p = amg.Params(max_coarse=1, omega=1.0, smoother=1)
+    h = amg.setup(s.blocks, s.dofs, p)
+    lev = h.levels[0]
+    Afull = np.block([[lev.csr[f][g].toarray() for g in range(2)] for f in range(2)])
+    n, dofs = lev.n, lev.dofs
+    order = np.lexsort((np.arange(n), lev.fc_colour))
+    rng = np.random.default_rng(13)
+    b = rng.standard_normal(Afull.shape[0])
+    x = rng.standard_normal(Afull.shape[0])
+    n0 = n * dofs[0]
+    y0, y1 = amg.fc(lev, x[:n0], x[n0:], b[:n0], b[n0:], p)
+    ref = _node_order_gs(Afull, dofs, n, order, b, x)
+    assert np.allclose(np.concatenate([y0, y1]), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
