@@ -104,10 +104,35 @@ __device__ __forceinline__ void store_vec<float, 4>(float* __restrict__ p, const
 template <class T, int P>
 constexpr int sell_chunk() { return P >= 4 && sizeof(T) == 4 ? 4 : CHUNK; }
 
+// Column indices, masks and value offsets of one chunk of slots.
+template <int CH>
+struct SlotChunk {
+    int j[CH];
+    uint32_t m[CH];
+    int64_t vg[CH];
+};
+
+// the chunk of slots t0, t0 + P, ... of slice s (slots past the width: empty)
+template <class T, int P, int CH>
+__device__ __forceinline__ void fetch_chunk(const SellView<T>& A, int s, int lane, int t0, SlotChunk<CH>& c) {
+    const int w = A.width[s];
+    const int64_t cb = A.coff[s];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+        const int tt = t0 + u * P;
+        const bool live = tt < w;
+        c.m[u] = live ? A.mask[cb + tt] : 0u;
+        c.vg[u] = live ? A.voff[cb + tt] : 0;
+        c.j[u] = live ? A.col[(cb + tt) * WAVE + lane] : -1;
+    }
+}
+
 // SKIPD: the slot holding column `self` (the row's own node) is left out.
+// pre (split slices only): the first chunk, fetched by the caller ahead of time.
 template <class T, int BR, int BC, int MODE, int P, bool SKIPD = false>
 __device__ __forceinline__ void sell_sub(const SellView<T>& A, int s, int lane, int part, const T* __restrict__ xa,
-                                         const T* __restrict__ xb, int cstart, T (&acc)[BR], int self = -1) {
+                                         const T* __restrict__ xb, int cstart, T (&acc)[BR], int self = -1,
+                                         const SlotChunk<sell_chunk<T, P>()>* pre = nullptr) {
     constexpr int CH = sell_chunk<T, P>();
     constexpr bool PF = P >= 4;
     const int w = A.width[s];
@@ -125,7 +150,18 @@ __device__ __forceinline__ void sell_sub(const SellView<T>& A, int s, int lane, 
             j[u] = live ? A.col[(cb + tt) * WAVE + lane] : -1;
         }
     };
-    if (PF) fetch(part);
+    if (PF) {
+        if (pre) {
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                j[u] = pre->j[u];
+                m[u] = pre->m[u];
+                vg[u] = pre->vg[u];
+            }
+        } else {
+            fetch(part);
+        }
+    }
     for (int t = part; t < w; t += P * CH) {
         if (!PF) fetch(t);
         int jc[CH];
@@ -206,18 +242,27 @@ __global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_gs(GsArgs<T> a,
 #pragma unroll
         for (int r = 0; r < D; ++r) acc[r] = T(0);
     }
-    // small levels (split slices): the row's own data is fetched before the sums, so its
-    // latency overlaps theirs instead of following them
-    T dv[D * D];
-    if (P > 1 && part == 0 && valid)
-        load_masked<T, D * D>(a.dinv.val + a.dinv.voff[a.dinv.coff[s]] * WAVE + lane, a.dinv.mask[a.dinv.coff[s]],
-                              dv);
+    // small levels (split slices): the row's own data, and the coupling part's first slots,
+    // are fetched before the sums, so their latency overlaps the sums' instead of following
+    T dv[D * D], xo[D];
+    T w = a.omega;
+    constexpr int CH = sell_chunk<T, P>();
+    SlotChunk<CH> cpre;
+    if (P > 1 && valid) {
+        if (part == 0) {
+            load_masked<T, D * D>(a.dinv.val + a.dinv.voff[a.dinv.coff[s]] * WAVE + lane,
+                                  a.dinv.mask[a.dinv.coff[s]], dv);
+            if (!ZX) load_vec<T, D>(a.x + (int64_t)row * D, xo);
+            if (a.w_row) w = a.w_row[row];
+        }
+        if (CPL && P >= 4) fetch_chunk<T, P, CH>(a.cpl, s, lane, part, cpre);
+    }
     if (valid) {
         if (!a.skip_off) {
             if (ZX) sell_sub<T, D, D, 2, P>(a.off, s, lane, part, a.t, nullptr, a.cstart, acc);
             else sell_sub<T, D, D, 1, P>(a.off, s, lane, part, a.t, a.x, a.cstart, acc);
         }
-        if (CPL) sell_sub<T, D, D, 0, P>(a.cpl, s, lane, part, a.xg, nullptr, 0, acc);
+        if (CPL) sell_sub<T, D, D, 0, P>(a.cpl, s, lane, part, a.xg, nullptr, 0, acc, -1, P >= 4 ? &cpre : nullptr);
     }
     combine_parts<T, D, P>(acc, wave, part, lane);
     if (part != 0 || !valid) return;
@@ -233,14 +278,13 @@ __global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_gs(GsArgs<T> a,
         tn[r] = sum;
     }
     if (!act) return;
-    const T w = a.w_row ? a.w_row[row] : a.omega;
+    if (P == 1 && a.w_row) w = a.w_row[row];
     T xn[D];
     if (ZX) {
 #pragma unroll
         for (int r = 0; r < D; ++r) xn[r] = w * tn[r];
     } else {
-        T xo[D];
-        load_vec<T, D>(a.x + (int64_t)row * D, xo);
+        if (P == 1) load_vec<T, D>(a.x + (int64_t)row * D, xo);
 #pragma unroll
         for (int r = 0; r < D; ++r) xn[r] = xo[r] + w * (tn[r] - xo[r]);
     }
