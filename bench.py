@@ -139,10 +139,24 @@ def profile_steps(blocks, system, b, form, rtol, mlp):
     out["levels"] = levels
     h.close()
     out["vcycle_bytes"] = bytes_total
+    # every launch of the smoother, residual and transfer kernels bracketed by events (mode 1)
+    h, _, info = run_step(blocks, system, b, form, rtol, 1, mlp)
     if form == "fp64":
-        h, _, info = run_step(blocks, system, b, form, rtol, 1, mlp)
         out["kernel_stats"] = {k: h.timing_get(k) for k in (0, 1, 2, 3)}
-        h.close()
+    cycles = max(h.timing_get(4)["launches"], 1)
+    names = {0: "smoother, post", 1: "residual", 3: "smoother, other", 5: "restriction", 6: "prolongation"}
+    launches = []
+    for l in range(h.num_levels() - 1):
+        for k, nm in names.items():
+            st = h.timing_get(k if l == 0 else 64 + 8 * l + k)
+            if st["launches"] == 0:
+                continue
+            launches.append({"level": l, "kind": nm, "launches_per_cycle": st["launches"] / cycles,
+                             "us_per_cycle": 1e3 * st["total_ms"] / cycles,
+                             "avg_us": 1e3 * st["total_ms"] / st["launches"],
+                             "alg_GBps": st["bytes"] / (st["total_ms"] * 1e-3) / 1e9 if st["total_ms"] else None})
+    out["launch_stats"] = launches
+    h.close()
     return out
 
 
@@ -382,6 +396,7 @@ def main():
             "vcycle_abi_ms": vc_ms,
             "vcycle_abi_hbm_frac": vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "per_level": prof["levels"],
+            "per_launch_kind": prof["launch_stats"],
             "kernel_stats": prof.get("kernel_stats"),
         }
     ref = "fp64" if "fp64" in xs else forms[0]
