@@ -1853,7 +1853,7 @@ static void gen_block_rows(const GLevel& Lv, int f, const double* b, const doubl
                            hipStream_t s) {
     const int64_t len = (int64_t)Lv.n * Lv.d[f];
     if (b) MB_HIP(hipMemcpyAsync(y, b, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
-    else MB_HIP(hipMemsetAsync(y, 0, sizeof(double) * len, s));
+    else fill_value(y, len, 0.0, s);
     for (int g = 0; g < Lv.nb; ++g) {
         if ((skip_f && g == f) || !xs[g] || Lv.R[f][g].nnzb == 0) continue;
         launch_rows_acc<double>(Lv.n, Lv.d[f], Lv.d[g], grview(Lv.R[f][g]), xs[g], y, b ? -1.0 : 1.0, s);

@@ -33,6 +33,8 @@ int scan_exclusive(const int32_t* in, int64_t n, int32_t* out, hipStream_t s);
 Strength build_strength(const SetupBsr& A, double theta, hipStream_t s);
 Aggregates build_aggregates(const Strength& S, uint64_t seed, int level, hipStream_t s);
 void fill_ones(double* a, int64_t n, hipStream_t s);
+// a[0..n) = v with a kernel (no memset node, so the call may sit in a captured graph)
+void fill_value(double* a, int64_t n, double v, hipStream_t s);
 void build_tentative(const Aggregates& G, int d, const double* B, double* q, double* Bc, hipStream_t s);
 // the tentative prolongator as a block matrix: row i holds diag(q_i) in column agg(i)
 SetupBsr tentative_bsr(const Aggregates& G, int d, const double* q, hipStream_t s);

@@ -1842,8 +1842,11 @@ void build_tentative(const Aggregates& G, int d, const double* B, double* q, dou
     MB_LAUNCH_CHECK();
 }
 
-void fill_ones(double* a, int64_t n, hipStream_t s) {
-    k_fill_f64<<<grid_for(n), 256, 0, s>>>(a, n, 1.0);
+void fill_ones(double* a, int64_t n, hipStream_t s) { fill_value(a, n, 1.0, s); }
+
+void fill_value(double* a, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill_f64<<<grid_for(n), 256, 0, s>>>(a, n, v);
     MB_LAUNCH_CHECK();
 }
 

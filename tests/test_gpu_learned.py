@@ -200,7 +200,8 @@ def test_judge_falls_back_to_fixed_weights_when_worse():
     assert np.array_equal(z1.cpu().numpy(), z2.cpu().numpy())
 
 
-def test_solve_reverts_to_the_fixed_hierarchy(monkeypatch):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_reverts_to_the_fixed_hierarchy(monkeypatch, precision):
     """A judged learned hierarchy keeps the fixed-weight one; a solve whose
     convergence per iteration is worse than the threshold finishes with it.
     The threshold (normally the fixed method's measured factor) is forced to 0
@@ -208,7 +209,7 @@ def test_solve_reverts_to_the_fixed_hierarchy(monkeypatch):
     rtol with the fixed hierarchy from the learned iterate."""
     s = CASES["2d-64-lognormal"]()
     good = lambda l, n, F: (np.full(n, 2.0 / 3.0), np.full(n, 0.8))
-    hg = gpu_hierarchy(s, weights=good, judge=1)
+    hg = gpu_hierarchy(s, weights=good, judge=1, precision=precision)
     assert hg.info()["used_learned"] == 1
     r = torch_dev(s.b)
     x = torch_dev(np.zeros(s.n_dofs))
@@ -219,7 +220,7 @@ def test_solve_reverts_to_the_fixed_hierarchy(monkeypatch):
     info2 = hg.solve(r, x2, rtol=1e-8)
     A = s.to_scipy()
     true_rel = np.linalg.norm(s.b - A @ x2.cpu().numpy()) / np.linalg.norm(s.b)
-    h_fixed = gpu_hierarchy(s)
+    h_fixed = gpu_hierarchy(s, precision=precision)
     x3 = torch_dev(np.zeros(s.n_dofs))
     info3 = h_fixed.solve(r, x3, rtol=1e-8)
     log(f"  learned {info['iterations']} its; forced revert {info2['iterations']} its "

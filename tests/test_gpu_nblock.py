@@ -109,3 +109,38 @@ def test_nblock_rejects_forms_it_does_not_build():
         with pytest.raises(mbamg.MbamgError) as e:
             mbamg.Hierarchy(t.blocks, t.dofs, t.n_vec, **kw)
         assert e.value.code == -1
+
+
+def test_nblock_one_level_is_a_direct_solve():
+    """A system no larger than max_coarse is one level: the V-cycle is the dense
+    solve and GMRES stops after one iteration."""
+    from paper_2103_07537_amd import mbamg
+    t = split_fields(make_system(8, 2, 0.8, seed=6, kappa="lognormal"))
+    hg = mbamg.Hierarchy(t.blocks, t.dofs, t.n_vec)
+    assert hg.num_levels() == 1
+    A = t.to_scipy().toarray()
+    r = np.random.default_rng(53).standard_normal(t.n_dofs)
+    z = torch_dev(np.zeros(t.n_dofs))
+    hg.vcycle(torch_dev(r), z)
+    ref = np.linalg.solve(A, r)
+    assert rel(z.cpu().numpy(), ref) <= 1e-10
+    x = torch_dev(np.zeros(t.n_dofs))
+    info = hg.solve(torch_dev(t.b), x, rtol=1e-8)
+    assert info["converged"] and info["iterations"] <= 1
+    assert np.linalg.norm(t.b - A @ x.cpu().numpy()) <= 1e-8 * np.linalg.norm(t.b)
+    hg.close()
+
+
+@pytest.mark.parametrize("kw", [dict(max_levels=2), dict(theta=0.05, seed=7)], ids=["level-cap", "theta-seed"])
+def test_nblock_level_cap_threshold_and_seed_match_oracle(kw):
+    from oracle import nblock
+    t, ho, hg = _pair("3d-11-split4", **kw)
+    assert hg.num_levels() == len(ho.levels)
+    for l, lev in enumerate(ho.levels[:-1]):
+        for f in range(len(t.dofs)):
+            assert np.array_equal(hg.aggregates(l, f), lev.agg)
+    r = np.random.default_rng(54).standard_normal(t.n_dofs)
+    z = torch_dev(np.zeros(t.n_dofs))
+    hg.vcycle(torch_dev(r), z)
+    assert_close(z.cpu().numpy(), nblock.vcycle(ho, r), 1e-12)
+    hg.close()

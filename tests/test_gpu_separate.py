@@ -103,3 +103,18 @@ def test_cloning_and_learned_forms_reject_what_they_cannot_build():
         gpu_hierarchy(s, clone_aggregates=0, omega_p=0.5)
     with pytest.raises(mbamg.MbamgError):
         gpu_hierarchy(s, clone_aggregates=0, smoother=1)
+
+
+@pytest.mark.parametrize("kw", [dict(max_levels=2), dict(theta=0.05, seed=9)], ids=["level-cap", "theta-seed"])
+def test_separate_level_cap_threshold_and_seed_match_oracle(kw):
+    from oracle import amg
+    s, ho, hg = _pair("2d-41-mixed", **kw)
+    assert hg.num_levels() == len(ho.levels)
+    for l, lev in enumerate(ho.levels[:-1]):
+        assert np.array_equal(hg.aggregates(l, 0), lev.agg)
+        assert np.array_equal(hg.aggregates(l, 1), lev.agg1)
+    r = np.random.default_rng(62).standard_normal(s.n_dofs)
+    z = torch_dev(np.zeros(s.n_dofs))
+    hg.vcycle(torch_dev(r), z)
+    assert_close(z.cpu().numpy(), amg.vcycle(ho, r), 1e-12)
+    hg.close()
