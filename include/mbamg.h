@@ -126,8 +126,10 @@ typedef struct {
     int32_t judge;            /* learned != 0: also build the fixed-weight hierarchy, estimate both
                                  convergence factors with mbamg_probe and keep the better one; a kept
                                  learned hierarchy holds the fixed-weight one as its fallback, and a
-                                 solve whose observed convergence is worse than the fixed method's
-                                 factor finishes with it (mbamg_info.reverted) (1) */
+                                 solve that stalls with it (a complete restart cycle reducing the
+                                 residual by less than 0.99 per iteration on average, or a residual
+                                 that is not finite) finishes with the fixed-weight one from its
+                                 current iterate (mbamg_info.reverted) (1) */
     mbamg_weight_fn weight_fn;
     void* weight_ctx;
     int32_t smoother;         /* 0: damped block Gauss-Seidel over the two blocks (Sec. 4.3.2, Algorithm 1);
@@ -145,9 +147,8 @@ typedef struct {
     double conv_factor;       /* (rel_residual)^(1/iterations) */
     double op_complexity;     /* sum over levels of structural block entries / level 0 */
     double t_setup_ms, t_solve_ms;
-    int32_t reverted;         /* 1: the solve of a judged learned hierarchy found its convergence worse than
-                                 the fixed-weight method's measured factor and finished with the fixed-weight
-                                 hierarchy (used_learned is then 0) */
+    int32_t reverted;         /* 1: the solve of a judged learned hierarchy stalled and finished with the
+                                 fixed-weight hierarchy (used_learned is then 0) */
 } mbamg_info;
 
 typedef struct mbamg_hierarchy mbamg_hierarchy;

@@ -202,32 +202,33 @@ def test_judge_falls_back_to_fixed_weights_when_worse():
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_solve_reverts_to_the_fixed_hierarchy(monkeypatch, precision):
-    """A judged learned hierarchy keeps the fixed-weight one; a solve whose
-    convergence per iteration is worse than the threshold finishes with it.
-    The threshold (normally the fixed method's measured factor) is forced to 0
-    here, so the solve reverts after its first iterations and still reaches
-    rtol with the fixed hierarchy from the learned iterate."""
+    """A judged learned hierarchy keeps the fixed-weight one; a solve that
+    stalls over a complete restart cycle finishes with it.  The stall threshold
+    (0.99 per iteration) is forced to 0 here, so the solve reverts at the end
+    of its first cycle (restart 8) and still reaches rtol with the fixed
+    hierarchy from the learned iterate."""
     s = CASES["2d-64-lognormal"]()
     good = lambda l, n, F: (np.full(n, 2.0 / 3.0), np.full(n, 0.8))
-    hg = gpu_hierarchy(s, weights=good, judge=1, precision=precision)
+    hg = gpu_hierarchy(s, weights=good, judge=1, precision=precision, restart=8)
     assert hg.info()["used_learned"] == 1
     r = torch_dev(s.b)
     x = torch_dev(np.zeros(s.n_dofs))
     info = hg.solve(r, x, rtol=1e-8)
     assert info["reverted"] == 0 and info["used_learned"] == 1 and info["converged"]
+    assert info["iterations"] > 8
     monkeypatch.setenv("MBAMG_REVERT_RHO", "0")
     x2 = torch_dev(np.zeros(s.n_dofs))
     info2 = hg.solve(r, x2, rtol=1e-8)
     A = s.to_scipy()
     true_rel = np.linalg.norm(s.b - A @ x2.cpu().numpy()) / np.linalg.norm(s.b)
-    h_fixed = gpu_hierarchy(s, precision=precision)
+    h_fixed = gpu_hierarchy(s, precision=precision, restart=8)
     x3 = torch_dev(np.zeros(s.n_dofs))
     info3 = h_fixed.solve(r, x3, rtol=1e-8)
     log(f"  learned {info['iterations']} its; forced revert {info2['iterations']} its "
         f"(rel {info2['rel_residual']:.2e}); fixed alone {info3['iterations']} its")
     assert info2["reverted"] == 1 and info2["used_learned"] == 0 and info2["converged"]
     assert info2["rel_residual"] <= 1e-8 and true_rel <= 1e-8 * (1 + 1e-3)
-    # reverted after the minimum number of learned iterations, then the fixed method
+    # reverted after the first learned cycle, then the fixed method
     assert 8 <= info2["iterations"] <= 8 + info3["iterations"] + 2
     # the revert is per solve: without the override the next solve keeps the learned form
     monkeypatch.delenv("MBAMG_REVERT_RHO")
@@ -235,3 +236,21 @@ def test_solve_reverts_to_the_fixed_hierarchy(monkeypatch, precision):
     info4 = hg.solve(r, x4, rtol=1e-8)
     assert info4["reverted"] == 0 and info4["iterations"] == info["iterations"]
     assert np.array_equal(x4.cpu().numpy(), x.cpu().numpy())
+
+
+def test_solve_does_not_revert_a_learned_preconditioner_that_converges():
+    """On the 2D 512^2 field whose first iterations reduce the residual more
+    slowly than the fixed method's probe factor (while the fixed method's own
+    GMRES reduces more slowly still), the learned solve runs to the end."""
+    from paper_2103_07537_amd import learned as L
+    s = workload("2d-512-lognormal", seed=1)
+    mlp = L.load(L.DEFAULT_WEIGHTS)
+    from paper_2103_07537_amd import mbamg
+    hg = mbamg.Hierarchy(mbamg.to_device(s), s.dofs, s.n_vec, precision=1, mlp=mlp, judge=1)
+    assert hg.info()["used_learned"] == 1
+    x = torch_dev(np.zeros(s.n_dofs))
+    info = hg.solve(torch_dev(s.b), x, rtol=1e-8)
+    log(f"  2d-512 seed 1 judged learned: {info['iterations']} its, reverted {info['reverted']}")
+    assert info["converged"] and info["reverted"] == 0 and info["used_learned"] == 1
+    assert info["iterations"] < 120
+    hg.close()
