@@ -501,7 +501,9 @@ static void order_and_slice(BlockLevel& B, int n, int ncol, const int32_t* rp = 
 enum class PartKind { Off = 0, Cpl = 1, Diag = 2, Dinv = 3 };
 
 // coarse levels with at most this many rows per colour (on average) take the row form
-constexpr int ROWS_PER_COLOUR_MAX = 2048;
+// (measured crossover of the two layouts' colour passes on 4 x 4 FP64 blocks: 2.8K rows
+// 6.9 us in the row form against 12.5 us sliced, 11K rows 15.6 against 13.6 us)
+constexpr int ROWS_PER_COLOUR_MAX = 8192;
 
 // Waves per slice (1..16) for a launch over `slices` slices of `width` slots
 // on average: wide slices are shared by more waves until the launch has
@@ -1077,10 +1079,12 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
         // latency-bound launch, and one wavefront per row (four on rows of 4 x 4 blocks) shortens
         // its chain of dependent loads (the 128^3 workload's third level, 7461 nodes in 11
         // colours: 10.8 -> 7.3 us per pass; 2735 nodes in 28 colours with smoothed transfers:
-        // 15 -> 6.7 us).  Larger levels keep the sliced layout, whose rows are sorted by length
-        // within each colour when their lengths differ (the smoothed-transfer form's second
-        // level, 188,588 nodes in 18 colours: 1.56 -> 1.36 ms per V-cycle against one wavefront
-        // per row).  The row form's sliced parts are not built.
+        // 15 -> 6.7 us; the 64^3 workload's second level, 23,915 nodes in 9 colours: 819 -> 665 us
+        // per FP64 V-cycle).  Larger levels keep the sliced layout, whose rows are sorted by
+        // length within each colour when their lengths differ (the 128^3 workload's second
+        // level, 188,588 nodes: 9 colours 0.80 against 1.10 ms per FP64 V-cycle in the row form;
+        // 18 colours with smoothed transfers 1.36 against 1.56 ms).  The row form's sliced parts
+        // are not built.
         const int max_colours = std::max(Lv.blk[0].n_colours, Lv.blk[1].n_colours);
         bool rows_level = l > 0 && (int64_t)std::max(Lv.n, Lv.n1) <= (int64_t)ROWS_PER_COLOUR_MAX * max_colours;
         // MBAMG_ROWS_FORM (tests): "rows" forces the row form on every coarse level, anything else the sliced one
