@@ -2581,8 +2581,9 @@ mbamg_status mbamg_vcycle_bytes(const mbamg_hierarchy* h, double* bytes) {
 
 mbamg_status mbamg_level_vcycle_bytes(const mbamg_hierarchy* h, int32_t level, double* down, double* up) {
     return guarded([&]() -> mbamg_status {
-        MB_CHECK(h && down && up && level >= 0 && level < (int)h->L.size(), MBAMG_E_INVALID, "bad argument");
+        MB_CHECK(h && down && up, MBAMG_E_INVALID, "NULL argument");
         MB_CHECK(h->nb == 2, MBAMG_E_STATE, "the byte model covers two-block hierarchies");
+        MB_CHECK(level >= 0 && level < (int)h->L.size(), MBAMG_E_INVALID, "bad argument");
         level_vcycle_bytes(h, level, *down, *up);
         return MBAMG_OK;
     });
