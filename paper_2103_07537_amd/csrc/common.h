@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <stdexcept>
 #include <string>
+#include <cstring>
 #include <vector>
 
 #include "../../include/mbamg.h"
@@ -129,6 +130,40 @@ struct DevBuf {
         return h;
     }
 };
+// Several device arrays copied to host vectors through one page-locked buffer
+// with one synchronisation of the stream.
+struct HostCopies {
+    struct Item {
+        const void* src;
+        void* dst;
+        size_t bytes;
+    };
+    std::vector<Item> items;
+    template <class T>
+    void add(const DevBuf<T>& b, std::vector<T>& out, size_t count) {
+        out.resize(count);
+        if (count) items.push_back({b.p, out.data(), count * sizeof(T)});
+    }
+    void run(hipStream_t s) {
+        size_t total = 0;
+        for (const Item& it : items) total += (it.bytes + 15) & ~(size_t)15;
+        if (!total) return;
+        PinnedBuf<char> st(total);
+        size_t off = 0;
+        for (const Item& it : items) {
+            MB_HIP(hipMemcpyAsync(st.p + off, it.src, it.bytes, hipMemcpyDeviceToHost, s));
+            off += (it.bytes + 15) & ~(size_t)15;
+        }
+        MB_HIP(hipStreamSynchronize(s));
+        off = 0;
+        for (const Item& it : items) {
+            std::memcpy(it.dst, st.p + off, it.bytes);
+            off += (it.bytes + 15) & ~(size_t)15;
+        }
+        items.clear();
+    }
+};
+
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -568,13 +568,16 @@ static void build_part(SellPart& P, PartKind kind, const BlockLevel& B, const Se
         P.v32.alloc(std::max<int64_t>(P.n_groups, 1) * WAVE);
         cast_to_f32(P.v64.p, P.v32.p, P.n_groups * WAVE, s);
     }
-    // host copies for the byte model
-    P.h_width = P.width.download(s, ns);
-    std::vector<int32_t> c32 = coff32.download(s, ns + 1);
+    // host copies for the byte model, with one synchronisation (which also keeps the
+    // temporaries alive until the kernels have finished)
+    std::vector<int32_t> c32;
+    HostCopies hc;
+    hc.add(P.width, P.h_width, (size_t)ns);
+    hc.add(coff32, c32, (size_t)ns + 1);
+    hc.add(slot_nz, P.h_slot_nz, (size_t)nsl);
+    hc.add(sblk, P.h_slot_blocks, (size_t)nsl);
+    hc.run(s);
     P.h_coff.assign(c32.begin(), c32.end());
-    P.h_slot_nz = slot_nz.download(s, nsl);
-    P.h_slot_blocks = sblk.download(s, nsl);
-    MB_HIP(hipStreamSynchronize(s));   // keep the temporaries alive until the kernels finish
 }
 
 template <class T>
