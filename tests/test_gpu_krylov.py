@@ -1,0 +1,54 @@
+"""GMRES edges on the GPU against the oracle: restart lengths from 3 to the
+largest the library takes (31), the FP32-refined form with a short restart,
+and iteration caps that stop the solve early (NOT_CONVERGED with the true
+residual of the returned iterate)."""
+import numpy as np
+import pytest
+
+from gpu_util import gpu_hierarchy, log, rel, torch_dev
+from paper_2103_07537_amd.inputs import make_system
+
+pytestmark = pytest.mark.gpu
+
+
+def _system():
+    return make_system(23, 2, 0.7, seed=3, kappa="lognormal", blk1_scale=2.0, a10_scale=0.5)
+
+
+@pytest.mark.parametrize("restart", [3, 5, 31])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_restart_lengths_match_oracle(restart, precision):
+    from oracle import amg
+    s = _system()
+    ho = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=60), n_vec=s.n_vec)
+    hg = gpu_hierarchy(s, max_coarse=60, restart=restart, precision=precision)
+    x = torch_dev(np.zeros(s.n_dofs))
+    info = hg.solve(torch_dev(s.b), x, rtol=1e-8)
+    xo, io = amg.gmres(ho, s.b, rtol=1e-8, restart=restart)
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(s.b - s.to_scipy() @ xg) / np.linalg.norm(s.b)
+    log(f"  restart {restart} precision {precision}: gpu {info['iterations']} oracle {io.iterations} "
+        f"true residual {res:.2e}")
+    assert info["converged"] and res <= 1e-8 * (1 + 1e-6)
+    assert abs(info["iterations"] - io.iterations) <= 1
+    if info["iterations"] == io.iterations:
+        assert rel(xg, xo) <= 1e-8
+    hg.close()
+
+
+@pytest.mark.parametrize("cap", [0, 3])
+def test_iteration_cap_returns_the_iterate_and_its_true_residual(cap):
+    from paper_2103_07537_amd import mbamg
+    s = _system()
+    hg = gpu_hierarchy(s, max_coarse=60, max_iters=cap)
+    x = torch_dev(np.zeros(s.n_dofs))
+    info = hg.solve(torch_dev(s.b), x, rtol=1e-8)
+    assert not info["converged"] and info["iterations"] == cap
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(s.b - s.to_scipy() @ xg) / np.linalg.norm(s.b)
+    assert abs(info["rel_residual"] - res) <= 1e-10 * max(res, 1.0)
+    if cap == 0:
+        assert np.all(xg == 0.0) and info["rel_residual"] == 1.0
+    else:
+        assert res < 1.0
+    hg.close()
