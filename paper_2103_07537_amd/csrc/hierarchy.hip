@@ -113,6 +113,7 @@ struct Level {
     Aggregates G1;                             // block 1's own aggregates (separate aggregation)
     bool separate = false;
     BlockLevel blk[2];
+    int resid_split = 1;                       // waves per slice in the residual (one launch, both blocks)
     // smoothed prolongators (natural order) and the weights that built them
     bool smoothed = false, damped = false;
     SetupBsr P[2], PT[2];
@@ -1174,6 +1175,18 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
                 std::fprintf(stderr, "[mbamg setup] level %d block %d: %d nodes, %d colours, %d slices, %.1f slots/slice, "
                              "split %d\n", l, f, nf, B.n_colours, B.n_slices, avg_width, B.split);
         }
+        // the residual is one launch over both blocks' slices, not one colour: its split is
+        // chosen for the whole level, up to about 32K waves (MBAMG_SLICE_SPLIT forces both)
+        Lv.resid_split = std::max(Lv.blk[0].split, Lv.blk[1].split);
+        if (l > 0 && !Lv.blk[0].rows && !Lv.blk[1].rows && !form_override("MBAMG_SLICE_SPLIT")) {
+            int64_t slots = 0, slices = 0;
+            for (int f = 0; f < 2; ++f) {
+                const BlockLevel& B = Lv.blk[f];
+                for (int sl = 0; sl < B.n_slices; ++sl) slots += B.off.h_width[sl] + B.cpl.h_width[sl];
+                slices += B.n_slices;
+            }
+            Lv.resid_split = slot_split((double)slices, slices ? (double)slots / (double)slices : 0.0, 32768);
+        }
         clk.mark("sliced parts", l);
         if (p.smoother == 1) {
             // nodal-block Gauss-Seidel over the full node blocks: both blocks in one colour
@@ -1555,7 +1568,7 @@ static void resid(mbamg_hierarchy* h, int l, const T* b, const T* x, T* r, hipSt
         launch_resid_rows<T>(Lv.d[0], ra, s);
         return;
     }
-    launch_resid<T>(Lv.d[0], std::max(Lv.blk[0].split, Lv.blk[1].split), a, s);
+    launch_resid<T>(Lv.d[0], Lv.resid_split, a, s);
 }
 
 // One V-cycle on level l from a zero guess: out = MGV(0, b).
