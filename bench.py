@@ -310,8 +310,9 @@ def measured_traffic(workload_name, kind):
                 kv[k] = v
         if (kv.get("workload") == workload_name and kv.get("kind") == str(kind)
                 and kv.get("source_sha256") == sha):
-            return float(kv["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
-    return None, None
+            vc = float(kv["vcycle_traffic_bytes"]) if "vcycle_traffic_bytes" in kv else None
+            return float(kv["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT), vc
+    return None, None, None
 
 
 def main():
@@ -417,7 +418,13 @@ def main():
         per_launch_bytes = s["bytes"] / max(s["launches"], 1)
         avg_ms = s["total_ms"] / max(s["launches"], 1)
         achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
-        traffic, tsrc = measured_traffic(args.workload, kind)
+        traffic, tsrc, vc_traffic = measured_traffic(args.workload, kind)
+        if vc_traffic:
+            # the whole FP64 V-cycle's counted HBM bytes (same counter runs) over its in-solver time
+            f64 = results["fp64"]
+            f64["vcycle_measured_bytes"] = vc_traffic
+            f64["vcycle_measured_GBps"] = vc_traffic / (f64["vcycle_ms"] * 1e-3) / 1e9
+            f64["vcycle_measured_frac"] = f64["vcycle_measured_GBps"] / HBM_PEAK_GBS
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": names[kind],
                 "launches": s["launches"], "avg_us": avg_ms * 1e3, "alg_bytes_per_launch": per_launch_bytes,
