@@ -68,5 +68,26 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+def build_test_driver(verbose: bool = False) -> str:
+    """The tests' C-ABI driver (tests/abi_driver.cpp): a plain HIP program that
+    links libmbamg.so and uses include/mbamg.h only."""
+    root = os.path.dirname(HERE)
+    out_dir = os.path.join(root, "tests", "_build")
+    os.makedirs(out_dir, exist_ok=True)
+    out = os.path.join(out_dir, "abi_driver")
+    cmd = [hipcc(), "-O2", "-std=c++17", "-I", os.path.join(root, "include"),
+           os.path.join(root, "tests", "abi_driver.cpp"), "-L", HERE, "-lmbamg",
+           "-Wl,-rpath,$ORIGIN/../../paper_2103_07537_amd", "-o", out + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if p.returncode != 0:
+        print(p.stdout.decode(errors="replace"), file=sys.stderr)
+        raise RuntimeError("hipcc failed for tests/abi_driver.cpp")
+    os.replace(out + ".tmp", out)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_test_driver(verbose=True))
