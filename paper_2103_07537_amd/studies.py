@@ -14,8 +14,11 @@ one GPU, timed with the device synchronised on both sides.
     python -m paper_2103_07537_amd.studies sweeps   --workload 2d-512-lognormal --precision 1
     python -m paper_2103_07537_amd.studies smoother --workload 3d-64
     python -m paper_2103_07537_amd.studies coupling --workload 2d-256
+    python -m paper_2103_07537_amd.studies learned  --workload 2d-512-lognormal --precision 1
 
-(`coupling`: both smoothers as the coupling inside the nodes grows.)
+(`coupling`: both smoothers as the coupling inside the nodes grows; `learned`:
+on held-out fields, the fixed method against the trained network and the best
+uniform pair of prolongator-smoothing weight and damping.)
 
 Each point prints one JSON line; a markdown table follows on stderr.
 """
@@ -34,6 +37,10 @@ SWEEPS = ((1, 1), (2, 1), (1, 2), (2, 2))
 SMOOTHERS = (0, 1)
 # strength of the generator's coupling inside the nodes, against the vector Laplacian's diagonal
 NODE_COUPLINGS = (0.0, 0.05, 0.1, 0.2, 0.3, 0.5)
+# held-out fields of the learned-form comparison, and the uniform pairs searched for the best one
+HELD_OUT = (5000, 5001, 5002, 5003, 5004)
+OMEGA_P_GRID = (0.0, 1.0 / 3.0, 0.5, 2.0 / 3.0, 5.0 / 6.0)
+OMEGA_S_GRID = (0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1)
 
 
 def run_point(blocks, system, b, *, repeats: int = 3, rtol: float = 1e-8, **params) -> dict:
@@ -67,10 +74,37 @@ def study(kind: str, name: str, *, seed: int = 1, precision: int = 0, repeats: i
     from . import mbamg
     from .inputs import workload
     mbamg.lib()
+    out = []
+    if kind == "learned":
+        # per held-out field: the fixed method, the trained network (judged), and the best
+        # uniform (omega_P, omega_S) pair, each a fresh setup + solve
+        from .learned import DEFAULT_WEIGHTS, load
+        mlp = load(DEFAULT_WEIGHTS)
+        for sd in (points or HELD_OUT):
+            s = workload(name, seed=sd)
+            blocks = mbamg.to_device(s)
+            b = torch.from_numpy(s.b).cuda()
+            rows = [("fixed", run_point(blocks, s, b, repeats=repeats, precision=precision)),
+                    ("network", run_point(blocks, s, b, repeats=repeats, precision=precision, mlp=mlp, judge=1))]
+            best = None
+            for wp in OMEGA_P_GRID:
+                for ws in OMEGA_S_GRID:
+                    r = run_point(blocks, s, b, repeats=1, precision=precision, omega_p=wp, omega=ws)
+                    key = (not r["converged"], r["iterations"])
+                    if best is None or key < best[0]:
+                        best = (key, wp, ws)
+            rows.append((f"best uniform ({best[1]:.3f}, {best[2]:.1f})",
+                         run_point(blocks, s, b, repeats=repeats, precision=precision, omega_p=best[1],
+                                   omega=best[2])))
+            for label, r in rows:
+                r["params"] = dict(seed=sd, weights=label)
+                r["workload"] = name
+                r["unknowns"] = s.n_dofs
+                out.append(r)
+        return out
     s = workload(name, seed=seed)
     blocks = mbamg.to_device(s)
     b = torch.from_numpy(s.b).cuda()
-    out = []
     if kind == "omega":
         for w in (points or OMEGAS):
             out.append(run_point(blocks, s, b, repeats=repeats, precision=precision, omega=w))
@@ -113,7 +147,7 @@ def table(rows: list) -> str:
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("kind", choices=["omega", "sweeps", "smoother", "coupling"])
+    ap.add_argument("kind", choices=["omega", "sweeps", "smoother", "coupling", "learned"])
     ap.add_argument("--workload", default="2d-256")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--precision", type=int, default=0, choices=[0, 1])
