@@ -1637,6 +1637,7 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
             a.q[f] = qmptr<T>(Lv.blk[f]);
             a.in[f] = V.r.p + (f ? n0 : 0);
             a.out[f] = C.b.p + (f ? nc0 : 0);
+            a.order[f] = Nx.blk[f].d_iperm.p;   // coarse rows in natural (aggregate) order
         }
         const bool tx = h->time_launches();
         TimerScope ts(h, s, tx, launch_kind(l, 5), tx ? tentative_restrict_bytes(Lv, Nx, (int)sizeof(T)) : 0.0);

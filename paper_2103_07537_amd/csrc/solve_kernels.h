@@ -120,6 +120,10 @@ struct TransferArgs {
     const T* q[2];             // prolongation: per fine row; restriction: per member, in member-list order
     const T* in[2];
     T* out[2];
+    // restriction: the coarse row each group of lanes takes, in launch order (NULL: row i for
+    // group i); the next level's natural order keeps neighbouring aggregates, whose members
+    // share the fine rows' cache lines, in neighbouring groups
+    const int32_t* order[2];
 };
 
 // P: waves per slice (1, 2 or 4); the slice's slots are split among them.

@@ -742,6 +742,7 @@ __global__ __launch_bounds__(256) void k_restrict(TransferArgs<T> a) {
         f = 1;
         if (k >= a.n_rows[1]) return;   // whole groups
     }
+    if (a.order[f]) k = a.order[f][k];
     const int32_t* mp = a.map[f];
     const int32_t* mi = a.idx[f];
     T acc[D];
