@@ -79,6 +79,13 @@ struct BlockLevel {
     // smoothed transfers: P rows of this level, P^T rows of the next level (sliced by the next level)
     SellPart pro, res;
     int pro_split = 1, res_split = 1;          // waves per slice in the transfer kernels
+    // P^T's slices: the next level's rows in natural (aggregate) order, 64 per slice; the
+    // restriction writes slice row r to the next level's colour-order row iperm[r]
+    DevBuf<int32_t> res_row0, res_nrow;
+    int res_slices = 0;
+    // few wide P^T rows (small next levels): the restriction in row form, one wavefront per row
+    bool res_rows = false;
+    RowPart rres;
     int res_group = 4;                         // lanes per coarse row in the tentative restriction
     int row_split = 1;                         // row form smoother: wavefronts per row (1, or 4 with 4 x 4 blocks)
     // coarse levels with long rows: the smoother and residual run on the row form
@@ -534,6 +541,27 @@ static int transfer_split(const SellPart& P, int n_slices) {
     for (int w : P.h_width) slots += w;
     const double avg = n_slices ? (double)slots / n_slices : 0.0;
     return slot_split(n_slices, avg, 32768);
+}
+
+// next levels of at most this many rows take the restriction in row form
+constexpr int RES_ROWS_MAX = 16384;
+
+// Slices of 64 consecutive rows of an n-row matrix in natural order (identity
+// row order), for parts whose rows need not follow a colour order.
+static void natural_slicing(BlockLevel& B, int n, hipStream_t s) {
+    B.n = n;
+    B.n_slices = (int)ceil_div(n, WAVE);
+    B.h_row0.resize(B.n_slices);
+    B.h_nrow.resize(B.n_slices);
+    for (int sl = 0; sl < B.n_slices; ++sl) {
+        B.h_row0[sl] = sl * WAVE;
+        B.h_nrow[sl] = std::min(WAVE, n - sl * WAVE);
+    }
+    B.perm.resize(n);
+    for (int i = 0; i < n; ++i) B.perm[i] = i;
+    B.row0.upload(B.h_row0, s);
+    B.nrow.upload(B.h_nrow, s);
+    B.d_perm.upload(B.perm, s);
 }
 
 // Pack one part of block row f into masked slices on the device.  A: the
@@ -1217,9 +1245,24 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
             BlockLevel& B = Lv.blk[f];
             BlockLevel& C = Nx.blk[f];
             build_part(B.pro, PartKind::Cpl, B, &Lv.P[f], C.d_iperm.p, Lv.P[f].val.p, B.d, B.d, want32, s);
-            build_part(B.res, PartKind::Cpl, C, &Lv.PT[f], B.d_iperm.p, Lv.PT[f].val.p, B.d, B.d, want32, s);
+            // P^T sliced over the next level's rows in natural order: neighbouring aggregates,
+            // whose rows gather the same fine rows, share slices and stay on one XCD (in the
+            // colour order a slice mixes aggregates from all over the domain: 4x the
+            // algorithmic bytes fetched on the finest level)
+            BlockLevel nat;
+            natural_slicing(nat, Nx.nodes(f), s);
+            build_part(B.res, PartKind::Cpl, nat, &Lv.PT[f], B.d_iperm.p, Lv.PT[f].val.p, B.d, B.d, want32, s);
+            B.res_row0 = std::move(nat.row0);
+            B.res_nrow = std::move(nat.nrow);
+            B.res_slices = nat.n_slices;
+            // a next level of at most RES_ROWS_MAX rows has few, wide P^T rows (hundreds of
+            // blocks): one wavefront per row instead of a few slices' long chains (MBAMG_XFER_FORM
+            // = rows | sliced forces a form, for tests; the summation order differs)
+            B.res_rows = Nx.nodes(f) <= RES_ROWS_MAX;
+            if (const char* fo = form_override("MBAMG_XFER_FORM")) B.res_rows = std::strcmp(fo, "rows") == 0;
+            if (B.res_rows) build_rows(B.rres, Nx.nodes(f), nat.d_perm.p, Lv.PT[f], B.d_iperm.p, want32, s);
             B.pro_split = transfer_split(B.pro, B.n_slices);
-            B.res_split = transfer_split(B.res, C.n_slices);
+            B.res_split = transfer_split(B.res, B.res_slices);
         }
         for (int f = 0; f < 2 && Lv.damped; ++f) {
             BlockLevel& B = Lv.blk[f];
@@ -1612,14 +1655,31 @@ static void vcycle_level(mbamg_hierarchy* h, int l, const T* b, T* out, hipStrea
     Level& Nx = *h->L[l + 1];
     Vecs<T>& C = vecs<T>(Nx);
     const int64_t nc0 = (int64_t)Nx.n * Nx.d[0];
-    if (Lv.smoothed) {
+    if (Lv.smoothed && Lv.blk[0].res_rows) {
+        XferRowArgs<T> a{};
+        for (int f = 0; f < 2; ++f) {
+            a.n[f] = Nx.nodes(f);
+            a.A[f] = rview<T>(Lv.blk[f].rres);
+            a.x[f] = V.r.p + (f ? n0 : 0);
+            a.y[f] = C.b.p + (f ? nc0 : 0);
+            a.out_row[f] = Nx.blk[f].d_iperm.p;
+        }
+        a.accumulate = 0;
+        const bool tx = h->time_launches();
+        double xb = 0.0;
+        if (tx)
+            for (int f = 0; f < 2; ++f) xb += xfer_bytes(Lv.blk[f].res, Nx.n, Lv.n, Lv.d[f], (int)sizeof(T), false);
+        TimerScope ts(h, s, tx, launch_kind(l, 5), xb);
+        launch_xfer_rows<T>(Lv.d[0], a, s);
+    } else if (Lv.smoothed) {
         XferArgs<T> a{};
         for (int f = 0; f < 2; ++f) {
-            a.s_count[f] = Nx.blk[f].n_slices;
-            a.sl[f] = Nx.blk[f].slices();
+            a.s_count[f] = Lv.blk[f].res_slices;
+            a.sl[f] = {Lv.blk[f].res_row0.p, Lv.blk[f].res_nrow.p};
             a.A[f] = Lv.blk[f].res.view<T>();
             a.x[f] = V.r.p + (f ? n0 : 0);
             a.y[f] = C.b.p + (f ? nc0 : 0);
+            a.out_row[f] = Nx.blk[f].d_iperm.p;
         }
         a.accumulate = 0;
         const bool tx = h->time_launches();

@@ -135,11 +135,26 @@ struct XferArgs {
     const T* x[2];
     T* y[2];
     int accumulate;
+    const int32_t* out_row[2];   // row of y each slice row writes (NULL: the slice row itself)
 };
 
 // P waves share each slice's slots (1, 2 or 4)
 template <class T>
 void launch_xfer(int d, int P, const XferArgs<T>& a, hipStream_t s);
+
+// A transfer in row form: one wavefront per row of P or P^T (rows of block 0,
+// then block 1), for few wide rows.
+template <class T>
+struct XferRowArgs {
+    int n[2];
+    RowView<T> A[2];
+    const T* x[2];
+    T* y[2];
+    int accumulate;
+    const int32_t* out_row[2];   // row of y each matrix row writes (NULL: the row itself)
+};
+template <class T>
+void launch_xfer_rows(int d, const XferRowArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_gs(int d, int P, bool zero_x, bool has_cpl, const GsArgs<T>& a, hipStream_t s);
 template <class T>

@@ -599,6 +599,56 @@ __global__ __launch_bounds__(256) void k_resid_rows(ResidRowArgs<T> a) {
     store_vec<T, D>(a.r[f] + (int64_t)row * D, out);
 }
 
+// y = A x (or y += A x when accumulating) for a transfer in row form: one
+// wavefront per row, the row's blocks read as in the row-form smoother.
+template <class T, int D>
+__global__ __launch_bounds__(256) void k_xfer_rows(XferRowArgs<T> a) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    int row = blockIdx.x * WPB + wave_id();
+    int f = 0;
+    if (row >= a.n[0]) {
+        row -= a.n[0];
+        f = 1;
+        if (row >= a.n[1]) return;   // whole wavefront
+    }
+    T acc[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) acc[r] = T(0);
+    if constexpr (D == 4) row_sub_c<T, D, 0, false>(a.A[f], row, lane, a.x[f], nullptr, 0, acc);
+    else row_sub<T, D, D, 0, false>(a.A[f], row, lane, a.x[f], nullptr, 0, acc);
+    wave_sum_vec<T, D>(acc);
+    if (lane != WAVE - 1) return;
+    const int orow = a.out_row[f] ? a.out_row[f][row] : row;
+    T out[D];
+    if (a.accumulate) {
+        T y[D];
+        load_vec<T, D>(a.y[f] + (int64_t)orow * D, y);
+#pragma unroll
+        for (int r = 0; r < D; ++r) out[r] = y[r] - acc[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < D; ++r) out[r] = -acc[r];
+    }
+    store_vec<T, D>(a.y[f] + (int64_t)orow * D, out);
+}
+
+template <class T>
+void launch_xfer_rows(int d, const XferRowArgs<T>& a, hipStream_t s) {
+    const int64_t total = (int64_t)a.n[0] + a.n[1];
+    if (total <= 0) return;
+    const unsigned grid = (unsigned)ceil_div(total, WPB);
+    switch (d) {
+        case 1: k_xfer_rows<T, 1><<<grid, 256, 0, s>>>(a); break;
+        case 2: k_xfer_rows<T, 2><<<grid, 256, 0, s>>>(a); break;
+        case 3: k_xfer_rows<T, 3><<<grid, 256, 0, s>>>(a); break;
+        case 4: k_xfer_rows<T, 4><<<grid, 256, 0, s>>>(a); break;
+        default: throw Error(MBAMG_E_INVALID, "dofs per node must be 1..4");
+    }
+    MB_LAUNCH_CHECK();
+}
+template void launch_xfer_rows<double>(int, const XferRowArgs<double>&, hipStream_t);
+template void launch_xfer_rows<float>(int, const XferRowArgs<float>&, hipStream_t);
+
 // y += sign * A x for one block A_fg of any block shape (br, bc <= 4) in row
 // form (rows in block f's colour order, columns in block g's): one thread per
 // row, the row's blocks in their stored order.  Used where a system has more
@@ -707,17 +757,18 @@ __global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_xfer(XferArgs<T
     if (valid) sell_sub<T, D, D, 0, P>(a.A[f], sidx, lane, part, a.x[f], nullptr, 0, acc);
     combine_parts<T, D, P>(acc, wave, part, lane);
     if (part != 0 || !valid || lane >= nrow) return;
+    const int orow = a.out_row[f] ? a.out_row[f][row] : row;
     T out[D];
     if (a.accumulate) {
         T y[D];
-        load_vec<T, D>(a.y[f] + (int64_t)row * D, y);
+        load_vec<T, D>(a.y[f] + (int64_t)orow * D, y);
 #pragma unroll
         for (int r = 0; r < D; ++r) out[r] = y[r] - acc[r];
     } else {
 #pragma unroll
         for (int r = 0; r < D; ++r) out[r] = -acc[r];
     }
-    store_vec<T, D>(a.y[f] + (int64_t)row * D, out);
+    store_vec<T, D>(a.y[f] + (int64_t)orow * D, out);
 }
 
 // Sum over aligned groups of G lanes, valid in each group's last lane, per component.

@@ -135,3 +135,26 @@ def test_restriction_groups_match_oracle(group, monkeypatch):
     hg.vcycle(torch_dev(r), z)
     assert_close(z.cpu().numpy(), amg.vcycle(ho, r), 1e-12)
     hg.close()
+
+
+# The smoothed restriction runs on P^T sliced over the next level's rows in
+# natural order, or, for small next levels, one wavefront per row: the two
+# forms sum in different orders, and both are pinned to the oracle's V-cycle,
+# on a 3D case (4 x 4 blocks, the 16-byte row reads) and a 2D one (3 x 3).
+@pytest.mark.parametrize("form", ["rows", "sliced"])
+@pytest.mark.parametrize("case", ["3d", "2d"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_smoothed_restriction_forms_match_oracle(form, case, precision, monkeypatch):
+    from oracle import amg
+    from gpu_util import assert_close, torch_dev
+    s = make_system(11, 3, 2.0, seed=5, kappa="lognormal") if case == "3d" else make_system(30, 2, 0.9, seed=4)
+    ho = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=60, weights=weights_fn), n_vec=s.n_vec)
+    monkeypatch.setenv("MBAMG_XFER_FORM", form)
+    hg = gpu_hierarchy(s, max_coarse=60, precision=precision, weights=weights_fn, judge=0)
+    log(f"form={form} case={case} precision={precision} levels={hg.num_levels()}")
+    assert hg.num_levels() == len(ho.levels) >= 3
+    r = np.random.default_rng(9).standard_normal(s.n_dofs)
+    z = torch_dev(np.zeros(s.n_dofs))
+    hg.vcycle(torch_dev(r), z)
+    assert_close(z.cpu().numpy(), amg.vcycle(ho, r), 1e-12 if precision == 0 else 1e-5)
+    hg.close()
