@@ -121,6 +121,7 @@ struct Level {
     bool separate = false;
     BlockLevel blk[2];
     int resid_split = 1;                       // waves per slice in the residual (one launch, both blocks)
+    DevBuf<int32_t> resid_order[2];            // the residual's slice order per block (empty: identity)
     // smoothed prolongators (natural order) and the weights that built them
     bool smoothed = false, damped = false;
     SetupBsr P[2], PT[2];
@@ -541,6 +542,20 @@ static int transfer_split(const SellPart& P, int n_slices) {
     for (int w : P.h_width) slots += w;
     const double avg = n_slices ? (double)slots / n_slices : 0.0;
     return slot_split(n_slices, avg, 32768);
+}
+
+// A permutation of a level's slices (colour-major, colour_slice[c] .. [c+1])
+// that lists, for x = 0..7, the x-th eighth of every colour's slices.
+static std::vector<int32_t> slab_order(const std::vector<int>& colour_slice) {
+    const int nc = (int)colour_slice.size() - 1;
+    std::vector<int32_t> o;
+    o.reserve(nc >= 0 ? (size_t)colour_slice.back() : 0);
+    for (int x = 0; x < 8; ++x)
+        for (int c = 0; c < nc; ++c) {
+            const int64_t b = colour_slice[c], len = colour_slice[c + 1] - b;
+            for (int64_t k = len * x / 8; k < len * (x + 1) / 8; ++k) o.push_back((int32_t)(b + k));
+        }
+    return o;
 }
 
 // next levels of at most this many rows take the restriction in row form
@@ -1215,6 +1230,12 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
             }
             Lv.resid_split = slot_split((double)slices, slices ? (double)slots / (double)slices : 0.0, 32768);
         }
+        // the residual's launch order: the same eighth of every colour together, so the blocks
+        // each XCD takes (contiguous launch ranges) cover one slab of the domain in all colours
+        // and their neighbour gathers stay in its L2 (in colour order an XCD's range spans a
+        // whole colour, i.e. the whole domain)
+        if (l > 0 && !Lv.blk[0].rows && !Lv.blk[1].rows)
+            for (int f = 0; f < 2; ++f) Lv.resid_order[f].upload(slab_order(Lv.blk[f].colour_slice), s);
         clk.mark("sliced parts", l);
         if (p.smoother == 1) {
             // nodal-block Gauss-Seidel over the full node blocks: both blocks in one colour
@@ -1594,6 +1615,7 @@ static void resid(mbamg_hierarchy* h, int l, const T* b, const T* x, T* r, hipSt
         a.b[f] = b ? b + off : nullptr;
         a.x[f] = x + off;
         a.r[f] = r + off;
+        a.order[f] = Lv.resid_order[f].p;
     }
     const bool timed = h->time_launches() && kind >= 0 && (l == 0 || kind == 1);
     double bytes = timed ? resid_bytes(Lv, (int)sizeof(T), b != nullptr) : 0.0;

@@ -100,6 +100,7 @@ struct ResidRowArgs {
     const T* b[2];             // NULL for a plain operator apply
     const T* x[2];
     T* r[2];
+    const int32_t* order[2];   // slice of each launch position (NULL: the position itself)
 };
 
 template <class T>
@@ -110,6 +111,7 @@ struct ResidArgs {
     const T* b[2];             // NULL for a plain operator apply
     const T* x[2];
     T* r[2];
+    const int32_t* order[2];   // slice of each launch position (NULL: the position itself)
 };
 
 template <class T>

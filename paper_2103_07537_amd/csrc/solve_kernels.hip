@@ -699,6 +699,8 @@ __global__ __launch_bounds__(waves_per_block<P>() * WAVE) void k_resid(ResidArgs
     if (!valid) {   // padding wave of a split slice: read any existing slice, write nothing
         f = a.s_count[0] > 0 ? 0 : 1;
         sidx = 0;
+    } else if (a.order[f]) {
+        sidx = a.order[f][sidx];
     }
     const int g = 1 - f;
     const int lane = threadIdx.x & (WAVE - 1);
