@@ -785,8 +785,10 @@ __device__ __forceinline__ void group_sum_vec(T (&acc)[D]) {
 // scattered over the fine vector, so many are fetched at once; the weights q
 // are stored in member-list order, so only r is gathered)
 template <class T, int D, int G>
-__global__ __launch_bounds__(256) void k_restrict(TransferArgs<T> a) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_restrict(TransferArgs<T> a, int padded_blocks) {
+    // consecutive coarse rows (neighbouring aggregates, which share fine rows' cache lines)
+    // go to the same XCD
+    const int64_t t = (int64_t)xcd_block(padded_blocks) * blockDim.x + threadIdx.x;
     int k = (int)(t / G);
     const int gl = (int)(t % G);
     int f = 0;
@@ -1031,12 +1033,13 @@ template void launch_xfer<float>(int, int, const XferArgs<float>&, hipStream_t);
 
 template <class T, int D>
 static void restrict_dispatch(int64_t total, int G, const TransferArgs<T>& a, hipStream_t s) {
-    const unsigned grid = (unsigned)ceil_div(total * G, 256);
+    const unsigned grid = (unsigned)(ceil_div(ceil_div(total * G, 256), 8) * 8);
+    const int pb = (int)grid;
     switch (G) {
-        case 4: k_restrict<T, D, 4><<<grid, 256, 0, s>>>(a); break;
-        case 8: k_restrict<T, D, 8><<<grid, 256, 0, s>>>(a); break;
-        case 16: k_restrict<T, D, 16><<<grid, 256, 0, s>>>(a); break;
-        default: k_restrict<T, D, 64><<<grid, 256, 0, s>>>(a); break;
+        case 4: k_restrict<T, D, 4><<<grid, 256, 0, s>>>(a, pb); break;
+        case 8: k_restrict<T, D, 8><<<grid, 256, 0, s>>>(a, pb); break;
+        case 16: k_restrict<T, D, 16><<<grid, 256, 0, s>>>(a, pb); break;
+        default: k_restrict<T, D, 64><<<grid, 256, 0, s>>>(a, pb); break;
     }
 }
 
