@@ -246,9 +246,9 @@ struct DonorLink {
 
 thread_local std::string g_last_error;
 
-// Krylov scalar buffer layout (device and pinned host copies)
-constexpr int KB_D1 = 0, KB_C1 = KMAXQ, KB_D2 = 2 * KMAXQ, KB_C2 = 3 * KMAXQ, KB_NU0 = 4 * KMAXQ,
-              KB_NU1 = 4 * KMAXQ + 1, KB_NU2 = 4 * KMAXQ + 2, KB_TOTAL = 4 * KMAXQ + 3;
+// Krylov scalar buffer layout (device and pinned host copies): the dot pass's
+// sums, the update pass's sums, two norms
+constexpr int KB_D1 = 0, KB_D2 = KMAXQ, KB_NU0 = 2 * KMAXQ, KB_NU1 = 2 * KMAXQ + 1, KB_TOTAL = 2 * KMAXQ + 2;
 
 }  // namespace mbamg
 
@@ -265,12 +265,11 @@ struct mbamg_hierarchy {
     int coarse_n = 0;
     // Krylov workspace
     int64_t n_fine = 0;
-    DevBuf<double> V, Z64, w, xw, bw, ztmp, partial, hbuf, ybuf, sig2;
+    DevBuf<double> V, Z64, w, xw, bw, ztmp, partial, hbuf, ybuf, coef;
     DevBuf<float> mlp;             // network parameters (5122) followed by feature mean and std (12 + 12)
     double* hbuf_host = nullptr;   // pinned: Krylov scalars read back each iteration
-    double* sig2_host = nullptr;
+    double* coef_host = nullptr;   // pinned: the update pass's coefficients going up
     double* y_host = nullptr;
-    int64_t reorth_count = 0;
     double judge_rho[2] = {0.0, 0.0};   // probe factors of the learned and the fixed hierarchy
     // a learned hierarchy the judge kept holds the fixed-weight one it was judged against: a
     // solve that stalls with the learned preconditioner finishes with it
@@ -295,7 +294,7 @@ struct mbamg_hierarchy {
         for (auto& t : timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
         for (auto e : event_pool) (void)hipEventDestroy(e);
         if (hbuf_host) (void)hipHostFree(hbuf_host);
-        if (sig2_host) (void)hipHostFree(sig2_host);
+        if (coef_host) (void)hipHostFree(coef_host);
         if (y_host) (void)hipHostFree(y_host);
     }
 };
@@ -1344,9 +1343,9 @@ static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, D
     h->partial.alloc((size_t)KBLOCKS * KMAXQ);
     h->hbuf.alloc(KB_TOTAL);
     h->ybuf.alloc(KMAXQ);
-    h->sig2.alloc(KMAXQ);
+    h->coef.alloc(KC_TOTAL);
     MB_HIP(hipHostMalloc((void**)&h->hbuf_host, sizeof(double) * KB_TOTAL, hipHostMallocDefault));
-    MB_HIP(hipHostMalloc((void**)&h->sig2_host, sizeof(double) * KMAXQ, hipHostMallocDefault));
+    MB_HIP(hipHostMalloc((void**)&h->coef_host, sizeof(double) * KC_TOTAL, hipHostMallocDefault));
     MB_HIP(hipHostMalloc((void**)&h->y_host, sizeof(double) * KMAXQ, hipHostMallocDefault));
     MB_HIP(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
@@ -1936,9 +1935,9 @@ static void gen_setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t 
     h->partial.alloc((size_t)KBLOCKS * KMAXQ);
     h->hbuf.alloc(KB_TOTAL);
     h->ybuf.alloc(KMAXQ);
-    h->sig2.alloc(KMAXQ);
+    h->coef.alloc(KC_TOTAL);
     MB_HIP(hipHostMalloc((void**)&h->hbuf_host, sizeof(double) * KB_TOTAL, hipHostMallocDefault));
-    MB_HIP(hipHostMalloc((void**)&h->sig2_host, sizeof(double) * KMAXQ, hipHostMallocDefault));
+    MB_HIP(hipHostMalloc((void**)&h->coef_host, sizeof(double) * KC_TOTAL, hipHostMallocDefault));
     MB_HIP(hipHostMalloc((void**)&h->y_host, sizeof(double) * KMAXQ, hipHostMallocDefault));
     MB_HIP(hipStreamSynchronize(s));
     h->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -2117,8 +2116,8 @@ static void apply_A(mbamg_hierarchy* h, const double* x, double* w, hipStream_t 
 static double norm2_dev(mbamg_hierarchy* h, const double* v, hipStream_t s) {
     const int nb = krylov_blocks(h->n_fine);
     double* kb = h->hbuf.p;
-    launch_orth(h->n_fine, 0, nullptr, 0, nullptr, v, nullptr, false, h->partial.p, nb, s);
-    launch_orth_reduce(h->partial.p, nb, 0, false, h->sig2.p, kb, kb, kb + KB_NU0, s);
+    launch_orth(h->n_fine, 0, nullptr, 0, v, h->partial.p, nb, s);
+    launch_orth_reduce(h->partial.p, nb, 0, nullptr, kb + KB_NU0, nullptr, s);
     double r = 0.0;
     MB_HIP(hipMemcpyAsync(&r, kb + KB_NU0, sizeof(double), hipMemcpyDeviceToHost, s));
     MB_HIP(hipStreamSynchronize(s));
@@ -2126,11 +2125,25 @@ static double norm2_dev(mbamg_hierarchy* h, const double* v, hipStream_t s) {
 }
 
 // Restarted GMRES (FGMRES when the cycle runs in FP32), right preconditioned.
-// The Arnoldi basis is kept unnormalised: V_true[q] = sig[q] * V[q], so the
-// normalisation needs no separate pass.  Orthogonalisation is classical
-// Gram-Schmidt with one reorthogonalisation when the new vector lost more
-// than a factor 1/sqrt(2) of its norm ("twice is enough", Daniel, Gragg,
-// Kaufman & Stewart 1976; Giraud, Langou & Rozloznik 2005).
+// Orthogonalisation is classical Gram-Schmidt run twice ("twice is enough",
+// Giraud, Langou & Rozloznik 2005) with the second pass delayed by one step
+// (DCGS2, Swirydowicz et al. 2020; Bielich et al. 2022), so each step reads the
+// basis twice (a dot pass, an update pass) rather than three times:
+//   step j holds Q_0..Q_{j-1} (orthonormal) and the candidate u_j, projected
+//   once, with a_j = Q^T u_j and |u_j|^2 from the previous update pass, so
+//   nu_j = sqrt(|u_j|^2 - |a_j|^2) = |u_j - Q a_j|.  The preconditioner and the
+//   operator are applied to u_j itself: zt_j = M u_j, w = A zt_j.  The direction
+//   the Arnoldi process wants is z_j = (zt_j - sum_i a_{j,i} z_i) / nu_j, whose
+//   image A z_j = (w - Q_{j+1} c) / nu_j with c = H_{0..j,0..j-1} a_j (the
+//   Arnoldi relation of the earlier columns), so
+//     H[l][j] = (b_l - c_l) / nu_j + a_{j+1,l}        (l < j, b = Q^T w)
+//     H[j][j] = ((u_j.w - a_j.b) / nu_j - c_j) / nu_j + a_{j+1,j}
+//     H[j+1][j] = nu_{j+1}
+//   where the update pass writes Q_j = (u_j - Q a_j) / nu_j and the next
+//   candidate u_{j+1} = (w - Q b - Q_j (u_j.w - a_j.b) / nu_j) / nu_j and sums
+//   a_{j+1} and |u_{j+1}|^2.  The iterate gains Z y = Zt t with
+//   zt_j = sum_i a_{j,i} z_i + nu_j z_j, i.e. U t = y for the upper-triangular U
+//   of the a's and nu's.
 // Solve-time fallback of a judged learned hierarchy (the setup's probe judge
 // decides which preconditioner a solve starts with): when a complete restart
 // cycle of the learned preconditioner reduces the residual by less than
@@ -2165,26 +2178,32 @@ static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, d
     int its = 0;
     double rel = 0.0;
     mbamg_status st = MBAMG_OK;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), sig(m + 1);
+    // H: the least-squares matrix (rotated as it grows), Hr: its unrotated columns
+    // (the Arnoldi relation), Ac[j][i] = a_{j,i}, nuv[j] = nu_j
+    const int ld = m + 1;
+    std::vector<double> H((size_t)ld * m), Hr((size_t)ld * m), cs(m), sn(m), g(ld), y(m), t(m), nuv(ld),
+        Ac((size_t)ld * ld);
     double* hb = h->hbuf_host;
     double* kb = h->hbuf.p;
+    double* ch = h->coef_host;
     const int nb = krylov_blocks(n);
     if (bnorm == 0.0) {
         MB_HIP(hipMemsetAsync(h->xw.p, 0, sizeof(double) * n, s));
         rel = 0.0;
     } else {
         while (true) {
-            // true residual into V_0
+            // true residual into V_0: the first candidate, with a_0 = () and nu_0 = beta
             if (h->nb > 2) gen_resid(h, 0, h->bw.p, h->xw.p, h->V.p, s);
             else resid<double>(h, 0, h->bw.p, h->xw.p, h->V.p, s, 1);
             const double beta = std::sqrt(norm2_dev(h, h->V.p, s));
             rel = beta / bnorm;
             if (beta <= rtol * bnorm) break;
             if (its >= h->p.max_iters) { st = MBAMG_NOT_CONVERGED; break; }
-            sig[0] = 1.0 / beta;
-            h->sig2_host[0] = sig[0] * sig[0];
-            MB_HIP(hipMemcpyAsync(h->sig2.p, h->sig2_host, sizeof(double), hipMemcpyHostToDevice, s));
+            nuv[0] = beta;
+            ch[KC_INV_NU] = 1.0 / beta;
+            MB_HIP(hipMemcpyAsync(h->coef.p + KC_INV_NU, ch + KC_INV_NU, sizeof(double), hipMemcpyHostToDevice, s));
             std::fill(g.begin(), g.end(), 0.0);
+            std::fill(Hr.begin(), Hr.end(), 0.0);
             g[0] = beta;
             int k = 0;
             for (int j = 0; j < m; ++j) {
@@ -2194,41 +2213,45 @@ static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, d
                 float* zj32 = fp32 ? h->Z32.p + (size_t)j * n : nullptr;
                 apply_precond(h, vj, zj64, zj32, s);
                 apply_A(h, zj64, h->w.p, s);
-                const int nq = j + 1;
-                // pass 1: d1 = V^T w, nu0 = |w|^2
-                launch_orth(n, nq, h->V.p, n, nullptr, h->w.p, nullptr, true, h->partial.p, nb, s);
-                launch_orth_reduce(h->partial.p, nb, nq, true, h->sig2.p, kb + KB_D1, kb + KB_C1, kb + KB_NU0, s);
-                // pass 2: V_{j+1} = w - sum c1 V, d2 = V^T V_{j+1}, nu1 = |V_{j+1}|^2
-                launch_orth(n, nq, h->V.p, n, kb + KB_C1, h->w.p, vn, true, h->partial.p, nb, s);
-                launch_orth_reduce(h->partial.p, nb, nq, true, h->sig2.p, kb + KB_D2, kb + KB_C2, kb + KB_NU1, s);
+                // dot pass: b = Q^T w and u_j . w; c_j on the device
+                launch_orth(n, j + 1, h->V.p, n, h->w.p, h->partial.p, nb, s);
+                launch_orth_reduce(h->partial.p, nb, j + 1, kb + KB_D1, nullptr, h->coef.p, s);
+                // update pass: Q_j over u_j, u_{j+1} into V_{j+1}, a_{j+1} and |u_{j+1}|^2
+                launch_dcgs_update(n, j, h->V.p, n, h->coef.p, vj, h->w.p, vn, h->partial.p, nb, s);
+                launch_orth_reduce(h->partial.p, nb, j + 1, kb + KB_D2, kb + KB_NU1, nullptr, s);
                 MB_HIP(hipMemcpyAsync(hb, kb, sizeof(double) * KB_TOTAL, hipMemcpyDeviceToHost, s));
                 MB_HIP(hipStreamSynchronize(s));
-                double* col = &H[(size_t)j * (m + 1)];
-                double nu = hb[KB_NU1];
-                if (nu >= 0.5 * hb[KB_NU0]) {
-                    for (int q = 0; q <= j; ++q) col[q] = sig[j] * sig[q] * hb[KB_D1 + q];
-                } else {
-                    // pass 3: reorthogonalise in place
-                    launch_orth(n, nq, h->V.p, n, kb + KB_C2, vn, vn, false, h->partial.p, nb, s);
-                    launch_orth_reduce(h->partial.p, nb, nq, false, h->sig2.p, kb, kb, kb + KB_NU2, s);
-                    MB_HIP(hipMemcpyAsync(hb + KB_NU2, kb + KB_NU2, sizeof(double), hipMemcpyDeviceToHost, s));
-                    MB_HIP(hipStreamSynchronize(s));
-                    nu = hb[KB_NU2];
-                    for (int q = 0; q <= j; ++q) col[q] = sig[j] * sig[q] * (hb[KB_D1 + q] + hb[KB_D2 + q]);
-                    ++h->reorth_count;
+                const double* bq = hb + KB_D1;
+                const double* an = hb + KB_D2;
+                const double* aj = &Ac[(size_t)j * ld];
+                const double nuj = nuv[j];
+                double ab = 0.0;
+                for (int i = 0; i < j; ++i) ab += aj[i] * bq[i];
+                double* raw = &Hr[(size_t)j * ld];
+                for (int l = 0; l <= j; ++l) {
+                    double c = 0.0;
+                    for (int i = std::max(0, l - 1); i < j; ++i) c += Hr[(size_t)i * ld + l] * aj[i];
+                    const double proj = l < j ? bq[l] : (bq[j] - ab) / nuj;
+                    raw[l] = (proj - c) / nuj + an[l];
                 }
-                const double hn = sig[j] * std::sqrt(nu);
-                col[j + 1] = hn;
-                if (nu > 0.0) {
-                    sig[j + 1] = 1.0 / std::sqrt(nu);
-                    h->sig2_host[j + 1] = sig[j + 1] * sig[j + 1];
-                    MB_HIP(hipMemcpyAsync(h->sig2.p + j + 1, h->sig2_host + j + 1, sizeof(double),
-                                          hipMemcpyHostToDevice, s));
+                double nu2 = hb[KB_NU1];
+                for (int l = 0; l <= j; ++l) nu2 -= an[l] * an[l];
+                // nu2 <= 0: the candidate lies in the basis (breakdown)
+                const double nun = nu2 > 0.0 && std::isfinite(nu2) ? std::sqrt(nu2) : 0.0;
+                raw[j + 1] = nun;
+                nuv[j + 1] = nun;
+                for (int l = 0; l <= j; ++l) Ac[(size_t)(j + 1) * ld + l] = an[l];
+                if (nun > 0.0 && j + 1 < m) {
+                    for (int l = 0; l <= j; ++l) ch[KC_A + l] = an[l];
+                    ch[KC_INV_NU] = 1.0 / nun;
+                    MB_HIP(hipMemcpyAsync(h->coef.p, ch, sizeof(double) * KC_TOTAL, hipMemcpyHostToDevice, s));
                 }
+                double* col = &H[(size_t)j * ld];
+                for (int l = 0; l <= j + 1; ++l) col[l] = raw[l];
                 for (int i = 0; i < j; ++i) {
-                    double t = cs[i] * col[i] + sn[i] * col[i + 1];
+                    double tq = cs[i] * col[i] + sn[i] * col[i + 1];
                     col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-                    col[i] = t;
+                    col[i] = tq;
                 }
                 double den = std::hypot(col[j], col[j + 1]);
                 cs[j] = den != 0.0 ? col[j] / den : 1.0;
@@ -2239,19 +2262,24 @@ static mbamg_status solve_impl(mbamg_hierarchy* h, const double* b, double* x, d
                 g[j] = cs[j] * g[j];
                 ++its;
                 k = j + 1;
-                if (std::fabs(g[j + 1]) <= rtol * bnorm || its >= h->p.max_iters || nu == 0.0) break;
+                if (std::fabs(g[j + 1]) <= rtol * bnorm || its >= h->p.max_iters || nun == 0.0) break;
                 if (can_revert && k == m && !(std::pow(std::fabs(g[j + 1]) / beta, 1.0 / k) <= revert_rho)) {
                     revert = true;
                     break;
                 }
             }
-            // back substitution H[:k,:k] y = g[:k]; x += sum_j y_j sig_j Z_j
+            // back substitution H[:k,:k] y = g[:k], then U t = y; x += sum_j t_j zt_j
             for (int i = k - 1; i >= 0; --i) {
                 double sum = g[i];
-                for (int c = i + 1; c < k; ++c) sum -= H[(size_t)c * (m + 1) + i] * y[c];
-                y[i] = sum / H[(size_t)i * (m + 1) + i];
+                for (int c = i + 1; c < k; ++c) sum -= H[(size_t)c * ld + i] * y[c];
+                y[i] = sum / H[(size_t)i * ld + i];
             }
-            for (int i = 0; i < k; ++i) h->y_host[i] = y[i] * sig[i];
+            for (int i = k - 1; i >= 0; --i) {
+                double sum = y[i];
+                for (int l = i + 1; l < k; ++l) sum -= Ac[(size_t)l * ld + i] * t[l];
+                t[i] = sum / nuv[i];
+            }
+            for (int i = 0; i < k; ++i) h->y_host[i] = t[i];
             MB_HIP(hipMemcpyAsync(h->ybuf.p, h->y_host, sizeof(double) * k, hipMemcpyHostToDevice, s));
             if (fp32) launch_combine32(n, k, h->Z32.p, n, h->ybuf.p, h->xw.p, s);
             else launch_combine(n, k, h->Z64.p, n, h->ybuf.p, h->xw.p, s);

@@ -180,13 +180,27 @@ void launch_prolong(int d, const TransferArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_coarse(int n, const double* inv, const T* x, T* y, hipStream_t s);
 
-// Krylov helpers (FP64).  Reductions are two-pass and deterministic.
-constexpr int KMAXQ = 33;        // basis vectors + 1 slot for a norm
+// Krylov helpers (FP64).  Reductions are two-pass and deterministic: per-block
+// partial sums stored slot-major (partial[q * KBLOCKS + block]), then one
+// workgroup sums every slot in a fixed order.
+constexpr int KMAXQ = 33;        // basis vectors + 2 slots (a dot with the candidate, a norm)
 constexpr int KBLOCKS = 1024;
-void launch_orth(int64_t n, int nq, const double* V, int64_t ldv, const double* c, const double* w, double* out,
-                 bool dots, double* partial, int nblocks, hipStream_t s);
-void launch_orth_reduce(const double* partial, int nblocks, int nq, bool dots, const double* sig2, double* d,
-                        double* cf, double* nu, hipStream_t s);
+// layout of the coefficient buffer of the delayed-reorthogonalisation update:
+// [0, KMAXQ) a (reorthogonalisation coefficients of the candidate),
+// [KMAXQ, 2 KMAXQ) b (projections of the new vector), then 1/nu and c_j
+constexpr int KC_A = 0, KC_B = KMAXQ, KC_INV_NU = 2 * KMAXQ, KC_CJ = 2 * KMAXQ + 1, KC_TOTAL = 2 * KMAXQ + 2;
+// partial[q] = sum V_q . w (q < nq), partial[nq] = sum w . w
+void launch_orth(int64_t n, int nq, const double* V, int64_t ldv, const double* w, double* partial, int nblocks,
+                 hipStream_t s);
+// One pass of the delayed reorthogonalisation step (see the kernel)
+void launch_dcgs_update(int64_t n, int nq, const double* V, int64_t ldv, const double* coef, double* u,
+                        const double* w, double* out, double* partial, int nblocks, hipStream_t s);
+// r_q = sum over blocks of partial[q] for q = 0..nq: d[q] = r_q (q < nq, d may be
+// NULL), *nu = r_nq (may be NULL); with coef (the dot pass of the delayed
+// reorthogonalisation, nq - 1 basis vectors and the candidate):
+// coef[KC_B + q] = r_q (q < nq - 1), coef[KC_CJ] = (r_{nq-1} - sum_q coef[KC_A + q] r_q) coef[KC_INV_NU]
+void launch_orth_reduce(const double* partial, int nblocks, int nq, double* d, double* nu, double* coef,
+                        hipStream_t s);
 void launch_combine(int64_t n, int k, const double* Z, int64_t ldz, const double* y, double* x, hipStream_t s);
 void launch_combine32(int64_t n, int k, const float* Z, int64_t ldz, const double* y, double* x, hipStream_t s);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);

@@ -1107,77 +1107,127 @@ __device__ inline double block_sum(double v, double* sh) {
     return r;
 }
 
-// One pass of Gram-Schmidt over the basis V_0..V_{nq-1} (stored column by
-// column, ldv apart):
-//   u = w - sum_q c_q V_q          (c == NULL: u = w)
-//   out = u                         (when out != NULL; out may alias w)
-//   partial[b*KMAXQ + q] = sum V_q . u over this block's elements (dots != 0)
-//   partial[b*KMAXQ + nq] = sum u . u
-// All loads of one element are issued before any use; NQ bounds nq.
+// Dot pass: partial[q][block] = sum V_q . w over this block's elements (q < nq),
+// partial[nq][block] = sum w . w.  All loads of one element are issued before any
+// use; NQ bounds nq.
 template <int NQ>
 __global__ __launch_bounds__(256) void k_orth(int64_t n, int nq, const double* __restrict__ V, int64_t ldv,
-                                              const double* __restrict__ c, const double* w, double* out, int dots,
-                                              double* __restrict__ partial) {
+                                              const double* __restrict__ w, double* __restrict__ partial) {
     __shared__ double sh[4];
-    double cq[NQ], acc[NQ];
+    double acc[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        cq[q] = (c != nullptr && q < nq) ? c[q] : 0.0;
-        acc[q] = 0.0;
-    }
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     double nn = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
         double v[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            if (q < nq) v[q] = V[q * ldv + e];
-            else v[q] = 0.0;
-        }
-        double u = w[e];
-        if (c != nullptr) {
+        for (int q = 0; q < NQ; ++q) v[q] = q < nq ? V[q * ldv + e] : 0.0;
+        const double u = w[e];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) u -= cq[q] * v[q];
-        }
-        if (out != nullptr) out[e] = u;
-        if (dots) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) acc[q] += v[q] * u;
-        }
+        for (int q = 0; q < NQ; ++q) acc[q] += v[q] * u;
         nn += u * u;
     }
-    if (dots) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            if (q < nq) {
-                double r = block_sum(acc[q], sh);
-                if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * KMAXQ + q] = r;
-            }
+    for (int q = 0; q < NQ; ++q) {
+        if (q < nq) {
+            const double r = block_sum(acc[q], sh);
+            if (threadIdx.x == 0) partial[(int64_t)q * KBLOCKS + blockIdx.x] = r;
         }
     }
-    double r = block_sum(nn, sh);
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * KMAXQ + nq] = r;
+    const double r = block_sum(nn, sh);
+    if (threadIdx.x == 0) partial[(int64_t)nq * KBLOCKS + blockIdx.x] = r;
 }
 
-// Final sums in a fixed order: d[q] = sum_b partial[b][q], cf[q] = sig2[q] * d[q]
-// for q < nq (when dots != 0), nu = sum_b partial[b][nq].
-__global__ void k_orth_reduce(const double* __restrict__ partial, int nb, int nq, int dots,
-                              const double* __restrict__ sig2, double* __restrict__ d, double* __restrict__ cf,
-                              double* __restrict__ nu) {
+// Update pass of classical Gram-Schmidt with delayed reorthogonalisation
+// (DCGS2: Swirydowicz, Langou, Ananthan, Yang & Thomas 2020; Bielich et al.
+// 2022).  Q_0..Q_{nq-1} are final orthonormal basis vectors, u the candidate for
+// Q_nq (projected once), w the operator applied to the preconditioned u, and
+// coef holds a = Q^T u (found by the previous update pass), b = Q^T w, 1/nu with
+// nu = |u - Q a|, and c_j = (u . w - a . b) / nu.  Per element:
+//   q  = (u - sum_k a_k Q_k) / nu            (the reorthogonalised candidate, over u)
+//   un = (w - sum_k b_k Q_k - c_j q) / nu     (the next candidate, projected once)
+// and the dots a' = [Q q]^T un and |un|^2 for the next step:
+// partial[k] = Q_k . un (k < nq), partial[nq] = q . un, partial[nq + 1] = un . un.
+template <int NQ>
+__global__ __launch_bounds__(256) void k_dcgs_update(int64_t n, int nq, const double* __restrict__ V, int64_t ldv,
+                                                     const double* __restrict__ coef, double* u,
+                                                     const double* __restrict__ w, double* __restrict__ out,
+                                                     double* __restrict__ partial) {
     __shared__ double sh[4];
-    for (int q = dots ? 0 : nq; q <= nq; ++q) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) v += partial[(int64_t)b * KMAXQ + q];
-        double r = block_sum(v, sh);
-        if (threadIdx.x == 0) {
-            if (q < nq) {
-                d[q] = r;
-                cf[q] = sig2[q] * r;
-            } else {
-                *nu = r;
-            }
+    __shared__ double ca[NQ], cb[NQ];
+    if (threadIdx.x < NQ) {
+        ca[threadIdx.x] = (int)threadIdx.x < nq ? coef[KC_A + threadIdx.x] : 0.0;
+        cb[threadIdx.x] = (int)threadIdx.x < nq ? coef[KC_B + threadIdx.x] : 0.0;
+    }
+    const double inv_nu = coef[KC_INV_NU];
+    const double cj = coef[KC_CJ];
+    __syncthreads();
+    double acc[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) acc[k] = 0.0;
+    double accq = 0.0, nn = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        double v[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) v[k] = k < nq ? V[k * ldv + e] : 0.0;
+        double q = u[e];
+        double un = w[e];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            q -= ca[k] * v[k];
+            un -= cb[k] * v[k];
         }
-        __syncthreads();
+        q *= inv_nu;
+        un = (un - cj * q) * inv_nu;
+        u[e] = q;
+        out[e] = un;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) acc[k] += v[k] * un;
+        accq += q * un;
+        nn += un * un;
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        if (k < nq) {
+            const double r = block_sum(acc[k], sh);
+            if (threadIdx.x == 0) partial[(int64_t)k * KBLOCKS + blockIdx.x] = r;
+        }
+    }
+    double r = block_sum(accq, sh);
+    if (threadIdx.x == 0) partial[(int64_t)nq * KBLOCKS + blockIdx.x] = r;
+    r = block_sum(nn, sh);
+    if (threadIdx.x == 0) partial[(int64_t)(nq + 1) * KBLOCKS + blockIdx.x] = r;
+}
+
+// Final sums in a fixed order, one wavefront per slot: lane l adds the blocks
+// l, l + 64, ... in turn, then a butterfly over the wavefront.  r_q for q = 0..nq:
+// d[q] = r_q (q < nq), *nu = r_nq; with coef, the delayed-reorthogonalisation
+// coefficients b (r_q, q < nq - 1) and c_j (see launch_orth_reduce).
+__global__ __launch_bounds__(1024) void k_orth_reduce(const double* __restrict__ partial, int nb, int nq,
+                                                      double* __restrict__ d, double* __restrict__ nu,
+                                                      double* __restrict__ coef) {
+    __shared__ double res[KMAXQ];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (WAVE - 1);
+    for (int q = wave; q <= nq; q += (int)(blockDim.x >> 6)) {
+        double v = 0.0;
+        for (int b = lane; b < nb; b += WAVE) v += partial[(int64_t)q * KBLOCKS + b];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+        if (lane == 0) res[q] = v;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (d != nullptr && t < nq) d[t] = res[t];
+    if (nu != nullptr && t == 0) *nu = res[nq];
+    if (coef != nullptr) {
+        if (t < nq - 1) coef[KC_B + t] = res[t];
+        if (t == 0) {
+            double ab = 0.0;
+            for (int k = 0; k < nq - 1; ++k) ab += coef[KC_A + k] * res[k];
+            coef[KC_CJ] = (res[nq - 1] - ab) * coef[KC_INV_NU];
+        }
     }
 }
 
@@ -1244,19 +1294,31 @@ static unsigned stream_grid(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n, 256)));
 }
 
-void launch_orth(int64_t n, int nq, const double* V, int64_t ldv, const double* c, const double* w, double* out,
-                 bool dots, double* partial, int nblocks, hipStream_t s) {
-    MB_CHECK(nq >= 0 && nq <= KMAXQ - 1, MBAMG_E_INVALID, "too many Krylov vectors");
-    const int d = dots ? 1 : 0;
-    if (nq <= 8) k_orth<8><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, c, w, out, d, partial);
-    else if (nq <= 16) k_orth<16><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, c, w, out, d, partial);
-    else k_orth<32><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, c, w, out, d, partial);
+void launch_orth(int64_t n, int nq, const double* V, int64_t ldv, const double* w, double* partial, int nblocks,
+                 hipStream_t s) {
+    MB_CHECK(nq >= 0 && nq <= KMAXQ - 1 && nblocks >= 1 && nblocks <= KBLOCKS, MBAMG_E_INVALID,
+             "too many Krylov vectors");
+    if (nq <= 8) k_orth<8><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, w, partial);
+    else if (nq <= 16) k_orth<16><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, w, partial);
+    else k_orth<32><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, w, partial);
     MB_LAUNCH_CHECK();
 }
 
-void launch_orth_reduce(const double* partial, int nblocks, int nq, bool dots, const double* sig2, double* d,
-                        double* cf, double* nu, hipStream_t s) {
-    k_orth_reduce<<<1, 256, 0, s>>>(partial, nblocks, nq, dots ? 1 : 0, sig2, d, cf, nu);
+void launch_dcgs_update(int64_t n, int nq, const double* V, int64_t ldv, const double* coef, double* u,
+                        const double* w, double* out, double* partial, int nblocks, hipStream_t s) {
+    MB_CHECK(nq >= 0 && nq <= KMAXQ - 2 && nq <= 32 && nblocks >= 1 && nblocks <= KBLOCKS, MBAMG_E_INVALID,
+             "too many Krylov vectors");
+    if (nq <= 8) k_dcgs_update<8><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, coef, u, w, out, partial);
+    else if (nq <= 16) k_dcgs_update<16><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, coef, u, w, out, partial);
+    else k_dcgs_update<32><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, coef, u, w, out, partial);
+    MB_LAUNCH_CHECK();
+}
+
+void launch_orth_reduce(const double* partial, int nblocks, int nq, double* d, double* nu, double* coef,
+                        hipStream_t s) {
+    MB_CHECK(nq >= 0 && nq <= KMAXQ - 1 && nblocks >= 1 && nblocks <= KBLOCKS && (coef == nullptr || nq >= 1),
+             MBAMG_E_INVALID, "invalid Krylov reduction");
+    k_orth_reduce<<<1, 1024, 0, s>>>(partial, nblocks, nq, d, nu, coef);
     MB_LAUNCH_CHECK();
 }
 
