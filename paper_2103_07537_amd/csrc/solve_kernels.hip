@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <utility>
 
 namespace mbamg {
 
@@ -1107,22 +1108,23 @@ __device__ inline double block_sum(double v, double* sh) {
     return r;
 }
 
-// Dot pass: partial[q][block] = sum V_q . w over this block's elements (q < nq),
-// partial[nq][block] = sum w . w.  All loads of one element are issued before any
-// use; NQ bounds nq.
+// Dot pass: partial[q][block] = sum V_q . w over this block's elements (q < NQ),
+// partial[NQ][block] = sum w . w.  NQ is the exact count (one instance per
+// count: guarded loads would cost a branch each and registers for the
+// predicates); all loads of one element are issued before any use.
 template <int NQ>
-__global__ __launch_bounds__(256) void k_orth(int64_t n, int nq, const double* __restrict__ V, int64_t ldv,
+__global__ __launch_bounds__(256) void k_orth(int64_t n, const double* __restrict__ V, int64_t ldv,
                                               const double* __restrict__ w, double* __restrict__ partial) {
     __shared__ double sh[4];
-    double acc[NQ];
+    double acc[NQ > 0 ? NQ : 1];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     double nn = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        double v[NQ];
+        double v[NQ > 0 ? NQ : 1];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) v[q] = q < nq ? V[q * ldv + e] : 0.0;
+        for (int q = 0; q < NQ; ++q) v[q] = V[q * ldv + e];
         const double u = w[e];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc[q] += v[q] * u;
@@ -1130,54 +1132,53 @@ __global__ __launch_bounds__(256) void k_orth(int64_t n, int nq, const double* _
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        if (q < nq) {
-            const double r = block_sum(acc[q], sh);
-            if (threadIdx.x == 0) partial[(int64_t)q * KBLOCKS + blockIdx.x] = r;
-        }
+        const double r = block_sum(acc[q], sh);
+        if (threadIdx.x == 0) partial[(int64_t)q * KBLOCKS + blockIdx.x] = r;
     }
     const double r = block_sum(nn, sh);
-    if (threadIdx.x == 0) partial[(int64_t)nq * KBLOCKS + blockIdx.x] = r;
+    if (threadIdx.x == 0) partial[(int64_t)NQ * KBLOCKS + blockIdx.x] = r;
 }
 
 // Update pass of classical Gram-Schmidt with delayed reorthogonalisation
 // (DCGS2: Swirydowicz, Langou, Ananthan, Yang & Thomas 2020; Bielich et al.
-// 2022).  Q_0..Q_{nq-1} are final orthonormal basis vectors, u the candidate for
-// Q_nq (projected once), w the operator applied to the preconditioned u, and
+// 2022).  Q_0..Q_{NQ-1} are final orthonormal basis vectors, u the candidate for
+// Q_NQ (projected once), w the operator applied to the preconditioned u, and
 // coef holds a = Q^T u (found by the previous update pass), b = Q^T w, 1/nu with
 // nu = |u - Q a|, and c_j = (u . w - a . b) / nu.  Per element:
 //   q  = (u - sum_k a_k Q_k) / nu            (the reorthogonalised candidate, over u)
 //   un = (w - sum_k b_k Q_k - c_j q) / nu     (the next candidate, projected once)
 // and the dots a' = [Q q]^T un and |un|^2 for the next step:
-// partial[k] = Q_k . un (k < nq), partial[nq] = q . un, partial[nq + 1] = un . un.
+// partial[k] = Q_k . un (k < NQ), partial[NQ] = q . un, partial[NQ + 1] = un . un.
+// NQ is the exact count, as in k_orth.
 template <int NQ>
-__global__ __launch_bounds__(256) void k_dcgs_update(int64_t n, int nq, const double* __restrict__ V, int64_t ldv,
+__global__ __launch_bounds__(256) void k_dcgs_update(int64_t n, const double* __restrict__ V, int64_t ldv,
                                                      const double* __restrict__ coef, double* u,
                                                      const double* __restrict__ w, double* __restrict__ out,
                                                      double* __restrict__ partial) {
     __shared__ double sh[4];
-    __shared__ double ca[NQ], cb[NQ];
+    __shared__ double cab[2 * (NQ > 0 ? NQ : 1)];
     if (threadIdx.x < NQ) {
-        ca[threadIdx.x] = (int)threadIdx.x < nq ? coef[KC_A + threadIdx.x] : 0.0;
-        cb[threadIdx.x] = (int)threadIdx.x < nq ? coef[KC_B + threadIdx.x] : 0.0;
+        cab[threadIdx.x] = coef[KC_A + threadIdx.x];
+        cab[NQ + threadIdx.x] = coef[KC_B + threadIdx.x];
     }
     const double inv_nu = coef[KC_INV_NU];
     const double cj = coef[KC_CJ];
     __syncthreads();
-    double acc[NQ];
+    double acc[NQ > 0 ? NQ : 1];
 #pragma unroll
     for (int k = 0; k < NQ; ++k) acc[k] = 0.0;
     double accq = 0.0, nn = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        double v[NQ];
+        double v[NQ > 0 ? NQ : 1];
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) v[k] = k < nq ? V[k * ldv + e] : 0.0;
+        for (int k = 0; k < NQ; ++k) v[k] = V[k * ldv + e];
         double q = u[e];
         double un = w[e];
 #pragma unroll
         for (int k = 0; k < NQ; ++k) {
-            q -= ca[k] * v[k];
-            un -= cb[k] * v[k];
+            q -= cab[k] * v[k];
+            un -= cab[NQ + k] * v[k];
         }
         q *= inv_nu;
         un = (un - cj * q) * inv_nu;
@@ -1190,15 +1191,13 @@ __global__ __launch_bounds__(256) void k_dcgs_update(int64_t n, int nq, const do
     }
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
-        if (k < nq) {
-            const double r = block_sum(acc[k], sh);
-            if (threadIdx.x == 0) partial[(int64_t)k * KBLOCKS + blockIdx.x] = r;
-        }
+        const double r = block_sum(acc[k], sh);
+        if (threadIdx.x == 0) partial[(int64_t)k * KBLOCKS + blockIdx.x] = r;
     }
     double r = block_sum(accq, sh);
-    if (threadIdx.x == 0) partial[(int64_t)nq * KBLOCKS + blockIdx.x] = r;
+    if (threadIdx.x == 0) partial[(int64_t)NQ * KBLOCKS + blockIdx.x] = r;
     r = block_sum(nn, sh);
-    if (threadIdx.x == 0) partial[(int64_t)(nq + 1) * KBLOCKS + blockIdx.x] = r;
+    if (threadIdx.x == 0) partial[(int64_t)(NQ + 1) * KBLOCKS + blockIdx.x] = r;
 }
 
 // Final sums in a fixed order, one wavefront per slot: lane l adds the blocks
@@ -1294,23 +1293,61 @@ static unsigned stream_grid(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n, 256)));
 }
 
+// one instance per basis size 0..32
+template <template <int> class L, int... Q>
+static void by_count(int nq, std::integer_sequence<int, Q...>, const typename L<0>::Args& a) {
+    ((nq == Q ? (L<Q>::run(a), 0) : 0), ...);
+}
+
+struct OrthArgs {
+    int64_t n;
+    const double* V;
+    int64_t ldv;
+    const double* w;
+    double* partial;
+    int nblocks;
+    hipStream_t s;
+};
+template <int Q>
+struct OrthLaunch {
+    using Args = OrthArgs;
+    static void run(const OrthArgs& a) { k_orth<Q><<<a.nblocks, 256, 0, a.s>>>(a.n, a.V, a.ldv, a.w, a.partial); }
+};
+
+struct DcgsArgs {
+    int64_t n;
+    const double* V;
+    int64_t ldv;
+    const double* coef;
+    double* u;
+    const double* w;
+    double* out;
+    double* partial;
+    int nblocks;
+    hipStream_t s;
+};
+template <int Q>
+struct DcgsLaunch {
+    using Args = DcgsArgs;
+    static void run(const DcgsArgs& a) {
+        k_dcgs_update<Q><<<a.nblocks, 256, 0, a.s>>>(a.n, a.V, a.ldv, a.coef, a.u, a.w, a.out, a.partial);
+    }
+};
+
 void launch_orth(int64_t n, int nq, const double* V, int64_t ldv, const double* w, double* partial, int nblocks,
                  hipStream_t s) {
-    MB_CHECK(nq >= 0 && nq <= KMAXQ - 1 && nblocks >= 1 && nblocks <= KBLOCKS, MBAMG_E_INVALID,
+    MB_CHECK(nq >= 0 && nq <= KMAXQ - 1 && nq <= 32 && nblocks >= 1 && nblocks <= KBLOCKS, MBAMG_E_INVALID,
              "too many Krylov vectors");
-    if (nq <= 8) k_orth<8><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, w, partial);
-    else if (nq <= 16) k_orth<16><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, w, partial);
-    else k_orth<32><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, w, partial);
+    by_count<OrthLaunch>(nq, std::make_integer_sequence<int, 33>{}, OrthArgs{n, V, ldv, w, partial, nblocks, s});
     MB_LAUNCH_CHECK();
 }
 
 void launch_dcgs_update(int64_t n, int nq, const double* V, int64_t ldv, const double* coef, double* u,
                         const double* w, double* out, double* partial, int nblocks, hipStream_t s) {
-    MB_CHECK(nq >= 0 && nq <= KMAXQ - 2 && nq <= 32 && nblocks >= 1 && nblocks <= KBLOCKS, MBAMG_E_INVALID,
+    MB_CHECK(nq >= 0 && nq <= KMAXQ - 2 && nq <= 31 && nblocks >= 1 && nblocks <= KBLOCKS, MBAMG_E_INVALID,
              "too many Krylov vectors");
-    if (nq <= 8) k_dcgs_update<8><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, coef, u, w, out, partial);
-    else if (nq <= 16) k_dcgs_update<16><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, coef, u, w, out, partial);
-    else k_dcgs_update<32><<<nblocks, 256, 0, s>>>(n, nq, V, ldv, coef, u, w, out, partial);
+    by_count<DcgsLaunch>(nq, std::make_integer_sequence<int, 32>{},
+                         DcgsArgs{n, V, ldv, coef, u, w, out, partial, nblocks, s});
     MB_LAUNCH_CHECK();
 }
 
