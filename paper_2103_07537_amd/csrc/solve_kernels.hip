@@ -1210,8 +1210,17 @@ __global__ __launch_bounds__(1024) void k_orth_reduce(const double* __restrict__
     __shared__ double res[KMAXQ];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & (WAVE - 1);
     for (int q = wave; q <= nq; q += (int)(blockDim.x >> 6)) {
+        // all of a lane's loads issued before the first add (KBLOCKS / WAVE of them)
+        static_assert(KBLOCKS % WAVE == 0, "whole rounds of block partials");
+        double t[KBLOCKS / WAVE];
+#pragma unroll
+        for (int u = 0; u < KBLOCKS / WAVE; ++u) {
+            const int b = lane + u * WAVE;
+            t[u] = b < nb ? partial[(int64_t)q * KBLOCKS + b] : 0.0;
+        }
         double v = 0.0;
-        for (int b = lane; b < nb; b += WAVE) v += partial[(int64_t)q * KBLOCKS + b];
+#pragma unroll
+        for (int u = 0; u < KBLOCKS / WAVE; ++u) v += t[u];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
         if (lane == 0) res[q] = v;
