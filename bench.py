@@ -321,8 +321,8 @@ def main():
         counter_run(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in the design notes but not built)"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (sharding the hierarchy "
+                                   "over several GPUs is not implemented)"}))
         sys.exit(2)
     import torch
     from paper_2103_07537_amd import mbamg

@@ -825,13 +825,13 @@ static void finish_coarse(mbamg_hierarchy* h, hipStream_t s) {
     h->coarse_pending.reset();
 }
 
-// from: a build of the same blocks with the same level-0 parameters
+// from: a setup of the same blocks with the same level-0 parameters
 // (aggregation, precision) running at the same time; its level-0 aggregates
-// and smoother data are copied instead of recomputed.  to: this build
+// and smoother data are copied instead of recomputed.  to: this setup
 // publishes its own level-0 aggregates and smoother data there.
 static void setup_impl(mbamg_hierarchy* h, const mbamg_bsr* Ab, hipStream_t s, DonorLink* from, DonorLink* to,
                        bool defer_coarse) {
-    struct Publish {   // on every exit, whatever this build has not published is not coming
+    struct Publish {   // on every exit, whatever this setup has not published is not coming
         DonorLink* to;
         ~Publish() { if (to) to->close(); }
     } publish_guard{to};
