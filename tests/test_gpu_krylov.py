@@ -1,11 +1,12 @@
 """GMRES edges on the GPU against the oracle: restart lengths from 3 to the
 largest the library takes (31), the FP32-refined form with a short restart,
-and iteration caps that stop the solve early (NOT_CONVERGED with the true
-residual of the returned iterate)."""
+iteration caps that stop the solve early (NOT_CONVERGED with the true
+residual of the returned iterate), and the shortest restarts (1 and 2) under a
+cap."""
 import numpy as np
 import pytest
 
-from gpu_util import gpu_hierarchy, log, rel, torch_dev
+from gpu_util import assert_close, gpu_hierarchy, log, rel, torch_dev
 from paper_2103_07537_amd.inputs import make_system
 
 pytestmark = pytest.mark.gpu
@@ -51,4 +52,24 @@ def test_iteration_cap_returns_the_iterate_and_its_true_residual(cap):
         assert np.all(xg == 0.0) and info["rel_residual"] == 1.0
     else:
         assert res < 1.0
+    hg.close()
+
+
+@pytest.mark.parametrize("restart", [1, 2])
+def test_shortest_restarts_match_oracle_under_a_cap(restart):
+    """GMRES(1) and GMRES(2), which do not reach 1e-8 on this system, stopped
+    after 12 iterations on both sides: the iterates agree element by element.
+    With one basis vector per cycle the orthogonalisation never reorthogonalises
+    a candidate; with two it does once per cycle."""
+    from oracle import amg
+    s = _system()
+    ho = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=60), n_vec=s.n_vec)
+    hg = gpu_hierarchy(s, max_coarse=60, restart=restart, max_iters=12)
+    x = torch_dev(np.zeros(s.n_dofs))
+    info = hg.solve(torch_dev(s.b), x, rtol=1e-8)
+    xo, io = amg.gmres(ho, s.b, rtol=1e-8, restart=restart, max_iters=12)
+    log(f"  restart {restart}: gpu {info['iterations']} ({info['converged']}), oracle {io.iterations} "
+        f"({io.converged}), relative residual {info['rel_residual']:.3e}")
+    assert info["iterations"] == io.iterations == 12 and not info["converged"] and not io.converged
+    assert_close(x.cpu().numpy(), xo, 1e-9, f"GMRES({restart}) iterate")
     hg.close()
