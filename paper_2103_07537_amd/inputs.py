@@ -427,6 +427,23 @@ class NBlockSystem:
         return sp.bmat([[blk.to_scipy() for blk in row] for row in self.blocks], format="csr")
 
 
+def leading_components(s: BlockSystem, k: int) -> BlockSystem:
+    """The 2 x 2 system restricted to the first k components of every node of
+    both blocks (a principal submatrix, so positive real when s is): two
+    blocks of k dofs per node, for 1 <= k <= the blocks' dofs.  Every stored
+    node block is kept (possibly zero), so the block patterns do not change."""
+    if not s.co_located or s.dofs[0] != s.dofs[1] or not 1 <= k <= s.dofs[0]:
+        raise ValueError("co-located blocks with at least k dofs per node")
+    blocks = [[Bsr(n_brows=B.n_brows, n_bcols=B.n_bcols, row_ptr=B.row_ptr.copy(), col_idx=B.col_idx.copy(),
+                   vals=np.ascontiguousarray(B.vals[:, :k, :k])) for B in row] for row in s.blocks]
+    d = s.dofs[0]
+    b0 = s.b[:s.N * d].reshape(s.N, d)[:, :k]
+    b1 = s.b[s.N * d:].reshape(s.N, d)[:, :k]
+    return BlockSystem(dim=s.dim, n=s.n, N=s.N, dofs=(k, k), n_vec=(min(s.n_vec[0], k), min(s.n_vec[1], k)),
+                       blocks=blocks, b=np.concatenate([b0.reshape(-1), b1.reshape(-1)]),
+                       params=dict(s.params, components=k))
+
+
 def split_fields(s: BlockSystem, split_second: bool = True) -> NBlockSystem:
     """The 4 x 4 field split of a co-located 2 x 2 system: each block's vector
     and scalar components become fields of their own -- (u, p, b, r), with

@@ -68,3 +68,20 @@ def test_study_table_marks_unconverged_points():
     t = studies.table(rows).splitlines()
     assert t[2].startswith("| omega=0.8 | 12 |") and "precision" not in t[2]
     assert "1000 (not converged)" in t[3]
+
+
+@pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (3, 1), (3, 3)])
+def test_leading_components_is_the_principal_submatrix(dim, k):
+    """The k-component system is the rows and columns of the first k components
+    of every node of both blocks, and its right-hand side is b's same entries."""
+    from paper_2103_07537_amd.inputs import leading_components
+    s = make_system(5, dim, 0.6, seed=4, kappa="lognormal", a10_scale=0.5)
+    t = leading_components(s, k)
+    d = s.dofs[0]
+    keep = np.array([node * d + c for node in range(2 * s.N) for c in range(k)])
+    A = s.to_scipy().toarray()
+    assert t.dofs == (k, k) and t.n_dofs == 2 * s.N * k
+    assert np.array_equal(t.to_scipy().toarray(), A[np.ix_(keep, keep)])
+    assert np.array_equal(t.b, s.b[keep])
+    with pytest.raises(ValueError):
+        leading_components(s, d + 1)
