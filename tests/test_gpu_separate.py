@@ -1,6 +1,7 @@
 """Separate aggregation per block on the GPU against the oracle (Sec. 4.3.1:
 fields on different node sets, each block aggregated from its own diagonal
-block), on the mixed systems whose block 1 lives on a grid twice as coarse:
+block), on the mixed systems whose block 1 lives on a grid twice as coarse
+and on co-located blocks aggregated each on its own:
 per-block aggregates and colours identical as integers on every level, the
 Galerkin blocks with P00 != P11 element by element, V-cycles element by
 element (FP64 1e-12, FP32 1e-5), and solves (iterations within +-1, solutions
@@ -10,7 +11,7 @@ import pytest
 import scipy.sparse as sp
 
 from gpu_util import assert_close, gpu_hierarchy, log, rel, torch_dev
-from paper_2103_07537_amd.inputs import make_mixed_system
+from paper_2103_07537_amd.inputs import make_mixed_system, make_system
 
 pytestmark = pytest.mark.gpu
 
@@ -18,6 +19,9 @@ CASES = {
     "2d-41-mixed": lambda: make_mixed_system(41, 2, 0.8, seed=3, kappa="lognormal"),
     "2d-13-mixed": lambda: make_mixed_system(13, 2, 1.5, seed=7),
     "3d-15-mixed": lambda: make_mixed_system(15, 3, 0.6, seed=5, kappa="lognormal"),
+    # co-located fields aggregated separately: the second strength graph and MIS-2
+    # run on A11's own pattern and values over the same nodes
+    "2d-23-colocated": lambda: make_system(23, 2, 0.7, seed=3, kappa="lognormal", blk1_scale=2.0, a10_scale=0.5),
 }
 
 
@@ -73,7 +77,7 @@ def test_separate_vcycle_matches_oracle(case, precision):
     hg.close()
 
 
-@pytest.mark.parametrize("case", ["2d-41-mixed", "3d-15-mixed"])
+@pytest.mark.parametrize("case", ["2d-41-mixed", "3d-15-mixed", "2d-23-colocated"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_separate_solve_matches_oracle(case, precision):
     from oracle import amg
@@ -118,3 +122,31 @@ def test_separate_level_cap_threshold_and_seed_match_oracle(kw):
     hg.vcycle(torch_dev(r), z)
     assert_close(z.cpu().numpy(), amg.vcycle(ho, r), 1e-12)
     hg.close()
+
+
+def test_colocated_separate_aggregation_reproduces_cloning():
+    """Co-located blocks whose strength graphs give the same aggregates (here
+    A11 is a scaled copy of A00's structure): aggregating each block on its own
+    builds the cloned hierarchy -- the same aggregates, coarse operators and
+    V-cycle."""
+    s = CASES["2d-23-colocated"]()
+    hs = gpu_hierarchy(s, clone_aggregates=0, max_coarse=60)
+    hc = gpu_hierarchy(s, max_coarse=60)
+    assert hs.num_levels() == hc.num_levels() >= 3
+    for l in range(hc.num_levels() - 1):
+        assert np.array_equal(hs.aggregates(l, 0), hc.aggregates(l, 0))
+        assert np.array_equal(hs.aggregates(l, 1), hc.aggregates(l, 0))
+    for l in range(1, hc.num_levels()):
+        for f in range(2):
+            for g in range(2):
+                rs, cs, vs = hs.level_block(l, f, g)
+                rc, cc, vc = hc.level_block(l, f, g)
+                assert np.array_equal(rs, rc) and np.array_equal(cs, cc)
+                assert np.max(np.abs(vs - vc)) <= 1e-13 * np.max(np.abs(vc))
+    r = np.random.default_rng(71).standard_normal(s.n_dofs)
+    zs, zc = torch_dev(np.zeros(s.n_dofs)), torch_dev(np.zeros(s.n_dofs))
+    hs.vcycle(torch_dev(r), zs)
+    hc.vcycle(torch_dev(r), zc)
+    assert_close(zs.cpu().numpy(), zc.cpu().numpy(), 1e-12, "separate against cloned V-cycle")
+    hs.close()
+    hc.close()
