@@ -280,7 +280,10 @@ mbamg_status mbamg_mlp_adam(float* params, const float* grad, float* m, float* v
  * iters >= 5.  Synchronous. */
 mbamg_status mbamg_probe(mbamg_hierarchy* h, int32_t iters, uint64_t seed, double* rho, void* hip_stream);
 
-/* Change the uniform smoother damping (levels without per-aggregate damping). */
+/* Change the uniform smoother damping omega (Algorithm 1's damping of each block
+ * update) of levels without per-aggregate damping, and of a judged learned
+ * hierarchy's fixed-weight fallback.  omega must be finite and > 0
+ * (MBAMG_E_INVALID otherwise).  Host only; takes effect from the next V-cycle. */
 mbamg_status mbamg_set_omega(mbamg_hierarchy* h, double omega);
 
 /* ---- measurement -------------------------------------------------------- */

@@ -2406,7 +2406,7 @@ mbamg_status mbamg_setup(const mbamg_bsr* A_blocks, const mbamg_field_map* fm, c
             MB_CHECK(fm->dofs[0] >= 1 && fm->dofs[0] <= 4 && fm->dofs[1] == fm->dofs[0], MBAMG_E_INVALID,
                      "both blocks must have the same 1..4 dofs per node");
         }
-        MB_CHECK(p->omega > 0.0 && p->bgs_sweeps >= 1 && p->inner_sweeps >= 1 && p->max_levels >= 1 &&
+        MB_CHECK(p->omega > 0.0 && std::isfinite(p->omega) && p->bgs_sweeps >= 1 && p->inner_sweeps >= 1 && p->max_levels >= 1 &&
                      p->restart >= 1 && p->restart <= KMAXQ - 2 && p->max_iters >= 0 && p->theta >= 0.0,
                  MBAMG_E_INVALID, "invalid parameters");
         MB_CHECK(p->clone_aggregates != 0 || (p->learned == 0 && p->omega_p == 0.0 && p->smoother == 0),
@@ -2789,8 +2789,13 @@ mbamg_status mbamg_probe(mbamg_hierarchy* h, int32_t iters, uint64_t seed, doubl
 }
 
 mbamg_status mbamg_set_omega(mbamg_hierarchy* h, double omega) {
-    if (!h || !(omega > 0.0)) { g_last_error = "bad argument"; return MBAMG_E_INVALID; }
+    if (!h || !(omega > 0.0) || !std::isfinite(omega)) {
+        g_last_error = "omega must be finite and > 0";
+        return MBAMG_E_INVALID;
+    }
     h->p.omega = omega;
+    // a judged learned hierarchy's fixed-weight fallback smooths with the same damping
+    if (h->fallback) h->fallback->p.omega = omega;
     return MBAMG_OK;
 }
 

@@ -203,3 +203,31 @@ def test_ratio_stop_on_the_finest_level_is_a_direct_solve():
     ref = np.linalg.solve(s.to_scipy().toarray(), s.b)
     assert_close(z.cpu().numpy(), ref, 1e-11, "one-level V-cycle")
     hg.close()
+
+
+def test_set_omega_equals_a_hierarchy_built_with_it():
+    """Changing the smoother damping of a built hierarchy gives, bit for bit, the
+    V-cycle of a hierarchy set up with that damping, and the oracle's; a damping
+    that is not finite and positive is refused, there and at setup."""
+    from oracle import amg
+    from paper_2103_07537_amd import mbamg
+    s = make_system(23, 2, 0.7, seed=3, blk1_scale=2.0, a10_scale=0.5)
+    hg = gpu_hierarchy(s, max_coarse=60)
+    hg.set_omega(0.55)
+    fresh = gpu_hierarchy(s, max_coarse=60, omega=0.55)
+    ho = amg.setup(s.blocks, s.dofs, amg.Params(max_coarse=60, omega=0.55), n_vec=s.n_vec)
+    r = np.random.default_rng(91).standard_normal(s.n_dofs)
+    z1, z2 = torch_dev(np.zeros(s.n_dofs)), torch_dev(np.zeros(s.n_dofs))
+    hg.vcycle(torch_dev(r), z1)
+    fresh.vcycle(torch_dev(r), z2)
+    assert np.array_equal(z1.cpu().numpy(), z2.cpu().numpy())
+    assert_close(z1.cpu().numpy(), amg.vcycle(ho, r), 1e-12, "V-cycle after set_omega")
+    for bad in (0.0, -0.5, float("nan"), float("inf")):
+        with pytest.raises(mbamg.MbamgError) as e:
+            hg.set_omega(bad)
+        assert e.value.code == -1
+    with pytest.raises(mbamg.MbamgError) as e:
+        gpu_hierarchy(s, max_coarse=60, omega=float("inf"))
+    assert e.value.code == -1
+    hg.close()
+    fresh.close()
